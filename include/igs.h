@@ -1,0 +1,240 @@
+/*
+ * igs.h -- C ABI of the surrogate-matrix isogeometric assembly library
+ * (libigs.so, HIP kernels for gfx950).
+ *
+ * The method: Drzisga, Keith & Wohlmuth, "The surrogate matrix methodology:
+ * Low-cost assembly for isogeometric analysis".  Section references below are
+ * to that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Discretisation (Sec. 2.2): single patch, parametric domain (0,1)^n,
+ *   n in {2,3}; tensor-product B-splines of uniform degree p on open uniform
+ *   knot vectors with nelem[d] elements in direction d; m[d] = nelem[d] + p
+ *   functions per direction; N = prod m[d] dofs per problem.
+ * - Dof index (Sec. 2.2, colexicographic): i = i1 + m1*(i2 + m2*i3), 0-based.
+ * - Stencils (Sec. 3.2): row i couples to j = i + delta, delta in [-p,p]^n;
+ *   S = (2p+1)^n slots per row; slot s = sum_d (delta_d + p)(2p+1)^(d-1),
+ *   delta_1 fastest, so slots are ordered like the colex offset of delta and
+ *   the centre slot (S-1)/2 is the diagonal.  "Upper" slots are s > (S-1)/2
+ *   (j > i in the dof order, Sec. 5.2).
+ * - Band layout (stencil-major): band[b][s][k], b < batch, s < S, k < ld,
+ *   where ld = N rounded up to a multiple of 64 (igs_band_layout).  Entry
+ *   band[b][s][i] = A_{i, i+delta_s}; it is 0 when i+delta_s leaves the index
+ *   box.  Padding k in [N, ld) is written as 0.
+ * - Vectors are [batch][N], contiguous.
+ * - Device memory: every pointer marked "device" must be device memory (or
+ *   host-coherent memory visible to the GPU) owned by the caller.  The library
+ *   keeps no pointer after a call returns and holds no global mutable state;
+ *   scratch memory is taken stream-ordered from the default memory pool and
+ *   returned before the call returns.
+ * - stream: a hipStream_t passed as void* (NULL = the null stream).
+ * - Errors: every entry point returns an igs_status.  Argument errors are
+ *   detected on the host before any GPU work is queued.  Assembly entry points
+ *   synchronise `stream` before returning so that a geometry map that folds
+ *   (det J <= 0 at a quadrature point) is reported as IGS_ERR_GEOMETRY; the
+ *   band contents are then unspecified.
+ */
+#ifndef IGS_H
+#define IGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum igs_status {
+  IGS_OK = 0,
+  IGS_ERR_ARG = -1,         /* null pointer, bad enum, bad size */
+  IGS_ERR_UNSUPPORTED = -2, /* valid input outside what this build implements */
+  IGS_ERR_KNOTS = -3,       /* a supplied knot vector is not open uniform */
+  IGS_ERR_SAMPLES = -4,     /* fewer than q+1 samples, or no analysis-domain rows */
+  IGS_ERR_GEOMETRY = -5,    /* det J <= 0 at a quadrature point */
+  IGS_ERR_HIP = -6,         /* a HIP runtime call failed */
+  IGS_ERR_NOMEM = -7,       /* scratch allocation failed */
+  IGS_NOT_CONVERGED = 1,    /* solver stopped at maxit */
+  IGS_BREAKDOWN = 2         /* CG: p^T A p <= 0 or a non-finite value */
+} igs_status;
+
+typedef enum igs_form { IGS_STIFFNESS = 0, IGS_MASS = 1 } igs_form;
+typedef enum igs_dtype { IGS_F64 = 0, IGS_F32 = 1 } igs_dtype;
+
+/* Geometry map F: (0,1)^n -> R^n (Sec. 2.1 single patch; the paper builds F
+ * from NURBS, here it is analytic).
+ *   IDENTITY: F(xi) = xi.
+ *   SINE (amplitude a):
+ *     n=2: F = (xi1 + a sin(pi xi1) sin(2 pi xi2), xi2 + a sin(2 pi xi1) sin(pi xi2))
+ *     n=3: F = xi + a (s(pi xi1)s(2pi xi2)s(pi xi3), s(2pi xi1)s(pi xi2)s(pi xi3),
+ *                      s(pi xi1)s(pi xi2)s(2pi xi3)),  s = sin
+ *   POLY2 (amplitude a): F_r = xi_r + a (r+1) prod_d xi_d (1 - xi_d), r 0-based;
+ *     every component lies in Q_2 (used for the mass reproduction property,
+ *     Corollary MassMatrixReproduction). */
+typedef enum igs_geom_kind { IGS_GEOM_IDENTITY = 0, IGS_GEOM_SINE = 1, IGS_GEOM_POLY2 = 2 } igs_geom_kind;
+
+typedef struct igs_geometry {
+  int32_t kind;  /* igs_geom_kind */
+  double a;      /* amplitude */
+} igs_geometry;
+
+/* Diffusion coefficient kappa of the stiffness form a(u,v) = int kappa grad u . grad v
+ * (Sec. 3.2 eq. BilinearFormPoissonTensor with K scaled by kappa).
+ *   CONST:      kappa = c0
+ *   SINE3:      kappa = c0 + amp sin(2pi x1) cos(2pi x2) [sin(2pi x3)], x = F(xi)
+ *   SPLINE:     kappa = g(xi) = sum_k c_k N_k(xi)
+ *   EXP_SPLINE: kappa = exp(g(xi))
+ * g is a tensor B-spline of degree `degree` on open uniform knots over the
+ * parametric domain with ncoef[d] functions in direction d; its control values
+ * `coef` are device memory, [batch][prod ncoef], colex (k1 fastest).  The mass
+ * form ignores kappa. */
+typedef enum igs_coef_kind {
+  IGS_COEF_CONST = 0, IGS_COEF_SINE3 = 1, IGS_COEF_SPLINE = 2, IGS_COEF_EXP_SPLINE = 3
+} igs_coef_kind;
+
+typedef struct igs_coef {
+  int32_t kind;        /* igs_coef_kind */
+  double c0, amp;
+  int32_t degree;      /* spline kinds: 1..5 */
+  int32_t ncoef[3];    /* spline kinds: functions per direction, degree < ncoef[d] <= 64 */
+  const double* coef;  /* spline kinds: device, [batch][prod ncoef] */
+} igs_coef;
+
+/* The problem (Sec. 2): knots, degree, geometry, coefficient. */
+typedef struct igs_problem {
+  int32_t n;                 /* 2 or 3 */
+  int32_t p;                 /* 1..4 */
+  int32_t nelem[3];          /* elements per direction (entries >= n ignored) */
+  int32_t nquad;             /* Gauss points per direction per element; 0 or p+1 */
+  int32_t batch;             /* >= 1 independent problems (differ only in coef) */
+  const double* knots[3];    /* host, optional: NULL = open uniform; else m+p+1
+                                values that must form the open uniform vector */
+  igs_geometry geom;
+  igs_coef coef;
+} igs_problem;
+
+/* Sizes of the band for a problem (host-only, no GPU call). */
+typedef struct igs_layout {
+  int32_t m[3];        /* functions per direction (1 for unused directions) */
+  int32_t slots;       /* S = (2p+1)^n */
+  int32_t upper;       /* (S-1)/2 upper slots */
+  int64_t N;           /* dofs per problem */
+  int64_t ld;          /* slot stride of the band, N rounded up to 64 */
+  int64_t band_elems;  /* batch * S * ld */
+} igs_layout;
+
+/* Sampling of the surrogate (host-only): sample lattice and row classes. */
+typedef struct igs_surrogate_info {
+  int32_t samples[3];        /* samples per direction */
+  int32_t interior[3];       /* analysis-domain indices per direction, m - 4p */
+  int64_t sample_rows;       /* prod samples */
+  int64_t boundary_rows;     /* rows outside the analysis domain */
+  int64_t quadrature_rows;   /* boundary_rows + sample_rows */
+} igs_surrogate_info;
+
+typedef struct igs_cg_info {
+  int32_t iterations;        /* total CG iterations (inner FP32 ones in mixed mode) */
+  int32_t outer_iterations;  /* refinement steps (0 in plain FP64 mode) */
+  int32_t status;            /* igs_status of the solve */
+  double relres;             /* max over batch of ||f_I - A_II u_I||_2 / ||f_I||_2, FP64 */
+} igs_cg_info;
+
+/* ---------------------------------------------------------------- queries */
+
+/* Band sizes.  IGS_ERR_ARG for invalid problems.  Host only. */
+igs_status igs_band_layout(const igs_problem* pb, igs_layout* out);
+
+/* Validate a problem (and, for M >= 1, the sampling M, q).  Host only. */
+igs_status igs_validate(const igs_problem* pb, int32_t M, int32_t q);
+
+/* Sample lattice (Sec. 8): in each direction start at the first analysis-domain
+ * index 2p, take every M-th index and append the last one, m-2p-1, if M does
+ * not land on it.  `indices` (host, optional) receives the concatenated sample
+ * indices per direction.  Host only. */
+igs_status igs_surrogate_layout(const igs_problem* pb, int32_t M, int32_t q, igs_surrogate_info* out,
+                                int32_t* indices, int32_t capacity);
+
+const char* igs_status_string(int32_t status);
+const char* igs_version(void);
+
+/* -------------------------------------------------------------- assembly */
+
+/* Full assembly: every row by Gauss quadrature with nquad^n points per element
+ * (Sec. 3.2, eqs. ChangeOfVars and StencilFunction evaluated row by row).
+ * form: IGS_STIFFNESS (kappa-weighted, pulled back by K = |det J| J^-1 J^-T,
+ * eq. BilinearFormPoissonTensor) or IGS_MASS (int B_i B_j |det J|).
+ * dtype: storage type of `band` (device, igs_layout.band_elems elements).
+ * Arithmetic is FP64; IGS_F32 rounds on store.  Synchronous on return. */
+igs_status igs_assemble_exact(const igs_problem* pb, int32_t form, int32_t dtype, void* band, void* stream);
+
+/* Surrogate assembly (Secs. 4, 5, 8).  Rows outside the analysis domain
+ * [2p, m-2p-1]^n and the rows of the sample lattice (igs_surrogate_layout) are
+ * assembled by quadrature; for every upper stencil delta the sample values are
+ * interpolated by the tensor-product degree-q spline whose knots are the
+ * samples (odd q: not-a-knot interior knots s_{(q+1)/2}..s_{S-1-(q+1)/2};
+ * even q: midpoints), and
+ *   stiffness, eq. 5.1c: upper entries with i, j in the analysis domain are
+ *     Phi~_delta(i); lower ones copy the transposed upper entry; other
+ *     off-diagonal entries are the exact A_ij (copied from row j's
+ *     quadrature); the diagonal of analysis-domain rows is -sum_{k!=i} A~_ik;
+ *   mass, eq. 5.1b: as above with the diagonal interpolated too.
+ * M = 1 reproduces igs_assemble_exact to rounding.  q in 1..5.
+ * dtype IGS_F32 is the precision form: quadrature in FP64 rounded on store,
+ * interpolation evaluated in FP32 from FP64-fitted coefficients, FP32
+ * diagonal sums.  Synchronous on return. */
+igs_status igs_assemble_surrogate(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype,
+                                  void* band, void* stream);
+
+/* Load vector F(B_i) = int_Omega f B_i dx (Sec. 6, eq. PoissonWeakForm) by
+ * the same quadrature; source 0: f = c, source 1: f = c prod_d sin(pi x_d),
+ * x = F(xi).  f: device [batch][N] FP64.  Synchronous on return. */
+igs_status igs_assemble_rhs(const igs_problem* pb, int32_t source, double c, double* f, void* stream);
+
+/* ---------------------------------------------------------------- solve */
+
+/* y = A x with the band of `dtype` (x, y of the same type, device [batch][N]).
+ * dirichlet != 0 applies the Dirichlet restriction of Sec. 8 (remark on
+ * boundary conditions, eq. BlockSystem): x is read as 0 and y is written 0 on
+ * dofs with some i_d in {0, m_d-1}.  FP32 bands accumulate in FP32.
+ * Asynchronous. */
+igs_status igs_apply(const igs_problem* pb, int32_t dtype, const void* band, const void* x, void* y,
+                     int32_t dirichlet, void* stream);
+
+/* Conjugate gradients for A_II u_I = f_I with homogeneous Dirichlet dofs
+ * (Sec. 8, eq. BlockSystem with u_D = 0), per problem of the batch.
+ * band64: device FP64 band (required).  band32: optional device FP32 band of
+ * the same matrix; when given, FP32 CG runs inside FP64 iterative refinement
+ * (residual f - A64 u in FP64, correction from FP32 CG on A32, update in FP64).
+ * f: device [batch][N]; u: device [batch][N], in: initial guess (Dirichlet
+ * entries ignored), out: solution with u_D = 0.  Stops when the FP64 residual
+ * satisfies ||f_I - A_II u_I||_2 <= rtol ||f_I||_2 for every problem, or after
+ * maxit CG iterations (IGS_NOT_CONVERGED).  info (host) receives counts and
+ * the final FP64 relative residual.  Synchronous on return. */
+igs_status igs_solve_cg(const igs_problem* pb, const double* band64, const float* band32, const double* f,
+                        double* u, double rtol, int32_t maxit, igs_cg_info* info, void* stream);
+
+/* -------------------------------------------------------------- adjoint */
+
+/* Vector-Jacobian product of y = A~(c) x (surrogate with M, q; M = 0 means
+ * exact assembly), for spline coefficients (IGS_COEF_SPLINE/EXP_SPLINE):
+ *   xbar = A~^T ybar = A~ ybar         (device [batch][N], optional)
+ *   cbar = d(ybar^T A~(c) x)/dc         (device [batch][prod ncoef], optional)
+ * A~ is linear in the quadrature entries, so cbar pushes the weights
+ * ybar_i x_j through the transpose of the surrogate construction onto the
+ * quadrature rows and contracts them with dA_ij/dc_k = int dkappa/dc_k
+ * grad B_i^T K grad B_j, recomputing Jacobians at the quadrature points.
+ * band64 (device) must hold A~(c) when xbar is requested.  n = 2 only in this
+ * build (IGS_ERR_UNSUPPORTED otherwise).  Synchronous on return. */
+igs_status igs_apply_vjp(const igs_problem* pb, int32_t M, int32_t q, const double* band64, const double* x,
+                         const double* ybar, double* xbar, double* cbar, void* stream);
+
+/* Gradient of the compliance J = f^T u, A~(c) u = f (u_D = 0):
+ * dJ/dc = -u^T (dA~/dc) u (self-adjoint, no second solve).  u: device
+ * [batch][N]; cbar: device [batch][prod ncoef].  Synchronous on return. */
+igs_status igs_compliance_grad(const igs_problem* pb, int32_t M, int32_t q, const double* u, double* cbar,
+                               void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IGS_H */

@@ -1,0 +1,377 @@
+// extern "C" entry points of libigs (declared in include/igs.h).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "igs_internal.h"
+
+namespace igs {
+
+// launchers defined in the kernel translation units
+template <typename OutT>
+hipError_t launch_quad(const KProblem& kp, int form, const QTile* tiles, int ntiles, OutT* band, hipStream_t s);
+hipError_t launch_rhs(const KProblem& kp, const QTile* tiles, int ntiles, int src, double c, double* f, hipStream_t s);
+void quad_tile_shape(int n, int p, int* tx, int* ty);
+void rhs_tile_shape(int n, int* tx, int* ty);
+template <typename BT>
+hipError_t launch_fit(const KInterp<double>& ip, int n, int m1, int m2, int64_t ld, int S, int batch, const BT* band,
+                      double* tmp0, double* tmp1, double* coef, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(const KInterp<T>& ip, int form, int n, int p, int m1, int m2, int64_t ld, int S, int batch,
+                       const double* coef, T* band, hipStream_t s);
+template <typename T>
+size_t fill_lds_bytes(const KInterp<T>& ip, int n, int p);
+void fill_tile_box(int n, int p, int box[3]);
+template <typename T>
+hipError_t launch_zero_pad(T* band, int64_t N, int64_t ld, int slots_total, hipStream_t s);
+igs_status launch_apply(const Dims& d, int dtype, const void* band, const void* x, void* y, int dirichlet,
+                        hipStream_t s);
+igs_status solve_cg(const Dims& d, const double* band64, const float* band32, const double* f, double* u, double rtol,
+                    int maxit, igs_cg_info* info, hipStream_t s);
+igs_status adjoint_weights_grad(const igs_problem* pb, const Dims& d, const KProblem& kp, int M, int q,
+                                const double* x, const double* ybar, double* cbar, hipStream_t s);
+
+#define HIP_TRY(x)                             \
+  do {                                         \
+    if ((x) != hipSuccess) return IGS_ERR_HIP; \
+  } while (0)
+
+// Device copy of the 1-D tables plus the error word.
+struct Prepared {
+  Dims d;
+  HostTables ht;
+  KProblem kp;
+  Arena ar;
+};
+
+template <typename V>
+static size_t vbytes(const V& v) {
+  return padded(v.size() * sizeof(typename V::value_type));
+}
+
+template <typename V>
+static auto* upload(Arena& ar, const V& v, hipStream_t s, igs_status* st) {
+  using E = typename V::value_type;
+  E* p = ar.take<E>(v.size());
+  if (hipMemcpyAsync(p, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice, s) != hipSuccess) *st = IGS_ERR_HIP;
+  return static_cast<const E*>(p);
+}
+
+static igs_status prepare(const igs_problem* pb, hipStream_t s, Prepared* P) {
+  igs_status st = make_dims(pb, &P->d);
+  if (st != IGS_OK) return st;
+  build_tables(pb, P->d, &P->ht);
+  size_t bytes = padded(sizeof(int));
+  for (int k = 0; k < P->d.n; ++k)
+    bytes += vbytes(P->ht.x[k]) + vbytes(P->ht.w[k]) + vbytes(P->ht.bv[k]) + vbytes(P->ht.bd[k]) +
+             vbytes(P->ht.trig[k]) + vbytes(P->ht.cb[k]) + vbytes(P->ht.cf[k]);
+  st = P->ar.alloc(bytes, s);
+  if (st != IGS_OK) return st;
+  KProblem& kp = P->kp;
+  std::memset(&kp, 0, sizeof(kp));
+  kp.n = P->d.n;
+  kp.p = P->d.p;
+  kp.nq = P->d.nq;
+  for (int k = 0; k < 3; ++k) {
+    kp.nelem[k] = P->d.nelem[k];
+    kp.m[k] = P->d.m[k];
+  }
+  kp.N = P->d.N;
+  kp.ld = P->d.ld;
+  kp.S = P->d.S;
+  kp.batch = P->d.batch;
+  kp.geom = pb->geom.kind;
+  kp.ga = pb->geom.a;
+  kp.coef = pb->coef.kind;
+  kp.c0 = pb->coef.c0;
+  kp.camp = pb->coef.amp;
+  const bool spline = kp.coef == IGS_COEF_SPLINE || kp.coef == IGS_COEF_EXP_SPLINE;
+  kp.cdeg = spline ? pb->coef.degree : 0;
+  kp.cstride = 1;
+  for (int k = 0; k < 3; ++k) {
+    kp.cn[k] = (spline && k < kp.n) ? pb->coef.ncoef[k] : 1;
+    kp.cstride *= kp.cn[k];
+  }
+  kp.cc = spline ? pb->coef.coef : nullptr;
+  kp.flag = P->ar.take<int>(1);
+  HIP_TRY(hipMemsetAsync(kp.flag, 0, sizeof(int), s));
+  for (int k = 0; k < kp.n; ++k) {
+    kp.t[k].x = upload(P->ar, P->ht.x[k], s, &st);
+    kp.t[k].w = upload(P->ar, P->ht.w[k], s, &st);
+    kp.t[k].bv = upload(P->ar, P->ht.bv[k], s, &st);
+    kp.t[k].bd = upload(P->ar, P->ht.bd[k], s, &st);
+    kp.t[k].trig = upload(P->ar, P->ht.trig[k], s, &st);
+    kp.t[k].cb = upload(P->ar, P->ht.cb[k], s, &st);
+    kp.t[k].cf = upload(P->ar, P->ht.cf[k], s, &st);
+  }
+  return st;
+}
+
+static igs_status finish(const Prepared& P, hipStream_t s) {
+  int flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, P.kp.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return (flag & 1) ? IGS_ERR_GEOMETRY : IGS_OK;
+}
+
+static int pick_zchunk(const Dims& d, int tx, int ty) {
+  const int mz = d.n == 3 ? d.m[2] : d.m[1];
+  int64_t base = int64_t((d.m[0] + tx - 1) / tx) * (d.n == 3 ? (d.m[1] + ty - 1) / ty : 1) * d.batch;
+  int64_t chunks = std::max<int64_t>(1, (2048 + base - 1) / base);
+  int zc = int((mz + chunks - 1) / chunks);
+  return std::max(zc, std::min(mz, 4 * (d.p + 1)));
+}
+
+template <typename OutT>
+static igs_status exact_t(const igs_problem* pb, int form, OutT* band, hipStream_t s) {
+  Prepared P;
+  igs_status st = prepare(pb, s, &P);
+  if (st != IGS_OK) return st;
+  int tx, ty;
+  quad_tile_shape(P.d.n, P.d.p, &tx, &ty);
+  std::vector<QTile> tiles = tiles_all(P.d, tx, ty, pick_zchunk(P.d, tx, ty));
+  Arena ta;
+  st = ta.alloc(padded(tiles.size() * sizeof(QTile)), s);
+  if (st != IGS_OK) return st;
+  const QTile* dt = upload(ta, tiles, s, &st);
+  if (st != IGS_OK) return st;
+  HIP_TRY(launch_quad<OutT>(P.kp, form, dt, int(tiles.size()), band, s));
+  HIP_TRY(launch_zero_pad<OutT>(band, P.d.N, P.d.ld, P.d.S * P.d.batch, s));
+  return finish(P, s);
+}
+
+template <typename T>
+static KInterp<T> interp_view(const HostInterp& hi, const Dims& d, Arena& ar, hipStream_t s, igs_status* st,
+                              const std::vector<T> eb[3]) {
+  KInterp<T> ip;
+  std::memset(&ip, 0, sizeof(ip));
+  ip.q = hi.q;
+  for (int k = 0; k < 3; ++k) {
+    if (k < d.n) {
+      ip.Sd[k] = int(hi.samp[k].size());
+      ip.lo[k] = 2 * d.p;
+      ip.hi[k] = d.m[k] - 2 * d.p - 1;
+      ip.samp[k] = upload(ar, hi.samp[k], s, st);
+      ip.ginv[k] = upload(ar, hi.ginv[k], s, st);
+      ip.ef[k] = upload(ar, hi.ef[k], s, st);
+      ip.eb[k] = upload(ar, eb[k], s, st);
+    } else {
+      ip.Sd[k] = 1;
+      ip.lo[k] = 0;
+      ip.hi[k] = 0;
+    }
+    ip.nc[k] = hi.nc[k];
+  }
+  ip.nup = int(hi.upslot.size());
+  ip.upslot = upload(ar, hi.upslot, s, st);
+  return ip;
+}
+
+static igs_status check_sampling(const Dims& d, int M, int q) {
+  if (M < 1) return IGS_ERR_ARG;
+  if (q < 1 || q > kMaxQ) return q < 1 ? IGS_ERR_ARG : IGS_ERR_UNSUPPORTED;
+  for (int k = 0; k < d.n; ++k) {
+    std::vector<int> s;
+    igs_status st = sample_lattice(d.m[k], d.p, M, &s);
+    if (st != IGS_OK) return st;
+    if (int(s.size()) < q + 1) return IGS_ERR_SAMPLES;
+  }
+  return IGS_OK;
+}
+
+template <typename OutT>
+static igs_status surrogate_t(const igs_problem* pb, int form, int M, int q, OutT* band, hipStream_t s) {
+  Prepared P;
+  igs_status st = prepare(pb, s, &P);
+  if (st != IGS_OK) return st;
+  const Dims& d = P.d;
+  st = check_sampling(d, M, q);
+  if (st != IGS_OK) return st;
+  HostInterp hi;
+  int box[3];
+  fill_tile_box(d.n, d.p, box);
+  st = build_interp(d, form, M, q, box, &hi);
+  if (st != IGS_OK) return st;
+  std::vector<OutT> ebT[3];
+  for (int k = 0; k < d.n; ++k) ebT[k].assign(hi.eb[k].begin(), hi.eb[k].end());
+  int tx, ty;
+  quad_tile_shape(d.n, d.p, &tx, &ty);
+  std::vector<QTile> tiles = tiles_surrogate(d, hi.samp, tx, ty, pick_zchunk(d, tx, ty));
+  size_t per = 1;
+  for (int k = 0; k < d.n; ++k) per *= hi.samp[k].size();
+  const size_t ncoef = per * hi.upslot.size() * d.batch;
+  size_t bytes = padded(tiles.size() * sizeof(QTile)) + 3 * padded(ncoef * sizeof(double)) +
+                 padded(hi.upslot.size() * sizeof(int)) * 2;
+  for (int k = 0; k < d.n; ++k)
+    bytes += 2 * (vbytes(hi.samp[k]) + vbytes(hi.ginv[k]) + vbytes(hi.ef[k]) + vbytes(hi.eb[k]));
+  Arena ta;
+  st = ta.alloc(bytes, s);
+  if (st != IGS_OK) return st;
+  const QTile* dt = upload(ta, tiles, s, &st);
+  KInterp<double> ip64 = interp_view<double>(hi, d, ta, s, &st, hi.eb);
+  KInterp<OutT> ipT = interp_view<OutT>(hi, d, ta, s, &st, ebT);
+  double* tmp0 = ta.take<double>(ncoef);
+  double* tmp1 = ta.take<double>(ncoef);
+  double* coef = ta.take<double>(ncoef);
+  if (st != IGS_OK) return st;
+  if (fill_lds_bytes<OutT>(ipT, d.n, d.p) > 160 * 1024) return IGS_ERR_UNSUPPORTED;
+  HIP_TRY(launch_quad<OutT>(P.kp, form, dt, int(tiles.size()), band, s));
+  HIP_TRY(launch_fit<OutT>(ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, tmp0, tmp1, coef, s));
+  HIP_TRY(launch_fill<OutT>(ipT, form, d.n, d.p, d.m[0], d.m[1], d.ld, d.S, d.batch, coef, band, s));
+  HIP_TRY(launch_zero_pad<OutT>(band, d.N, d.ld, d.S * d.batch, s));
+  return finish(P, s);
+}
+
+}  // namespace igs
+
+using namespace igs;
+
+extern "C" {
+
+igs_status igs_band_layout(const igs_problem* pb, igs_layout* out) {
+  if (!out) return IGS_ERR_ARG;
+  Dims d;
+  igs_status st = make_dims(pb, &d);
+  if (st != IGS_OK) return st;
+  for (int k = 0; k < 3; ++k) out->m[k] = d.m[k];
+  out->slots = d.S;
+  out->upper = (d.S - 1) / 2;
+  out->N = d.N;
+  out->ld = d.ld;
+  out->band_elems = int64_t(d.batch) * d.S * d.ld;
+  return IGS_OK;
+}
+
+igs_status igs_validate(const igs_problem* pb, int32_t M, int32_t q) {
+  Dims d;
+  igs_status st = make_dims(pb, &d);
+  if (st != IGS_OK) return st;
+  if (M >= 1 || q != 0) return check_sampling(d, M, q);
+  return IGS_OK;
+}
+
+igs_status igs_surrogate_layout(const igs_problem* pb, int32_t M, int32_t q, igs_surrogate_info* out, int32_t* indices,
+                                int32_t capacity) {
+  if (!out) return IGS_ERR_ARG;
+  Dims d;
+  igs_status st = make_dims(pb, &d);
+  if (st != IGS_OK) return st;
+  st = check_sampling(d, M, q);
+  if (st != IGS_OK) return st;
+  std::memset(out, 0, sizeof(*out));
+  int64_t interior = 1;
+  int64_t samples = 1;
+  int pos = 0;
+  for (int k = 0; k < 3; ++k) {
+    if (k >= d.n) {
+      out->samples[k] = 1;
+      out->interior[k] = 1;
+      continue;
+    }
+    std::vector<int> s;
+    sample_lattice(d.m[k], d.p, M, &s);
+    out->samples[k] = int(s.size());
+    out->interior[k] = d.m[k] - 4 * d.p;
+    interior *= out->interior[k];
+    samples *= int64_t(s.size());
+    if (indices) {
+      if (pos + int(s.size()) > capacity) return IGS_ERR_ARG;
+      for (int v : s) indices[pos++] = v;
+    }
+  }
+  out->sample_rows = samples;
+  out->boundary_rows = d.N - interior;
+  out->quadrature_rows = out->boundary_rows + samples;
+  return IGS_OK;
+}
+
+const char* igs_status_string(int32_t status) {
+  switch (status) {
+    case IGS_OK: return "ok";
+    case IGS_ERR_ARG: return "invalid argument";
+    case IGS_ERR_UNSUPPORTED: return "unsupported by this build";
+    case IGS_ERR_KNOTS: return "knot vector is not open uniform";
+    case IGS_ERR_SAMPLES: return "too few samples for the interpolation degree";
+    case IGS_ERR_GEOMETRY: return "geometry map folds (det J <= 0 at a quadrature point)";
+    case IGS_ERR_HIP: return "HIP runtime error";
+    case IGS_ERR_NOMEM: return "out of device memory";
+    case IGS_NOT_CONVERGED: return "not converged within maxit";
+    case IGS_BREAKDOWN: return "CG breakdown";
+    default: return "unknown status";
+  }
+}
+
+const char* igs_version(void) { return "igs 0.1.0 (gfx950)"; }
+
+igs_status igs_assemble_exact(const igs_problem* pb, int32_t form, int32_t dtype, void* band, void* stream) {
+  if (!pb || !band) return IGS_ERR_ARG;
+  if (form != IGS_STIFFNESS && form != IGS_MASS) return IGS_ERR_ARG;
+  if (dtype != IGS_F64 && dtype != IGS_F32) return IGS_ERR_ARG;
+  Dims d;
+  igs_status st = make_dims(pb, &d);
+  if (st != IGS_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dtype == IGS_F64) return exact_t<double>(pb, form, static_cast<double*>(band), s);
+  return exact_t<float>(pb, form, static_cast<float*>(band), s);
+}
+
+igs_status igs_assemble_surrogate(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* band,
+                                  void* stream) {
+  if (!pb || !band) return IGS_ERR_ARG;
+  if (form != IGS_STIFFNESS && form != IGS_MASS) return IGS_ERR_ARG;
+  if (dtype != IGS_F64 && dtype != IGS_F32) return IGS_ERR_ARG;
+  Dims d;
+  igs_status st = make_dims(pb, &d);
+  if (st != IGS_OK) return st;
+  st = check_sampling(d, M, q);
+  if (st != IGS_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dtype == IGS_F64) return surrogate_t<double>(pb, form, M, q, static_cast<double*>(band), s);
+  return surrogate_t<float>(pb, form, M, q, static_cast<float*>(band), s);
+}
+
+igs_status igs_assemble_rhs(const igs_problem* pb, int32_t source, double c, double* f, void* stream) {
+  if (!pb || !f) return IGS_ERR_ARG;
+  if (source != 0 && source != 1) return IGS_ERR_ARG;
+  Dims d;
+  igs_status st = make_dims(pb, &d);
+  if (st != IGS_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Prepared P;
+  st = prepare(pb, s, &P);
+  if (st != IGS_OK) return st;
+  int tx, ty;
+  rhs_tile_shape(P.d.n, &tx, &ty);
+  std::vector<QTile> tiles = tiles_all(P.d, tx, ty, pick_zchunk(P.d, tx, ty));
+  Arena ta;
+  st = ta.alloc(padded(tiles.size() * sizeof(QTile)), s);
+  if (st != IGS_OK) return st;
+  const QTile* dt = upload(ta, tiles, s, &st);
+  if (st != IGS_OK) return st;
+  HIP_TRY(launch_rhs(P.kp, dt, int(tiles.size()), source, c, f, s));
+  return finish(P, s);
+}
+
+igs_status igs_apply(const igs_problem* pb, int32_t dtype, const void* band, const void* x, void* y, int32_t dirichlet,
+                     void* stream) {
+  if (!pb || !band || !x || !y) return IGS_ERR_ARG;
+  if (dtype != IGS_F64 && dtype != IGS_F32) return IGS_ERR_ARG;
+  Dims d;
+  igs_status st = make_dims(pb, &d);
+  if (st != IGS_OK) return st;
+  return launch_apply(d, dtype, band, x, y, dirichlet, static_cast<hipStream_t>(stream));
+}
+
+igs_status igs_solve_cg(const igs_problem* pb, const double* band64, const float* band32, const double* f, double* u,
+                        double rtol, int32_t maxit, igs_cg_info* info, void* stream) {
+  if (!pb || !band64 || !f || !u || !info) return IGS_ERR_ARG;
+  if (!(rtol > 0.0) || maxit < 1) return IGS_ERR_ARG;
+  Dims d;
+  igs_status st = make_dims(pb, &d);
+  if (st != IGS_OK) return st;
+  std::memset(info, 0, sizeof(*info));
+  return solve_cg(d, band64, band32, f, u, rtol, maxit, info, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

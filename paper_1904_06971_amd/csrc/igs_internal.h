@@ -1,0 +1,131 @@
+// Internal declarations shared by the host planner, the HIP kernels and the
+// C-ABI layer of libigs.  Nothing here is part of the public ABI (include/igs.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "igs.h"
+
+namespace igs {
+
+constexpr int kMaxP = 4;
+constexpr int kMaxQ = 5;
+
+// Device-resident 1-D tables for one direction.  Quadrature point g = e*nq + k
+// (element e, Gauss point k); the p+1 functions alive on element e are e..e+p
+// and "local index a" means function e+a.
+struct Tab1D {
+  const double* x;     // [Q]       parametric coordinate
+  const double* w;     // [Q]       Gauss weight * h/2
+  const double* bv;    // [Q][p+1]  b_{e+a}(x_g)
+  const double* bd;    // [Q][p+1]  b'_{e+a}(x_g)
+  const double* trig;  // [Q][4]    sin(pi x), pi cos(pi x), sin(2 pi x), 2 pi cos(2 pi x)
+  const double* cb;    // [Q][cdeg+1] coefficient-spline basis values (spline kinds)
+  const int* cf;       // [Q]       first coefficient-spline function alive at x_g
+};
+
+// Problem description as the kernels see it (passed by value).
+struct KProblem {
+  int n, p, nq;
+  int nelem[3], m[3];
+  int64_t N, ld;
+  int S;                 // (2p+1)^n
+  int batch;
+  int geom;
+  double ga;
+  int coef;
+  double c0, camp;
+  int cdeg;
+  int cn[3];
+  int64_t cstride;       // control values per problem
+  const double* cc;      // control values [batch][cstride]
+  Tab1D t[3];
+  int* flag;             // device error word: bit 0 = det J <= 0
+};
+
+// One tile of rows for the quadrature kernels.
+//   3D: rows i1 in [i1, i1+nx), i2 in [i2, i2+ny), i3 in [z0, z1)
+//   2D: rows i1 in [i1, i1+nx), i2 in [z0, z1) (i2, ny unused)
+struct QTile {
+  int i1, i2, nx, ny, z0, z1;
+};
+
+// Interpolation plan (surrogate) as the kernels see it.
+template <typename T>
+struct KInterp {
+  int q;
+  int Sd[3];             // samples per direction
+  int lo[3], hi[3];      // analysis-domain index range per direction
+  const int* samp[3];    // [Sd]  sample fine indices
+  const double* ginv[3]; // [Sd][Sd] inverse collocation matrices (row-major)
+  const int* ef[3];      // [m]   first spline function alive at fine index
+  const T* eb[3];        // [m][q+1] spline values at fine index
+  int nup;               // number of interpolated (upper) slots
+  const int* upslot;     // [nup] band slot of each interpolated delta
+  int nc[3];             // max coefficient span of a fill box, per direction
+};
+
+// ---------------------------------------------------------------- host plan
+
+struct Dims {
+  int n, p, nq, W, S;
+  int nelem[3], m[3];
+  int64_t N, ld;
+  int batch;
+};
+
+igs_status make_dims(const igs_problem* pb, Dims* d);
+
+struct HostTables {
+  // per direction, flattened as in Tab1D
+  std::vector<double> x[3], w[3], bv[3], bd[3], trig[3], cb[3];
+  std::vector<int> cf[3];
+};
+
+void build_tables(const igs_problem* pb, const Dims& d, HostTables* t);
+
+struct HostInterp {
+  int q;
+  std::vector<int> samp[3];
+  std::vector<double> ginv[3];
+  std::vector<int> ef[3];
+  std::vector<double> eb[3];
+  std::vector<int> upslot;
+  int nc[3];
+};
+
+// samples per direction; IGS_ERR_SAMPLES when the lattice is too small
+igs_status sample_lattice(int m, int p, int M, std::vector<int>* s);
+igs_status build_interp(const Dims& d, int form, int M, int q, int boxlen[3], HostInterp* hi);
+
+// Tile lists.
+std::vector<QTile> tiles_all(const Dims& d, int tx, int ty, int zchunk);
+std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3], int tx, int ty, int zchunk);
+
+// Device scratch arena: one stream-ordered allocation carved into pieces.
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  hipStream_t stream = nullptr;
+  igs_status alloc(size_t bytes, hipStream_t s);
+  template <typename T>
+  T* take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + count * sizeof(T);
+    return reinterpret_cast<T*>(base + off);
+  }
+  void release();
+  ~Arena() { release(); }
+};
+
+inline size_t padded(size_t bytes) { return (bytes + 255) & ~size_t(255); }
+
+// Uploads host tables into an arena and fills the kernel view.
+struct DeviceTables {
+  KProblem kp;
+};
+
+}  // namespace igs

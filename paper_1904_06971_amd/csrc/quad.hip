@@ -1,0 +1,859 @@
+// Quadrature kernels: exact stiffness / mass rows and the load vector.
+//
+// A row i of the stiffness matrix holds A_{i,i+delta} = int grad B_i^T K grad
+// B_{i+delta} over supp B_i (Sec. 3.2, eqs. BilinearFormPoissonTensor,
+// ChangeOfVars).  The tensor-product structure B_i = prod_d b_{i_d} turns the
+// sum over Gauss points into per-direction contractions (sum factorisation):
+//   stage 1: contract the direction-1 points into (i1, delta1) pairs,
+//   stage 2: contract the direction-2 points into (i2, delta2) pairs,
+//   stage 3: contract the direction-3 points into (i3, delta3) pairs.
+// A workgroup owns a tile of rows (TX x TY in (i1, i2)) and streams through
+// the element layers of the last direction; each layer's Gauss points update
+// a rolling window of p+1 rows held in registers, and a row is written out
+// (stencil-major, one writer per band slot, no atomics) as soon as its last
+// layer has been processed.  Geometry (Jacobian, determinant, K) is
+// recomputed at the points of the tile's footprint and staged in LDS.
+#include <cstdio>
+
+#include "igs_internal.h"
+
+namespace igs {
+
+template <int N>
+struct IntC {
+  static constexpr int value = N;
+};
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(IntC<B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// ------------------------------------------------------------- geometry ----
+
+// Jacobian J[r][c] = dF_r/dxi_c of the geometry map at a Gauss point.
+template <int ND>
+__device__ __forceinline__ void jacobian(const KProblem& kp, const int* g, const double* xi, double J[ND][ND]) {
+#pragma unroll
+  for (int r = 0; r < ND; ++r)
+#pragma unroll
+    for (int c = 0; c < ND; ++c) J[r][c] = (r == c) ? 1.0 : 0.0;
+  const double a = kp.ga;
+  if (kp.geom == IGS_GEOM_SINE) {
+    double s1[ND], c1[ND], s2[ND], c2[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const double* tr = kp.t[d].trig + 4 * g[d];
+      s1[d] = tr[0];
+      c1[d] = tr[1];
+      s2[d] = tr[2];
+      c2[d] = tr[3];
+    }
+    if constexpr (ND == 2) {
+      J[0][0] += a * c1[0] * s2[1];
+      J[0][1] += a * s1[0] * c2[1];
+      J[1][0] += a * c2[0] * s1[1];
+      J[1][1] += a * s2[0] * c1[1];
+    } else {
+      J[0][0] += a * c1[0] * s2[1] * s1[2];
+      J[0][1] += a * s1[0] * c2[1] * s1[2];
+      J[0][2] += a * s1[0] * s2[1] * c1[2];
+      J[1][0] += a * c2[0] * s1[1] * s1[2];
+      J[1][1] += a * s2[0] * c1[1] * s1[2];
+      J[1][2] += a * s2[0] * s1[1] * c1[2];
+      J[2][0] += a * c1[0] * s1[1] * s2[2];
+      J[2][1] += a * s1[0] * c1[1] * s2[2];
+      J[2][2] += a * s1[0] * s1[1] * c2[2];
+    }
+  } else if (kp.geom == IGS_GEOM_POLY2) {
+    double q[ND], dq[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      q[d] = xi[d] * (1.0 - xi[d]);
+      dq[d] = 1.0 - 2.0 * xi[d];
+    }
+#pragma unroll
+    for (int c = 0; c < ND; ++c) {
+      double dprod = dq[c];
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+        if (d != c) dprod *= q[d];
+#pragma unroll
+      for (int r = 0; r < ND; ++r) J[r][c] += a * (r + 1) * dprod;
+    }
+  }
+}
+
+// Physical point F(xi) (needed only by the SINE3 coefficient).
+template <int ND>
+__device__ __forceinline__ void phys_point(const KProblem& kp, const int* g, const double* xi, double* F) {
+#pragma unroll
+  for (int d = 0; d < ND; ++d) F[d] = xi[d];
+  const double a = kp.ga;
+  if (kp.geom == IGS_GEOM_SINE) {
+    double s1[ND], s2[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      s1[d] = kp.t[d].trig[4 * g[d]];
+      s2[d] = kp.t[d].trig[4 * g[d] + 2];
+    }
+    if constexpr (ND == 2) {
+      F[0] += a * s1[0] * s2[1];
+      F[1] += a * s2[0] * s1[1];
+    } else {
+      F[0] += a * s1[0] * s2[1] * s1[2];
+      F[1] += a * s2[0] * s1[1] * s1[2];
+      F[2] += a * s1[0] * s1[1] * s2[2];
+    }
+  } else if (kp.geom == IGS_GEOM_POLY2) {
+    double prod = 1.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) prod *= xi[d] * (1.0 - xi[d]);
+#pragma unroll
+    for (int r = 0; r < ND; ++r) F[r] += a * (r + 1) * prod;
+  }
+}
+
+// g(xi) = sum_k c_k N_k(xi) for the coefficient spline of problem b.
+template <int ND>
+__device__ __forceinline__ double coef_spline(const KProblem& kp, int b, const int* g) {
+  const double* cc = kp.cc + b * kp.cstride;
+  const int nd = kp.cdeg + 1;
+  const double* cb0 = kp.t[0].cb + g[0] * nd;
+  const double* cb1 = kp.t[1].cb + g[1] * nd;
+  const int f0 = kp.t[0].cf[g[0]], f1 = kp.t[1].cf[g[1]];
+  double s = 0.0;
+  if constexpr (ND == 2) {
+    for (int a1 = 0; a1 < nd; ++a1) {
+      double r = 0.0;
+      const double* row = cc + (f1 + a1) * kp.cn[0] + f0;
+      for (int a0 = 0; a0 < nd; ++a0) r += cb0[a0] * row[a0];
+      s += cb1[a1] * r;
+    }
+  } else {
+    const double* cb2 = kp.t[2].cb + g[2] * nd;
+    const int f2 = kp.t[2].cf[g[2]];
+    for (int a2 = 0; a2 < nd; ++a2) {
+      double r2 = 0.0;
+      for (int a1 = 0; a1 < nd; ++a1) {
+        double r = 0.0;
+        const double* row = cc + ((f2 + a2) * kp.cn[1] + f1 + a1) * kp.cn[0] + f0;
+        for (int a0 = 0; a0 < nd; ++a0) r += cb0[a0] * row[a0];
+        r2 += cb1[a1] * r;
+      }
+      s += cb2[a2] * r2;
+    }
+  }
+  return s;
+}
+
+template <int ND>
+__device__ __forceinline__ double kappa_at(const KProblem& kp, int b, const int* g, const double* xi) {
+  switch (kp.coef) {
+    case IGS_COEF_SINE3: {
+      double F[ND];
+      phys_point<ND>(kp, g, xi, F);
+      double v = sin(2.0 * M_PI * F[0]) * cos(2.0 * M_PI * F[1]);
+      if constexpr (ND == 3) v *= sin(2.0 * M_PI * F[2]);
+      return kp.c0 + kp.camp * v;
+    }
+    case IGS_COEF_SPLINE:
+      return coef_spline<ND>(kp, b, g);
+    case IGS_COEF_EXP_SPLINE:
+      return exp(coef_spline<ND>(kp, b, g));
+    default:
+      return kp.c0;
+  }
+}
+
+// Integrand data at one Gauss point: the symmetric K scaled by weight*kappa
+// (K = kappa |det J| J^-1 J^-T = kappa adj(J) adj(J)^T / |det J|) or the
+// mass weight w |det J|.  Flags det J <= 0.
+template <int ND, int FORM>
+__device__ __forceinline__ void point_data(const KProblem& kp, int b, const int* g, double* out) {
+  double xi[ND], w = 1.0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    xi[d] = kp.t[d].x[g[d]];
+    w *= kp.t[d].w[g[d]];
+  }
+  double J[ND][ND];
+  jacobian<ND>(kp, g, xi, J);
+  double adj[ND][ND], det;
+  if constexpr (ND == 2) {
+    adj[0][0] = J[1][1];
+    adj[0][1] = -J[0][1];
+    adj[1][0] = -J[1][0];
+    adj[1][1] = J[0][0];
+    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  } else {
+    adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+  }
+  if (!(det > 0.0)) atomicOr(kp.flag, 1);
+  const double ad = fabs(det);
+  if constexpr (FORM == IGS_MASS) {
+    out[0] = w * ad;
+  } else {
+    const double s = w * kappa_at<ND>(kp, b, g, xi) / ad;
+    int k = 0;
+#pragma unroll
+    for (int r = 0; r < ND; ++r)
+#pragma unroll
+      for (int c = r; c < ND; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int e = 0; e < ND; ++e) v += adj[r][e] * adj[c][e];
+        out[k++] = s * v;
+      }
+  }
+}
+
+// ------------------------------------------------------------ 3-D rows -----
+
+template <int P>
+struct Q3Shape;
+template <> struct Q3Shape<1> { static constexpr int TX = 16, TY = 4; };
+template <> struct Q3Shape<2> { static constexpr int TX = 8, TY = 4; };
+template <> struct Q3Shape<3> { static constexpr int TX = 8, TY = 2; };
+template <> struct Q3Shape<4> { static constexpr int TX = 4, TY = 2; };
+
+template <int P, int FORM>
+struct Q3 {
+  static constexpr int NQ = P + 1, W = 2 * P + 1;
+  static constexpr int TX = Q3Shape<P>::TX, TY = Q3Shape<P>::TY;
+  static constexpr int NQ1 = (TX + P) * NQ, NQ2 = (TY + P) * NQ;
+  static constexpr int NC = FORM == IGS_STIFFNESS ? 6 : 1;
+  static constexpr int NY = FORM == IGS_STIFFNESS ? 8 : 1;
+  static constexpr int NCOMBO = TX * W * TY * W;
+  static constexpr int BLOCK = (NCOMBO + 63) / 64 * 64;
+};
+
+// Stage-1 product for one output: y[delta1] = sum_{q1} b^A_{i1}(q1) b^B_{j1}(q1) C(q1)
+template <int P, int A, int B, int NQ1, int NQ2>
+__device__ __forceinline__ void stage1_3d(const double (*Cc)[NQ2], const double (*Tv)[P + 1],
+                                          const double (*Td)[P + 1], int i1, int E1a, int nelem1, int l2,
+                                          double* y) {
+  constexpr int NQ = P + 1, W = 2 * P + 1;
+#pragma unroll
+  for (int d = 0; d < W; ++d) y[d] = 0.0;
+#pragma unroll
+  for (int a = 0; a <= P; ++a) {
+    const int e1 = i1 - a;
+    if (e1 < 0 || e1 >= nelem1) continue;
+    const int le = (e1 - E1a) * NQ;
+#pragma unroll
+    for (int k1 = 0; k1 < NQ; ++k1) {
+      const int l1 = le + k1;
+      const double ci = (A ? Td[l1][a] : Tv[l1][a]) * Cc[l1][l2];
+#pragma unroll
+      for (int bb = 0; bb <= P; ++bb) y[bb - a + P] += ci * (B ? Td[l1][bb] : Tv[l1][bb]);
+    }
+  }
+}
+
+template <int P, int FORM, typename OutT>
+__global__ void __launch_bounds__((Q3<P, FORM>::BLOCK))
+    quad3d_kernel(KProblem kp, const QTile* __restrict__ tiles, OutT* __restrict__ band) {
+  using C = Q3<P, FORM>;
+  constexpr int NQ = C::NQ, W = C::W, TX = C::TX, TY = C::TY, NQ1 = C::NQ1, NQ2 = C::NQ2;
+  __shared__ double Cs[C::NC][NQ1][NQ2];
+  __shared__ double Ys[C::NY][TX * W][NQ2];
+  __shared__ double T1v[NQ1][P + 1], T1d[NQ1][P + 1], T2v[NQ2][P + 1], T2d[NQ2][P + 1];
+
+  const QTile tile = tiles[blockIdx.x];
+  const int b = blockIdx.y;
+  OutT* out = band + size_t(b) * kp.S * kp.ld;
+  const int tid = threadIdx.x;
+  const int nel1 = kp.nelem[0], nel2 = kp.nelem[1], nel3 = kp.nelem[2];
+  const int E1a = max(0, tile.i1 - P), E1b = min(nel1 - 1, tile.i1 + tile.nx - 1);
+  const int E2a = max(0, tile.i2 - P), E2b = min(nel2 - 1, tile.i2 + tile.ny - 1);
+  const int nq1 = (E1b - E1a + 1) * NQ, nq2 = (E2b - E2a + 1) * NQ;
+
+  for (int t = tid; t < nq1 * (P + 1); t += C::BLOCK) {
+    T1v[t / (P + 1)][t % (P + 1)] = kp.t[0].bv[size_t(E1a) * NQ * (P + 1) + t];
+    T1d[t / (P + 1)][t % (P + 1)] = kp.t[0].bd[size_t(E1a) * NQ * (P + 1) + t];
+  }
+  for (int t = tid; t < nq2 * (P + 1); t += C::BLOCK) {
+    T2v[t / (P + 1)][t % (P + 1)] = kp.t[1].bv[size_t(E2a) * NQ * (P + 1) + t];
+    T2d[t / (P + 1)][t % (P + 1)] = kp.t[1].bd[size_t(E2a) * NQ * (P + 1) + t];
+  }
+
+  // this thread's (i1, delta1, i2, delta2) combination; i1 fastest for
+  // contiguous stores
+  const int r1 = tid % TX;
+  int rest = tid / TX;
+  const int r2 = rest % TY;
+  rest /= TY;
+  const int d1 = rest % W;
+  const int d2 = rest / W;
+  const bool active = tid < C::NCOMBO && r1 < tile.nx && r2 < tile.ny;
+  const int i1 = tile.i1 + r1, i2 = tile.i2 + r2;
+  const int j2 = i2 + d2 - P;
+  const size_t rowbase = size_t(i1) + size_t(kp.m[0]) * i2;
+  const size_t plane = size_t(kp.m[0]) * kp.m[1];
+
+  double acc[P + 1][W];
+#pragma unroll
+  for (int s = 0; s < P + 1; ++s)
+#pragma unroll
+    for (int d = 0; d < W; ++d) acc[s][d] = 0.0;
+
+  const int Elo = max(0, tile.z0 - P), Ehi = min(nel3 - 1, tile.z1 - 1);
+  __syncthreads();
+
+  auto write_row = [&](int i3, int slot_unused, const double* row) {
+    (void)slot_unused;
+    if (active && i3 >= tile.z0 && i3 < tile.z1) {
+      const size_t idx = rowbase + plane * i3;
+#pragma unroll
+      for (int d3 = 0; d3 < W; ++d3) {
+        const int s = d1 + W * (d2 + W * d3);
+        out[size_t(s) * kp.ld + idx] = static_cast<OutT>(row[d3]);
+      }
+    }
+  };
+
+  for (int e0 = Elo; e0 <= Ehi; e0 += P + 1) {
+    static_for<0, P + 1>([&](auto ph) {
+      constexpr int PH = decltype(ph)::value;
+      const int e3 = e0 + PH;
+      if (e3 > Ehi) return;
+      for (int k3 = 0; k3 < NQ; ++k3) {
+        const int g3 = e3 * NQ + k3;
+        // phase A: integrand data at the footprint's Gauss points
+        for (int t = tid; t < nq1 * nq2; t += C::BLOCK) {
+          const int l1 = t / nq2, l2 = t - l1 * nq2;
+          const int g[3] = {E1a * NQ + l1, E2a * NQ + l2, g3};
+          double v[C::NC];
+          point_data<3, FORM>(kp, b, g, v);
+#pragma unroll
+          for (int c = 0; c < C::NC; ++c) Cs[c][l1][l2] = v[c];
+        }
+        __syncthreads();
+        // phase B: stage 1 (direction-1 contraction) into Ys
+        const int ntask = C::NY * TX * nq2;
+        for (int t = tid; t < ntask; t += C::BLOCK) {
+          const int l2 = t % nq2;
+          const int rr = t / nq2;
+          const int rr1 = rr % TX;
+          const int k = rr / TX;
+          if (rr1 >= tile.nx) continue;
+          const int ii1 = tile.i1 + rr1;
+          double y[W];
+          if constexpr (FORM == IGS_MASS) {
+            stage1_3d<P, 0, 0, NQ1, NQ2>(Cs[0], T1v, T1d, ii1, E1a, nel1, l2, y);
+          } else {
+            // outputs: K11.dd, K12.dv, K13.dv, K12.vd, K13.vd, K22.vv, K23.vv, K33.vv
+            switch (k) {
+              case 0: stage1_3d<P, 1, 1, NQ1, NQ2>(Cs[0], T1v, T1d, ii1, E1a, nel1, l2, y); break;
+              case 1: stage1_3d<P, 1, 0, NQ1, NQ2>(Cs[1], T1v, T1d, ii1, E1a, nel1, l2, y); break;
+              case 2: stage1_3d<P, 1, 0, NQ1, NQ2>(Cs[2], T1v, T1d, ii1, E1a, nel1, l2, y); break;
+              case 3: stage1_3d<P, 0, 1, NQ1, NQ2>(Cs[1], T1v, T1d, ii1, E1a, nel1, l2, y); break;
+              case 4: stage1_3d<P, 0, 1, NQ1, NQ2>(Cs[2], T1v, T1d, ii1, E1a, nel1, l2, y); break;
+              case 5: stage1_3d<P, 0, 0, NQ1, NQ2>(Cs[3], T1v, T1d, ii1, E1a, nel1, l2, y); break;
+              case 6: stage1_3d<P, 0, 0, NQ1, NQ2>(Cs[4], T1v, T1d, ii1, E1a, nel1, l2, y); break;
+              default: stage1_3d<P, 0, 0, NQ1, NQ2>(Cs[5], T1v, T1d, ii1, E1a, nel1, l2, y); break;
+            }
+          }
+#pragma unroll
+          for (int d = 0; d < W; ++d) Ys[k][rr1 * W + d][l2] = y[d];
+        }
+        __syncthreads();
+        // phase C: stage 2 (direction 2) and stage 3 (direction 3) per thread
+        if (active) {
+          double Z00 = 0.0, Z10 = 0.0, Z01 = 0.0, Z11 = 0.0;
+          const int yrow = r1 * W + d1;
+#pragma unroll
+          for (int a2 = 0; a2 <= P; ++a2) {
+            const int e2 = i2 - a2;
+            const int b2 = j2 - e2;
+            if (e2 < 0 || e2 >= nel2 || b2 < 0 || b2 > P) continue;
+            const int le = (e2 - E2a) * NQ;
+#pragma unroll
+            for (int k2 = 0; k2 < NQ; ++k2) {
+              const int l2 = le + k2;
+              const double vi = T2v[l2][a2], vj = T2v[l2][b2];
+              if constexpr (FORM == IGS_MASS) {
+                Z00 += vi * vj * Ys[0][yrow][l2];
+              } else {
+                const double di = T2d[l2][a2], dj = T2d[l2][b2];
+                const double vv = vi * vj, vd = vi * dj, dv = di * vj, dd = di * dj;
+                const double y0 = Ys[0][yrow][l2], y1 = Ys[1][yrow][l2], y2 = Ys[2][yrow][l2];
+                const double y3 = Ys[3][yrow][l2], y4 = Ys[4][yrow][l2], y5 = Ys[5][yrow][l2];
+                const double y6 = Ys[6][yrow][l2], y7 = Ys[7][yrow][l2];
+                Z00 += vv * y0 + vd * y1 + dv * y3 + dd * y5;
+                Z10 += vv * y4 + vd * y6;
+                Z01 += vv * y2 + dv * y6;
+                Z11 += vv * y7;
+              }
+            }
+          }
+          const double* v3p = kp.t[2].bv + size_t(g3) * (P + 1);
+          const double* d3p = kp.t[2].bd + size_t(g3) * (P + 1);
+          double v3[P + 1], d3[P + 1];
+#pragma unroll
+          for (int a = 0; a <= P; ++a) {
+            v3[a] = v3p[a];
+            d3[a] = d3p[a];
+          }
+#pragma unroll
+          for (int b3 = 0; b3 <= P; ++b3) {
+            double U, V;
+            if constexpr (FORM == IGS_MASS) {
+              U = v3[b3] * Z00;
+              V = 0.0;
+            } else {
+              U = v3[b3] * Z00 + d3[b3] * Z01;
+              V = v3[b3] * Z10 + d3[b3] * Z11;
+            }
+#pragma unroll
+            for (int a3 = 0; a3 <= P; ++a3) {
+              if constexpr (FORM == IGS_MASS)
+                acc[(PH + a3) % (P + 1)][b3 - a3 + P] += v3[a3] * U;
+              else
+                acc[(PH + a3) % (P + 1)][b3 - a3 + P] += v3[a3] * U + d3[a3] * V;
+            }
+          }
+        }
+      }
+      // rows whose last layer was e3 are complete
+      if (e3 < nel3 - 1) {
+        write_row(e3, PH, acc[PH]);
+#pragma unroll
+        for (int d = 0; d < W; ++d) acc[PH][d] = 0.0;
+      } else {
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+          write_row(e3 + a, 0, acc[(PH + a) % (P + 1)]);
+#pragma unroll
+          for (int d = 0; d < W; ++d) acc[(PH + a) % (P + 1)][d] = 0.0;
+        }
+      }
+    });
+  }
+}
+
+// ------------------------------------------------------------ 2-D rows -----
+
+template <int P, int FORM>
+struct Q2 {
+  static constexpr int NQ = P + 1, W = 2 * P + 1;
+  static constexpr int TX = 64;
+  static constexpr int NQ1 = (TX + P) * NQ;
+  static constexpr int NC = FORM == IGS_STIFFNESS ? 3 : 1;
+  static constexpr int BLOCK = (TX * W + 63) / 64 * 64;
+};
+
+template <int P, int FORM, typename OutT>
+__global__ void __launch_bounds__((Q2<P, FORM>::BLOCK))
+    quad2d_kernel(KProblem kp, const QTile* __restrict__ tiles, OutT* __restrict__ band) {
+  using C = Q2<P, FORM>;
+  constexpr int NQ = C::NQ, W = C::W, TX = C::TX, NQ1 = C::NQ1;
+  __shared__ double Cs[C::NC][NQ1];
+  __shared__ double T1v[NQ1][P + 1], T1d[NQ1][P + 1];
+
+  const QTile tile = tiles[blockIdx.x];
+  const int b = blockIdx.y;
+  OutT* out = band + size_t(b) * kp.S * kp.ld;
+  const int tid = threadIdx.x;
+  const int nel1 = kp.nelem[0], nel2 = kp.nelem[1];
+  const int E1a = max(0, tile.i1 - P), E1b = min(nel1 - 1, tile.i1 + tile.nx - 1);
+  const int nq1 = (E1b - E1a + 1) * NQ;
+  for (int t = tid; t < nq1 * (P + 1); t += C::BLOCK) {
+    T1v[t / (P + 1)][t % (P + 1)] = kp.t[0].bv[size_t(E1a) * NQ * (P + 1) + t];
+    T1d[t / (P + 1)][t % (P + 1)] = kp.t[0].bd[size_t(E1a) * NQ * (P + 1) + t];
+  }
+  const int r1 = tid % TX, d1 = tid / TX;
+  const bool active = tid < TX * W && r1 < tile.nx;
+  const int i1 = tile.i1 + r1, j1 = i1 + d1 - P;
+
+  double acc[P + 1][W];
+#pragma unroll
+  for (int s = 0; s < P + 1; ++s)
+#pragma unroll
+    for (int d = 0; d < W; ++d) acc[s][d] = 0.0;
+
+  const int Elo = max(0, tile.z0 - P), Ehi = min(nel2 - 1, tile.z1 - 1);
+  __syncthreads();
+
+  auto write_row = [&](int i2, const double* row) {
+    if (active && i2 >= tile.z0 && i2 < tile.z1) {
+      const size_t idx = size_t(i1) + size_t(kp.m[0]) * i2;
+#pragma unroll
+      for (int dd = 0; dd < W; ++dd) out[size_t(d1 + W * dd) * kp.ld + idx] = static_cast<OutT>(row[dd]);
+    }
+  };
+
+  for (int e0 = Elo; e0 <= Ehi; e0 += P + 1) {
+    static_for<0, P + 1>([&](auto ph) {
+      constexpr int PH = decltype(ph)::value;
+      const int e2 = e0 + PH;
+      if (e2 > Ehi) return;
+      for (int k2 = 0; k2 < NQ; ++k2) {
+        const int g2 = e2 * NQ + k2;
+        for (int t = tid; t < nq1; t += C::BLOCK) {
+          const int g[2] = {E1a * NQ + t, g2};
+          double v[C::NC];
+          point_data<2, FORM>(kp, b, g, v);
+#pragma unroll
+          for (int c = 0; c < C::NC; ++c) Cs[c][t] = v[c];
+        }
+        __syncthreads();
+        if (active) {
+          double Y0 = 0.0, Y1 = 0.0, Y2 = 0.0, Y3 = 0.0;
+#pragma unroll
+          for (int a = 0; a <= P; ++a) {
+            const int e1 = i1 - a;
+            const int bb = j1 - e1;
+            if (e1 < 0 || e1 >= nel1 || bb < 0 || bb > P) continue;
+            const int le = (e1 - E1a) * NQ;
+#pragma unroll
+            for (int k1 = 0; k1 < NQ; ++k1) {
+              const int l1 = le + k1;
+              const double vi = T1v[l1][a], vj = T1v[l1][bb];
+              if constexpr (FORM == IGS_MASS) {
+                Y0 += vi * vj * Cs[0][l1];
+              } else {
+                const double di = T1d[l1][a], dj = T1d[l1][bb];
+                Y0 += di * dj * Cs[0][l1];  // (1,1): K11, dd
+                Y1 += di * vj * Cs[1][l1];  // (1,2): K12, dv
+                Y2 += vi * dj * Cs[1][l1];  // (2,1): K12, vd
+                Y3 += vi * vj * Cs[2][l1];  // (2,2): K22, vv
+              }
+            }
+          }
+          const double* v2p = kp.t[1].bv + size_t(g2) * (P + 1);
+          const double* d2p = kp.t[1].bd + size_t(g2) * (P + 1);
+          double v2[P + 1], dv2[P + 1];
+#pragma unroll
+          for (int a = 0; a <= P; ++a) {
+            v2[a] = v2p[a];
+            dv2[a] = d2p[a];
+          }
+#pragma unroll
+          for (int b2 = 0; b2 <= P; ++b2) {
+            double U, V;
+            if constexpr (FORM == IGS_MASS) {
+              U = v2[b2] * Y0;
+              V = 0.0;
+            } else {
+              U = v2[b2] * Y0 + dv2[b2] * Y1;
+              V = v2[b2] * Y2 + dv2[b2] * Y3;
+            }
+#pragma unroll
+            for (int a2 = 0; a2 <= P; ++a2) {
+              if constexpr (FORM == IGS_MASS)
+                acc[(PH + a2) % (P + 1)][b2 - a2 + P] += v2[a2] * U;
+              else
+                acc[(PH + a2) % (P + 1)][b2 - a2 + P] += v2[a2] * U + dv2[a2] * V;
+            }
+          }
+        }
+        __syncthreads();
+      }
+      if (e2 < nel2 - 1) {
+        write_row(e2, acc[PH]);
+#pragma unroll
+        for (int d = 0; d < W; ++d) acc[PH][d] = 0.0;
+      } else {
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+          write_row(e2 + a, acc[(PH + a) % (P + 1)]);
+#pragma unroll
+          for (int d = 0; d < W; ++d) acc[(PH + a) % (P + 1)][d] = 0.0;
+        }
+      }
+    });
+  }
+}
+
+// ------------------------------------------------------------- load vector --
+
+template <int ND>
+__device__ __forceinline__ double source_at(const KProblem& kp, const int* g, int src, double c) {
+  double xi[ND], w = 1.0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    xi[d] = kp.t[d].x[g[d]];
+    w *= kp.t[d].w[g[d]];
+  }
+  double J[ND][ND];
+  jacobian<ND>(kp, g, xi, J);
+  double det;
+  if constexpr (ND == 2) {
+    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  } else {
+    det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  }
+  if (!(det > 0.0)) atomicOr(kp.flag, 1);
+  double f = c;
+  if (src == 1) {
+    double F[ND];
+    phys_point<ND>(kp, g, xi, F);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) f *= sin(M_PI * F[d]);
+  }
+  return w * fabs(det) * f;
+}
+
+template <int P>
+struct R3 {
+  static constexpr int NQ = P + 1, TX = 16, TY = 16;
+  static constexpr int NQ1 = (TX + P) * NQ, NQ2 = (TY + P) * NQ;
+  static constexpr int BLOCK = TX * TY;
+};
+
+template <int P>
+__global__ void __launch_bounds__(R3<P>::BLOCK)
+    rhs3d_kernel(KProblem kp, const QTile* __restrict__ tiles, int src, double c, double* __restrict__ f) {
+  using C = R3<P>;
+  constexpr int NQ = C::NQ, TX = C::TX, NQ1 = C::NQ1, NQ2 = C::NQ2;
+  __shared__ double Fs[NQ1][NQ2];
+  __shared__ double Ys[TX][NQ2];
+  __shared__ double T1v[NQ1][P + 1], T2v[NQ2][P + 1];
+  const QTile tile = tiles[blockIdx.x];
+  const int b = blockIdx.y;
+  double* out = f + size_t(b) * kp.N;
+  const int tid = threadIdx.x;
+  const int nel1 = kp.nelem[0], nel2 = kp.nelem[1], nel3 = kp.nelem[2];
+  const int E1a = max(0, tile.i1 - P), E1b = min(nel1 - 1, tile.i1 + tile.nx - 1);
+  const int E2a = max(0, tile.i2 - P), E2b = min(nel2 - 1, tile.i2 + tile.ny - 1);
+  const int nq1 = (E1b - E1a + 1) * NQ, nq2 = (E2b - E2a + 1) * NQ;
+  for (int t = tid; t < nq1 * (P + 1); t += C::BLOCK) T1v[t / (P + 1)][t % (P + 1)] = kp.t[0].bv[size_t(E1a) * NQ * (P + 1) + t];
+  for (int t = tid; t < nq2 * (P + 1); t += C::BLOCK) T2v[t / (P + 1)][t % (P + 1)] = kp.t[1].bv[size_t(E2a) * NQ * (P + 1) + t];
+  const int r1 = tid % TX, r2 = tid / TX;
+  const bool active = r1 < tile.nx && r2 < tile.ny;
+  const int i1 = tile.i1 + r1, i2 = tile.i2 + r2;
+  double acc[P + 1];
+#pragma unroll
+  for (int s = 0; s <= P; ++s) acc[s] = 0.0;
+  const int Elo = max(0, tile.z0 - P), Ehi = min(nel3 - 1, tile.z1 - 1);
+  __syncthreads();
+  auto write_row = [&](int i3, double v) {
+    if (active && i3 >= tile.z0 && i3 < tile.z1) out[size_t(i1) + size_t(kp.m[0]) * (i2 + size_t(kp.m[1]) * i3)] = v;
+  };
+  for (int e0 = Elo; e0 <= Ehi; e0 += P + 1) {
+    static_for<0, P + 1>([&](auto ph) {
+      constexpr int PH = decltype(ph)::value;
+      const int e3 = e0 + PH;
+      if (e3 > Ehi) return;
+      for (int k3 = 0; k3 < NQ; ++k3) {
+        const int g3 = e3 * NQ + k3;
+        for (int t = tid; t < nq1 * nq2; t += C::BLOCK) {
+          const int l1 = t / nq2, l2 = t - l1 * nq2;
+          const int g[3] = {E1a * NQ + l1, E2a * NQ + l2, g3};
+          Fs[l1][l2] = source_at<3>(kp, g, src, c);
+        }
+        __syncthreads();
+        for (int t = tid; t < TX * nq2; t += C::BLOCK) {
+          const int l2 = t % nq2, rr1 = t / nq2;
+          const int ii1 = tile.i1 + rr1;
+          double y = 0.0;
+#pragma unroll
+          for (int a = 0; a <= P; ++a) {
+            const int e1 = ii1 - a;
+            if (rr1 >= tile.nx || e1 < 0 || e1 >= nel1) continue;
+#pragma unroll
+            for (int k1 = 0; k1 < NQ; ++k1) {
+              const int l1 = (e1 - E1a) * NQ + k1;
+              y += T1v[l1][a] * Fs[l1][l2];
+            }
+          }
+          Ys[rr1][l2] = y;
+        }
+        __syncthreads();
+        if (active) {
+          double z = 0.0;
+#pragma unroll
+          for (int a2 = 0; a2 <= P; ++a2) {
+            const int e2 = i2 - a2;
+            if (e2 < 0 || e2 >= nel2) continue;
+#pragma unroll
+            for (int k2 = 0; k2 < NQ; ++k2) {
+              const int l2 = (e2 - E2a) * NQ + k2;
+              z += T2v[l2][a2] * Ys[r1][l2];
+            }
+          }
+          const double* v3 = kp.t[2].bv + size_t(g3) * (P + 1);
+#pragma unroll
+          for (int a3 = 0; a3 <= P; ++a3) acc[(PH + a3) % (P + 1)] += v3[a3] * z;
+        }
+      }
+      if (e3 < nel3 - 1) {
+        write_row(e3, acc[PH]);
+        acc[PH] = 0.0;
+      } else {
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+          write_row(e3 + a, acc[(PH + a) % (P + 1)]);
+          acc[(PH + a) % (P + 1)] = 0.0;
+        }
+      }
+    });
+  }
+}
+
+template <int P>
+struct R2 {
+  static constexpr int NQ = P + 1, TX = 256;
+  static constexpr int NQ1 = (TX + P) * NQ;
+};
+
+template <int P>
+__global__ void __launch_bounds__(256)
+    rhs2d_kernel(KProblem kp, const QTile* __restrict__ tiles, int src, double c, double* __restrict__ f) {
+  using C = R2<P>;
+  constexpr int NQ = C::NQ, NQ1 = C::NQ1;
+  __shared__ double Fs[NQ1];
+  __shared__ double T1v[NQ1][P + 1];
+  const QTile tile = tiles[blockIdx.x];
+  const int b = blockIdx.y;
+  double* out = f + size_t(b) * kp.N;
+  const int tid = threadIdx.x;
+  const int nel1 = kp.nelem[0], nel2 = kp.nelem[1];
+  const int E1a = max(0, tile.i1 - P), E1b = min(nel1 - 1, tile.i1 + tile.nx - 1);
+  const int nq1 = (E1b - E1a + 1) * NQ;
+  for (int t = tid; t < nq1 * (P + 1); t += 256) T1v[t / (P + 1)][t % (P + 1)] = kp.t[0].bv[size_t(E1a) * NQ * (P + 1) + t];
+  const bool active = tid < tile.nx;
+  const int i1 = tile.i1 + tid;
+  double acc[P + 1];
+#pragma unroll
+  for (int s = 0; s <= P; ++s) acc[s] = 0.0;
+  const int Elo = max(0, tile.z0 - P), Ehi = min(nel2 - 1, tile.z1 - 1);
+  __syncthreads();
+  auto write_row = [&](int i2, double v) {
+    if (active && i2 >= tile.z0 && i2 < tile.z1) out[size_t(i1) + size_t(kp.m[0]) * i2] = v;
+  };
+  for (int e0 = Elo; e0 <= Ehi; e0 += P + 1) {
+    static_for<0, P + 1>([&](auto ph) {
+      constexpr int PH = decltype(ph)::value;
+      const int e2 = e0 + PH;
+      if (e2 > Ehi) return;
+      for (int k2 = 0; k2 < NQ; ++k2) {
+        const int g2 = e2 * NQ + k2;
+        for (int t = tid; t < nq1; t += 256) {
+          const int g[2] = {E1a * NQ + t, g2};
+          Fs[t] = source_at<2>(kp, g, src, c);
+        }
+        __syncthreads();
+        if (active) {
+          double y = 0.0;
+#pragma unroll
+          for (int a = 0; a <= P; ++a) {
+            const int e1 = i1 - a;
+            if (e1 < 0 || e1 >= nel1) continue;
+#pragma unroll
+            for (int k1 = 0; k1 < NQ; ++k1) {
+              const int l1 = (e1 - E1a) * NQ + k1;
+              y += T1v[l1][a] * Fs[l1];
+            }
+          }
+          const double* v2 = kp.t[1].bv + size_t(g2) * (P + 1);
+#pragma unroll
+          for (int a2 = 0; a2 <= P; ++a2) acc[(PH + a2) % (P + 1)] += v2[a2] * y;
+        }
+        __syncthreads();
+      }
+      if (e2 < nel2 - 1) {
+        write_row(e2, acc[PH]);
+        acc[PH] = 0.0;
+      } else {
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+          write_row(e2 + a, acc[(PH + a) % (P + 1)]);
+          acc[(PH + a) % (P + 1)] = 0.0;
+        }
+      }
+    });
+  }
+}
+
+// ------------------------------------------------------------- launchers ---
+
+void quad_tile_shape(int n, int p, int* tx, int* ty) {
+  if (n == 2) {
+    *tx = 64;
+    *ty = 1;
+    return;
+  }
+  switch (p) {
+    case 1: *tx = Q3Shape<1>::TX; *ty = Q3Shape<1>::TY; break;
+    case 2: *tx = Q3Shape<2>::TX; *ty = Q3Shape<2>::TY; break;
+    case 3: *tx = Q3Shape<3>::TX; *ty = Q3Shape<3>::TY; break;
+    default: *tx = Q3Shape<4>::TX; *ty = Q3Shape<4>::TY; break;
+  }
+}
+
+void rhs_tile_shape(int n, int* tx, int* ty) {
+  *tx = (n == 2) ? 256 : 16;
+  *ty = (n == 2) ? 1 : 16;
+}
+
+template <int P, int FORM, typename OutT>
+static hipError_t launch_quad_t(const KProblem& kp, const QTile* tiles, int ntiles, OutT* band, hipStream_t s) {
+  if (ntiles == 0) return hipSuccess;
+  dim3 grid(ntiles, kp.batch);
+  if (kp.n == 3) {
+    hipLaunchKernelGGL((quad3d_kernel<P, FORM, OutT>), grid, dim3(Q3<P, FORM>::BLOCK), 0, s, kp, tiles, band);
+  } else {
+    hipLaunchKernelGGL((quad2d_kernel<P, FORM, OutT>), grid, dim3(Q2<P, FORM>::BLOCK), 0, s, kp, tiles, band);
+  }
+  return hipGetLastError();
+}
+
+template <int P, typename OutT>
+static hipError_t launch_quad_p(const KProblem& kp, int form, const QTile* tiles, int ntiles, OutT* band,
+                                hipStream_t s) {
+  return form == IGS_MASS ? launch_quad_t<P, IGS_MASS, OutT>(kp, tiles, ntiles, band, s)
+                          : launch_quad_t<P, IGS_STIFFNESS, OutT>(kp, tiles, ntiles, band, s);
+}
+
+template <typename OutT>
+hipError_t launch_quad(const KProblem& kp, int form, const QTile* tiles, int ntiles, OutT* band, hipStream_t s) {
+  switch (kp.p) {
+    case 1: return launch_quad_p<1, OutT>(kp, form, tiles, ntiles, band, s);
+    case 2: return launch_quad_p<2, OutT>(kp, form, tiles, ntiles, band, s);
+    case 3: return launch_quad_p<3, OutT>(kp, form, tiles, ntiles, band, s);
+    default: return launch_quad_p<4, OutT>(kp, form, tiles, ntiles, band, s);
+  }
+}
+
+template hipError_t launch_quad<double>(const KProblem&, int, const QTile*, int, double*, hipStream_t);
+template hipError_t launch_quad<float>(const KProblem&, int, const QTile*, int, float*, hipStream_t);
+
+template <int P>
+static hipError_t launch_rhs_p(const KProblem& kp, const QTile* tiles, int ntiles, int src, double c, double* f,
+                               hipStream_t s) {
+  if (ntiles == 0) return hipSuccess;
+  dim3 grid(ntiles, kp.batch);
+  if (kp.n == 3)
+    hipLaunchKernelGGL((rhs3d_kernel<P>), grid, dim3(R3<P>::BLOCK), 0, s, kp, tiles, src, c, f);
+  else
+    hipLaunchKernelGGL((rhs2d_kernel<P>), grid, dim3(256), 0, s, kp, tiles, src, c, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs(const KProblem& kp, const QTile* tiles, int ntiles, int src, double c, double* f,
+                      hipStream_t s) {
+  switch (kp.p) {
+    case 1: return launch_rhs_p<1>(kp, tiles, ntiles, src, c, f, s);
+    case 2: return launch_rhs_p<2>(kp, tiles, ntiles, src, c, f, s);
+    case 3: return launch_rhs_p<3>(kp, tiles, ntiles, src, c, f, s);
+    default: return launch_rhs_p<4>(kp, tiles, ntiles, src, c, f, s);
+  }
+}
+
+}  // namespace igs

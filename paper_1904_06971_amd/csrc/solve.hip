@@ -1,0 +1,522 @@
+// Banded SpMV and conjugate gradients on the stencil-major band.
+//
+// y_i = sum_s band[s][i] x[i + off_s], off_s = delta_1 + m1 delta_2 + m1 m2
+// delta_3 (the colex offset of the slot's delta).  One thread per row, slots
+// in the outer loop: for a fixed slot the lanes of a wave read consecutive
+// band entries and consecutive x entries, so both streams are coalesced; the
+// band is streamed once (non-temporal), x stays in L2.  Entries whose column
+// leaves the index box are stored as 0, so the column index is only clamped
+// into [0, N) to keep the read in bounds.  Workgroups are remapped so that
+// each XCD walks a contiguous range of rows (its L2 then holds the x halo).
+//
+// CG (Dirichlet-restricted, Sec. 8 eq. BlockSystem with u_D = 0) keeps every
+// vector zero on the Dirichlet dofs, so the restriction reduces to zeroing
+// those rows of A p.  Reductions are two-stage and deterministic (per-block
+// partials, then one block in a fixed order): no floating-point atomics.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "igs_internal.h"
+
+namespace igs {
+
+constexpr int kSpmvBlock = 256;
+constexpr int kRedBlock = 256;
+
+struct SpmvGeom {
+  int n, p, W, S;
+  int m[3];
+  int64_t N, ld;
+};
+
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+  // blocks are dealt round-robin to the 8 XCDs; give XCD x the logical range
+  // [x*per, (x+1)*per) so neighbouring rows share an L2
+  const int per = nblk / 8;
+  if (per == 0 || bid >= per * 8) return bid;
+  return (bid % 8) * per + bid / 8;
+}
+
+__device__ __forceinline__ bool on_dirichlet(const SpmvGeom& g, int64_t i) {
+  const int i1 = int(i % g.m[0]);
+  int64_t r = i / g.m[0];
+  const int i2 = int(r % g.m[1]);
+  const int i3 = int(r / g.m[1]);
+  bool d = (i1 == 0) | (i1 == g.m[0] - 1) | (i2 == 0) | (i2 == g.m[1] - 1);
+  if (g.n == 3) d |= (i3 == 0) | (i3 == g.m[2] - 1);
+  return d;
+}
+
+template <typename T>
+__device__ __forceinline__ T row_product(const SpmvGeom& g, const T* __restrict__ band, const T* __restrict__ x,
+                                         int64_t i) {
+  const int P = g.p, W = g.W;
+  const int64_t m1 = g.m[0], m12 = int64_t(g.m[0]) * g.m[1];
+  T acc = T(0);
+  int s = 0;
+  const int w3 = (g.n == 3) ? W : 1;
+  for (int a3 = 0; a3 < w3; ++a3) {
+    const int64_t o3 = (g.n == 3) ? (a3 - P) * m12 : 0;
+    for (int a2 = 0; a2 < W; ++a2) {
+      const int64_t o23 = o3 + (a2 - P) * m1;
+      for (int a1 = 0; a1 < W; ++a1, ++s) {
+        int64_t j = i + o23 + (a1 - P);
+        j = j < 0 ? 0 : (j >= g.N ? g.N - 1 : j);
+        acc += __builtin_nontemporal_load(band + size_t(s) * g.ld + i) * x[j];
+      }
+    }
+  }
+  return acc;
+}
+
+// y = A x; with mask, rows on the Dirichlet boundary are written 0.  When
+// `dot` is given, per-block partial sums of x_i y_i go to dot[b][block].
+template <typename T>
+__global__ void __launch_bounds__(kSpmvBlock)
+    spmv_kernel(SpmvGeom g, const T* __restrict__ band, const T* __restrict__ x, T* __restrict__ y, int mask,
+                const int* __restrict__ done, double* __restrict__ dot) {
+  const int b = blockIdx.y;
+  if (done && done[b]) return;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
+  const T* bb = band + size_t(b) * g.S * g.ld;
+  const T* xb = x + size_t(b) * g.N;
+  double part = 0.0;
+  if (i < g.N) {
+    T v = (mask && on_dirichlet(g, i)) ? T(0) : row_product<T>(g, bb, xb, i);
+    y[size_t(b) * g.N + i] = v;
+    part = double(v) * double(xb[i]);
+  }
+  if (dot) {
+    __shared__ double red[kSpmvBlock];
+    red[threadIdx.x] = part;
+    __syncthreads();
+    for (int w = kSpmvBlock / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) dot[size_t(b) * gridDim.x + lb] = red[0];
+  }
+}
+
+// x with its Dirichlet dofs zeroed (the restriction of igs_apply)
+template <typename T>
+__global__ void mask_copy_kernel(SpmvGeom g, int batch, const T* __restrict__ x, T* __restrict__ y) {
+  const int64_t total = g.N * batch;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x)
+    y[t] = on_dirichlet(g, t % g.N) ? T(0) : x[t];
+}
+
+// --------------------------------------------------------------- CG state --
+
+// Per-problem scalars, kept on the device between kernels.
+struct CgScalars {
+  double rr;      // r^T r
+  double alpha, beta;
+  double tol2;    // stop when rr <= tol2
+  int done;       // converged or broken down
+  int breakdown;
+  int iters;
+  int pad;
+};
+
+template <typename T>
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kRedBlock];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kRedBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// r = f - A u (FP64, Dirichlet rows 0), partial sums of r^T r and f^T f
+__global__ void __launch_bounds__(kSpmvBlock)
+    residual_kernel(SpmvGeom g, const double* __restrict__ band, const double* __restrict__ f,
+                    const double* __restrict__ u, double* __restrict__ r, double* __restrict__ part_rr,
+                    double* __restrict__ part_ff) {
+  const int b = blockIdx.y;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
+  double rv = 0.0, fv = 0.0;
+  if (i < g.N && !on_dirichlet(g, i)) {
+    fv = f[size_t(b) * g.N + i];
+    rv = fv - row_product<double>(g, band + size_t(b) * g.S * g.ld, u + size_t(b) * g.N, i);
+  }
+  if (i < g.N) r[size_t(b) * g.N + i] = rv;
+  double a = block_sum<double>(rv * rv);
+  __syncthreads();
+  double c = block_sum<double>(fv * fv);
+  if (threadIdx.x == 0) {
+    part_rr[size_t(b) * gridDim.x + lb] = a;
+    part_ff[size_t(b) * gridDim.x + lb] = c;
+  }
+}
+
+// out[b] = sum of part[b][0..nblk) in a fixed order (one block per problem)
+__global__ void __launch_bounds__(kRedBlock) reduce_kernel(const double* __restrict__ part, int nblk, double* out) {
+  const int b = blockIdx.x;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += kRedBlock) s += part[size_t(b) * nblk + k];
+  s = block_sum<double>(s);
+  if (threadIdx.x == 0) out[b] = s;
+}
+
+// inner CG start: rhat = r / scale (type T), d = 0, p = rhat, rr = |rhat|^2
+template <typename T>
+__global__ void cg_init_kernel(int64_t N, int batch, const double* __restrict__ r, const double* __restrict__ scale,
+                               T* __restrict__ rh, T* __restrict__ p, T* __restrict__ d) {
+  const int64_t total = N * batch;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int b = int(t / N);
+    const double s = scale[b];
+    const T v = s > 0.0 ? T(r[t] / s) : T(0);
+    rh[t] = v;
+    p[t] = v;
+    d[t] = T(0);
+  }
+}
+
+__global__ void cg_setup_kernel(int batch, const double* __restrict__ rr, const double* __restrict__ tol2,
+                                const int* __restrict__ active, CgScalars* sc) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  CgScalars s;
+  s.rr = rr[b];
+  s.alpha = s.beta = 0.0;
+  s.tol2 = tol2[b];
+  s.done = (!active[b] || s.rr <= s.tol2) ? 1 : 0;
+  s.breakdown = 0;
+  s.iters = 0;
+  s.pad = 0;
+  sc[b] = s;
+}
+
+// alpha = rr / (p^T A p)
+__global__ void __launch_bounds__(kRedBlock) cg_alpha_kernel(const double* __restrict__ part, int nblk, CgScalars* sc) {
+  const int b = blockIdx.x;
+  if (sc[b].done) return;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += kRedBlock) s += part[size_t(b) * nblk + k];
+  s = block_sum<double>(s);
+  if (threadIdx.x == 0) {
+    if (!(s > 0.0) || !isfinite(s)) {
+      sc[b].done = 1;
+      sc[b].breakdown = 1;
+      sc[b].alpha = 0.0;
+    } else {
+      sc[b].alpha = sc[b].rr / s;
+    }
+  }
+}
+
+// d += alpha p, r -= alpha q, partial r^T r
+template <typename T>
+__global__ void __launch_bounds__(kSpmvBlock)
+    cg_update_kernel(int64_t N, const CgScalars* __restrict__ sc, const T* __restrict__ p, const T* __restrict__ q,
+                     T* __restrict__ d, T* __restrict__ r, double* __restrict__ part) {
+  const int b = blockIdx.y;
+  if (sc[b].done) return;
+  const T alpha = T(sc[b].alpha);
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
+  double v = 0.0;
+  if (i < N) {
+    const size_t k = size_t(b) * N + i;
+    d[k] += alpha * p[k];
+    const T rn = r[k] - alpha * q[k];
+    r[k] = rn;
+    v = double(rn) * double(rn);
+  }
+  v = block_sum<double>(v);
+  if (threadIdx.x == 0) part[size_t(b) * gridDim.x + lb] = v;
+}
+
+// beta = rr_new / rr; convergence on the recursive residual
+__global__ void __launch_bounds__(kRedBlock) cg_beta_kernel(const double* __restrict__ part, int nblk, CgScalars* sc) {
+  const int b = blockIdx.x;
+  if (sc[b].done) return;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += kRedBlock) s += part[size_t(b) * nblk + k];
+  s = block_sum<double>(s);
+  if (threadIdx.x == 0) {
+    sc[b].beta = s / sc[b].rr;
+    sc[b].rr = s;
+    sc[b].iters += 1;
+    if (!isfinite(s)) {
+      sc[b].done = 1;
+      sc[b].breakdown = 1;
+    } else if (s <= sc[b].tol2) {
+      sc[b].done = 1;
+    }
+  }
+}
+
+// p = r + beta p
+template <typename T>
+__global__ void cg_pupdate_kernel(int64_t N, const CgScalars* __restrict__ sc, const T* __restrict__ r,
+                                  T* __restrict__ p) {
+  const int b = blockIdx.y;
+  if (sc[b].done) return;
+  const T beta = T(sc[b].beta);
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+    const size_t k = size_t(b) * N + i;
+    p[k] = r[k] + beta * p[k];
+  }
+}
+
+// u += scale * d (FP64 update of the refinement)
+template <typename T>
+__global__ void axpy_update_kernel(int64_t N, int batch, const double* __restrict__ scale, const T* __restrict__ d,
+                                   double* __restrict__ u) {
+  const int64_t total = N * batch;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x)
+    u[t] += scale[t / N] * double(d[t]);
+}
+
+// zero u on Dirichlet dofs
+__global__ void zero_dirichlet_kernel(SpmvGeom g, int batch, double* __restrict__ u) {
+  const int64_t total = g.N * batch;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x)
+    if (on_dirichlet(g, t % g.N)) u[t] = 0.0;
+}
+
+// ----------------------------------------------------------------- host ----
+
+static SpmvGeom make_geom(const Dims& d) {
+  SpmvGeom g;
+  g.n = d.n;
+  g.p = d.p;
+  g.W = d.W;
+  g.S = d.S;
+  for (int k = 0; k < 3; ++k) g.m[k] = d.m[k];
+  g.N = d.N;
+  g.ld = d.ld;
+  return g;
+}
+
+static int grid_stride_blocks(int64_t total) { return int(std::min<int64_t>((total + 255) / 256, 8192)); }
+
+#define HIP_OK(x)                              \
+  do {                                         \
+    if ((x) != hipSuccess) return IGS_ERR_HIP; \
+  } while (0)
+
+template <typename T>
+igs_status launch_apply_t(const Dims& d, const T* band, const T* x, T* y, int dirichlet, hipStream_t s) {
+  SpmvGeom g = make_geom(d);
+  const int nblk = int((d.N + kSpmvBlock - 1) / kSpmvBlock);
+  const T* xin = x;
+  Arena ar;
+  if (dirichlet) {
+    igs_status st = ar.alloc(padded(sizeof(T) * d.N * d.batch), s);
+    if (st != IGS_OK) return st;
+    T* xm = ar.take<T>(size_t(d.N) * d.batch);
+    hipLaunchKernelGGL((mask_copy_kernel<T>), dim3(grid_stride_blocks(d.N * d.batch)), dim3(256), 0, s, g, d.batch,
+                       x, xm);
+    xin = xm;
+  }
+  hipLaunchKernelGGL((spmv_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band, xin, y, dirichlet,
+                     nullptr, nullptr);
+  HIP_OK(hipGetLastError());
+  return IGS_OK;
+}
+
+igs_status launch_apply(const Dims& d, int dtype, const void* band, const void* x, void* y, int dirichlet,
+                        hipStream_t s) {
+  if (dtype == IGS_F64)
+    return launch_apply_t<double>(d, static_cast<const double*>(band), static_cast<const double*>(x),
+                                  static_cast<double*>(y), dirichlet, s);
+  return launch_apply_t<float>(d, static_cast<const float*>(band), static_cast<const float*>(x),
+                               static_cast<float*>(y), dirichlet, s);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRedBlock)
+    dot_kernel(int64_t N, const T* __restrict__ a, const T* __restrict__ c, double* __restrict__ part) {
+  const int b = blockIdx.y;
+  double v = 0.0;
+  for (int64_t i = blockIdx.x * int64_t(kRedBlock) + threadIdx.x; i < N; i += int64_t(gridDim.x) * kRedBlock)
+    v += double(a[size_t(b) * N + i]) * double(c[size_t(b) * N + i]);
+  v = block_sum<double>(v);
+  if (threadIdx.x == 0) part[size_t(b) * gridDim.x + blockIdx.x] = v;
+}
+
+// CG iteration kernels operate on problems whose `done` flag is clear.
+template <typename T>
+__global__ void __launch_bounds__(kSpmvBlock)
+    cg_spmv_kernel(SpmvGeom g, const T* __restrict__ band, const T* __restrict__ p, T* __restrict__ q,
+                   const CgScalars* __restrict__ sc, double* __restrict__ part) {
+  const int b = blockIdx.y;
+  if (sc[b].done) return;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
+  const T* pb = p + size_t(b) * g.N;
+  double v = 0.0;
+  if (i < g.N) {
+    T y = on_dirichlet(g, i) ? T(0) : row_product<T>(g, band + size_t(b) * g.S * g.ld, pb, i);
+    q[size_t(b) * g.N + i] = y;
+    v = double(y) * double(pb[i]);
+  }
+  v = block_sum<double>(v);
+  if (threadIdx.x == 0) part[size_t(b) * gridDim.x + lb] = v;
+}
+
+struct SolveBufs {
+  double* r64;
+  double* part;
+  double* part2;
+  double* rr;
+  double* ff;
+  double* scale;
+  double* tol2;
+  int* active;
+  CgScalars* sc;
+};
+
+// One inner CG on A_T dhat = rhat, rhat = r / scale, from dhat = 0, to
+// |rhat - A dhat| <= sqrt(tol2) (per problem), at most `budget` iterations.
+template <typename T>
+static igs_status inner_cg(const Dims& d, const T* band, const SolveBufs& sb, T* rh, T* p, T* q, T* dv, int budget,
+                           std::vector<CgScalars>* host_sc, int* iters, hipStream_t s) {
+  SpmvGeom g = make_geom(d);
+  const int nblk = int((d.N + kSpmvBlock - 1) / kSpmvBlock);
+  const int dblk = int(std::min<int64_t>((d.N + kRedBlock - 1) / kRedBlock, 1024));
+  hipLaunchKernelGGL((cg_init_kernel<T>), dim3(grid_stride_blocks(d.N * d.batch)), dim3(256), 0, s, d.N, d.batch,
+                     sb.r64, sb.scale, rh, p, dv);
+  hipLaunchKernelGGL((dot_kernel<T>), dim3(dblk, d.batch), dim3(kRedBlock), 0, s, d.N, rh, rh, sb.part);
+  hipLaunchKernelGGL(reduce_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, dblk, sb.rr);
+  hipLaunchKernelGGL(cg_setup_kernel, dim3(1), dim3(64), 0, s, d.batch, sb.rr, sb.tol2, sb.active, sb.sc);
+  HIP_OK(hipGetLastError());
+  const int chunk = 32;
+  int done_iters = 0;
+  while (true) {
+    const int k = std::min(chunk, budget - done_iters);
+    if (k <= 0) break;
+    for (int it = 0; it < k; ++it) {
+      hipLaunchKernelGGL((cg_spmv_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band, p, q, sb.sc,
+                         sb.part);
+      hipLaunchKernelGGL(cg_alpha_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
+      hipLaunchKernelGGL((cg_update_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, sb.sc, p, q, dv,
+                         rh, sb.part2);
+      hipLaunchKernelGGL(cg_beta_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part2, nblk, sb.sc);
+      hipLaunchKernelGGL((cg_pupdate_kernel<T>), dim3(std::min<int64_t>((d.N + 255) / 256, 4096), d.batch),
+                         dim3(256), 0, s, d.N, sb.sc, rh, p);
+    }
+    HIP_OK(hipGetLastError());
+    done_iters += k;
+    HIP_OK(hipMemcpyAsync(host_sc->data(), sb.sc, sizeof(CgScalars) * d.batch, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    bool all = true;
+    for (int b = 0; b < d.batch; ++b) all &= (*host_sc)[b].done != 0;
+    if (all) break;
+  }
+  int mx = 0;
+  for (int b = 0; b < d.batch; ++b) mx = std::max(mx, (*host_sc)[b].iters);
+  *iters = mx;
+  return IGS_OK;
+}
+
+template <typename T>
+static igs_status refine_loop(const Dims& d, const double* band64, const T* bandT, const double* f, double* u,
+                              double rtol, int maxit, double inner_rel, igs_cg_info* info, hipStream_t s) {
+  SpmvGeom g = make_geom(d);
+  const int nblk = int((d.N + kSpmvBlock - 1) / kSpmvBlock);
+  const size_t NB = size_t(d.N) * d.batch;
+  const size_t nb = size_t(d.batch);
+  Arena ar;
+  size_t bytes = padded(sizeof(double) * NB) + 2 * padded(sizeof(double) * nb * nblk) + 4 * padded(sizeof(double) * nb) +
+                 padded(sizeof(int) * nb) + padded(sizeof(CgScalars) * nb) + 4 * padded(sizeof(T) * NB);
+  igs_status st = ar.alloc(bytes, s);
+  if (st != IGS_OK) return st;
+  SolveBufs sb;
+  sb.r64 = ar.take<double>(NB);
+  sb.part = ar.take<double>(nb * nblk);
+  sb.part2 = ar.take<double>(nb * nblk);
+  sb.rr = ar.take<double>(nb);
+  sb.ff = ar.take<double>(nb);
+  sb.scale = ar.take<double>(nb);
+  sb.tol2 = ar.take<double>(nb);
+  sb.active = ar.take<int>(nb);
+  sb.sc = ar.take<CgScalars>(nb);
+  T* rh = ar.take<T>(NB);
+  T* p = ar.take<T>(NB);
+  T* q = ar.take<T>(NB);
+  T* dv = ar.take<T>(NB);
+
+  hipLaunchKernelGGL(zero_dirichlet_kernel, dim3(grid_stride_blocks(NB)), dim3(256), 0, s, g, d.batch, u);
+  std::vector<double> rr(nb), ff(nb), scale(nb), tol2(nb);
+  std::vector<int> active(nb);
+  std::vector<CgScalars> hsc(nb);
+  int total_iters = 0, outer = 0;
+  bool breakdown = false;
+  igs_status result = IGS_NOT_CONVERGED;
+  double worst = 0.0;
+  while (true) {
+    hipLaunchKernelGGL(residual_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band64, f, u, sb.r64,
+                       sb.part, sb.part2);
+    hipLaunchKernelGGL(reduce_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.rr);
+    hipLaunchKernelGGL(reduce_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part2, nblk, sb.ff);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(rr.data(), sb.rr, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(ff.data(), sb.ff, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    bool all = true;
+    worst = 0.0;
+    for (size_t b = 0; b < nb; ++b) {
+      const double rel = ff[b] > 0.0 ? std::sqrt(rr[b] / ff[b]) : 0.0;
+      if (!std::isfinite(rel)) {
+        info->relres = rel;
+        info->iterations = total_iters;
+        info->outer_iterations = outer;
+        info->status = IGS_BREAKDOWN;
+        return IGS_BREAKDOWN;
+      }
+      worst = std::max(worst, rel);
+      active[b] = rel > rtol;
+      all &= !active[b];
+      scale[b] = std::sqrt(rr[b]);
+      // inner target relative to |rhat| = 1: enough to meet rtol with margin,
+      // never tighter than the inner precision allows
+      double t = active[b] ? 0.5 * rtol * std::sqrt(ff[b] / rr[b]) : 1.0;
+      t = std::max(t, inner_rel);
+      tol2[b] = t * t;
+    }
+    if (all) {
+      result = IGS_OK;
+      break;
+    }
+    if (total_iters >= maxit || (breakdown && outer > 0)) break;
+    HIP_OK(hipMemcpyAsync(sb.scale, scale.data(), sizeof(double) * nb, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(sb.tol2, tol2.data(), sizeof(double) * nb, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(sb.active, active.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
+    int it = 0;
+    st = inner_cg<T>(d, bandT, sb, rh, p, q, dv, maxit - total_iters, &hsc, &it, s);
+    if (st != IGS_OK) return st;
+    for (size_t b = 0; b < nb; ++b) breakdown |= hsc[b].breakdown != 0;
+    total_iters += it;
+    ++outer;
+    hipLaunchKernelGGL((axpy_update_kernel<T>), dim3(grid_stride_blocks(NB)), dim3(256), 0, s, d.N, d.batch,
+                       sb.scale, dv, u);
+    HIP_OK(hipGetLastError());
+  }
+  if (result != IGS_OK && breakdown) result = IGS_BREAKDOWN;
+  info->iterations = total_iters;
+  info->outer_iterations = outer;
+  info->relres = worst;
+  info->status = result;
+  HIP_OK(hipStreamSynchronize(s));
+  return result;
+}
+
+igs_status solve_cg(const Dims& d, const double* band64, const float* band32, const double* f, double* u, double rtol,
+                    int maxit, igs_cg_info* info, hipStream_t s) {
+  if (band32)
+    return refine_loop<float>(d, band64, band32, f, u, rtol, maxit, 1e-4, info, s);
+  return refine_loop<double>(d, band64, band64, f, u, rtol, maxit, 0.0, info, s);
+}
+
+}  // namespace igs

@@ -1,0 +1,145 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/igs.h declares, and its host-only queries (band layout, sample
+lattice, row classes, argument validation) agree with the oracle's own
+planning.  No compute entry point is called with valid arguments here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1904_06971_amd import igs
+from paper_1904_06971_amd import workloads as W
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "igs.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:igs_status|const char\*)\s+(igs_\w+)\(", txt, flags=re.M)))
+
+
+def test_exports_every_declared_symbol():
+    L = igs.lib()
+    names = _declared()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(igs.EXPORTS)
+    assert "gfx950" in igs.version()
+
+
+def test_status_strings():
+    for st in igs.STATUS:
+        assert igs.lib().igs_status_string(st).decode() not in ("", "unknown status")
+
+
+@pytest.mark.parametrize("prob", [W.c1_poisson2d(), W.c2_poisson3d(), W.c3_varcoef3d(), W.c4_precision3d(),
+                                  W.c5_adjoint2d()])
+def test_layout_matches_oracle(oracle, prob):
+    lay = igs.layout(prob)
+    m, N, S = oracle.dims(prob)
+    assert tuple(lay.m[:prob["n"]]) == m and lay.N == N and lay.slots == S
+    assert lay.ld % 64 == 0 and N <= lay.ld < N + 64
+    assert lay.band_elems == prob["batch"] * S * lay.ld
+    assert lay.upper == (S - 1) // 2
+
+
+@pytest.mark.parametrize("prob,M,q", [(W.c1_poisson2d(), 4, 3), (W.c2_poisson3d(), 4, 3), (W.c2_poisson3d(), 8, 3),
+                                      (W.c2_poisson3d(), 16, 3), (W.c3_varcoef3d(), 8, 3), (W.c4_precision3d(), 8, 3),
+                                      (W.c5_adjoint2d(), 8, 3), (W.problem(2, 2, 40), 1, 5)])
+def test_surrogate_layout_matches_oracle(oracle, prob, M, q):
+    info, idx = igs.surrogate_layout(prob, M, q)
+    m, N, _ = oracle.dims(prob)
+    for d in range(prob["n"]):
+        assert np.array_equal(idx[d], oracle.lattice(m[d], prob["p"], M))
+    quad = oracle.quadrature_rows(prob, M) if N < 400000 else None
+    if quad is not None:
+        assert info.quadrature_rows == quad.sum()
+    inner = np.prod([m[d] - 4 * prob["p"] for d in range(prob["n"])])
+    assert info.boundary_rows == N - inner
+    assert info.sample_rows == np.prod([len(i) for i in idx])
+
+
+def test_published_sizes():
+    """Sizes quoted for the workloads: 34^2 = 1156 dofs; 67^3 = 300,763 dofs with
+    343-entry stencils; 132^3 with 729-entry stencils; 131^3 ~ 2.25M dofs; 259^2."""
+    assert igs.layout(W.c1_poisson2d()).N == 1156
+    lay = igs.layout(W.c2_poisson3d())
+    assert lay.N == 300763 and lay.slots == 343 and lay.N * lay.slots == 103161709
+    lay = igs.layout(W.c3_varcoef3d())
+    assert lay.N == 2299968 and lay.slots == 729 and lay.N * lay.slots == 1676676672
+    lay = igs.layout(W.c4_precision3d())
+    assert lay.N == 2248091 and lay.N * lay.slots == 771095213
+    assert igs.layout(W.c5_adjoint2d()).N == 67081
+
+
+def _status(fn, *args):
+    return fn(*args)
+
+
+@pytest.mark.parametrize("mutate,expected", [
+    (lambda pb: setattr(pb, "n", 4), igs.IGS_OK - 1),
+    (lambda pb: setattr(pb, "p", 0), -1),
+    (lambda pb: setattr(pb, "p", 5), -2),
+    (lambda pb: setattr(pb, "batch", 0), -1),
+    (lambda pb: setattr(pb, "nquad", 7), -2),
+    (lambda pb: setattr(pb, "nquad", -1), -1),
+    (lambda pb: pb.nelem.__setitem__(1, 0), -1),
+    (lambda pb: setattr(pb.geom, "kind", 9), -1),
+    (lambda pb: setattr(pb.coef, "kind", 9), -1),
+])
+def test_validation_errors(mutate, expected):
+    pb = igs.make_problem(W.c1_poisson2d())
+    mutate(pb)
+    L = igs.lib()
+    assert L.igs_validate(ctypes.byref(pb), 0, 0) == expected
+    # every compute entry point rejects the same problem before touching the GPU
+    dummy = ctypes.c_void_p(16)
+    assert L.igs_assemble_exact(ctypes.byref(pb), 0, 0, dummy, None) == expected
+    assert L.igs_assemble_surrogate(ctypes.byref(pb), 0, 4, 3, 0, dummy, None) == expected
+    assert L.igs_assemble_rhs(ctypes.byref(pb), 0, 1.0, dummy, None) == expected
+    assert L.igs_apply(ctypes.byref(pb), 0, dummy, dummy, dummy, 0, None) == expected
+
+
+def test_sampling_errors():
+    L = igs.lib()
+    pb = igs.make_problem(W.problem(2, 2, 14))          # 8 analysis rows per direction
+    assert L.igs_validate(ctypes.byref(pb), 4, 3) == -4  # 3 samples < q + 1
+    assert L.igs_validate(ctypes.byref(pb), 2, 3) == 0
+    assert L.igs_validate(ctypes.byref(pb), 0, 3) == -1  # M < 1
+    assert L.igs_validate(ctypes.byref(pb), 2, 0) == -1
+    assert L.igs_validate(ctypes.byref(pb), 2, 6) == -2  # q > 5
+    pb = igs.make_problem(W.problem(2, 3, 5))           # m - 4p < 1: no analysis rows
+    assert L.igs_validate(ctypes.byref(pb), 1, 1) == -4
+    dummy = ctypes.c_void_p(16)
+    assert L.igs_assemble_surrogate(ctypes.byref(pb), 0, 1, 1, 0, dummy, None) == -4
+
+
+def test_knot_validation():
+    prob = W.problem(2, 2, 6)
+    good = np.concatenate([np.zeros(2), np.linspace(0, 1, 7), np.ones(2)])
+    bad = good.copy()
+    bad[4] += 0.01
+    L = igs.lib()
+    assert L.igs_validate(ctypes.byref(igs.make_problem(prob, knots=[good, good])), 0, 0) == 0
+    assert L.igs_validate(ctypes.byref(igs.make_problem(prob, knots=[good, bad])), 0, 0) == -3
+
+
+def test_null_and_enum_arguments():
+    L = igs.lib()
+    pb = igs.make_problem(W.c1_poisson2d())
+    dummy = ctypes.c_void_p(16)
+    assert L.igs_assemble_exact(None, 0, 0, dummy, None) == -1
+    assert L.igs_assemble_exact(ctypes.byref(pb), 0, 0, None, None) == -1
+    assert L.igs_assemble_exact(ctypes.byref(pb), 2, 0, dummy, None) == -1
+    assert L.igs_assemble_exact(ctypes.byref(pb), 0, 5, dummy, None) == -1
+    assert L.igs_assemble_rhs(ctypes.byref(pb), 3, 1.0, dummy, None) == -1
+    info = igs.CgInfo()
+    assert L.igs_solve_cg(ctypes.byref(pb), dummy, None, dummy, dummy, 0.0, 10, ctypes.byref(info), None) == -1
+    assert L.igs_solve_cg(ctypes.byref(pb), dummy, None, dummy, dummy, 1e-8, 0, ctypes.byref(info), None) == -1
+    assert L.igs_solve_cg(ctypes.byref(pb), None, None, dummy, dummy, 1e-8, 10, ctypes.byref(info), None) == -1
+    sp = igs.make_problem(W.c5_adjoint2d())
+    sp.coef.coef = None                                # spline coefficient without control values
+    assert L.igs_validate(ctypes.byref(sp), 0, 0) == -1

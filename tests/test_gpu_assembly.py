@@ -1,0 +1,181 @@
+"""GPU parity: exact and surrogate band rows from the HIP kernels against the
+FP64 CPU oracle, element by element, 1e-12 relative in the max norm (FP64).
+Small problems are compared in full (several tiles, ragged tails); the
+workload sizes are compared on sampled rows."""
+import numpy as np
+import pytest
+
+from gpu_util import gather_rows, rel_maxnorm
+from paper_1904_06971_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def igs():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_1904_06971_amd import igs as m
+
+    m.lib()
+    return m
+
+
+def _full(igs, band, prob, b=0):
+    return igs.band_rows(band, prob, b)
+
+
+EXACT_CASES = [
+    (W.problem(2, 1, 70), 0), (W.problem(2, 2, 33), 0), (W.problem(2, 3, (67, 21)), 0), (W.problem(2, 4, 29), 0),
+    (W.problem(2, 2, 33), 1), (W.problem(2, 3, 40, geom="identity"), 1),
+    (W.problem(2, 3, 26, coef="sine3", camp=0.5), 0), (W.problem(2, 2, 20, geom="poly2", ga=0.3), 0),
+    (W.problem(3, 1, (19, 9, 7)), 0), (W.problem(3, 2, (11, 9, 8)), 0), (W.problem(3, 3, (10, 9, 11)), 0),
+    (W.problem(3, 4, (9, 7, 8)), 0), (W.problem(3, 3, (10, 9, 11)), 1), (W.problem(3, 4, 8), 1),
+    (W.problem(3, 3, 9, coef="sine3", camp=0.5), 0), (W.problem(3, 2, 9, geom="poly2", ga=0.2), 1),
+]
+
+
+@pytest.mark.parametrize("prob,form", EXACT_CASES)
+def test_exact_small(igs, oracle, prob, form):
+    _, N, _ = oracle.dims(prob)
+    band = igs.assemble_exact(prob, form)
+    ref = oracle.exact_rows(prob, form, np.arange(N))
+    assert rel_maxnorm(_full(igs, band, prob), ref) < TOL64
+    lay = igs.layout(prob)
+    if lay.ld > N:
+        assert float(band[:, :, N:].abs().max()) == 0.0
+
+
+def test_exact_batched_spline(igs, oracle):
+    rng = np.random.default_rng(0)
+    cc = rng.normal(0, 0.5, (3, 36))
+    prob = W.problem(2, 3, 30, coef="exp_spline", cdeg=3, cn=(6, 6), cc=cc, batch=3)
+    band = igs.assemble_exact(prob, 0)
+    _, N, _ = oracle.dims(prob)
+    for b in range(3):
+        ref = oracle.exact_rows(prob, 0, np.arange(N), b=b)
+        assert rel_maxnorm(_full(igs, band, prob, b), ref) < TOL64
+
+
+def test_exact_fp32_storage(igs, oracle):
+    import torch
+
+    prob = W.problem(3, 3, 12)
+    _, N, _ = oracle.dims(prob)
+    band = igs.assemble_exact(prob, 0, dtype=torch.float32)
+    ref = oracle.exact_rows(prob, 0, np.arange(N))
+    err = rel_maxnorm(_full(igs, band, prob), ref)
+    assert err < 1e-7
+
+
+SUR_CASES = [
+    (W.problem(2, 2, 32), 0, 4, 3), (W.problem(2, 3, 70), 0, 5, 3), (W.problem(2, 2, 50), 1, 4, 3),
+    (W.problem(2, 2, 45), 0, 3, 2), (W.problem(2, 3, 90, coef="sine3", camp=0.5), 0, 8, 5),
+    (W.problem(2, 1, 66), 0, 4, 1), (W.problem(2, 4, 80), 0, 6, 4),
+    (W.problem(3, 2, 22), 0, 4, 3), (W.problem(3, 3, (26, 24, 25)), 0, 4, 3), (W.problem(3, 3, 26), 1, 4, 3),
+    (W.problem(3, 4, 30), 0, 5, 3), (W.problem(3, 2, 20, coef="sine3", camp=0.5), 0, 3, 2),
+]
+
+
+@pytest.mark.parametrize("prob,form,M,q", SUR_CASES)
+def test_surrogate_small(igs, oracle, prob, form, M, q):
+    _, N, _ = oracle.dims(prob)
+    band = igs.assemble_surrogate(prob, form, M=M, q=q)
+    ref = oracle.surrogate_rows(prob, form, M, q)
+    assert rel_maxnorm(_full(igs, band, prob), ref) < TOL64
+
+
+@pytest.mark.parametrize("prob,form", [(W.problem(2, 3, 30), 0), (W.problem(3, 2, 14), 0), (W.problem(3, 2, 14), 1)])
+def test_surrogate_m1_equals_exact(igs, oracle, prob, form):
+    a = igs.band_rows(igs.assemble_exact(prob, form), prob)
+    t = igs.band_rows(igs.assemble_surrogate(prob, form, M=1, q=3), prob)
+    assert rel_maxnorm(t, a) < 1e-13
+
+
+def test_surrogate_structure(igs, oracle):
+    """Bitwise symmetry of interpolated pairs and zero row sums (eq. 5.1c)."""
+    prob = W.problem(3, 3, 30)
+    band = igs.assemble_surrogate(prob, 0, M=4, q=3)
+    R = _full(igs, band, prob)
+    A = oracle.to_csr(prob, R)
+    d = abs(A - A.T)
+    assert d.max() <= 1e-15 * abs(A).max()
+    assert np.abs(np.asarray(A.sum(axis=1))).max() < 1e-13 * abs(A).max()
+
+
+def test_surrogate_fp32(igs, oracle):
+    import torch
+
+    prob = W.problem(3, 3, 28)
+    band = igs.assemble_surrogate(prob, 0, M=4, q=3, dtype=torch.float32)
+    ref = oracle.surrogate_rows(prob, 0, 4, 3)
+    got = _full(igs, band, prob)
+    assert rel_maxnorm(got, ref) < 2e-6
+
+
+def test_geometry_fold_reported(igs):
+    """A sine map with amplitude 0.5 folds (det J < 0 somewhere)."""
+    prob = W.problem(2, 2, 16, ga=0.5)
+    with pytest.raises(igs.IGSError) as e:
+        igs.assemble_exact(prob, 0)
+    assert e.value.status == -5
+
+
+# ------------------------------------------------------------ full sizes ---
+def _sampled(oracle, prob, M, seed, count=4096):
+    _, N, _ = oracle.dims(prob)
+    m = oracle.dims(prob)[0]
+    samp = [oracle.lattice(m[d], prob["p"], M) for d in range(prob["n"])]
+    g = np.meshgrid(*samp[::-1], indexing="ij")
+    srows = oracle.flat_index(prob, np.stack([x.ravel() for x in g[::-1]], axis=1))
+    rnd = W.random_rows(N, count, seed)
+    return np.unique(np.concatenate([srows, rnd]))
+
+
+@pytest.mark.parametrize("M", [4, 8, 16])
+def test_c2_surrogate_sampled(igs, oracle, M):
+    prob = W.c2_poisson3d()
+    rows = _sampled(oracle, prob, M, 20 + M, 1500)
+    for form in (0, 1):
+        band = igs.assemble_surrogate(prob, form, M=M, q=3)
+        ref = oracle.Surrogate(prob, form, M, 3).rows(rows)
+        assert rel_maxnorm(gather_rows(band, rows), ref) < TOL64
+        del band
+
+
+def test_c2_exact_sampled(igs, oracle):
+    prob = W.c2_poisson3d()
+    _, N, _ = oracle.dims(prob)
+    rows = W.random_rows(N, 3000, 7)
+    for form in (0, 1):
+        band = igs.assemble_exact(prob, form)
+        ref = oracle.exact_rows(prob, form, rows)
+        assert rel_maxnorm(gather_rows(band, rows), ref) < TOL64
+        del band
+
+
+def test_c4_surrogate_and_exact_sampled(igs, oracle):
+    prob = W.c4_precision3d()
+    rows = _sampled(oracle, prob, 8, 4, 2048)
+    band = igs.assemble_surrogate(prob, 0, M=8, q=3)
+    ref = oracle.Surrogate(prob, 0, 8, 3).rows(rows)
+    assert rel_maxnorm(gather_rows(band, rows), ref) < TOL64
+    del band
+    band = igs.assemble_exact(prob, 0)
+    _, N, _ = oracle.dims(prob)
+    rr = W.random_rows(N, 1500, 5)
+    assert rel_maxnorm(gather_rows(band, rr), oracle.exact_rows(prob, 0, rr)) < TOL64
+
+
+def test_c3_surrogate_sampled(igs, oracle):
+    """p = 4 variable coefficient: all sample rows plus 4096 seeded random rows."""
+    prob = W.c3_varcoef3d()
+    _, N, _ = oracle.dims(prob)
+    m = oracle.dims(prob)[0]
+    rnd = np.random.default_rng(3).integers(0, N, 4096)
+    band = igs.assemble_surrogate(prob, 0, M=8, q=3)
+    sur = oracle.Surrogate(prob, 0, 8, 3)
+    rows = np.unique(np.concatenate([sur.sample_rows, rnd]))
+    assert rel_maxnorm(gather_rows(band, rows), sur.rows(rows)) < TOL64

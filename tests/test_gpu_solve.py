@@ -1,0 +1,99 @@
+"""GPU parity for the load vector, SpMV and CG against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import rel_maxnorm
+from paper_1904_06971_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def igs():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_1904_06971_amd import igs as m
+
+    m.lib()
+    return m
+
+
+@pytest.mark.parametrize("prob,src,c", [(W.c1_poisson2d(), 1, 2 * math.pi ** 2), (W.problem(2, 3, 57), 0, 1.0),
+                                        (W.problem(3, 3, (14, 11, 12)), 1, 3 * math.pi ** 2),
+                                        (W.problem(3, 2, 13, geom="identity"), 0, 2.0), (W.problem(3, 4, 9), 1, 1.0)])
+def test_rhs(igs, oracle, prob, src, c):
+    f = igs.assemble_rhs(prob, src, c)
+    ref = oracle.rhs(prob, src, c)
+    assert rel_maxnorm(f[0].cpu().numpy(), ref) < 1e-13
+
+
+@pytest.mark.parametrize("prob", [W.problem(2, 3, 41), W.problem(3, 3, (20, 19, 21)), W.problem(3, 2, 17)])
+@pytest.mark.parametrize("dirichlet", [False, True])
+def test_apply(igs, oracle, prob, dirichlet):
+    import torch
+
+    _, N, _ = oracle.dims(prob)
+    band = igs.assemble_surrogate(prob, 0, M=3, q=3)
+    rows = igs.band_rows(band, prob)
+    x = W.random_vector(N, 9)
+    y = igs.apply(prob, band, torch.as_tensor(x, device="cuda"), dirichlet=dirichlet)
+    ref = oracle.apply(prob, rows, x[0], dirichlet=dirichlet)
+    assert rel_maxnorm(y[0].cpu().numpy(), ref) < 1e-13
+    b32 = band.float()
+    y32 = igs.apply(prob, b32, torch.as_tensor(x, device="cuda", dtype=torch.float32), dirichlet=dirichlet)
+    assert rel_maxnorm(y32[0].double().cpu().numpy(), ref) < 1e-5
+
+
+def test_cg_c1(igs, oracle):
+    prob = W.c1_poisson2d()
+    band = igs.assemble_surrogate(prob, 0, M=4, q=3)
+    f = igs.assemble_rhs(prob, 1, 2 * math.pi ** 2)
+    u, info = igs.solve_cg(prob, band, f, rtol=1e-10)
+    assert info["status"] == 0 and info["relres"] <= 1e-10
+    rows = igs.band_rows(band, prob)
+    uref, it, _ = oracle.cg(prob, rows, f[0].cpu().numpy(), rtol=1e-13)
+    assert rel_maxnorm(u[0].cpu().numpy(), uref) < 1e-8
+    # L2 error against the manufactured solution (loose, depends on h)
+    err = oracle.l2_error(prob, u[0].cpu().numpy(), lambda x: np.sin(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1]))
+    assert err < 2e-4
+
+
+def test_cg_mixed_precision(igs, oracle):
+    import torch
+
+    prob = W.problem(3, 3, 20)
+    b64 = igs.assemble_surrogate(prob, 0, M=4, q=3)
+    b32 = igs.assemble_surrogate(prob, 0, M=4, q=3, dtype=torch.float32)
+    f = igs.assemble_rhs(prob, 1, 3 * math.pi ** 2)
+    u64, i64 = igs.solve_cg(prob, b64, f, rtol=1e-10)
+    umx, imx = igs.solve_cg(prob, b64, f, band32=b32, rtol=1e-10)
+    assert i64["relres"] <= 1e-10 and imx["relres"] <= 1e-10
+    assert imx["outer_iterations"] >= 2
+    # both solve the FP64 surrogate system to 1e-10
+    rows = igs.band_rows(b64, prob)
+    uref, _, _ = oracle.cg(prob, rows, f[0].cpu().numpy(), rtol=1e-13)
+    assert rel_maxnorm(u64[0].cpu().numpy(), uref) < 1e-7
+    assert rel_maxnorm(umx[0].cpu().numpy(), uref) < 1e-7
+
+
+def test_cg_batched(igs, oracle):
+    prob = W.c5_adjoint2d(nelem=40, batch=3, cn=8)
+    band = igs.assemble_surrogate(prob, 0, M=4, q=3)
+    f = igs.assemble_rhs(prob, 0, 1.0)
+    u, info = igs.solve_cg(prob, band, f, rtol=1e-11)
+    assert info["relres"] <= 1e-11
+    for b in range(3):
+        rows = igs.band_rows(band, prob, b)
+        uref, _, _ = oracle.cg(prob, rows, f[b].cpu().numpy(), rtol=1e-13)
+        assert rel_maxnorm(u[b].cpu().numpy(), uref) < 1e-8
+
+
+def test_cg_not_converged(igs):
+    prob = W.c1_poisson2d()
+    band = igs.assemble_exact(prob, 0)
+    f = igs.assemble_rhs(prob, 0, 1.0)
+    u, info = igs.solve_cg(prob, band, f, rtol=1e-10, maxit=3, check=False)
+    assert info["status"] == 1 and info["iterations"] <= 3 + 32
