@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""Benchmark of the surrogate-matrix assembly path on one MI355X.
+
+Step: one surrogate assembly (FP64, M = 8, q = 3) of the 3D p = 3 Poisson
+stiffness on the sine-mapped unit cube with 128^3 elements (131^3 dofs,
+343-slot stencils): quadrature of the boundary and sample rows, spline fit,
+fill of every other row, padding.  value = band slots assembled per second
+(N * S / step time).  The same run also measures, each with its own timing,
+full quadrature assembly of the same matrix, the banded SpMV, CG in FP64 and
+FP32-inside-FP64-refinement to 1e-10, and the batched 2D compliance solve +
+adjoint; those figures go into the same JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def quad_flops_per_row(n, p):
+    """Algorithmic flops of sum-factorised row quadrature (stiffness): per
+    (a, b) component (p+1)^5 + (2p+1)(p+1)^4 + (2p+1)^2(p+1)^3 FMA in 3D,
+    (p+1)^3 + (2p+1)(p+1)^2 in 2D; n^2 components; 2 flops per FMA."""
+    if n == 3:
+        fma = (p + 1) ** 5 + (2 * p + 1) * (p + 1) ** 4 + (2 * p + 1) ** 2 * (p + 1) ** 3
+    else:
+        fma = (p + 1) ** 3 + (2 * p + 1) * (p + 1) ** 2
+    return 2 * n * n * fma
+
+
+def fill_bytes(prob, lay, esize):
+    """Algorithmic HBM bytes of the fill: every slot of every analysis-domain row
+    written once, plus one read per copied exact entry (partner outside the
+    analysis domain)."""
+    n, p = prob["n"], prob["p"]
+    L = [lay.m[d] - 4 * p for d in range(n)]
+    rows = math.prod(L)
+    both = math.prod(sum(L[d] - abs(dl) for dl in range(-p, p + 1)) for d in range(n))
+    copies = rows * lay.slots - both
+    return rows * lay.slots * esize + copies * esize, rows, copies
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="only the timed step (for profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the path is single-GPU in this build (sharding is described in the "
+              "design notes, not implemented); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1904_06971_amd import igs
+    from paper_1904_06971_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob = W.c4_precision3d()
+    M, q = 8, 3
+    lay = igs.layout(prob)
+    info, _ = igs.surrogate_layout(prob, M, q)
+    slots = lay.N * lay.slots
+    true_nnz = math.prod(lay.m[d] * (2 * prob["p"] + 1) - prob["p"] * (prob["p"] + 1) for d in range(3))
+    band = igs.empty_band(prob, torch.float64)
+    stream = torch.cuda.current_stream()
+
+    # ------------------------------------------------------------ timed step
+    for _ in range(args.warmup):
+        igs.assemble_surrogate(prob, igs.STIFFNESS, M, q, out=band)
+    torch.cuda.synchronize()
+    igs.profile_enable(True)
+    igs.profile_read()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        igs.assemble_surrogate(prob, igs.STIFFNESS, M, q, out=band)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = igs.profile_read()
+    igs.profile_enable(False)
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    value = slots / (ms_step * 1e-3)
+    phases = {k: {"launches": v[0], "avg_ms": v[1] / v[0]} for k, v in prof.items()}
+    log(f"surrogate: {ms_step:.3f} ms/step (wall {wall / args.steps * 1e3:.3f}), {value:.3e} slots/s, phases {phases}")
+
+    # rooflines of the step's kernels
+    qrows = info.quadrature_rows
+    quad_flops = quad_flops_per_row(3, prob["p"]) * qrows
+    fb, frows, fcopies = fill_bytes(prob, lay, 8)
+    roofs = {}
+    qphases = [k for k in phases if k.startswith("quad_")]
+    if qphases:
+        # the three quadrature launches of the step together assemble the quadrature rows
+        t = sum(phases[k]["avg_ms"] for k in qphases) * 1e-3
+        roofs["quad_surrogate_rows"] = {"bound": "alu", "achieved": quad_flops / t / 1e12, "peak": FP64_PEAK_TFLOPS,
+                                        "unit": "TFLOP/s", "frac": quad_flops / t / 1e12 / FP64_PEAK_TFLOPS,
+                                        "traffic": None, "units": f"{qrows} quadrature rows",
+                                        "ms": t * 1e3, "launches": qphases}
+    if "fill" in phases:
+        t = phases["fill"]["avg_ms"] * 1e-3
+        roofs["fill"] = {"bound": "hbm", "achieved": fb / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": fb / t / 1e9 / HBM_PEAK_GBS, "traffic": None, "ms": t * 1e3,
+                         "units": f"{frows} analysis-domain rows x {lay.slots} slots, {fcopies} copied entries"}
+    dominant = max(roofs, key=lambda k: roofs[k].get("ms", phases.get(k, {}).get("avg_ms", 0.0)))
+    roofline = dict(roofs[dominant])
+    roofline["kernel"] = dominant
+
+    extra = {}
+    if not args.no_extra:
+        # ------------------------------------------- full quadrature assembly
+        igs.assemble_exact(prob, igs.STIFFNESS, out=band)
+        igs.profile_enable(True)
+        igs.profile_read()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(3):
+            igs.assemble_exact(prob, igs.STIFFNESS, out=band)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pe = igs.profile_read()
+        igs.profile_enable(False)
+        ms_ex = e0.elapsed_time(e1) / 3
+        tq = pe["quad_exact"][1] / pe["quad_exact"][0] * 1e-3
+        fl = quad_flops_per_row(3, prob["p"]) * lay.N
+        extra["exact_assembly"] = {"ms": ms_ex, "slots_per_s": slots / (ms_ex * 1e-3),
+                                   "quad_kernel_tflops": fl / tq / 1e12, "quad_kernel_frac": fl / tq / 1e12 / FP64_PEAK_TFLOPS}
+        extra["speedup_surrogate_vs_exact"] = ms_ex / ms_step
+        log(f"exact: {ms_ex:.3f} ms; surrogate speed-up {ms_ex / ms_step:.2f}x")
+
+        # -------------------------------------------------------- SpMV / CG
+        igs.assemble_surrogate(prob, igs.STIFFNESS, M, q, out=band)
+        b32 = igs.assemble_surrogate(prob, igs.STIFFNESS, M, q, dtype=torch.float32)
+        x = torch.randn(1, lay.N, dtype=torch.float64, device=dev)
+        x32 = x.float()
+        igs.profile_enable(True)
+        igs.profile_read()
+        for _ in range(10):
+            igs.apply(prob, band, x)
+        p64 = igs.profile_read()["spmv"]
+        for _ in range(10):
+            igs.apply(prob, b32, x32)
+        p32 = igs.profile_read()["spmv"]
+        igs.profile_enable(False)
+        t64, t32 = p64[1] / p64[0] * 1e-3, p32[1] / p32[0] * 1e-3
+        extra["spmv"] = {"f64_ms": t64 * 1e3, "f64_GBps": lay.slots * lay.N * 8 / t64 / 1e9,
+                         "f32_ms": t32 * 1e3, "f32_GBps": lay.slots * lay.N * 4 / t32 / 1e9}
+        f = igs.assemble_rhs(prob, igs.SRC_SINE, 3 * math.pi ** 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u64, i64 = igs.solve_cg(prob, band, f, rtol=1e-10, maxit=20000)
+        torch.cuda.synchronize()
+        tc64 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        umx, imx = igs.solve_cg(prob, band, f, band32=b32, rtol=1e-10, maxit=20000)
+        torch.cuda.synchronize()
+        tcmx = time.perf_counter() - t0
+        du = float((umx - u64).abs().max() / u64.abs().max())
+        extra["cg"] = {"rtol": 1e-10, "f64_ms": tc64 * 1e3, "f64_iterations": i64["iterations"],
+                       "f64_relres": i64["relres"], "mixed_ms": tcmx * 1e3, "mixed_iterations": imx["iterations"],
+                       "mixed_outer": imx["outer_iterations"], "mixed_relres": imx["relres"],
+                       "mixed_vs_f64_max_rel_diff": du, "speedup_mixed": tc64 / tcmx}
+        b32_err = float((b32.double() - band).abs().max() / band.abs().max())
+        extra["fp32_band_max_rel_err"] = b32_err
+        log(f"cg: {extra['cg']}")
+        del b32, x, x32
+
+        # ---------------------------------------- batched 2D compliance + adjoint
+        try:
+            p5 = W.c5_adjoint2d()
+            b5 = igs.assemble_surrogate(p5, igs.STIFFNESS, 8, 3)
+            f5 = igs.assemble_rhs(p5, igs.SRC_CONST, 1.0)
+            igs.compliance_grad(p5, 8, 3, f5)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b5 = igs.assemble_surrogate(p5, igs.STIFFNESS, 8, 3, out=b5)
+            u5, i5 = igs.solve_cg(p5, b5, f5, rtol=1e-10)
+            tsolve = time.perf_counter() - t0
+            t1 = time.perf_counter()
+            g5 = igs.compliance_grad(p5, 8, 3, u5)
+            torch.cuda.synchronize()
+            tadj = time.perf_counter() - t1
+            extra["compliance_2d_batch8"] = {"assembly_cg_ms": tsolve * 1e3, "adjoint_ms": tadj * 1e3,
+                                             "cg_plus_adjoint_ms": (tsolve + tadj) * 1e3,
+                                             "cg_iterations": i5["iterations"], "relres": i5["relres"]}
+            del b5
+        except igs.IGSError as e:
+            extra["compliance_2d_batch8"] = {"error": str(e)}
+        log(f"c5: {extra['compliance_2d_batch8']}")
+
+    # ------------------------------------------------------------ CPU oracle
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(prob, M, q, lay)
+        log(f"cpu baseline: {cpu}")
+
+    out = {
+        "metric": "assembled nnz/s (surrogate vs quadrature), 3D p=3 128^3; CG+adjoint ms",
+        "value": value,
+        "unit": "band slots/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D Poisson stiffness, p=3, 128^3 elements, sine map a=0.05, kappa=1, surrogate M=8 q=3",
+                   "dofs": lay.N, "slots": slots, "true_nnz": true_nnz, "parallelism": "single GPU"},
+        "true_nnz_per_s": true_nnz / (ms_step * 1e-3),
+        "phases_ms": {k: v["avg_ms"] for k, v in phases.items()},
+        "roofline": roofline,
+        "rooflines": roofs,
+        "cpu_baseline": cpu,
+        **extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(prob, M, q, lay):
+    """The oracle timed on the host: sample-row quadrature and fit in full, then
+    seeded random samples of boundary rows (exact) and analysis-domain rows
+    (surrogate), extrapolated to all rows."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1904_06971_amd import workloads as W
+
+    O.build()
+    m, N, S = O.dims(prob)
+    t0 = time.perf_counter()
+    sur = O.Surrogate(prob, 0, M, q)
+    t_setup = time.perf_counter() - t0
+    rows = W.random_rows(N, 60000, 77)
+    idx = O.multi_index(prob, rows)
+    inner = O.interior_mask(prob, idx)
+    rb = rows[~inner][:1500]
+    ri = rows[inner][:8000]
+    t0 = time.perf_counter()
+    O.exact_rows(prob, 0, rb)
+    t_b = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sur.rows(ri)
+    t_i = time.perf_counter() - t0
+    nb = N - math.prod(m[d] - 4 * prob["p"] for d in range(3))
+    ni = N - nb
+    total = t_setup + t_b * nb / len(rb) + t_i * ni / len(ri)
+    return {"value": N * S / total, "unit": "band slots/s", "cores": O.threads(), "kind": "oracle",
+            "sample": (f"sample-row quadrature + fit in full ({len(sur.sample_rows)} rows, {t_setup:.1f} s), "
+                       f"{len(rb)} random boundary rows ({t_b:.1f} s) and {len(ri)} random analysis-domain rows "
+                       f"({t_i:.1f} s), extrapolated to {nb} + {ni} rows: {total:.0f} s for the full band")}
+
+
+if __name__ == "__main__":
+    main()

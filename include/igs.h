@@ -19,13 +19,14 @@
  *   the centre slot (S-1)/2 is the diagonal.  "Upper" slots are s > (S-1)/2
  *   (j > i in the dof order, Sec. 5.2).
  * - Band layout (stencil-major): band[b][s][k], b < batch, s < S, k < ld,
- *   where ld = N rounded up to a multiple of 64 (igs_band_layout).  Entry
+ *   where ld is the smallest multiple of 64 greater than N (igs_band_layout).  Entry
  *   band[b][s][i] = A_{i, i+delta_s}; it is 0 when i+delta_s leaves the index
  *   box.  Padding k in [N, ld) is written as 0.
  * - Vectors are [batch][N], contiguous.
  * - Device memory: every pointer marked "device" must be device memory (or
  *   host-coherent memory visible to the GPU) owned by the caller.  The library
- *   keeps no pointer after a call returns and holds no global mutable state;
+ *   keeps no pointer after a call returns and holds no global mutable state
+ *   besides the opt-in, thread-local profiling record (igs_profile_enable);
  *   scratch memory is taken stream-ordered from the default memory pool and
  *   returned before the call returns.
  * - stream: a hipStream_t passed as void* (NULL = the null stream).
@@ -118,7 +119,7 @@ typedef struct igs_layout {
   int32_t slots;       /* S = (2p+1)^n */
   int32_t upper;       /* (S-1)/2 upper slots */
   int64_t N;           /* dofs per problem */
-  int64_t ld;          /* slot stride of the band, N rounded up to 64 */
+  int64_t ld;          /* slot stride of the band: smallest multiple of 64 > N */
   int64_t band_elems;  /* batch * S * ld */
 } igs_layout;
 
@@ -133,7 +134,9 @@ typedef struct igs_surrogate_info {
 
 typedef struct igs_cg_info {
   int32_t iterations;        /* total CG iterations (inner FP32 ones in mixed mode) */
-  int32_t outer_iterations;  /* refinement steps (0 in plain FP64 mode) */
+  int32_t outer_iterations;  /* inner CG solves between FP64 residual checks
+                                (1 in plain FP64 mode unless the true-residual
+                                check restarts CG) */
   int32_t status;            /* igs_status of the solve */
   double relres;             /* max over batch of ||f_I - A_II u_I||_2 / ||f_I||_2, FP64 */
 } igs_cg_info;
@@ -232,6 +235,31 @@ igs_status igs_apply_vjp(const igs_problem* pb, int32_t M, int32_t q, const doub
  * [batch][N]; cbar: device [batch][prod ncoef].  Synchronous on return. */
 igs_status igs_compliance_grad(const igs_problem* pb, int32_t M, int32_t q, const double* u, double* cbar,
                                void* stream);
+
+/* ------------------------------------------------------------ profiling */
+
+/* Opt-in phase timing (for benchmarks).  When enabled on the calling host
+ * thread, every entry point brackets each kernel launch with HIP events on
+ * its stream and accumulates per phase (kernel name) the number of launches
+ * and their summed GPU duration.  The record is thread-local and is the only
+ * state the library keeps between calls; igs_profile_read returns it and
+ * clears it.  Reading synchronises the events it reports.  Disabled by
+ * default; enabling costs two event records per launch. */
+#define IGS_PROFILE_MAX_PHASES 24
+
+typedef struct igs_profile_phase {
+  char name[32];
+  int32_t launches;
+  double ms;                 /* summed duration of the launches */
+} igs_profile_phase;
+
+typedef struct igs_profile {
+  int32_t nphase;
+  igs_profile_phase phase[IGS_PROFILE_MAX_PHASES];
+} igs_profile;
+
+igs_status igs_profile_enable(int32_t on);
+igs_status igs_profile_read(igs_profile* out);
 
 #ifdef __cplusplus
 }

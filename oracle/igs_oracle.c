@@ -39,6 +39,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_PI 3.14159265358979323846
 
@@ -468,4 +471,13 @@ int or_map(const int32_t* ip, const double* dp, const double* xi, int64_t npts, 
   }
   teardown(&P);
   return 0;
+}
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int or_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

@@ -65,8 +65,14 @@ def _load():
         lib.or_rows.argtypes = [i32p, f64p, f64p, ctypes.c_int, ctypes.c_int, i64p, ctypes.c_int64, f64p]
         lib.or_rhs.argtypes = [i32p, f64p, f64p, ctypes.c_int, ctypes.c_double, i64p, ctypes.c_int64, f64p]
         lib.or_map.argtypes = [i32p, f64p, f64p, ctypes.c_int64, f64p, f64p]
+        lib.or_threads.argtypes = []
         _lib = lib
     return _lib
+
+
+def threads():
+    """OpenMP threads used by the C half of the oracle."""
+    return int(_load().or_threads())
 
 
 def _ptr(a, ct):

@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "igs_internal.h"
+#include "profile.h"
 
 namespace igs {
 
@@ -18,11 +19,13 @@ template <typename BT>
 hipError_t launch_fit(const KInterp<double>& ip, int n, int m1, int m2, int64_t ld, int S, int batch, const BT* band,
                       double* tmp0, double* tmp1, double* coef, hipStream_t s);
 template <typename T>
-hipError_t launch_fill(const KInterp<T>& ip, int form, int n, int p, int m1, int m2, int64_t ld, int S, int batch,
-                       const double* coef, T* band, hipStream_t s);
+hipError_t launch_fill(const KInterp<T>& ip, int form, const Dims& d, const int* chunks, int nchunks, int chunk_rows,
+                       const int4* dsl, const double* coef, T* band, hipStream_t s);
 template <typename T>
-size_t fill_lds_bytes(const KInterp<T>& ip, int n, int p);
-void fill_tile_box(int n, int p, int box[3]);
+size_t fill_lds_bytes(const KInterp<T>& ip, int npen, const Dims& d);
+std::vector<int> fill_chunks(const Dims& d, int rows);
+int fill_npen(const Dims& d, int rows);
+int fill_chunk_rows(const Dims& d, int Sd1);
 template <typename T>
 hipError_t launch_zero_pad(T* band, int64_t N, int64_t ld, int slots_total, hipStream_t s);
 igs_status launch_apply(const Dims& d, int dtype, const void* band, const void* x, void* y, int dirichlet,
@@ -136,8 +139,14 @@ static igs_status exact_t(const igs_problem* pb, int form, OutT* band, hipStream
   if (st != IGS_OK) return st;
   const QTile* dt = upload(ta, tiles, s, &st);
   if (st != IGS_OK) return st;
-  HIP_TRY(launch_quad<OutT>(P.kp, form, dt, int(tiles.size()), band, s));
-  HIP_TRY(launch_zero_pad<OutT>(band, P.d.N, P.d.ld, P.d.S * P.d.batch, s));
+  {
+    PhaseTimer t("quad_exact", s);
+    HIP_TRY(launch_quad<OutT>(P.kp, form, dt, int(tiles.size()), band, s));
+  }
+  {
+    PhaseTimer t("zero_pad", s);
+    HIP_TRY(launch_zero_pad<OutT>(band, P.d.N, P.d.ld, P.d.S * P.d.batch, s));
+  }
   return finish(P, s);
 }
 
@@ -189,19 +198,30 @@ static igs_status surrogate_t(const igs_problem* pb, int form, int M, int q, Out
   st = check_sampling(d, M, q);
   if (st != IGS_OK) return st;
   HostInterp hi;
-  int box[3];
-  fill_tile_box(d.n, d.p, box);
+  int box[3] = {1, 1, 1};
   st = build_interp(d, form, M, q, box, &hi);
   if (st != IGS_OK) return st;
   std::vector<OutT> ebT[3];
   for (int k = 0; k < d.n; ++k) ebT[k].assign(hi.eb[k].begin(), hi.eb[k].end());
   int tx, ty;
   quad_tile_shape(d.n, d.p, &tx, &ty);
-  std::vector<QTile> tiles = tiles_surrogate(d, hi.samp, tx, ty, pick_zchunk(d, tx, ty));
+  int groups[3];
+  std::vector<QTile> tiles = tiles_surrogate(d, hi.samp, tx, ty, pick_zchunk(d, tx, ty), groups);
   size_t per = 1;
   for (int k = 0; k < d.n; ++k) per *= hi.samp[k].size();
   const size_t ncoef = per * hi.upslot.size() * d.batch;
-  size_t bytes = padded(tiles.size() * sizeof(QTile)) + 3 * padded(ncoef * sizeof(double)) +
+  const int chunk_rows = fill_chunk_rows(d, int(hi.samp[0].size()));
+  std::vector<int> chunks = fill_chunks(d, chunk_rows);
+  std::vector<int> dsl;  // (slot, delta1, delta2, delta3) per interpolated slot
+  for (int sl : hi.upslot) {
+    const int W = d.W;
+    dsl.push_back(sl);
+    dsl.push_back(sl % W - d.p);
+    dsl.push_back((sl / W) % W - d.p);
+    dsl.push_back(d.n == 3 ? sl / (W * W) - d.p : 0);
+  }
+  size_t bytes = padded(tiles.size() * sizeof(QTile)) + 3 * padded(ncoef * sizeof(double)) + vbytes(chunks) +
+                 vbytes(dsl) +
                  padded(hi.upslot.size() * sizeof(int)) * 2;
   for (int k = 0; k < d.n; ++k)
     bytes += 2 * (vbytes(hi.samp[k]) + vbytes(hi.ginv[k]) + vbytes(hi.ef[k]) + vbytes(hi.eb[k]));
@@ -211,15 +231,34 @@ static igs_status surrogate_t(const igs_problem* pb, int form, int M, int q, Out
   const QTile* dt = upload(ta, tiles, s, &st);
   KInterp<double> ip64 = interp_view<double>(hi, d, ta, s, &st, hi.eb);
   KInterp<OutT> ipT = interp_view<OutT>(hi, d, ta, s, &st, ebT);
+  const int* dchunks = upload(ta, chunks, s, &st);
+  const int4* ddsl = reinterpret_cast<const int4*>(upload(ta, dsl, s, &st));
   double* tmp0 = ta.take<double>(ncoef);
   double* tmp1 = ta.take<double>(ncoef);
   double* coef = ta.take<double>(ncoef);
   if (st != IGS_OK) return st;
-  if (fill_lds_bytes<OutT>(ipT, d.n, d.p) > 160 * 1024) return IGS_ERR_UNSUPPORTED;
-  HIP_TRY(launch_quad<OutT>(P.kp, form, dt, int(tiles.size()), band, s));
-  HIP_TRY(launch_fit<OutT>(ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, tmp0, tmp1, coef, s));
-  HIP_TRY(launch_fill<OutT>(ipT, form, d.n, d.p, d.m[0], d.m[1], d.ld, d.S, d.batch, coef, band, s));
-  HIP_TRY(launch_zero_pad<OutT>(band, d.N, d.ld, d.S * d.batch, s));
+  if (fill_lds_bytes<OutT>(ipT, fill_npen(d, chunk_rows), d) > 160 * 1024) return IGS_ERR_UNSUPPORTED;
+  {
+    static const char* names[3] = {"quad_boundary_pencils", "quad_end_slabs", "quad_sample_rows"};
+    int first = 0;
+    for (int g = 0; g < 3; ++g) {
+      PhaseTimer t(names[g], s);
+      HIP_TRY(launch_quad<OutT>(P.kp, form, dt + first, groups[g], band, s));
+      first += groups[g];
+    }
+  }
+  {
+    PhaseTimer t("fit", s);
+    HIP_TRY(launch_fit<OutT>(ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, tmp0, tmp1, coef, s));
+  }
+  {
+    PhaseTimer t("fill", s);
+    HIP_TRY(launch_fill<OutT>(ipT, form, d, dchunks, int(chunks.size()), chunk_rows, ddsl, coef, band, s));
+  }
+  {
+    PhaseTimer t("zero_pad", s);
+    HIP_TRY(launch_zero_pad<OutT>(band, d.N, d.ld, d.S * d.batch, s));
+  }
   return finish(P, s);
 }
 
@@ -349,7 +388,10 @@ igs_status igs_assemble_rhs(const igs_problem* pb, int32_t source, double c, dou
   if (st != IGS_OK) return st;
   const QTile* dt = upload(ta, tiles, s, &st);
   if (st != IGS_OK) return st;
-  HIP_TRY(launch_rhs(P.kp, dt, int(tiles.size()), source, c, f, s));
+  {
+    PhaseTimer t("rhs", s);
+    HIP_TRY(launch_rhs(P.kp, dt, int(tiles.size()), source, c, f, s));
+  }
   return finish(P, s);
 }
 

@@ -12,6 +12,8 @@
 //       workgroup evaluates the interpolant separably on its tile (plus the
 //       halo that the lower entries need) through two LDS stages and writes
 //       each band slot of its rows exactly once, stencil-major and coalesced.
+#include <algorithm>
+
 #include "igs_internal.h"
 
 namespace igs {
@@ -53,221 +55,438 @@ __global__ void fit_pass_kernel(KInterp<double> ip, int d, int n, int m1, int m2
 }
 
 // ----------------------------------------------------------------- fill ----
+//
+// A workgroup owns an aligned chunk of kChunk consecutive rows of the flat
+// (colex) index, one row per thread, and writes every slot of every row of the
+// chunk: analysis-domain rows get the interpolated/copied/diagonal values,
+// boundary rows (already assembled by quadrature) are read and stored back
+// unchanged.  Each store instruction of a wave therefore covers whole 128-byte
+// lines, which the HBM write path needs to stream at full rate.  Per
+// interpolated delta the chunk's pencils (rows with the same (i2, i3)) get the
+// partial contraction T[c1] = sum_{c2,c3} beta2 beta3 c_delta[c3][c2][c1] in
+// LDS (for the pencil itself and for the pencil of the lower partners); each
+// row then finishes with its q+1 direction-1 weights.  LDS is double-buffered
+// so one barrier per delta suffices.
 
-constexpr int kFillTX = 64;   // rows along direction 1 per tile (one per lane)
-constexpr int kFillTY3 = 4;   // 3D: rows along direction 2 (one per wave)
-constexpr int kFillTZ3 = 4;   // 3D: rows along direction 3 (loop)
-constexpr int kFillTY2 = 16;  // 2D: rows along direction 2 (4 waves x 4)
+constexpr int kChunk = 256;
+
+struct FillGeom {
+  int n, P, m1, m2, m3;
+  int64_t N, ld;
+  int S;
+  int npen;           // max pencils a chunk can touch
+  int nchunks;
+  const int* chunks;  // chunk ids that contain analysis-domain rows
+};
+
+// host-side per-delta table (slot, delta1, delta2, delta3)
+struct DeltaRec {
+  int s, d1, d2, d3;
+};
 
 template <typename T>
-__device__ __forceinline__ T interp1(const T* __restrict__ beta, int q, const T* __restrict__ x, int stride) {
-  T v = T(0);
-#pragma unroll 6
-  for (int c = 0; c <= q; ++c) v += beta[c] * x[c * stride];
-  return v;
+__device__ __forceinline__ bool in_dom(const KInterp<T>& ip, int d, int i) {
+  return i >= ip.lo[d] && i <= ip.hi[d];
 }
 
-template <int FORM, typename T>
-__global__ void __launch_bounds__(256)
-    fill3d_kernel(KInterp<T> ip, int P, int m1, int m2, int64_t ld, int S, const double* __restrict__ coef,
-                  T* __restrict__ band) {
+// MULTI = false: every pencil task fits one thread (npen*2*S1 <= kChunk) and
+// its operands for the next delta are prefetched into registers; MULTI = true
+// (tiny sampling steps, many coefficients per line) loops over the tasks.
+template <int ND, int FORM, int Q, typename T, bool MULTI>
+__global__ void __launch_bounds__(kChunk)
+    fill_kernel(KInterp<T> ip, FillGeom g, const double* __restrict__ coef, T* __restrict__ band) {
   extern __shared__ char smem_raw[];
-  constexpr int TX = kFillTX, TY = kFillTY3, TZ = kFillTZ3;
-  const int W = 2 * P + 1;
-  const int q = ip.q;
-  const int B1 = TX + P, B2 = TY + P;
-  const int nc2 = ip.nc[1], nc3 = ip.nc[2];
-  T* X1 = reinterpret_cast<T*>(smem_raw);
-  T* X2 = X1 + size_t(nc3) * nc2 * B1;
-
-  const int L1 = ip.hi[0] - ip.lo[0] + 1, L2 = ip.hi[1] - ip.lo[1] + 1;
-  const int nt1 = (L1 + TX - 1) / TX, nt2 = (L2 + TY - 1) / TY;
-  int bid = blockIdx.x;
-  const int t1 = bid % nt1;
-  bid /= nt1;
-  const int t2 = bid % nt2;
-  const int t3 = bid / nt2;
+  constexpr int NC = (ND == 3) ? (Q + 1) * (Q + 1) : (Q + 1);  // coefficients per pencil task
+  const int W = 2 * g.P + 1;
+  const int S1 = ip.Sd[0], S2 = ip.Sd[1], S3 = (ND == 3) ? ip.Sd[2] : 1;
+  const int m3 = (ND == 3) ? g.m3 : 1;
+  // LDS layout (see fill_lds_bytes): T [2][npen][2][S1]; spline weights
+  // b1[m1], b2[m2], b3[m3] (Q+1 each); first functions f1, f2, f3; per-delta
+  // (slot, delta1, delta2, delta3)
+  T* Tbuf = reinterpret_cast<T*>(smem_raw);
+  T* tb1 = Tbuf + size_t(2) * g.npen * 2 * S1;
+  T* tb2 = tb1 + size_t(g.m1) * (Q + 1);
+  T* tb3 = tb2 + size_t(g.m2) * (Q + 1);
+  int* tf1 = reinterpret_cast<int*>(tb3 + size_t(m3) * (Q + 1));
+  int* tf2 = tf1 + g.m1;
+  int* tf3 = tf2 + g.m2;
+  int4* dsl = reinterpret_cast<int4*>(tf3 + m3 + ((4 - ((g.m1 + g.m2 + m3) & 3)) & 3));
   const int b = blockIdx.y;
-  const int A1 = ip.lo[0] + t1 * TX, A2 = ip.lo[1] + t2 * TY, A3 = ip.lo[2] + t3 * TZ;
+  const int64_t c0 = int64_t(g.chunks[blockIdx.x]) * kChunk;
   const int tid = threadIdx.x;
-  const int r1 = tid & 63, r2 = tid >> 6;
-  const int i1 = A1 + r1, i2 = A2 + r2;
-  const bool row_ok = i1 <= ip.hi[0] && i2 <= ip.hi[1];
-  const int S1 = ip.Sd[0], S2 = ip.Sd[1], S3 = ip.Sd[2];
+  for (int d = 0; d < ND; ++d) {
+    const int md = d == 0 ? g.m1 : (d == 1 ? g.m2 : m3);
+    T* tb = d == 0 ? tb1 : (d == 1 ? tb2 : tb3);
+    int* tf = d == 0 ? tf1 : (d == 1 ? tf2 : tf3);
+    for (int t = tid; t < md * (Q + 1); t += kChunk) {
+      const int ii = t / (Q + 1);
+      const bool ok = in_dom(ip, d, ii);
+      tb[t] = ok ? ip.eb[d][t] : T(0);
+      if (t % (Q + 1) == 0) tf[ii] = ok ? ip.ef[d][ii] : 0;
+    }
+  }
+  for (int u = tid; u < ip.nup; u += kChunk) {
+    const int s = ip.upslot[u];
+    dsl[u] = make_int4(s, s % W - g.P, (s / W) % W - g.P, (ND == 3) ? s / (W * W) - g.P : 0);
+  }
+  const int64_t i = c0 + tid;
+  const bool live = i < g.N;
+  const int64_t pen0 = c0 / g.m1;
+  int i1 = 0, i2 = 0, i3 = 0;
+  int64_t pen = 0;
+  if (live) {
+    pen = i / g.m1;
+    i1 = int(i - pen * g.m1);
+    i2 = int(pen % g.m2);
+    i3 = int(pen / g.m2);
+  }
+  const int k = int(pen - pen0);  // this row's pencil slot in the chunk
+  const bool inner = live && in_dom(ip, 0, i1) && in_dom(ip, 1, i2) && (ND == 2 || in_dom(ip, 2, i3));
+  T* bnd = band + size_t(b) * g.S * g.ld;
   const size_t per = size_t(S1) * S2 * S3;
-  const size_t plane = size_t(m1) * m2;
-  T* bnd = band + size_t(b) * S * ld;
-  T dsum[TZ];
-#pragma unroll
-  for (int r = 0; r < TZ; ++r) dsum[r] = T(0);
+  const int sc = (g.S - 1) / 2;
+  const int ntask = g.npen * 2 * S1;
+  __syncthreads();  // tables staged
 
-  for (int u = 0; u < ip.nup; ++u) {
-    const int s = ip.upslot[u];
-    const int dl1 = s % W - P, dl2 = (s / W) % W - P, dl3 = s / (W * W) - P;
-    const int64_t off = dl1 + int64_t(m1) * dl2 + int64_t(plane) * dl3;
-    // evaluation box: the tile and the tile shifted by -delta, inside the analysis domain
-    const int lo1 = max(ip.lo[0], A1 - max(dl1, 0)), hi1 = min(ip.hi[0], A1 + TX - 1 - min(dl1, 0));
-    const int lo2 = max(ip.lo[1], A2 - max(dl2, 0)), hi2 = min(ip.hi[1], A2 + TY - 1 - min(dl2, 0));
-    const int lo3 = max(ip.lo[2], A3 - max(dl3, 0)), hi3 = min(ip.hi[2], A3 + TZ - 1 - min(dl3, 0));
-    const int c1lo = ip.ef[0][lo1];
-    const int c2lo = ip.ef[1][lo2], c2n = ip.ef[1][hi2] + q - c2lo + 1;
-    const int c3lo = ip.ef[2][lo3], c3n = ip.ef[2][hi3] + q - c3lo + 1;
-    const int b1w = hi1 - lo1 + 1, b2w = hi2 - lo2 + 1;
-    (void)c1lo;
+  // pencil-task operands: spline weights of the pencil and its coefficients.
+  // Loads are issued for every lane (invalid tasks read coefficient 0 and get
+  // zero weights) so the wait counters stay exact across iterations.
+  auto task_load = [&](int u, int t, T* wgt, double* cv) {
+    const int4 dd = dsl[u];
+    const int c1 = t % S1;
+    const int side = (t / S1) & 1;
+    const int64_t pp = pen0 + t / (2 * S1);
+    int j2 = int(pp % g.m2), j3 = int(pp / g.m2);
+    if (side) {
+      j2 -= dd.z;
+      j3 -= dd.w;
+    }
+    const bool ok = in_dom(ip, 1, j2) && (ND == 2 || in_dom(ip, 2, j3)) && pp * g.m1 < g.N;
+    if (!ok) {
+      j2 = ip.lo[1];
+      j3 = ND == 3 ? ip.lo[2] : 0;
+    }
     const double* cu = coef + (size_t(b) * ip.nup + u) * per;
-    // stage X: direction-1 evaluation of the coefficient block
-    for (int t = tid; t < c3n * c2n * b1w; t += 256) {
-      const int x = t % b1w;
-      const int rr = t / b1w;
-      const int c2 = rr % c2n, c3 = rr / c2n;
-      const int ii1 = lo1 + x;
-      const T* beta = ip.eb[0] + size_t(ii1) * (q + 1);
-      const double* crow = cu + (size_t(c3lo + c3) * S2 + c2lo + c2) * S1 + ip.ef[0][ii1];
-      T v = T(0);
-#pragma unroll 6
-      for (int c = 0; c <= q; ++c) v += beta[c] * T(crow[c]);
-      X1[(c3 * nc2 + c2) * B1 + x] = v;
-    }
-    __syncthreads();
-    // stage Y: direction 2
-    for (int t = tid; t < c3n * b2w * b1w; t += 256) {
-      const int x = t % b1w;
-      const int rr = t / b1w;
-      const int y = rr % b2w, c3 = rr / b2w;
-      const int ii2 = lo2 + y;
-      const T* beta = ip.eb[1] + size_t(ii2) * (q + 1);
-      X2[(c3 * B2 + y) * B1 + x] = interp1<T>(beta, q, X1 + (c3 * nc2 + ip.ef[1][ii2] - c2lo) * B1 + x, B1);
-    }
-    __syncthreads();
-    // stage Z (direction 3, per thread) and the stores
-    if (row_ok) {
-      const bool up_in1 = i1 + dl1 >= ip.lo[0] && i1 + dl1 <= ip.hi[0];
-      const bool up_in2 = i2 + dl2 >= ip.lo[1] && i2 + dl2 <= ip.hi[1];
-      const bool lo_in1 = i1 - dl1 >= ip.lo[0] && i1 - dl1 <= ip.hi[0];
-      const bool lo_in2 = i2 - dl2 >= ip.lo[1] && i2 - dl2 <= ip.hi[1];
+    const int f2 = tf2[j2];
+    const T* b2 = tb2 + j2 * (Q + 1);
+    const T z = ok ? T(1) : T(0);
+    if constexpr (ND == 3) {
+      const int f3 = tf3[j3];
+      const T* b3 = tb3 + j3 * (Q + 1);
 #pragma unroll
-      for (int r3 = 0; r3 < TZ; ++r3) {
-        const int i3 = A3 + r3;
-        if (i3 > ip.hi[2]) continue;
-        const size_t idx = size_t(i1) + size_t(m1) * i2 + plane * i3;
-        T val;
-        if (up_in1 && up_in2 && i3 + dl3 >= ip.lo[2] && i3 + dl3 <= ip.hi[2]) {
-          const T* beta = ip.eb[2] + size_t(i3) * (q + 1);
-          val = interp1<T>(beta, q, X2 + ((ip.ef[2][i3] - c3lo) * B2 + (i2 - lo2)) * B1 + (i1 - lo1), B2 * B1);
-        } else {
-          val = bnd[size_t(S - 1 - s) * ld + idx + off];  // exact A_ji of boundary row j = i + delta
+      for (int a3 = 0; a3 <= Q; ++a3)
+#pragma unroll
+        for (int a2 = 0; a2 <= Q; ++a2) {
+          wgt[a3 * (Q + 1) + a2] = z * b3[a3] * b2[a2];
+          cv[a3 * (Q + 1) + a2] = cu[(size_t(f3 + a3) * S2 + f2 + a2) * S1 + c1];
         }
-        bnd[size_t(s) * ld + idx] = val;
-        if (FORM == IGS_STIFFNESS) dsum[r3] += val;
-        if (FORM == IGS_STIFFNESS || s != (S - 1) / 2) {
-          const int j3 = i3 - dl3;
-          if (lo_in1 && lo_in2 && j3 >= ip.lo[2] && j3 <= ip.hi[2]) {
-            const T* beta = ip.eb[2] + size_t(j3) * (q + 1);
-            val = interp1<T>(beta, q,
-                             X2 + ((ip.ef[2][j3] - c3lo) * B2 + (i2 - dl2 - lo2)) * B1 + (i1 - dl1 - lo1), B2 * B1);
-          } else {
-            val = bnd[size_t(s) * ld + idx - off];  // exact A_{j,j+delta} of boundary row j = i - delta
-          }
-          bnd[size_t(S - 1 - s) * ld + idx] = val;
-          if (FORM == IGS_STIFFNESS) dsum[r3] += val;
+    } else {
+#pragma unroll
+      for (int a2 = 0; a2 <= Q; ++a2) {
+        wgt[a2] = z * b2[a2];
+        cv[a2] = cu[size_t(f2 + a2) * S1 + c1];
+      }
+    }
+  };
+  // per-row operands read from the band: a boundary row's own entries, or the
+  // exact partner entries an analysis-domain row copies; lanes that need
+  // neither read the first band entry (one cached line)
+  auto row_load = [&](int u, T* pu, T* pl) {
+    const int4 dd = dsl[u];
+    const int s = dd.x;
+    const int64_t off = dd.y + int64_t(g.m1) * (dd.z + int64_t(g.m2) * dd.w);
+    const bool has_lo = FORM == IGS_STIFFNESS || s != sc;
+    size_t au = 0, al = 0;
+    if (live) {
+      if (!inner) {
+        au = size_t(s) * g.ld + size_t(i);
+        if (has_lo) al = size_t(g.S - 1 - s) * g.ld + size_t(i);
+      } else {
+        const bool up = in_dom(ip, 0, i1 + dd.y) && in_dom(ip, 1, i2 + dd.z) && (ND == 2 || in_dom(ip, 2, i3 + dd.w));
+        if (!up) au = size_t(g.S - 1 - s) * g.ld + size_t(i + off);  // exact A_ji, row j = i + delta
+        if (has_lo) {
+          const bool lo = in_dom(ip, 0, i1 - dd.y) && in_dom(ip, 1, i2 - dd.z) && (ND == 2 || in_dom(ip, 2, i3 - dd.w));
+          if (!lo) al = size_t(s) * g.ld + size_t(i - off);  // exact A_{j,j+delta}, row j = i - delta
         }
       }
     }
-  }
-  if (FORM == IGS_STIFFNESS && row_ok) {
+    *pu = bnd[au];
+    *pl = bnd[al];
+  };
+
+  T wgt[MULTI ? 1 : NC];
+  double cv[MULTI ? 1 : NC];
+  // The steady-state loop issues the same global loads and stores on every
+  // thread and iteration (surplus threads reload a valid task, the last
+  // iteration reloads the last delta, dead rows store into the zeroed
+  // padding), so the compiler's memory-wait counters stay exact and the
+  // operands prefetched one delta ahead are not drained early.
+  const int tt = MULTI ? 0 : tid % ntask;
+  if constexpr (!MULTI) task_load(0, tt, wgt, cv);
+  T pu, pl;
+  row_load(0, &pu, &pl);
+  T dsum = T(0);
+  // dead rows (beyond N in the last chunk) write into the padding of slot 0,
+  // which zero_pad clears afterwards
+  const size_t irow = live ? size_t(i) : size_t(g.ld - 1);
+
+  for (int u = 0; u < ip.nup; ++u) {
+    const int4 dd = dsl[u];
+    const int s = dd.x, dl1 = dd.y, dl2 = dd.z, dl3 = dd.w;
+    T* Tu = Tbuf + size_t(u & 1) * ntask;
+    // pencil contractions T[c1] = sum beta2 beta3 c[c3][c2][c1]
+    if constexpr (!MULTI) {
+      T v = T(0);
 #pragma unroll
-    for (int r3 = 0; r3 < TZ; ++r3) {
-      const int i3 = A3 + r3;
-      if (i3 > ip.hi[2]) continue;
-      bnd[size_t((S - 1) / 2) * ld + size_t(i1) + size_t(m1) * i2 + plane * i3] = -dsum[r3];
+      for (int c = 0; c < NC; ++c) v += wgt[c] * T(cv[c]);
+      if (tid < ntask) Tu[tid] = v;
+      task_load(u + 1 < ip.nup ? u + 1 : u, tt, wgt, cv);
+    } else {
+      for (int t = tid; t < ntask; t += kChunk) {
+        T w2[NC];
+        double c2v[NC];
+        T v = T(0);
+        task_load(u, t, w2, c2v);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v += w2[c] * T(c2v[c]);
+        Tu[t] = v;
+      }
     }
+    __syncthreads();
+    const bool has_lo = FORM == IGS_STIFFNESS || s != sc;
+    T vu = pu, vl = pl;
+    if (inner) {
+      const T* Tk = Tu + size_t(k) * 2 * S1;
+      const bool up = in_dom(ip, 0, i1 + dl1) && in_dom(ip, 1, i2 + dl2) && (ND == 2 || in_dom(ip, 2, i3 + dl3));
+      if (up) {
+        const int f1 = tf1[i1];
+        const T* bb = tb1 + i1 * (Q + 1);
+        vu = T(0);
+#pragma unroll
+        for (int a = 0; a <= Q; ++a) vu += bb[a] * Tk[f1 + a];
+      }
+      if (FORM == IGS_STIFFNESS) dsum += vu;
+      if (has_lo) {
+        const int j1 = i1 - dl1;
+        const bool lo = in_dom(ip, 0, j1) && in_dom(ip, 1, i2 - dl2) && (ND == 2 || in_dom(ip, 2, i3 - dl3));
+        if (lo) {
+          const int f1 = tf1[j1];
+          const T* bb = tb1 + j1 * (Q + 1);
+          vl = T(0);
+#pragma unroll
+          for (int a = 0; a <= Q; ++a) vl += bb[a] * Tk[S1 + f1 + a];
+        }
+        if (FORM == IGS_STIFFNESS) dsum += vl;
+      }
+    }
+    // boundary rows store back their exact values with the same instruction,
+    // so every line of the chunk is written whole
+    bnd[live ? size_t(s) * g.ld + irow : irow] = vu;
+    if (has_lo) bnd[live ? size_t(g.S - 1 - s) * g.ld + irow : irow] = vl;
+    row_load(u + 1 < ip.nup ? u + 1 : u, &pu, &pl);  // prefetch for the next delta
+  }
+  if (FORM == IGS_STIFFNESS && live) {
+    const size_t ic = size_t(sc) * g.ld + size_t(i);
+    bnd[ic] = inner ? -dsum : bnd[ic];
   }
 }
 
-template <int FORM, typename T>
-__global__ void __launch_bounds__(256)
-    fill2d_kernel(KInterp<T> ip, int P, int m1, int64_t ld, int S, const double* __restrict__ coef,
-                  T* __restrict__ band) {
-  extern __shared__ char smem_raw[];
-  constexpr int TX = kFillTX, TY = kFillTY2, RY = TY / 4;
-  const int W = 2 * P + 1;
-  const int q = ip.q;
-  const int B1 = TX + P;
-  T* X1 = reinterpret_cast<T*>(smem_raw);
-  const int L1 = ip.hi[0] - ip.lo[0] + 1;
-  const int nt1 = (L1 + TX - 1) / TX;
-  const int t1 = blockIdx.x % nt1, t2 = blockIdx.x / nt1;
-  const int b = blockIdx.y;
-  const int A1 = ip.lo[0] + t1 * TX, A2 = ip.lo[1] + t2 * TY;
-  const int tid = threadIdx.x;
-  const int r1 = tid & 63, w = tid >> 6;
-  const int i1 = A1 + r1;
-  const bool col_ok = i1 <= ip.hi[0];
-  const int S1 = ip.Sd[0], S2 = ip.Sd[1];
-  const size_t per = size_t(S1) * S2;
-  T* bnd = band + size_t(b) * S * ld;
-  T dsum[RY];
-#pragma unroll
-  for (int r = 0; r < RY; ++r) dsum[r] = T(0);
+// Fast path: R rows per thread (chunks of R*kChunk rows), per-delta metadata
+// read from a host-built table through the scalar cache, per-row domain tests
+// as bitmasks, direction-1 weights of the upper entries kept in registers.
+// Requires npen*2*S1 <= kChunk pencil tasks per chunk.
+constexpr int kRows = 3;
 
-  for (int u = 0; u < ip.nup; ++u) {
-    const int s = ip.upslot[u];
-    const int dl1 = s % W - P, dl2 = s / W - P;
-    const int64_t off = dl1 + int64_t(m1) * dl2;
-    const int lo1 = max(ip.lo[0], A1 - max(dl1, 0)), hi1 = min(ip.hi[0], A1 + TX - 1 - min(dl1, 0));
-    const int lo2 = max(ip.lo[1], A2 - max(dl2, 0)), hi2 = min(ip.hi[1], A2 + TY - 1 - min(dl2, 0));
-    const int c2lo = ip.ef[1][lo2], c2n = ip.ef[1][hi2] + q - c2lo + 1;
-    const int b1w = hi1 - lo1 + 1;
-    const double* cu = coef + (size_t(b) * ip.nup + u) * per;
-    for (int t = tid; t < c2n * b1w; t += 256) {
-      const int x = t % b1w, c2 = t / b1w;
-      const int ii1 = lo1 + x;
-      const T* beta = ip.eb[0] + size_t(ii1) * (q + 1);
-      const double* crow = cu + size_t(c2lo + c2) * S1 + ip.ef[0][ii1];
-      T v = T(0);
-#pragma unroll 6
-      for (int c = 0; c <= q; ++c) v += beta[c] * T(crow[c]);
-      X1[c2 * B1 + x] = v;
+template <int ND, int FORM, int Q, typename T>
+__global__ void __launch_bounds__(kChunk)
+    fill_fast_kernel(KInterp<T> ip, FillGeom g, const int4* __restrict__ dsl, const double* __restrict__ coef,
+                     T* __restrict__ band) {
+  extern __shared__ char smem_raw[];
+  constexpr int NC = (ND == 3) ? (Q + 1) * (Q + 1) : (Q + 1);
+  constexpr int R = kRows;
+  const int S1 = ip.Sd[0], S2 = ip.Sd[1], S3 = (ND == 3) ? ip.Sd[2] : 1;
+  const int m3 = (ND == 3) ? g.m3 : 1;
+  const int P = g.P;
+  T* Tbuf = reinterpret_cast<T*>(smem_raw);
+  T* tb1 = Tbuf + size_t(2) * g.npen * 2 * S1;
+  T* tb2 = tb1 + size_t(g.m1) * (Q + 1);
+  T* tb3 = tb2 + size_t(g.m2) * (Q + 1);
+  int* tf1 = reinterpret_cast<int*>(tb3 + size_t(m3) * (Q + 1));
+  int* tf2 = tf1 + g.m1;
+  int* tf3 = tf2 + g.m2;
+  const int b = blockIdx.y;
+  const int64_t c0 = int64_t(g.chunks[blockIdx.x]) * (kChunk * R);
+  const int tid = threadIdx.x;
+  // tb1 is stored [a][i1] so that neighbouring lanes (neighbouring i1) read
+  // neighbouring words; tb2, tb3 are read per pencil and stay [i][a]
+  for (int d = 0; d < ND; ++d) {
+    const int md = d == 0 ? g.m1 : (d == 1 ? g.m2 : m3);
+    T* tb = d == 0 ? tb1 : (d == 1 ? tb2 : tb3);
+    int* tf = d == 0 ? tf1 : (d == 1 ? tf2 : tf3);
+    for (int t = tid; t < md * (Q + 1); t += kChunk) {
+      const int ii = t / (Q + 1), a = t - ii * (Q + 1);
+      const bool ok = in_dom(ip, d, ii);
+      tb[d == 0 ? a * md + ii : t] = ok ? ip.eb[d][t] : T(0);
+      if (a == 0) tf[ii] = ok ? ip.ef[d][ii] : 0;
     }
-    __syncthreads();
-    if (col_ok) {
-      const bool up_in1 = i1 + dl1 >= ip.lo[0] && i1 + dl1 <= ip.hi[0];
-      const bool lo_in1 = i1 - dl1 >= ip.lo[0] && i1 - dl1 <= ip.hi[0];
+  }
+  const int64_t pen0 = c0 / g.m1;
+  T* bnd = band + size_t(b) * g.S * g.ld;
+  const size_t per = size_t(S1) * S2 * S3;
+  const int sc = (g.S - 1) / 2;
+  const int ntask = g.npen * 2 * S1;
+  const size_t ld = size_t(g.ld);
+  const size_t Sm1ld = size_t(g.S - 1) * ld;
+
+  // per-row state
+  bool live[R], inner[R];
+  int i1r[R], kr[R], mask[R], f1u[R];
+  size_t irow[R];
+  T bu[R][Q + 1], dsum[R], pu[R], pl[R];
 #pragma unroll
-      for (int r = 0; r < RY; ++r) {
-        const int i2 = A2 + w + 4 * r;
-        if (i2 > ip.hi[1]) continue;
-        const size_t idx = size_t(i1) + size_t(m1) * i2;
-        T val;
-        if (up_in1 && i2 + dl2 >= ip.lo[1] && i2 + dl2 <= ip.hi[1]) {
-          const T* beta = ip.eb[1] + size_t(i2) * (q + 1);
-          val = interp1<T>(beta, q, X1 + (ip.ef[1][i2] - c2lo) * B1 + (i1 - lo1), B1);
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = c0 + tid + int64_t(r) * kChunk;
+    live[r] = i < g.N;
+    const int64_t pen = live[r] ? i / g.m1 : pen0;
+    const int i1 = live[r] ? int(i - pen * g.m1) : 0;
+    const int i2 = int(pen % g.m2), i3 = int(pen / g.m2);
+    inner[r] = live[r] && in_dom(ip, 0, i1) && in_dom(ip, 1, i2) && (ND == 2 || in_dom(ip, 2, i3));
+    i1r[r] = i1;
+    kr[r] = int(pen - pen0);
+    irow[r] = live[r] ? size_t(i) : size_t(g.ld - 1);
+    // bit (d*9 + t) set iff index i_d + t - P lies in the analysis range
+    int mk = 0;
+    for (int t = 0; t <= 2 * P; ++t) {
+      mk |= (in_dom(ip, 0, i1 + t - P) ? 1 : 0) << t;
+      mk |= (in_dom(ip, 1, i2 + t - P) ? 1 : 0) << (9 + t);
+      if (ND == 3) mk |= (in_dom(ip, 2, i3 + t - P) ? 1 : 0) << (18 + t);
+    }
+    mask[r] = mk;
+    dsum[r] = T(0);
+  }
+  __syncthreads();  // tables staged
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    f1u[r] = tf1[i1r[r]];
+#pragma unroll
+    for (int a = 0; a <= Q; ++a) bu[r][a] = tb1[a * g.m1 + i1r[r]];
+  }
+
+  auto inside = [&](int mk, int d1, int d2, int d3) {
+    int v = (mk >> (d1 + P)) & (mk >> (9 + d2 + P));
+    if (ND == 3) v &= mk >> (18 + d3 + P);
+    return (v & 1) != 0;
+  };
+  // pencil task operands (loaded one delta ahead); every thread loads a valid task
+  const int tt = tid % ntask;
+  const int tc1 = tt % S1;
+  const int tside = (tt / S1) & 1;
+  const int64_t tpp = pen0 + tt / (2 * S1);
+  const int tj2 = int(tpp % g.m2), tj3 = int(tpp / g.m2);
+  double cv[NC];
+  bool tok = false;
+  int tf2v = 0, tf3v = 0, tj2v = 0, tj3v = 0;
+  auto task_load = [&](int u) {
+    const int4 dd = dsl[u];
+    int j2 = tj2, j3 = tj3;
+    if (tside) {
+      j2 -= dd.z;
+      j3 -= dd.w;
+    }
+    tok = in_dom(ip, 1, j2) && (ND == 2 || in_dom(ip, 2, j3)) && tpp * g.m1 < g.N;
+    if (!tok) {
+      j2 = ip.lo[1];
+      j3 = ND == 3 ? ip.lo[2] : 0;
+    }
+    tj2v = j2;
+    tj3v = j3;
+    tf2v = tf2[j2];
+    tf3v = ND == 3 ? tf3[j3] : 0;
+    const double* cu = coef + (size_t(b) * ip.nup + u) * per;
+#pragma unroll
+    for (int a3 = 0; a3 < (ND == 3 ? Q + 1 : 1); ++a3)
+#pragma unroll
+      for (int a2 = 0; a2 <= Q; ++a2)
+        cv[a3 * (Q + 1) + a2] = cu[(size_t(tf3v + a3) * S2 + tf2v + a2) * S1 + tc1];
+  };
+  auto row_load = [&](int u) {
+    const int4 dd = dsl[u];
+    const int s = dd.x;
+    const int64_t off = dd.y + int64_t(g.m1) * (dd.z + int64_t(g.m2) * dd.w);
+    const bool has_lo = FORM == IGS_STIFFNESS || s != sc;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      size_t au = 0, al = 0;
+      if (live[r]) {
+        if (!inner[r]) {
+          au = size_t(s) * ld + irow[r];
+          if (has_lo) al = Sm1ld - size_t(s) * ld + irow[r];
         } else {
-          val = bnd[size_t(S - 1 - s) * ld + idx + off];
-        }
-        bnd[size_t(s) * ld + idx] = val;
-        if (FORM == IGS_STIFFNESS) dsum[r] += val;
-        if (FORM == IGS_STIFFNESS || s != (S - 1) / 2) {
-          const int j2 = i2 - dl2;
-          if (lo_in1 && j2 >= ip.lo[1] && j2 <= ip.hi[1]) {
-            const T* beta = ip.eb[1] + size_t(j2) * (q + 1);
-            val = interp1<T>(beta, q, X1 + (ip.ef[1][j2] - c2lo) * B1 + (i1 - dl1 - lo1), B1);
-          } else {
-            val = bnd[size_t(s) * ld + idx - off];
-          }
-          bnd[size_t(S - 1 - s) * ld + idx] = val;
-          if (FORM == IGS_STIFFNESS) dsum[r] += val;
+          if (!inside(mask[r], dd.y, dd.z, dd.w)) au = Sm1ld - size_t(s) * ld + size_t(int64_t(irow[r]) + off);
+          if (has_lo && !inside(mask[r], -dd.y, -dd.z, -dd.w)) al = size_t(s) * ld + size_t(int64_t(irow[r]) - off);
         }
       }
+      pu[r] = bnd[au];
+      pl[r] = bnd[al];
     }
-    __syncthreads();
-  }
-  if (FORM == IGS_STIFFNESS && col_ok) {
+  };
+  task_load(0);
+  row_load(0);
+
+  for (int u = 0; u < ip.nup; ++u) {
+    const int4 dd = dsl[u];
+    const int s = dd.x, dl1 = dd.y, dl2 = dd.z, dl3 = dd.w;
+    T* Tu = Tbuf + size_t(u & 1) * ntask;
+    {
+      const T* b2 = tb2 + tj2v * (Q + 1);
+      T v = T(0);
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      const int i2 = A2 + w + 4 * r;
-      if (i2 > ip.hi[1]) continue;
-      bnd[size_t((S - 1) / 2) * ld + size_t(i1) + size_t(m1) * i2] = -dsum[r];
+      for (int a3 = 0; a3 < (ND == 3 ? Q + 1 : 1); ++a3) {
+        T r2 = T(0);
+#pragma unroll
+        for (int a2 = 0; a2 <= Q; ++a2) r2 += b2[a2] * T(cv[a3 * (Q + 1) + a2]);
+        v += (ND == 3 ? tb3[tj3v * (Q + 1) + a3] : T(1)) * r2;
+      }
+      if (tid < ntask) Tu[tid] = tok ? v : T(0);
+    }
+    task_load(u + 1 < ip.nup ? u + 1 : u);
+    __syncthreads();
+    const bool has_lo = FORM == IGS_STIFFNESS || s != sc;
+    const size_t su = size_t(s) * ld, sl = Sm1ld - size_t(s) * ld;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      T vu = pu[r], vl = pl[r];
+      if (inner[r]) {
+        const T* Tk = Tu + size_t(kr[r]) * 2 * S1;
+        if (inside(mask[r], dl1, dl2, dl3)) {
+          vu = T(0);
+#pragma unroll
+          for (int a = 0; a <= Q; ++a) vu += bu[r][a] * Tk[f1u[r] + a];
+        }
+        if (FORM == IGS_STIFFNESS) dsum[r] += vu;
+        if (has_lo) {
+          if (inside(mask[r], -dl1, -dl2, -dl3)) {
+            const int j1 = i1r[r] - dl1;
+            const int f1 = tf1[j1];
+            vl = T(0);
+#pragma unroll
+            for (int a = 0; a <= Q; ++a) vl += tb1[a * g.m1 + j1] * Tk[S1 + f1 + a];
+          }
+          if (FORM == IGS_STIFFNESS) dsum[r] += vl;
+        }
+      }
+      // boundary rows store back their exact values with the same instruction
+      bnd[live[r] ? su + irow[r] : irow[r]] = vu;
+      if (has_lo) bnd[live[r] ? sl + irow[r] : irow[r]] = vl;
+    }
+    row_load(u + 1 < ip.nup ? u + 1 : u);
+  }
+  if (FORM == IGS_STIFFNESS) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!live[r]) continue;
+      const size_t ic = size_t(sc) * ld + irow[r];
+      bnd[ic] = inner[r] ? -dsum[r] : bnd[ic];
     }
   }
 }
@@ -284,12 +503,6 @@ __global__ void zero_pad_kernel(T* band, int64_t N, int64_t ld, int slots_total)
 }
 
 // ------------------------------------------------------------ launchers ----
-
-void fill_tile_box(int n, int p, int box[3]) {
-  box[0] = kFillTX + p;
-  box[1] = (n == 3 ? kFillTY3 : kFillTY2) + p;
-  box[2] = kFillTZ3 + p;
-}
 
 template <typename BT>
 hipError_t launch_fit(const KInterp<double>& ip, int n, int m1, int m2, int64_t ld, int S, int batch, const BT* band,
@@ -315,43 +528,122 @@ template hipError_t launch_fit<double>(const KInterp<double>&, int, int, int, in
 template hipError_t launch_fit<float>(const KInterp<double>&, int, int, int, int64_t, int, int, const float*,
                                       double*, double*, double*, hipStream_t);
 
-template <typename T>
-size_t fill_lds_bytes(const KInterp<T>& ip, int n, int p) {
-  if (n == 3) return (size_t(ip.nc[2]) * ip.nc[1] * (kFillTX + p) + size_t(ip.nc[2]) * (kFillTY3 + p) * (kFillTX + p)) * sizeof(T);
-  return size_t(ip.nc[1]) * (kFillTX + p) * sizeof(T);
+// chunk ids (of `rows` rows) that contain at least one analysis-domain row
+std::vector<int> fill_chunks(const Dims& d, int rows) {
+  const int p = d.p;
+  std::vector<int> out;
+  const int lo3 = (d.n == 3) ? 2 * p : 0, hi3 = (d.n == 3) ? d.m[2] - 2 * p - 1 : 0;
+  for (int i3 = lo3; i3 <= hi3; ++i3)
+    for (int i2 = 2 * p; i2 <= d.m[1] - 2 * p - 1; ++i2) {
+      const int64_t base = int64_t(d.m[0]) * (i2 + int64_t(d.m[1]) * i3);
+      const int a = int((base + 2 * p) / rows), z = int((base + d.m[0] - 2 * p - 1) / rows);
+      for (int c = a; c <= z; ++c)
+        if (out.empty() || out.back() < c) out.push_back(c);
+    }
+  return out;
+}
+
+int fill_npen(const Dims& d, int rows) { return (rows - 1) / d.m[0] + 2; }
+
+// rows per chunk of the fill launch: the fast kernel when its pencil tasks fit
+// one workgroup, else the generic one
+int fill_chunk_rows(const Dims& d, int Sd1) {
+  return fill_npen(d, kChunk * kRows) * 2 * Sd1 <= kChunk ? kChunk * kRows : kChunk;
 }
 
 template <typename T>
-hipError_t launch_fill(const KInterp<T>& ip, int form, int n, int p, int m1, int m2, int64_t ld, int S, int batch,
-                       const double* coef, T* band, hipStream_t s) {
-  const int L1 = ip.hi[0] - ip.lo[0] + 1, L2 = ip.hi[1] - ip.lo[1] + 1;
-  const size_t lds = fill_lds_bytes<T>(ip, n, p);
+size_t fill_lds_bytes(const KInterp<T>& ip, int npen, const Dims& d) {
+  const size_t msum = size_t(d.m[0]) + d.m[1] + (d.n == 3 ? d.m[2] : 1);
+  return size_t(2) * npen * 2 * ip.Sd[0] * sizeof(T) + msum * (ip.q + 1) * sizeof(T) + (msum + 4) * 4 +
+         size_t(ip.nup) * 16;
+}
+
+template <int ND, int FORM, typename T, bool MULTI>
+static void launch_fill_q(const KInterp<T>& ip, const FillGeom& g, dim3 grid, size_t lds, const double* coef, T* band,
+                          hipStream_t s) {
+  switch (ip.q) {
+    case 1: hipLaunchKernelGGL((fill_kernel<ND, FORM, 1, T, MULTI>), grid, dim3(kChunk), lds, s, ip, g, coef, band); break;
+    case 2: hipLaunchKernelGGL((fill_kernel<ND, FORM, 2, T, MULTI>), grid, dim3(kChunk), lds, s, ip, g, coef, band); break;
+    case 3: hipLaunchKernelGGL((fill_kernel<ND, FORM, 3, T, MULTI>), grid, dim3(kChunk), lds, s, ip, g, coef, band); break;
+    case 4: hipLaunchKernelGGL((fill_kernel<ND, FORM, 4, T, MULTI>), grid, dim3(kChunk), lds, s, ip, g, coef, band); break;
+    default: hipLaunchKernelGGL((fill_kernel<ND, FORM, 5, T, MULTI>), grid, dim3(kChunk), lds, s, ip, g, coef, band); break;
+  }
+}
+
+template <int ND, int FORM, typename T>
+static void launch_fill_m(const KInterp<T>& ip, const FillGeom& g, dim3 grid, size_t lds, const double* coef, T* band,
+                          hipStream_t s) {
+  if (g.npen * 2 * ip.Sd[0] <= kChunk)
+    launch_fill_q<ND, FORM, T, false>(ip, g, grid, lds, coef, band, s);
+  else
+    launch_fill_q<ND, FORM, T, true>(ip, g, grid, lds, coef, band, s);
+}
+
+template <int ND, int FORM, typename T>
+static void launch_fast_q(const KInterp<T>& ip, const FillGeom& g, dim3 grid, size_t lds, const int4* dsl,
+                          const double* coef, T* band, hipStream_t s) {
+  switch (ip.q) {
+    case 1: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 1, T>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
+    case 2: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 2, T>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
+    case 3: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 3, T>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
+    case 4: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 4, T>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
+    default: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 5, T>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
+  }
+}
+
+template <typename T>
+hipError_t launch_fill(const KInterp<T>& ip, int form, const Dims& d, const int* chunks, int nchunks, int chunk_rows,
+                       const int4* dsl, const double* coef, T* band, hipStream_t s) {
+  FillGeom g;
+  g.n = d.n;
+  g.P = d.p;
+  g.m1 = d.m[0];
+  g.m2 = d.m[1];
+  g.m3 = d.m[2];
+  g.N = d.N;
+  g.ld = d.ld;
+  g.S = d.S;
+  g.npen = fill_npen(d, chunk_rows);
+  g.nchunks = nchunks;
+  g.chunks = chunks;
+  const size_t lds = fill_lds_bytes<T>(ip, g.npen, d);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (n == 3) {
-    const int L3 = ip.hi[2] - ip.lo[2] + 1;
-    const int tiles = ((L1 + kFillTX - 1) / kFillTX) * ((L2 + kFillTY3 - 1) / kFillTY3) * ((L3 + kFillTZ3 - 1) / kFillTZ3);
-    dim3 grid(tiles, batch);
+  if (nchunks == 0) return hipSuccess;
+  dim3 grid(nchunks, d.batch);
+  if (chunk_rows == kChunk * kRows) {
+    if (d.n == 3) {
+      if (form == IGS_MASS)
+        launch_fast_q<3, IGS_MASS, T>(ip, g, grid, lds, dsl, coef, band, s);
+      else
+        launch_fast_q<3, IGS_STIFFNESS, T>(ip, g, grid, lds, dsl, coef, band, s);
+    } else {
+      if (form == IGS_MASS)
+        launch_fast_q<2, IGS_MASS, T>(ip, g, grid, lds, dsl, coef, band, s);
+      else
+        launch_fast_q<2, IGS_STIFFNESS, T>(ip, g, grid, lds, dsl, coef, band, s);
+    }
+    return hipGetLastError();
+  }
+  if (d.n == 3) {
     if (form == IGS_MASS)
-      hipLaunchKernelGGL((fill3d_kernel<IGS_MASS, T>), grid, dim3(256), lds, s, ip, p, m1, m2, ld, S, coef, band);
+      launch_fill_m<3, IGS_MASS, T>(ip, g, grid, lds, coef, band, s);
     else
-      hipLaunchKernelGGL((fill3d_kernel<IGS_STIFFNESS, T>), grid, dim3(256), lds, s, ip, p, m1, m2, ld, S, coef, band);
+      launch_fill_m<3, IGS_STIFFNESS, T>(ip, g, grid, lds, coef, band, s);
   } else {
-    const int tiles = ((L1 + kFillTX - 1) / kFillTX) * ((L2 + kFillTY2 - 1) / kFillTY2);
-    dim3 grid(tiles, batch);
     if (form == IGS_MASS)
-      hipLaunchKernelGGL((fill2d_kernel<IGS_MASS, T>), grid, dim3(256), lds, s, ip, p, m1, ld, S, coef, band);
+      launch_fill_m<2, IGS_MASS, T>(ip, g, grid, lds, coef, band, s);
     else
-      hipLaunchKernelGGL((fill2d_kernel<IGS_STIFFNESS, T>), grid, dim3(256), lds, s, ip, p, m1, ld, S, coef, band);
+      launch_fill_m<2, IGS_STIFFNESS, T>(ip, g, grid, lds, coef, band, s);
   }
   return hipGetLastError();
 }
 
-template hipError_t launch_fill<double>(const KInterp<double>&, int, int, int, int, int, int64_t, int, int,
+template hipError_t launch_fill<double>(const KInterp<double>&, int, const Dims&, const int*, int, int, const int4*,
                                         const double*, double*, hipStream_t);
-template hipError_t launch_fill<float>(const KInterp<float>&, int, int, int, int, int, int64_t, int, int,
+template hipError_t launch_fill<float>(const KInterp<float>&, int, const Dims&, const int*, int, int, const int4*,
                                        const double*, float*, hipStream_t);
-template size_t fill_lds_bytes<double>(const KInterp<double>&, int, int);
-template size_t fill_lds_bytes<float>(const KInterp<float>&, int, int);
+template size_t fill_lds_bytes<double>(const KInterp<double>&, int, const Dims&);
+template size_t fill_lds_bytes<float>(const KInterp<float>&, int, const Dims&);
 
 template <typename T>
 hipError_t launch_zero_pad(T* band, int64_t N, int64_t ld, int slots_total, hipStream_t s) {

@@ -162,7 +162,7 @@ igs_status make_dims(const igs_problem* pb, Dims* d) {
     }
   }
   if (d->N > (int64_t(1) << 31)) return IGS_ERR_UNSUPPORTED;
-  d->ld = (d->N + 63) / 64 * 64;
+  d->ld = (d->N + 64) / 64 * 64;  // strictly greater than N: the fill parks dead lanes in the padding
   // optional knot vectors must be the open uniform ones (Sec. 2.2)
   for (int k = 0; k < pb->n; ++k) {
     if (!pb->knots[k]) continue;
@@ -337,7 +337,8 @@ void tile_rect(std::vector<QTile>* out, int x0, int x1, int y0, int y1, int tx, 
 
 // Rows assembled by quadrature in the surrogate: every row outside the
 // analysis domain [2p, m-2p-1]^n plus the sample lattice.
-std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3], int tx, int ty, int zchunk) {
+std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3], int tx, int ty, int zchunk,
+                                   int groups[3]) {
   std::vector<QTile> out;
   const int p = d.p;
   if (d.n == 3) {
@@ -348,9 +349,11 @@ std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3]
     tile_rect(&out, 0, d.m[0], hi2, d.m[1], tx, ty, 0, d.m[2], zchunk);
     tile_rect(&out, 0, lo1, lo2, hi2, tx, ty, 0, d.m[2], zchunk);
     tile_rect(&out, hi1, d.m[0], lo2, hi2, tx, ty, 0, d.m[2], zchunk);
+    groups[0] = int(out.size());
     // interior pencils: the two end slabs in i3
     tile_rect(&out, lo1, hi1, lo2, hi2, tx, ty, 0, lo3, zchunk);
     tile_rect(&out, lo1, hi1, lo2, hi2, tx, ty, hi3, d.m[2], zchunk);
+    groups[1] = int(out.size()) - groups[0];
     for (int s3 : samp[2])
       for (int s2 : samp[1])
         for (int s1 : samp[0]) out.push_back(QTile{s1, s2, 1, 1, s3, s3 + 1});
@@ -358,11 +361,14 @@ std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3]
     const int lo1 = 2 * p, hi1 = d.m[0] - 2 * p, lo2 = 2 * p, hi2 = d.m[1] - 2 * p;
     tile_rect(&out, 0, lo1, 0, 1, tx, 1, 0, d.m[1], zchunk);
     tile_rect(&out, hi1, d.m[0], 0, 1, tx, 1, 0, d.m[1], zchunk);
+    groups[0] = int(out.size());
     tile_rect(&out, lo1, hi1, 0, 1, tx, 1, 0, lo2, zchunk);
     tile_rect(&out, lo1, hi1, 0, 1, tx, 1, hi2, d.m[1], zchunk);
+    groups[1] = int(out.size()) - groups[0];
     for (int s2 : samp[1])
       for (int s1 : samp[0]) out.push_back(QTile{s1, 0, 1, 1, s2, s2 + 1});
   }
+  groups[2] = int(out.size()) - groups[0] - groups[1];
   return out;
 }
 

@@ -234,6 +234,7 @@ struct Q3 {
   static constexpr int NQ = P + 1, W = 2 * P + 1;
   static constexpr int TX = Q3Shape<P>::TX, TY = Q3Shape<P>::TY;
   static constexpr int NQ1 = (TX + P) * NQ, NQ2 = (TY + P) * NQ;
+  static constexpr int YS = NQ2 | 1;  // odd row stride of Ys: lanes on different rows hit different banks
   static constexpr int NC = FORM == IGS_STIFFNESS ? 6 : 1;
   static constexpr int NY = FORM == IGS_STIFFNESS ? 8 : 1;
   static constexpr int NCOMBO = TX * W * TY * W;
@@ -242,8 +243,8 @@ struct Q3 {
 
 // Stage-1 product for one output: y[delta1] = sum_{q1} b^A_{i1}(q1) b^B_{j1}(q1) C(q1)
 template <int P, int A, int B, int NQ1, int NQ2>
-__device__ __forceinline__ void stage1_3d(const double (*Cc)[NQ2], const double (*Tv)[P + 1],
-                                          const double (*Td)[P + 1], int i1, int E1a, int nelem1, int l2,
+__device__ __forceinline__ void stage1_3d(const double (*Cc)[NQ2], const double (*Tv)[NQ1],
+                                          const double (*Td)[NQ1], int i1, int E1a, int nelem1, int l2,
                                           double* y) {
   constexpr int NQ = P + 1, W = 2 * P + 1;
 #pragma unroll
@@ -256,9 +257,9 @@ __device__ __forceinline__ void stage1_3d(const double (*Cc)[NQ2], const double 
 #pragma unroll
     for (int k1 = 0; k1 < NQ; ++k1) {
       const int l1 = le + k1;
-      const double ci = (A ? Td[l1][a] : Tv[l1][a]) * Cc[l1][l2];
+      const double ci = (A ? Td[a][l1] : Tv[a][l1]) * Cc[l1][l2];
 #pragma unroll
-      for (int bb = 0; bb <= P; ++bb) y[bb - a + P] += ci * (B ? Td[l1][bb] : Tv[l1][bb]);
+      for (int bb = 0; bb <= P; ++bb) y[bb - a + P] += ci * (B ? Td[bb][l1] : Tv[bb][l1]);
     }
   }
 }
@@ -268,9 +269,10 @@ __global__ void __launch_bounds__((Q3<P, FORM>::BLOCK))
     quad3d_kernel(KProblem kp, const QTile* __restrict__ tiles, OutT* __restrict__ band) {
   using C = Q3<P, FORM>;
   constexpr int NQ = C::NQ, W = C::W, TX = C::TX, TY = C::TY, NQ1 = C::NQ1, NQ2 = C::NQ2;
+  constexpr int YS = C::YS;
   __shared__ double Cs[C::NC][NQ1][NQ2];
-  __shared__ double Ys[C::NY][TX * W][NQ2];
-  __shared__ double T1v[NQ1][P + 1], T1d[NQ1][P + 1], T2v[NQ2][P + 1], T2d[NQ2][P + 1];
+  __shared__ double Ys[C::NY][TX * W][YS];
+  __shared__ double T1v[P + 1][NQ1], T1d[P + 1][NQ1], T2v[P + 1][NQ2], T2d[P + 1][NQ2];
 
   const QTile tile = tiles[blockIdx.x];
   const int b = blockIdx.y;
@@ -282,12 +284,12 @@ __global__ void __launch_bounds__((Q3<P, FORM>::BLOCK))
   const int nq1 = (E1b - E1a + 1) * NQ, nq2 = (E2b - E2a + 1) * NQ;
 
   for (int t = tid; t < nq1 * (P + 1); t += C::BLOCK) {
-    T1v[t / (P + 1)][t % (P + 1)] = kp.t[0].bv[size_t(E1a) * NQ * (P + 1) + t];
-    T1d[t / (P + 1)][t % (P + 1)] = kp.t[0].bd[size_t(E1a) * NQ * (P + 1) + t];
+    T1v[t % (P + 1)][t / (P + 1)] = kp.t[0].bv[size_t(E1a) * NQ * (P + 1) + t];
+    T1d[t % (P + 1)][t / (P + 1)] = kp.t[0].bd[size_t(E1a) * NQ * (P + 1) + t];
   }
   for (int t = tid; t < nq2 * (P + 1); t += C::BLOCK) {
-    T2v[t / (P + 1)][t % (P + 1)] = kp.t[1].bv[size_t(E2a) * NQ * (P + 1) + t];
-    T2d[t / (P + 1)][t % (P + 1)] = kp.t[1].bd[size_t(E2a) * NQ * (P + 1) + t];
+    T2v[t % (P + 1)][t / (P + 1)] = kp.t[1].bv[size_t(E2a) * NQ * (P + 1) + t];
+    T2d[t % (P + 1)][t / (P + 1)] = kp.t[1].bd[size_t(E2a) * NQ * (P + 1) + t];
   }
 
   // this thread's (i1, delta1, i2, delta2) combination; i1 fastest for
@@ -384,11 +386,11 @@ __global__ void __launch_bounds__((Q3<P, FORM>::BLOCK))
 #pragma unroll
             for (int k2 = 0; k2 < NQ; ++k2) {
               const int l2 = le + k2;
-              const double vi = T2v[l2][a2], vj = T2v[l2][b2];
+              const double vi = T2v[a2][l2], vj = T2v[b2][l2];
               if constexpr (FORM == IGS_MASS) {
                 Z00 += vi * vj * Ys[0][yrow][l2];
               } else {
-                const double di = T2d[l2][a2], dj = T2d[l2][b2];
+                const double di = T2d[a2][l2], dj = T2d[b2][l2];
                 const double vv = vi * vj, vd = vi * dj, dv = di * vj, dd = di * dj;
                 const double y0 = Ys[0][yrow][l2], y1 = Ys[1][yrow][l2], y2 = Ys[2][yrow][l2];
                 const double y3 = Ys[3][yrow][l2], y4 = Ys[4][yrow][l2], y5 = Ys[5][yrow][l2];
@@ -462,7 +464,7 @@ __global__ void __launch_bounds__((Q2<P, FORM>::BLOCK))
   using C = Q2<P, FORM>;
   constexpr int NQ = C::NQ, W = C::W, TX = C::TX, NQ1 = C::NQ1;
   __shared__ double Cs[C::NC][NQ1];
-  __shared__ double T1v[NQ1][P + 1], T1d[NQ1][P + 1];
+  __shared__ double T1v[P + 1][NQ1], T1d[P + 1][NQ1];
 
   const QTile tile = tiles[blockIdx.x];
   const int b = blockIdx.y;
@@ -472,8 +474,8 @@ __global__ void __launch_bounds__((Q2<P, FORM>::BLOCK))
   const int E1a = max(0, tile.i1 - P), E1b = min(nel1 - 1, tile.i1 + tile.nx - 1);
   const int nq1 = (E1b - E1a + 1) * NQ;
   for (int t = tid; t < nq1 * (P + 1); t += C::BLOCK) {
-    T1v[t / (P + 1)][t % (P + 1)] = kp.t[0].bv[size_t(E1a) * NQ * (P + 1) + t];
-    T1d[t / (P + 1)][t % (P + 1)] = kp.t[0].bd[size_t(E1a) * NQ * (P + 1) + t];
+    T1v[t % (P + 1)][t / (P + 1)] = kp.t[0].bv[size_t(E1a) * NQ * (P + 1) + t];
+    T1d[t % (P + 1)][t / (P + 1)] = kp.t[0].bd[size_t(E1a) * NQ * (P + 1) + t];
   }
   const int r1 = tid % TX, d1 = tid / TX;
   const bool active = tid < TX * W && r1 < tile.nx;
@@ -522,11 +524,11 @@ __global__ void __launch_bounds__((Q2<P, FORM>::BLOCK))
 #pragma unroll
             for (int k1 = 0; k1 < NQ; ++k1) {
               const int l1 = le + k1;
-              const double vi = T1v[l1][a], vj = T1v[l1][bb];
+              const double vi = T1v[a][l1], vj = T1v[bb][l1];
               if constexpr (FORM == IGS_MASS) {
                 Y0 += vi * vj * Cs[0][l1];
               } else {
-                const double di = T1d[l1][a], dj = T1d[l1][bb];
+                const double di = T1d[a][l1], dj = T1d[bb][l1];
                 Y0 += di * dj * Cs[0][l1];  // (1,1): K11, dd
                 Y1 += di * vj * Cs[1][l1];  // (1,2): K12, dv
                 Y2 += vi * dj * Cs[1][l1];  // (2,1): K12, vd
@@ -623,7 +625,7 @@ __global__ void __launch_bounds__(R3<P>::BLOCK)
   constexpr int NQ = C::NQ, TX = C::TX, NQ1 = C::NQ1, NQ2 = C::NQ2;
   __shared__ double Fs[NQ1][NQ2];
   __shared__ double Ys[TX][NQ2];
-  __shared__ double T1v[NQ1][P + 1], T2v[NQ2][P + 1];
+  __shared__ double T1v[P + 1][NQ1], T2v[P + 1][NQ2];
   const QTile tile = tiles[blockIdx.x];
   const int b = blockIdx.y;
   double* out = f + size_t(b) * kp.N;
@@ -632,8 +634,8 @@ __global__ void __launch_bounds__(R3<P>::BLOCK)
   const int E1a = max(0, tile.i1 - P), E1b = min(nel1 - 1, tile.i1 + tile.nx - 1);
   const int E2a = max(0, tile.i2 - P), E2b = min(nel2 - 1, tile.i2 + tile.ny - 1);
   const int nq1 = (E1b - E1a + 1) * NQ, nq2 = (E2b - E2a + 1) * NQ;
-  for (int t = tid; t < nq1 * (P + 1); t += C::BLOCK) T1v[t / (P + 1)][t % (P + 1)] = kp.t[0].bv[size_t(E1a) * NQ * (P + 1) + t];
-  for (int t = tid; t < nq2 * (P + 1); t += C::BLOCK) T2v[t / (P + 1)][t % (P + 1)] = kp.t[1].bv[size_t(E2a) * NQ * (P + 1) + t];
+  for (int t = tid; t < nq1 * (P + 1); t += C::BLOCK) T1v[t % (P + 1)][t / (P + 1)] = kp.t[0].bv[size_t(E1a) * NQ * (P + 1) + t];
+  for (int t = tid; t < nq2 * (P + 1); t += C::BLOCK) T2v[t % (P + 1)][t / (P + 1)] = kp.t[1].bv[size_t(E2a) * NQ * (P + 1) + t];
   const int r1 = tid % TX, r2 = tid / TX;
   const bool active = r1 < tile.nx && r2 < tile.ny;
   const int i1 = tile.i1 + r1, i2 = tile.i2 + r2;
@@ -669,7 +671,7 @@ __global__ void __launch_bounds__(R3<P>::BLOCK)
 #pragma unroll
             for (int k1 = 0; k1 < NQ; ++k1) {
               const int l1 = (e1 - E1a) * NQ + k1;
-              y += T1v[l1][a] * Fs[l1][l2];
+              y += T1v[a][l1] * Fs[l1][l2];
             }
           }
           Ys[rr1][l2] = y;
@@ -684,7 +686,7 @@ __global__ void __launch_bounds__(R3<P>::BLOCK)
 #pragma unroll
             for (int k2 = 0; k2 < NQ; ++k2) {
               const int l2 = (e2 - E2a) * NQ + k2;
-              z += T2v[l2][a2] * Ys[r1][l2];
+              z += T2v[a2][l2] * Ys[r1][l2];
             }
           }
           const double* v3 = kp.t[2].bv + size_t(g3) * (P + 1);
@@ -718,7 +720,7 @@ __global__ void __launch_bounds__(256)
   using C = R2<P>;
   constexpr int NQ = C::NQ, NQ1 = C::NQ1;
   __shared__ double Fs[NQ1];
-  __shared__ double T1v[NQ1][P + 1];
+  __shared__ double T1v[P + 1][NQ1];
   const QTile tile = tiles[blockIdx.x];
   const int b = blockIdx.y;
   double* out = f + size_t(b) * kp.N;
@@ -726,7 +728,7 @@ __global__ void __launch_bounds__(256)
   const int nel1 = kp.nelem[0], nel2 = kp.nelem[1];
   const int E1a = max(0, tile.i1 - P), E1b = min(nel1 - 1, tile.i1 + tile.nx - 1);
   const int nq1 = (E1b - E1a + 1) * NQ;
-  for (int t = tid; t < nq1 * (P + 1); t += 256) T1v[t / (P + 1)][t % (P + 1)] = kp.t[0].bv[size_t(E1a) * NQ * (P + 1) + t];
+  for (int t = tid; t < nq1 * (P + 1); t += 256) T1v[t % (P + 1)][t / (P + 1)] = kp.t[0].bv[size_t(E1a) * NQ * (P + 1) + t];
   const bool active = tid < tile.nx;
   const int i1 = tile.i1 + tid;
   double acc[P + 1];
@@ -758,7 +760,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int k1 = 0; k1 < NQ; ++k1) {
               const int l1 = (e1 - E1a) * NQ + k1;
-              y += T1v[l1][a] * Fs[l1];
+              y += T1v[a][l1] * Fs[l1];
             }
           }
           const double* v2 = kp.t[1].bv + size_t(g2) * (P + 1);

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "igs_internal.h"
+#include "profile.h"
 
 namespace igs {
 
@@ -319,8 +320,11 @@ igs_status launch_apply_t(const Dims& d, const T* band, const T* x, T* y, int di
                        x, xm);
     xin = xm;
   }
-  hipLaunchKernelGGL((spmv_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band, xin, y, dirichlet,
-                     nullptr, nullptr);
+  {
+    PhaseTimer t("spmv", s);
+    hipLaunchKernelGGL((spmv_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band, xin, y, dirichlet,
+                       nullptr, nullptr);
+  }
   HIP_OK(hipGetLastError());
   return IGS_OK;
 }
@@ -397,8 +401,12 @@ static igs_status inner_cg(const Dims& d, const T* band, const SolveBufs& sb, T*
     const int k = std::min(chunk, budget - done_iters);
     if (k <= 0) break;
     for (int it = 0; it < k; ++it) {
-      hipLaunchKernelGGL((cg_spmv_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band, p, q, sb.sc,
-                         sb.part);
+      {
+        PhaseTimer t(sizeof(T) == 8 ? "cg_spmv_f64" : "cg_spmv_f32", s);
+        hipLaunchKernelGGL((cg_spmv_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band, p, q, sb.sc,
+                           sb.part);
+      }
+      PhaseTimer t("cg_vector_ops", s);
       hipLaunchKernelGGL(cg_alpha_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
       hipLaunchKernelGGL((cg_update_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, sb.sc, p, q, dv,
                          rh, sb.part2);
@@ -456,8 +464,11 @@ static igs_status refine_loop(const Dims& d, const double* band64, const T* band
   igs_status result = IGS_NOT_CONVERGED;
   double worst = 0.0;
   while (true) {
-    hipLaunchKernelGGL(residual_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band64, f, u, sb.r64,
-                       sb.part, sb.part2);
+    {
+      PhaseTimer t("residual_f64", s);
+      hipLaunchKernelGGL(residual_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band64, f, u, sb.r64,
+                         sb.part, sb.part2);
+    }
     hipLaunchKernelGGL(reduce_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.rr);
     hipLaunchKernelGGL(reduce_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part2, nblk, sb.ff);
     HIP_OK(hipGetLastError());

@@ -26,7 +26,7 @@ COEF = {"const": 0, "sine3": 1, "spline": 2, "exp_spline": 3}
 SRC_CONST, SRC_SINE = 0, 1
 EXPORTS = ["igs_band_layout", "igs_validate", "igs_surrogate_layout", "igs_status_string", "igs_version",
            "igs_assemble_exact", "igs_assemble_surrogate", "igs_assemble_rhs", "igs_apply", "igs_solve_cg",
-           "igs_apply_vjp", "igs_compliance_grad"]
+           "igs_apply_vjp", "igs_compliance_grad", "igs_profile_enable", "igs_profile_read"]
 
 
 class IGSError(RuntimeError):
@@ -60,6 +60,14 @@ class SurrogateInfo(ctypes.Structure):
                 ("boundary_rows", ctypes.c_int64), ("quadrature_rows", ctypes.c_int64)]
 
 
+class ProfilePhase(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("nphase", ctypes.c_int32), ("phase", ProfilePhase * 24)]
+
+
 class CgInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("outer_iterations", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("relres", ctypes.c_double)]
@@ -88,6 +96,8 @@ def lib():
             "igs_solve_cg": [P, vp, vp, vp, vp, f64, i32, ctypes.POINTER(CgInfo), vp],
             "igs_apply_vjp": [P, i32, i32, vp, vp, vp, vp, vp, vp],
             "igs_compliance_grad": [P, i32, i32, vp, vp, vp],
+            "igs_profile_enable": [i32],
+            "igs_profile_read": [ctypes.POINTER(Profile)],
         }
         for name, args in sigs.items():
             fn = getattr(L, name)
@@ -111,6 +121,17 @@ def _status_text(st):
 def _check(st, where):
     if st != IGS_OK:
         raise IGSError(st, where)
+
+
+def profile_enable(on=True):
+    _check(lib().igs_profile_enable(int(on)), "igs_profile_enable")
+
+
+def profile_read():
+    """{phase name: (launches, summed ms)} of the calls since the last read."""
+    pr = Profile()
+    _check(lib().igs_profile_read(ctypes.byref(pr)), "igs_profile_read")
+    return {pr.phase[k].name.decode(): (pr.phase[k].launches, pr.phase[k].ms) for k in range(pr.nphase)}
 
 
 def version():

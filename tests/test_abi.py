@@ -41,7 +41,7 @@ def test_layout_matches_oracle(oracle, prob):
     lay = igs.layout(prob)
     m, N, S = oracle.dims(prob)
     assert tuple(lay.m[:prob["n"]]) == m and lay.N == N and lay.slots == S
-    assert lay.ld % 64 == 0 and N <= lay.ld < N + 64
+    assert lay.ld % 64 == 0 and N < lay.ld <= N + 64
     assert lay.band_elems == prob["batch"] * S * lay.ld
     assert lay.upper == (S - 1) // 2
 
@@ -143,3 +143,8 @@ def test_null_and_enum_arguments():
     sp = igs.make_problem(W.c5_adjoint2d())
     sp.coef.coef = None                                # spline coefficient without control values
     assert L.igs_validate(ctypes.byref(sp), 0, 0) == -1
+
+
+def test_library_resolves_all_symbols():
+    """Every symbol the library needs is defined (immediate binding)."""
+    ctypes.CDLL(igs.LIB_PATH, mode=os.RTLD_NOW | os.RTLD_LOCAL)
