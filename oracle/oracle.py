@@ -467,10 +467,10 @@ def quadratic_form(prob, band_rows, u, v=None):
     return float(v @ (A @ u))
 
 
-def compliance_grad(prob, M, q, u, ks, b=0, surrogate=True):
-    """dJ/dc_k for J = f^T u with A~(c) u = f: dJ/dc_k = -u^T (dA~/dc_k) u.
-    dA~/dc_k is the surrogate construction (linear in the quadrature values)
-    applied to the exact derivative entries dA_ij/dc_k = int dkappa/dc_k ..."""
+def bilinear_grad(prob, M, q, ybar, x, ks, b=0, surrogate=True):
+    """d/dc_k (ybar^T A~(c) x) = ybar^T (dA~/dc_k) x.  dA~/dc_k is the surrogate
+    construction (linear in the quadrature values) applied to the exact
+    derivative entries dA_ij/dc_k = int dkappa/dc_k grad B_i^T K grad B_j."""
     _, N, _ = dims(prob)
     g = np.zeros(len(ks))
     for t, k in enumerate(ks):
@@ -479,8 +479,13 @@ def compliance_grad(prob, M, q, u, ks, b=0, surrogate=True):
             dband = Surrogate(prob, STIFFNESS, M, q, b, exact=ex).rows(np.arange(N))
         else:
             dband = ex(np.arange(N))
-        g[t] = -quadratic_form(prob, dband, u)
+        g[t] = quadratic_form(prob, dband, x, ybar)
     return g
+
+
+def compliance_grad(prob, M, q, u, ks, b=0, surrogate=True):
+    """dJ/dc_k for J = f^T u with A~(c) u = f: dJ/dc_k = -u^T (dA~/dc_k) u."""
+    return -bilinear_grad(prob, M, q, u, u, ks, b, surrogate)
 
 
 def l2_error(prob, u, exact_fn, nq=None):

@@ -1,19 +1,584 @@
 // Adjoint (vector-Jacobian product) of y = A~(c) x with respect to the
-// coefficient-spline control values.
+// B-spline control values c of the diffusion coefficient, for n = 2.
+//
+// A~ is linear in the quadrature values A_q (every entry of the rows outside
+// the analysis domain, the upper entries of the sample rows), so
+//   cbar_k = sum_{i,delta} ybar_i x_{i+delta} dA~_{i,delta}/dc_k
+//          = sum_{quadrature entries} wbar_{i,delta} dA_{i,delta}/dc_k,
+// where wbar is the band weight pushed through the transpose of the surrogate
+// construction (eqs. 5.1b/5.1c and the interpolation of Sec. 4.1):
+//   * diagonal rule (stiffness): an analysis-domain entry (i, delta != 0) also
+//     enters A~_ii with sign -1, so its weight is w_{i,delta} - w_{i,0};
+//   * copy rule: an analysis-domain entry whose partner j lies outside the
+//     domain is the exact A_{j,-delta}, so its weight moves to that entry;
+//   * interpolation: the weights G_delta(p) of Phi~_delta at analysis indices
+//     p go back through the spline evaluation (E^T) and the collocation
+//     inverse (G^-T) onto the sample values V_delta.
+// Then dA_{i,j}/dc_k = int dkappa/dc_k grad B_i^T Khat grad B_j with
+// dkappa/dc_k = N_k (spline) or kappa N_k (exp spline): a reverse sum-
+// factorised quadrature per element, with Jacobians recomputed at the Gauss
+// points, produces one value per Gauss point; a separable gather reduces those
+// onto the coefficients.  Every reduction is a gather in a fixed order: no
+// floating-point atomics, results are deterministic.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
 #include "igs_internal.h"
+#include "profile.h"
+
+namespace igs {
+
+template <typename T>
+hipError_t launch_fit_pass_plain(const KInterp<double>& ip, int d, int n, int batch, const double* in, double* out,
+                                 hipStream_t s);
+igs_status launch_apply(const Dims& d, int dtype, const void* band, const void* x, void* y, int dirichlet,
+                        hipStream_t s);
+
+namespace {
+
+struct AdjGeom {
+  int P, W, S, m1, m2;
+  int64_t N, ld;
+  int lo, hi1, hi2;          // analysis range [lo, hi_d]
+  int form;
+  int surrogate;             // 0: every row is a quadrature row
+  const unsigned char* is_s1;  // [m1] sample index flags
+  const unsigned char* is_s2;  // [m2]
+};
+
+__device__ __forceinline__ bool interior2(const AdjGeom& g, int i1, int i2) {
+  return i1 >= g.lo && i1 <= g.hi1 && i2 >= g.lo && i2 <= g.hi2;
+}
+
+__device__ __forceinline__ bool quad_row(const AdjGeom& g, int i1, int i2) {
+  if (!g.surrogate) return true;
+  if (!interior2(g, i1, i2)) return true;
+  return g.is_s1[i1] && g.is_s2[i2];
+}
+
+// weight of the analysis-domain entry (row j, offset -delta) that copies the
+// boundary entry (row b, offset delta), after the diagonal rule
+__device__ __forceinline__ double moved_weight(const AdjGeom& g, double yj, double xj, double xb) {
+  return g.form == IGS_STIFFNESS ? yj * (xb - xj) : yj * xb;
+}
+
+// wbar on the quadrature rows that are not sample rows (sample rows: zeros,
+// their upper slots are scattered in later)
+__global__ void adj_weights_kernel(AdjGeom g, const double* __restrict__ x, const double* __restrict__ yb,
+                                   double* __restrict__ wbar) {
+  const int b = blockIdx.y;
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= g.N) return;
+  const int i1 = int(i % g.m1), i2 = int(i / g.m1);
+  const double* xb = x + size_t(b) * g.N;
+  const double* yy = yb + size_t(b) * g.N;
+  double* w = wbar + size_t(b) * g.S * g.ld;
+  const bool inner = g.surrogate && interior2(g, i1, i2);
+  if (inner) {
+    if (g.is_s1[i1] && g.is_s2[i2])
+      for (int s = 0; s < g.S; ++s) w[size_t(s) * g.ld + i] = 0.0;
+    return;
+  }
+  const double yi = yy[i];
+  for (int s = 0; s < g.S; ++s) {
+    const int d1 = s % g.W - g.P, d2 = s / g.W - g.P;
+    const int j1 = i1 + d1, j2 = i2 + d2;
+    double v = 0.0;
+    if (j1 >= 0 && j1 < g.m1 && j2 >= 0 && j2 < g.m2) {
+      const int64_t j = i + d1 + int64_t(g.m1) * d2;
+      v = yi * xb[j];
+      if (g.surrogate && s != (g.S - 1) / 2 && interior2(g, j1, j2)) v += moved_weight(g, yy[j], xb[j], xb[i]);
+    }
+    w[size_t(s) * g.ld + i] = v;
+  }
+}
+
+// weight of Phi~_delta at analysis index p (both p and p+delta in the domain)
+__device__ __forceinline__ double interp_weight(const AdjGeom& g, const double* xb, const double* yy, int p1, int p2,
+                                                int d1, int d2) {
+  const int j1 = p1 + d1, j2 = p2 + d2;
+  if (!interior2(g, j1, j2)) return 0.0;
+  const int64_t p = p1 + int64_t(g.m1) * p2, j = j1 + int64_t(g.m1) * j2;
+  if (g.form == IGS_STIFFNESS) return (xb[j] - xb[p]) * (yy[p] - yy[j]);
+  if (d1 == 0 && d2 == 0) return yy[p] * xb[p];
+  return yy[p] * xb[j] + yy[j] * xb[p];
+}
+
+// H[b][u][p2][c1] = sum_{p1} E1[p1][c1] G_u(p1, p2)   (p2 over the analysis range)
+__global__ void adj_h_kernel(AdjGeom g, KInterp<double> ip, const int* __restrict__ plo1, const int* __restrict__ phi1,
+                             const double* __restrict__ x, const double* __restrict__ yb, double* __restrict__ H) {
+  const int S1 = ip.Sd[0];
+  const int L2 = g.hi2 - g.lo + 1;
+  const int64_t total = int64_t(ip.nup) * L2 * S1;
+  const int b = blockIdx.y;
+  const double* xb = x + size_t(b) * g.N;
+  const double* yy = yb + size_t(b) * g.N;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int c1 = int(t % S1);
+    const int64_t r = t / S1;
+    const int p2 = g.lo + int(r % L2);
+    const int u = int(r / L2);
+    const int s = ip.upslot[u];
+    const int d1 = s % g.W - g.P, d2 = s / g.W - g.P;
+    double acc = 0.0;
+    for (int p1 = plo1[c1]; p1 <= phi1[c1]; ++p1) {
+      const int a = c1 - ip.ef[0][p1];
+      if (a < 0 || a > ip.q) continue;
+      acc += ip.eb[0][size_t(p1) * (ip.q + 1) + a] * interp_weight(g, xb, yy, p1, p2, d1, d2);
+    }
+    H[(size_t(b) * ip.nup + u) * L2 * S1 + size_t(p2 - g.lo) * S1 + c1] = acc;
+  }
+}
+
+// Gc[b][u][c2][c1] = sum_{p2} E2[p2][c2] H[b][u][p2][c1]
+__global__ void adj_gc_kernel(AdjGeom g, KInterp<double> ip, const int* __restrict__ plo2, const int* __restrict__ phi2,
+                              int batch, const double* __restrict__ H, double* __restrict__ Gc) {
+  const int S1 = ip.Sd[0], S2 = ip.Sd[1];
+  const int L2 = g.hi2 - g.lo + 1;
+  const int64_t total = int64_t(batch) * ip.nup * S2 * S1;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int c1 = int(t % S1);
+    int64_t r = t / S1;
+    const int c2 = int(r % S2);
+    const int64_t bu = r / S2;
+    const double* h = H + size_t(bu) * L2 * S1;
+    double acc = 0.0;
+    for (int p2 = plo2[c2]; p2 <= phi2[c2]; ++p2) {
+      const int a = c2 - ip.ef[1][p2];
+      if (a < 0 || a > ip.q) continue;
+      acc += ip.eb[1][size_t(p2) * (ip.q + 1) + a] * h[size_t(p2 - g.lo) * S1 + c1];
+    }
+    Gc[t] = acc;
+  }
+}
+
+// wbar at the sample rows' upper slots = Vbar
+__global__ void adj_scatter_kernel(AdjGeom g, KInterp<double> ip, int batch, const double* __restrict__ Vbar,
+                                   double* __restrict__ wbar) {
+  const int S1 = ip.Sd[0], S2 = ip.Sd[1];
+  const int64_t total = int64_t(batch) * ip.nup * S2 * S1;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int k1 = int(t % S1);
+    int64_t r = t / S1;
+    const int k2 = int(r % S2);
+    r /= S2;
+    const int u = int(r % ip.nup);
+    const int b = int(r / ip.nup);
+    const int64_t row = ip.samp[0][k1] + int64_t(g.m1) * ip.samp[1][k2];
+    wbar[(size_t(b) * g.S + ip.upslot[u]) * g.ld + row] = Vbar[t];
+  }
+}
+
+// Reverse quadrature, one wave per element: gather the element's weight
+// matrix W[i][j] = wbar_{i, j-i} (quadrature rows only), contract it with the
+// basis derivatives at the element's Gauss points (direction 2, then
+// direction 1) into Ghat_ab(q) = sum W[i][j] d_a B_i(q) d_b B_j(q), and
+// store pv(q) = (dkappa/dc factor) * Khat_ab(q) Ghat_ab(q) per Gauss point.
+template <int P>
+__global__ void __launch_bounds__(256)
+    adj_elem_kernel(KProblem kp, AdjGeom g, const int2* __restrict__ elems, int nelems, const double* __restrict__ wbar,
+                    double* __restrict__ pv) {
+  constexpr int NP = P + 1, NL = NP * NP, NQ = P + 1;
+  __shared__ double Wl[4][NL * NL];
+  __shared__ double Tl[4][4][NP * NP * NQ];  // [wave][code2][a1*NP+b1][k2]
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int eidx = blockIdx.x * 4 + wv;
+  const int b = blockIdx.y;
+  const bool ok = eidx < nelems;
+  const int2 e = ok ? elems[eidx] : make_int2(0, 0);
+  const double* w = wbar + size_t(b) * g.S * g.ld;
+  // weights
+  for (int t = lane; t < NL * NL; t += 64) {
+    const int il = t / NL, jl = t % NL;
+    const int a1 = il % NP, a2 = il / NP, b1 = jl % NP, b2 = jl / NP;
+    const int i1 = e.x + a1, i2 = e.y + a2;
+    const int s = (b1 - a1 + P) + g.W * (b2 - a2 + P);
+    double v = 0.0;
+    if (ok && quad_row(g, i1, i2)) v = w[size_t(s) * g.ld + i1 + size_t(g.m1) * i2];
+    Wl[wv][t] = v;
+  }
+  __syncthreads();
+  // stage A: direction 2, codes (alpha2, beta2) = 00, 01, 10, 11
+  const double* bv2 = kp.t[1].bv;
+  const double* bd2 = kp.t[1].bd;
+  for (int t = lane; t < 4 * NP * NP * NQ; t += 64) {
+    const int k2 = t % NQ;
+    const int ab = (t / NQ) % (NP * NP);
+    const int code = t / (NQ * NP * NP);
+    const int a1 = ab / NP, b1 = ab % NP;
+    const size_t gq = size_t(e.y * NQ + k2) * NP;
+    double acc = 0.0;
+    for (int a2 = 0; a2 < NP; ++a2) {
+      const double fa = (code & 2) ? bd2[gq + a2] : bv2[gq + a2];
+      for (int b2 = 0; b2 < NP; ++b2) {
+        const double fb = (code & 1) ? bd2[gq + b2] : bv2[gq + b2];
+        acc += fa * fb * Wl[wv][(a1 + NP * a2) * NL + (b1 + NP * b2)];
+      }
+    }
+    Tl[wv][code][ab * NQ + k2] = acc;
+  }
+  __syncthreads();
+  // stage B and the point values: one lane per Gauss point of the element
+  if (ok && lane < NQ * NQ) {
+    const int k1 = lane % NQ, k2 = lane / NQ;
+    const int g1 = e.x * NQ + k1, g2 = e.y * NQ + k2;
+    const double* bv1 = kp.t[0].bv + size_t(g1) * NP;
+    const double* bd1 = kp.t[0].bd + size_t(g1) * NP;
+    // (a,b) = (1,1): alpha1 = beta1 = 1, code2 00; (1,2): (1,0), code 01;
+    // (2,1): (0,1), code 10; (2,2): (0,0), code 11
+    double G11 = 0.0, G12 = 0.0, G21 = 0.0, G22 = 0.0;
+    for (int a1 = 0; a1 < NP; ++a1)
+      for (int b1 = 0; b1 < NP; ++b1) {
+        const int ab = (a1 * NP + b1) * NQ + k2;
+        G11 += bd1[a1] * bd1[b1] * Tl[wv][0][ab];
+        G12 += bd1[a1] * bv1[b1] * Tl[wv][1][ab];
+        G21 += bv1[a1] * bd1[b1] * Tl[wv][2][ab];
+        G22 += bv1[a1] * bv1[b1] * Tl[wv][3][ab];
+      }
+    // Khat = w adj adj^T / |det J| at the point, kappa for the exp factor
+    const int gg[2] = {g1, g2};
+    double J[2][2];
+    const double xi[2] = {kp.t[0].x[g1], kp.t[1].x[g2]};
+    const double wq = kp.t[0].w[g1] * kp.t[1].w[g2];
+    J[0][0] = 1.0; J[0][1] = 0.0; J[1][0] = 0.0; J[1][1] = 1.0;
+    if (kp.geom == IGS_GEOM_SINE) {
+      const double* t1 = kp.t[0].trig + 4 * g1;
+      const double* t2 = kp.t[1].trig + 4 * g2;
+      J[0][0] += kp.ga * t1[1] * t2[2];
+      J[0][1] += kp.ga * t1[0] * t2[3];
+      J[1][0] += kp.ga * t1[3] * t2[0];
+      J[1][1] += kp.ga * t1[2] * t2[1];
+    } else if (kp.geom == IGS_GEOM_POLY2) {
+      const double q0 = xi[0] * (1 - xi[0]), q1 = xi[1] * (1 - xi[1]);
+      const double dq0 = 1 - 2 * xi[0], dq1 = 1 - 2 * xi[1];
+      for (int r = 0; r < 2; ++r) {
+        J[r][0] += kp.ga * (r + 1) * dq0 * q1;
+        J[r][1] += kp.ga * (r + 1) * q0 * dq1;
+      }
+    }
+    const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    if (!(det > 0.0)) atomicOr(kp.flag, 1);
+    const double a00 = J[1][1], a01 = -J[0][1], a10 = -J[1][0], a11 = J[0][0];
+    const double sc = wq / fabs(det);
+    const double K11 = sc * (a00 * a00 + a01 * a01);
+    const double K12 = sc * (a00 * a10 + a01 * a11);
+    const double K22 = sc * (a10 * a10 + a11 * a11);
+    double val = K11 * G11 + K12 * (G12 + G21) + K22 * G22;
+    if (kp.coef == IGS_COEF_EXP_SPLINE) {
+      const double* cc = kp.cc + b * kp.cstride;
+      const int nd = kp.cdeg + 1;
+      const double* c0 = kp.t[0].cb + size_t(g1) * nd;
+      const double* c1 = kp.t[1].cb + size_t(g2) * nd;
+      const int f0 = kp.t[0].cf[g1], f1 = kp.t[1].cf[g2];
+      double gsum = 0.0;
+      for (int r = 0; r < nd; ++r) {
+        double acc = 0.0;
+        for (int c = 0; c < nd; ++c) acc += c0[c] * cc[(f1 + r) * kp.cn[0] + f0 + c];
+        gsum += c1[r] * acc;
+      }
+      val *= exp(gsum);
+    }
+    (void)gg;
+    pv[size_t(b) * kp.nelem[0] * NQ * kp.nelem[1] * NQ + size_t(g2) * (kp.nelem[0] * NQ) + g1] = val;
+  }
+}
+
+// R[b][q2][k1] = sum_{q1} N_k1(q1) pv[b][q2][q1]
+__global__ void adj_red1_kernel(KProblem kp, const int* __restrict__ qlo, const int* __restrict__ qhi,
+                                const double* __restrict__ pv, double* __restrict__ R) {
+  const int Q1 = kp.nelem[0] * kp.nq, Q2 = kp.nelem[1] * kp.nq;
+  const int cn1 = kp.cn[0], nd = kp.cdeg + 1;
+  const int64_t total = int64_t(kp.batch) * Q2 * cn1;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int k1 = int(t % cn1);
+    const int64_t r = t / cn1;
+    const int q2 = int(r % Q2);
+    const int b = int(r / Q2);
+    const double* row = pv + (size_t(b) * Q2 + q2) * Q1;
+    double acc = 0.0;
+    for (int q1 = qlo[k1]; q1 <= qhi[k1]; ++q1) {
+      const int a = k1 - kp.t[0].cf[q1];
+      if (a < 0 || a >= nd) continue;
+      acc += kp.t[0].cb[size_t(q1) * nd + a] * row[q1];
+    }
+    R[t] = acc;
+  }
+}
+
+// cbar[b][k2][k1] = sum_{q2} N_k2(q2) R[b][q2][k1]
+__global__ void adj_red2_kernel(KProblem kp, const int* __restrict__ qlo, const int* __restrict__ qhi,
+                                const double* __restrict__ R, double* __restrict__ cbar) {
+  const int Q2 = kp.nelem[1] * kp.nq;
+  const int cn1 = kp.cn[0], cn2 = kp.cn[1], nd = kp.cdeg + 1;
+  const int64_t total = int64_t(kp.batch) * cn2 * cn1;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int k1 = int(t % cn1);
+    const int64_t r = t / cn1;
+    const int k2 = int(r % cn2);
+    const int b = int(r / cn2);
+    double acc = 0.0;
+    for (int q2 = qlo[k2]; q2 <= qhi[k2]; ++q2) {
+      const int a = k2 - kp.t[1].cf[q2];
+      if (a < 0 || a >= nd) continue;
+      acc += kp.t[1].cb[size_t(q2) * nd + a] * R[(size_t(b) * Q2 + q2) * cn1 + k1];
+    }
+    cbar[t] = acc;
+  }
+}
+
+__global__ void fill_zero_kernel(double* p, int64_t n) {
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x) p[t] = 0.0;
+}
+
+__global__ void negate_copy_kernel(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x) b[t] = -a[t];
+}
+
+int gs_blocks(int64_t n) { return int(std::min<int64_t>((n + 255) / 256, 16384)); }
+
+}  // namespace
+
+// declared in capi.cpp
+igs_status prepare_problem(const igs_problem* pb, hipStream_t s, Dims* d, KProblem* kp, Arena* ar, HostTables* ht);
+igs_status finish_problem(const KProblem& kp, hipStream_t s);
+
+#define ADJ_TRY(x)                             \
+  do {                                         \
+    if ((x) != hipSuccess) return IGS_ERR_HIP; \
+  } while (0)
+
+template <typename V>
+static size_t vb(const V& v) {
+  return padded(v.size() * sizeof(typename V::value_type));
+}
+
+template <typename V>
+static auto* up(Arena& ar, const V& v, hipStream_t s, igs_status* st) {
+  using E = typename V::value_type;
+  E* p = ar.take<E>(v.size());
+  if (hipMemcpyAsync(p, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice, s) != hipSuccess) *st = IGS_ERR_HIP;
+  return static_cast<const E*>(p);
+}
+
+// first/last index q with first(q) <= k <= first(q) + deg, for each k
+static void ranges(const std::vector<int>& first, int deg, int nk, int qa, int qb, std::vector<int>* lo,
+                   std::vector<int>* hi) {
+  lo->assign(nk, 0);
+  hi->assign(nk, -1);
+  std::vector<bool> seen(nk, false);
+  for (int qq = qa; qq <= qb; ++qq)
+    for (int a = 0; a <= deg; ++a) {
+      const int k = first[qq] + a;
+      if (k < 0 || k >= nk) continue;
+      if (!seen[k]) {
+        (*lo)[k] = qq;
+        seen[k] = true;
+      }
+      (*hi)[k] = qq;
+    }
+}
+
+static igs_status vjp(const igs_problem* pb, int M, int q, const double* band64, const double* x, const double* ybar,
+                      double* xbar, double* cbar, bool negate_y, hipStream_t s) {
+  Dims d;
+  KProblem kp;
+  Arena ar;
+  HostTables ht;
+  igs_status st = prepare_problem(pb, s, &d, &kp, &ar, &ht);
+  if (st != IGS_OK) return st;
+  if (d.n != 2) return IGS_ERR_UNSUPPORTED;
+  const bool want_c = cbar != nullptr;
+  if (want_c && pb->coef.kind != IGS_COEF_SPLINE && pb->coef.kind != IGS_COEF_EXP_SPLINE) return IGS_ERR_ARG;
+  const int form = IGS_STIFFNESS;
+  const bool sur = M >= 1;
+  HostInterp hi;
+  if (sur) {
+    int box[3] = {1, 1, 1};
+    st = build_interp(d, form, M, q, box, &hi);
+    if (st != IGS_OK) return st;
+  }
+  if (xbar && !band64) return IGS_ERR_ARG;
+  const size_t NB = size_t(d.N) * d.batch;
+  Arena wa;
+  // ybar (possibly negated), wbar, H, Gc, tmp, pv, R
+  const int L2 = d.m[1] - 4 * d.p;
+  const int S1 = sur ? int(hi.samp[0].size()) : 1, S2 = sur ? int(hi.samp[1].size()) : 1;
+  const int nup = sur ? int(hi.upslot.size()) : 0;
+  const int Q1 = d.nelem[0] * d.nq, Q2 = d.nelem[1] * d.nq;
+  std::vector<unsigned char> is1(d.m[0], 0), is2(d.m[1], 0);
+  if (sur) {
+    for (int v : hi.samp[0]) is1[v] = 1;
+    for (int v : hi.samp[1]) is2[v] = 1;
+  }
+  // elements whose (p+1)^2 rows include a quadrature row
+  std::vector<int> elems;
+  for (int e2 = 0; e2 < d.nelem[1]; ++e2)
+    for (int e1 = 0; e1 < d.nelem[0]; ++e1) {
+      bool any = !sur;
+      for (int a2 = 0; a2 <= d.p && !any; ++a2)
+        for (int a1 = 0; a1 <= d.p && !any; ++a1) {
+          const int i1 = e1 + a1, i2 = e2 + a2;
+          const bool inner = i1 >= 2 * d.p && i1 <= d.m[0] - 2 * d.p - 1 && i2 >= 2 * d.p && i2 <= d.m[1] - 2 * d.p - 1;
+          any = !inner || (is1[i1] && is2[i2]);
+        }
+      if (any) {
+        elems.push_back(e1);
+        elems.push_back(e2);
+      }
+    }
+  std::vector<int> plo1, phi1, plo2, phi2, qlo1, qhi1, qlo2, qhi2;
+  std::vector<double> gT[2];
+  if (sur) {
+    ranges(hi.ef[0], q, S1, 2 * d.p, d.m[0] - 2 * d.p - 1, &plo1, &phi1);
+    ranges(hi.ef[1], q, S2, 2 * d.p, d.m[1] - 2 * d.p - 1, &plo2, &phi2);
+    for (int k = 0; k < 2; ++k) {
+      const int Sk = int(hi.samp[k].size());
+      gT[k].resize(size_t(Sk) * Sk);
+      for (int r = 0; r < Sk; ++r)
+        for (int c = 0; c < Sk; ++c) gT[k][size_t(r) * Sk + c] = hi.ginv[k][size_t(c) * Sk + r];
+    }
+  }
+  if (want_c) {
+    ranges(ht.cf[0], pb->coef.degree, pb->coef.ncoef[0], 0, Q1 - 1, &qlo1, &qhi1);
+    ranges(ht.cf[1], pb->coef.degree, pb->coef.ncoef[1], 0, Q2 - 1, &qlo2, &qhi2);
+  }
+  size_t bytes = padded(NB * sizeof(double));
+  if (want_c) {
+    bytes += padded(size_t(d.batch) * d.S * d.ld * sizeof(double));
+    bytes += padded(size_t(d.batch) * Q1 * Q2 * sizeof(double)) + padded(size_t(d.batch) * Q2 * pb->coef.ncoef[0] * 8);
+    bytes += vb(elems) + vb(is1) + vb(is2) + vb(qlo1) + vb(qhi1) + vb(qlo2) + vb(qhi2);
+    if (sur) {
+      bytes += padded(size_t(d.batch) * nup * L2 * S1 * 8) + 3 * padded(size_t(d.batch) * nup * S1 * S2 * 8);
+      bytes += vb(plo1) + vb(phi1) + vb(plo2) + vb(phi2) + vb(gT[0]) + vb(gT[1]);
+      for (int k = 0; k < 2; ++k) bytes += vb(hi.samp[k]) + vb(hi.ef[k]) + vb(hi.eb[k]);
+      bytes += vb(hi.upslot);
+    }
+  }
+  st = wa.alloc(bytes, s);
+  if (st != IGS_OK) return st;
+  const double* yv = ybar;
+  if (negate_y) {
+    double* yn = wa.take<double>(NB);
+    hipLaunchKernelGGL(negate_copy_kernel, dim3(gs_blocks(NB)), dim3(256), 0, s, ybar, yn, int64_t(NB));
+    yv = yn;
+  }
+  if (xbar) {
+    PhaseTimer t("adj_xbar_spmv", s);
+    st = launch_apply(d, IGS_F64, band64, yv, xbar, 0, s);
+    if (st != IGS_OK) return st;
+  }
+  if (!want_c) return finish_problem(kp, s);
+
+  AdjGeom g;
+  g.P = d.p;
+  g.W = d.W;
+  g.S = d.S;
+  g.m1 = d.m[0];
+  g.m2 = d.m[1];
+  g.N = d.N;
+  g.ld = d.ld;
+  g.lo = 2 * d.p;
+  g.hi1 = d.m[0] - 2 * d.p - 1;
+  g.hi2 = d.m[1] - 2 * d.p - 1;
+  g.form = form;
+  g.surrogate = sur ? 1 : 0;
+  double* wbar = wa.take<double>(size_t(d.batch) * d.S * d.ld);
+  double* pv = wa.take<double>(size_t(d.batch) * Q1 * Q2);
+  double* R = wa.take<double>(size_t(d.batch) * Q2 * pb->coef.ncoef[0]);
+  const int2* delems = reinterpret_cast<const int2*>(up(wa, elems, s, &st));
+  g.is_s1 = up(wa, is1, s, &st);
+  g.is_s2 = up(wa, is2, s, &st);
+  const int* dq[4] = {up(wa, qlo1, s, &st), up(wa, qhi1, s, &st), up(wa, qlo2, s, &st), up(wa, qhi2, s, &st)};
+  if (st != IGS_OK) return st;
+  {
+    PhaseTimer t("adj_weights", s);
+    hipLaunchKernelGGL(adj_weights_kernel, dim3(int((d.N + 255) / 256), d.batch), dim3(256), 0, s, g, x, yv, wbar);
+  }
+  if (sur) {
+    KInterp<double> ip;
+    std::memset(&ip, 0, sizeof(ip));
+    ip.q = q;
+    for (int k = 0; k < 2; ++k) {
+      ip.Sd[k] = int(hi.samp[k].size());
+      ip.lo[k] = 2 * d.p;
+      ip.hi[k] = d.m[k] - 2 * d.p - 1;
+      ip.samp[k] = up(wa, hi.samp[k], s, &st);
+      ip.ef[k] = up(wa, hi.ef[k], s, &st);
+      ip.eb[k] = up(wa, hi.eb[k], s, &st);
+      ip.ginv[k] = up(wa, gT[k], s, &st);
+    }
+    ip.Sd[2] = 1;
+    ip.nup = nup;
+    ip.upslot = up(wa, hi.upslot, s, &st);
+    const int* p1l = up(wa, plo1, s, &st);
+    const int* p1h = up(wa, phi1, s, &st);
+    const int* p2l = up(wa, plo2, s, &st);
+    const int* p2h = up(wa, phi2, s, &st);
+    double* H = wa.take<double>(size_t(d.batch) * nup * L2 * S1);
+    double* Gc = wa.take<double>(size_t(d.batch) * nup * S1 * S2);
+    double* A = wa.take<double>(size_t(d.batch) * nup * S1 * S2);
+    double* Vb = wa.take<double>(size_t(d.batch) * nup * S1 * S2);
+    if (st != IGS_OK) return st;
+    PhaseTimer t("adj_interp", s);
+    hipLaunchKernelGGL(adj_h_kernel, dim3(gs_blocks(int64_t(nup) * L2 * S1), d.batch), dim3(256), 0, s, g, ip, p1l, p1h,
+                       x, yv, H);
+    hipLaunchKernelGGL(adj_gc_kernel, dim3(gs_blocks(int64_t(d.batch) * nup * S1 * S2)), dim3(256), 0, s, g, ip, p2l,
+                       p2h, d.batch, H, Gc);
+    ADJ_TRY(launch_fit_pass_plain<double>(ip, 0, 2, d.batch, Gc, A, s));
+    ADJ_TRY(launch_fit_pass_plain<double>(ip, 1, 2, d.batch, A, Vb, s));
+    hipLaunchKernelGGL(adj_scatter_kernel, dim3(gs_blocks(int64_t(d.batch) * nup * S1 * S2)), dim3(256), 0, s, g, ip,
+                       d.batch, Vb, wbar);
+  }
+  {
+    PhaseTimer t("adj_elements", s);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(gs_blocks(int64_t(d.batch) * Q1 * Q2)), dim3(256), 0, s, pv,
+                       int64_t(d.batch) * Q1 * Q2);
+    const int ne = int(elems.size() / 2);
+    dim3 grid((ne + 3) / 4, d.batch);
+    switch (d.p) {
+      case 1: hipLaunchKernelGGL((adj_elem_kernel<1>), grid, dim3(256), 0, s, kp, g, delems, ne, wbar, pv); break;
+      case 2: hipLaunchKernelGGL((adj_elem_kernel<2>), grid, dim3(256), 0, s, kp, g, delems, ne, wbar, pv); break;
+      case 3: hipLaunchKernelGGL((adj_elem_kernel<3>), grid, dim3(256), 0, s, kp, g, delems, ne, wbar, pv); break;
+      default: hipLaunchKernelGGL((adj_elem_kernel<4>), grid, dim3(256), 0, s, kp, g, delems, ne, wbar, pv); break;
+    }
+  }
+  {
+    PhaseTimer t("adj_coef_reduce", s);
+    hipLaunchKernelGGL(adj_red1_kernel, dim3(gs_blocks(int64_t(d.batch) * Q2 * pb->coef.ncoef[0])), dim3(256), 0, s, kp,
+                       dq[0], dq[1], pv, R);
+    hipLaunchKernelGGL(adj_red2_kernel, dim3(gs_blocks(int64_t(d.batch) * kp.cstride)), dim3(256), 0, s, kp, dq[2],
+                       dq[3], R, cbar);
+  }
+  ADJ_TRY(hipGetLastError());
+  return finish_problem(kp, s);
+}
+
+}  // namespace igs
 
 extern "C" {
 
 igs_status igs_apply_vjp(const igs_problem* pb, int32_t M, int32_t q, const double* band64, const double* x,
                          const double* ybar, double* xbar, double* cbar, void* stream) {
-  (void)pb; (void)M; (void)q; (void)band64; (void)x; (void)ybar; (void)xbar; (void)cbar; (void)stream;
-  return IGS_ERR_UNSUPPORTED;
+  if (!pb || !x || !ybar || (!xbar && !cbar)) return IGS_ERR_ARG;
+  if (M < 0) return IGS_ERR_ARG;
+  if (M >= 1) {
+    igs_status st = igs_validate(pb, M, q);
+    if (st != IGS_OK) return st;
+  }
+  return igs::vjp(pb, M, q, band64, x, ybar, xbar, cbar, false, static_cast<hipStream_t>(stream));
 }
 
 igs_status igs_compliance_grad(const igs_problem* pb, int32_t M, int32_t q, const double* u, double* cbar,
                                void* stream) {
-  (void)pb; (void)M; (void)q; (void)u; (void)cbar; (void)stream;
-  return IGS_ERR_UNSUPPORTED;
+  if (!pb || !u || !cbar) return IGS_ERR_ARG;
+  if (M < 0) return IGS_ERR_ARG;
+  if (M >= 1) {
+    igs_status st = igs_validate(pb, M, q);
+    if (st != IGS_OK) return st;
+  }
+  // dJ/dc = -u^T (dA~/dc) u: the vjp with x = u and ybar = -u
+  return igs::vjp(pb, M, q, nullptr, u, u, nullptr, cbar, true, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -118,6 +118,28 @@ static igs_status finish(const Prepared& P, hipStream_t s) {
   return (flag & 1) ? IGS_ERR_GEOMETRY : IGS_OK;
 }
 
+// used by the adjoint translation unit
+igs_status prepare_problem(const igs_problem* pb, hipStream_t s, Dims* d, KProblem* kp, Arena* ar, HostTables* ht) {
+  Prepared P;
+  igs_status st = prepare(pb, s, &P);
+  if (st != IGS_OK) return st;
+  *d = P.d;
+  *kp = P.kp;
+  *ht = P.ht;
+  std::swap(ar->base, P.ar.base);
+  std::swap(ar->size, P.ar.size);
+  std::swap(ar->used, P.ar.used);
+  std::swap(ar->stream, P.ar.stream);
+  return IGS_OK;
+}
+
+igs_status finish_problem(const KProblem& kp, hipStream_t s) {
+  int flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, kp.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return (flag & 1) ? IGS_ERR_GEOMETRY : IGS_OK;
+}
+
 static int pick_zchunk(const Dims& d, int tx, int ty) {
   const int mz = d.n == 3 ? d.m[2] : d.m[1];
   int64_t base = int64_t((d.m[0] + tx - 1) / tx) * (d.n == 3 ? (d.m[1] + ty - 1) / ty : 1) * d.batch;

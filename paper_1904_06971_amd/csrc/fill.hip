@@ -523,6 +523,19 @@ hipError_t launch_fit(const KInterp<double>& ip, int n, int m1, int m2, int64_t 
   return hipGetLastError();
 }
 
+// one separable pass out = (ginv_d applied along direction d) in, no gather
+template <typename T>
+hipError_t launch_fit_pass_plain(const KInterp<double>& ip, int d, int n, int batch, const double* in, double* out,
+                                 hipStream_t s) {
+  int64_t total = int64_t(ip.Sd[0]) * ip.Sd[1] * (n == 3 ? ip.Sd[2] : 1) * ip.nup * batch;
+  int blocks = int(std::min<int64_t>((total + 255) / 256, 65535));
+  hipLaunchKernelGGL((fit_pass_kernel<T, false>), dim3(blocks), dim3(256), 0, s, ip, d, n, 0, 0, int64_t(0), 0, batch,
+                     static_cast<const T*>(nullptr), in, out);
+  return hipGetLastError();
+}
+template hipError_t launch_fit_pass_plain<double>(const KInterp<double>&, int, int, int, const double*, double*,
+                                                  hipStream_t);
+
 template hipError_t launch_fit<double>(const KInterp<double>&, int, int, int, int64_t, int, int, const double*,
                                        double*, double*, double*, hipStream_t);
 template hipError_t launch_fit<float>(const KInterp<double>&, int, int, int, int64_t, int, int, const float*,
