@@ -109,15 +109,16 @@ def main():
     log(f"surrogate: {ms_step:.3f} ms/step (wall {wall / args.steps * 1e3:.3f}), {value:.3e} slots/s, phases {phases}")
 
     # rooflines of the step's kernels
-    qrows = info.quadrature_rows
-    quad_flops = quad_flops_per_row(3, prob["p"]) * qrows
+    fpr = quad_flops_per_row(3, prob["p"])
     fb, frows, fcopies = fill_bytes(prob, lay, 8)
     roofs = {}
-    if "quad_surrogate_rows" in phases:
-        t = phases["quad_surrogate_rows"]["avg_ms"] * 1e-3
-        roofs["quad_surrogate_rows"] = {"bound": "alu", "achieved": quad_flops / t / 1e12, "peak": FP64_PEAK_TFLOPS,
-                                        "unit": "TFLOP/s", "frac": quad_flops / t / 1e12 / FP64_PEAK_TFLOPS,
-                                        "traffic": None, "units": f"{qrows} quadrature rows", "ms": t * 1e3}
+    for name, rows in (("quad_boundary_rows", info.boundary_rows), ("quad_sample_rows", info.sample_rows)):
+        if name in phases:
+            t = phases[name]["avg_ms"] * 1e-3
+            tf = fpr * rows / t / 1e12
+            roofs[name] = {"bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": tf / FP64_PEAK_TFLOPS, "traffic": None, "units": f"{rows} quadrature rows",
+                           "ms": t * 1e3}
     if "fill" in phases:
         t = phases["fill"]["avg_ms"] * 1e-3
         roofs["fill"] = {"bound": "hbm", "achieved": fb / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -11,7 +11,8 @@ namespace igs {
 
 // launchers defined in the kernel translation units
 template <typename OutT>
-hipError_t launch_quad(const KProblem& kp, int form, const QTile* tiles, int ntiles, OutT* band, hipStream_t s);
+hipError_t launch_quad(const KProblem& kp, int form, const QTile* tiles, int ntiles, bool rows, OutT* band,
+                       hipStream_t s);
 hipError_t launch_rhs(const KProblem& kp, const QTile* tiles, int ntiles, int src, double c, double* f, hipStream_t s);
 void quad_tile_shape(int n, int p, int* tx, int* ty);
 void rhs_tile_shape(int n, int* tx, int* ty);
@@ -163,7 +164,7 @@ static igs_status exact_t(const igs_problem* pb, int form, OutT* band, hipStream
   if (st != IGS_OK) return st;
   {
     PhaseTimer t("quad_exact", s);
-    HIP_TRY(launch_quad<OutT>(P.kp, form, dt, int(tiles.size()), band, s));
+    HIP_TRY(launch_quad<OutT>(P.kp, form, dt, int(tiles.size()), false, band, s));
   }
   {
     PhaseTimer t("zero_pad", s);
@@ -261,10 +262,15 @@ static igs_status surrogate_t(const igs_problem* pb, int form, int M, int q, Out
   if (st != IGS_OK) return st;
   if (fill_lds_bytes<OutT>(ipT, fill_npen(d, chunk_rows), d) > 160 * 1024) return IGS_ERR_UNSUPPORTED;
   {
-    // one launch over the boundary pencils, the interior end slabs and the
-    // sample rows (groups[] keeps the split for diagnostics)
-    PhaseTimer t("quad_surrogate_rows", s);
-    HIP_TRY(launch_quad<OutT>(P.kp, form, dt, groups[0] + groups[1] + groups[2], band, s));
+    // rows outside the analysis domain: the boundary pencils and the interior
+    // pencils' end slabs, tiled
+    PhaseTimer t("quad_boundary_rows", s);
+    HIP_TRY(launch_quad<OutT>(P.kp, form, dt, groups[0] + groups[1], false, band, s));
+  }
+  {
+    // the sample rows: isolated, one workgroup each in 3-D (single-row tiles)
+    PhaseTimer t("quad_sample_rows", s);
+    HIP_TRY(launch_quad<OutT>(P.kp, form, dt + groups[0] + groups[1], groups[2], d.n == 3, band, s));
   }
   {
     PhaseTimer t("fit", s);

@@ -171,8 +171,9 @@ __device__ __forceinline__ double kappa_at(const KProblem& kp, int b, const int*
 
 // Integrand data at one Gauss point: the symmetric K scaled by weight*kappa
 // (K = kappa |det J| J^-1 J^-T = kappa adj(J) adj(J)^T / |det J|) or the
-// mass weight w |det J|.  Flags det J <= 0.
-template <int ND, int FORM>
+// mass weight w |det J|.  Flags det J <= 0.  VC = false: the coefficient is the
+// constant c0 (no coefficient code in the kernel).
+template <int ND, int FORM, bool VC = true>
 __device__ __forceinline__ void point_data(const KProblem& kp, int b, const int* g, double* out) {
   double xi[ND], w = 1.0;
 #pragma unroll
@@ -206,7 +207,7 @@ __device__ __forceinline__ void point_data(const KProblem& kp, int b, const int*
   if constexpr (FORM == IGS_MASS) {
     out[0] = w * ad;
   } else {
-    const double s = w * kappa_at<ND>(kp, b, g, xi) / ad;
+    const double s = w * (VC ? kappa_at<ND>(kp, b, g, xi) : kp.c0) / ad;
     int k = 0;
 #pragma unroll
     for (int r = 0; r < ND; ++r)
@@ -444,6 +445,469 @@ __global__ void __launch_bounds__((Q3<P, FORM>::BLOCK))
         }
       }
     });
+  }
+}
+
+// ------------------------------------------------ 3-D rows, register-blocked ---
+//
+// Same contraction order as quad3d_kernel with a different work mapping.  Wave
+// w owns the direction-2 combination (i2, delta2) = (tile.i2 + w / W, w % W - P)
+// and lane l the direction-1 combination (i1, delta1) = (tile.i1 + l % TX,
+// l / TX - P), so that one thread carries one (delta1, delta2) column of a row
+// pencil and its rolling window of P+1 rows x W delta3 values.  Per Gauss plane:
+//   stage 1  direction-1 contraction.  A wave owns one i1, so the 1-D basis
+//            values it needs are wave-uniform (scalar loads); its lanes own
+//            (component, l2).  Results go to Ys, two codes per 16 bytes.
+//   stage 2  direction-2 contraction, basis values wave-uniform again,
+//            4 direction-3 codes in registers;
+//   stage 3  direction-3 products into the rolling window;
+//   phase A  integrand data of the next plane at the footprint points -> Cs
+//            (same barrier interval as stages 2-3: they touch different buffers).
+
+// Read-only table viewed in the constant address space: loads at wave-uniform
+// addresses then go through the scalar cache into SGPRs.
+typedef const __attribute__((address_space(4))) double* cdptr;
+__device__ __forceinline__ cdptr uniform_table(const double* p) { return (cdptr)p; }
+
+template <int P>
+struct Q3BShape;
+template <> struct Q3BShape<1> { static constexpr int TY = 5; };
+template <> struct Q3BShape<2> { static constexpr int TY = 3; };
+template <> struct Q3BShape<3> { static constexpr int TY = 2; };
+
+// Stage-1 wave tasks.  A task fixes i1 and one of three product modes; its
+// lanes hold (component, l2).  Codes written to Ys (pair, half):
+//   0 dd.K11  1 dv.K12 | 2 dv.K13  3 vd.K12 | 4 vd.K13  5 vv.K22 | 6 vv.K23  7 vv.K33
+// (d/v = derivative/value of the i- and j-function in direction 1).
+//   S1_DDV  components K11, K12, K13: dd (kept for K11) and dv (kept for K12, K13)
+//   S1_VD   components K12, K13: vd
+//   S1_VV   components K22, K23, K33 (or the mass weight): vv
+enum { S1_DDV = 0, S1_VD = 1, S1_VV = 2 };
+
+template <int P, int FORM>
+struct Q3B {
+  static constexpr int NQ = P + 1, W = 2 * P + 1;
+  static constexpr int TX = 64 / W, TY = Q3BShape<P>::TY;
+  static constexpr int NWAVE = TY * W;
+  static constexpr int BLOCK = 64 * NWAVE;
+  static constexpr int NQ1 = (TX + P) * NQ, NQ2 = (TY + P) * NQ;
+  static constexpr bool STIFF = FORM == IGS_STIFFNESS;
+  static constexpr int NC = STIFF ? 6 : 1;
+  static constexpr int NMODE = STIFF ? 3 : 1;
+  // Cs component stride, congruent to NQ2 mod 32: lanes (component, l2) of a
+  // stage-1 wave then address consecutive banks
+  static constexpr int CS = (NQ1 * NQ2 + 31) / 32 * 32 + NQ2 % 32;
+  static constexpr int NPAIR = STIFF ? 4 : 1;  // Y codes, two per double2
+  static constexpr int YL = 65;                // odd lane pitch (double2) of Ys
+  static_assert(3 * NQ2 <= 64, "stage-1 lanes");
+};
+
+// Direction-1 contraction of one component column for one wave-uniform i1.
+// MODE S1_DDV: y0 = dd, y1 = dv;  S1_VD: y0 = vd;  S1_VV: y0 = vv.
+// cb points at the lane's component value at l1 = 0, ls is the l1 stride.
+template <int P, int MODE>
+__device__ __forceinline__ void stage1_core(const KProblem& kp, const double* cb, int ls, int i1, int E1a,
+                                            double* y0, double* y1) {
+  constexpr int NQ = P + 1, W = 2 * P + 1;
+#pragma unroll
+  for (int d = 0; d < W; ++d) y0[d] = y1[d] = 0.0;
+  const int nel1 = kp.nelem[0];
+#pragma unroll
+  for (int a = 0; a <= P; ++a) {
+    const int e1 = i1 - a;
+    if (e1 < 0 || e1 >= nel1) continue;
+    // a runtime loop over the element's points keeps the scalar basis loads
+    // of one point live at a time
+#pragma unroll 1
+    for (int k1 = 0; k1 < NQ; ++k1) {
+      const int g1 = e1 * NQ + k1;
+      cdptr tv = uniform_table(kp.t[0].bv) + size_t(g1) * (P + 1);
+      cdptr td = uniform_table(kp.t[0].bd) + size_t(g1) * (P + 1);
+      const double c = cb[((e1 - E1a) * NQ + k1) * ls];
+      if constexpr (MODE == S1_DDV) {
+        const double ud = td[a] * c;
+#pragma unroll
+        for (int b = 0; b <= P; ++b) {
+          y0[b - a + P] += ud * td[b];
+          y1[b - a + P] += ud * tv[b];
+        }
+      } else if constexpr (MODE == S1_VD) {
+        const double uv = tv[a] * c;
+#pragma unroll
+        for (int b = 0; b <= P; ++b) y0[b - a + P] += uv * td[b];
+      } else {
+        const double uv = tv[a] * c;
+#pragma unroll
+        for (int b = 0; b <= P; ++b) y0[b - a + P] += uv * tv[b];
+      }
+    }
+  }
+}
+
+// Lane -> (component, code) of a stage-1 task; ok = false for idle lanes.
+template <int MODE, bool STIFF>
+__device__ __forceinline__ void stage1_slot(int cl, int* comp, int* code0, int* code1, bool* ok) {
+  if constexpr (!STIFF) {
+    *ok = *ok && cl == 0;
+    *comp = 0;
+    *code0 = 0;
+    *code1 = -1;
+  } else if constexpr (MODE == S1_DDV) {
+    *ok = *ok && cl < 3;
+    *comp = cl;
+    *code0 = cl == 0 ? 0 : -1;  // dd.K11
+    *code1 = cl == 0 ? -1 : cl;  // dv.K12, dv.K13
+  } else if constexpr (MODE == S1_VD) {
+    *ok = *ok && cl < 2;
+    *comp = 1 + cl;
+    *code0 = 3 + cl;  // vd.K12, vd.K13
+    *code1 = -1;
+  } else {
+    *ok = *ok && cl < 3;
+    *comp = 3 + cl;
+    *code0 = 5 + cl;  // vv.K22, vv.K23, vv.K33
+    *code1 = -1;
+  }
+  if (!*ok) *comp = 0;
+}
+
+template <int P, int FORM, int MODE>
+__device__ __forceinline__ void stage1_b(const KProblem& kp, const double* __restrict__ Cs,
+                                         double* __restrict__ Ysd, int i1, int r1, int E1a, int nq2, int lane) {
+  using C = Q3B<P, FORM>;
+  constexpr int W = C::W, TX = C::TX, NQ2 = C::NQ2;
+  const int cl = lane / NQ2, l2 = lane - cl * NQ2;
+  bool ok = l2 < nq2;
+  int comp, code0, code1;
+  stage1_slot<MODE, C::STIFF>(cl, &comp, &code0, &code1, &ok);
+  double y0[W], y1[W];
+  stage1_core<P, MODE>(kp, Cs + comp * C::CS + (ok ? l2 : 0), NQ2, i1, E1a, y0, y1);
+  if (!ok) return;
+  double* row0 = Ysd + ((code0 >> 1) * NQ2 + l2) * (2 * C::YL) + (code0 & 1);
+  double* row1 = Ysd + ((code1 >> 1) * NQ2 + l2) * (2 * C::YL) + (code1 & 1);
+#pragma unroll
+  for (int d1 = 0; d1 < W; ++d1) {
+    const int col = 2 * (d1 * TX + r1);
+    if (code0 >= 0) row0[col] = y0[d1];
+    if (MODE == S1_DDV && code1 >= 0) row1[col] = y1[d1];
+  }
+}
+
+// ------------------------------------------------ 3-D rows, register-blocked ---
+//
+// Same contraction order as quad3d_kernel with a different work mapping.  Wave
+// w owns the direction-2 combination (i2, delta2) = (tile.i2 + w / W, w % W - P)
+// and lane l the direction-1 combination (i1, delta1) = (tile.i1 + l % TX,
+// l / TX - P): one thread carries one (delta1, delta2) column of a row pencil
+// and its window of the P+1 rows that the current element layer touches.
+// Row e3 + a of the window has collected delta3 in [-P, P - a] so far, so slot
+// a keeps W - a values; after the last plane of layer e3, row e3 is complete,
+// is stored, and the window shifts by one row.  Per Gauss plane:
+//   stage 1  direction-1 contraction: wave tasks (i1, mode) with wave-uniform
+//            basis values (scalar loads), lanes (component, l2); -> Ys
+//   stage 2  direction-2 contraction, basis values wave-uniform again, into 4
+//            direction-3 codes;
+//   stage 3  direction-3 products into the window;
+//   phase A  integrand data of the next plane at the footprint points -> Cs
+//            (same barrier interval as stages 2-3: they touch other buffers).
+
+template <int P, int FORM, bool VC, typename OutT>
+__global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
+    quad3d_tile_kernel(KProblem kp, const QTile* __restrict__ tiles, OutT* __restrict__ band) {
+  using C = Q3B<P, FORM>;
+  constexpr int NQ = C::NQ, W = C::W, TX = C::TX, NQ2 = C::NQ2, YL = C::YL;
+  __shared__ double Cs[C::NC * C::CS];
+  __shared__ double2 Ys[C::NPAIR * NQ2 * YL];
+
+  const QTile tile = tiles[blockIdx.x];
+  const int b = blockIdx.y;
+  OutT* out = band + size_t(b) * kp.S * kp.ld;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nel1 = kp.nelem[0], nel2 = kp.nelem[1], nel3 = kp.nelem[2];
+  const int E1a = max(0, tile.i1 - P), E1b = min(nel1 - 1, tile.i1 + tile.nx - 1);
+  const int E2a = max(0, tile.i2 - P), E2b = min(nel2 - 1, tile.i2 + tile.ny - 1);
+  const int nq1 = (E1b - E1a + 1) * NQ, nq2 = (E2b - E2a + 1) * NQ;
+
+  // stage-2/3 identity of this thread
+  const int r2 = wave / W, d2 = wave - r2 * W;
+  const int d1 = lane / TX, r1 = lane - d1 * TX;
+  const bool active = lane < TX * W && r1 < tile.nx && r2 < tile.ny;
+  const int i1 = tile.i1 + r1, i2 = tile.i2 + r2;
+  // this thread's column (delta1, delta2) of row (i1, i2, 0); delta3 steps by W^2 slots
+  OutT* const colp = out + size_t(d1 + W * d2) * kp.ld + size_t(i1) + size_t(kp.m[0]) * i2;
+  const size_t sstride = size_t(W * W) * kp.ld;
+  const size_t plane = size_t(kp.m[0]) * kp.m[1];
+
+  // window: acc[a][d] = row e3 + a, delta3 = d - P, d <= W - 1 - a
+  double acc[P + 1][W];
+#pragma unroll
+  for (int a = 0; a <= P; ++a)
+#pragma unroll
+    for (int d = 0; d < W; ++d) acc[a][d] = 0.0;
+
+  auto phase_a = [&](int g3) {
+    for (int t = tid; t < nq1 * nq2; t += C::BLOCK) {
+      const int l1 = t / nq2, l2 = t - l1 * nq2;
+      const int g[3] = {E1a * NQ + l1, E2a * NQ + l2, g3};
+      double v[C::NC];
+      point_data<3, FORM, VC>(kp, b, g, v);
+#pragma unroll
+      for (int c = 0; c < C::NC; ++c) Cs[c * C::CS + l1 * NQ2 + l2] = v[c];
+    }
+  };
+  auto stage1 = [&]() {
+    double* Ysd = reinterpret_cast<double*>(Ys);
+    for (int task = wave; task < C::NMODE * TX; task += C::NWAVE) {
+      const int mode = task / TX, rr1 = task - mode * TX;
+      if (rr1 >= tile.nx) continue;
+      if (!C::STIFF || mode == S1_VV)
+        stage1_b<P, FORM, S1_VV>(kp, Cs, Ysd, tile.i1 + rr1, rr1, E1a, nq2, lane);
+      else if (mode == S1_DDV)
+        stage1_b<P, FORM, S1_DDV>(kp, Cs, Ysd, tile.i1 + rr1, rr1, E1a, nq2, lane);
+      else
+        stage1_b<P, FORM, S1_VD>(kp, Cs, Ysd, tile.i1 + rr1, rr1, E1a, nq2, lane);
+    }
+  };
+  auto store_row = [&](int i3, int a) {
+    if (active && i3 >= tile.z0 && i3 < tile.z1) {
+      OutT* p = colp + plane * i3;
+#pragma unroll
+      for (int d3 = 0; d3 < W; ++d3) {
+        // entries beyond the triangle belong to partners past the last function: zero
+        double v = 0.0;
+        static_for<0, P + 1>([&](auto ac) {
+          constexpr int A = decltype(ac)::value;
+          if (A == a && d3 <= W - 1 - A) v = acc[A][d3];
+        });
+        p[d3 * sstride] = static_cast<OutT>(v);
+      }
+    }
+  };
+
+  const int Elo = max(0, tile.z0 - P), Ehi = min(nel3 - 1, tile.z1 - 1);
+  const int g0 = Elo * NQ, glast = Ehi * NQ + NQ - 1;
+  phase_a(g0);
+  __syncthreads();
+
+  for (int g3 = g0; g3 <= glast; ++g3) {
+    const int e3 = g3 / NQ, k3 = g3 - e3 * NQ;
+    stage1();
+    __syncthreads();
+    if (active) {
+      double Z00 = 0.0, Z10 = 0.0, Z01 = 0.0, Z11 = 0.0;
+#pragma unroll
+      for (int a2 = 0; a2 <= P; ++a2) {
+        const int e2 = i2 - a2;
+        const int b2 = a2 + d2 - P;
+        if (e2 < 0 || e2 >= nel2 || b2 < 0 || b2 > P) continue;
+#pragma unroll 1
+        for (int k2 = 0; k2 < NQ; ++k2) {
+          const int g2 = e2 * NQ + k2;
+          const int l2 = (e2 - E2a) * NQ + k2;
+          cdptr tv = uniform_table(kp.t[1].bv) + size_t(g2) * (P + 1);
+          cdptr td = uniform_table(kp.t[1].bd) + size_t(g2) * (P + 1);
+          const double vi = tv[a2], vj = tv[b2];
+          const double2* yp = Ys + l2 * YL + lane;
+          if constexpr (C::STIFF) {
+            const double di = td[a2], dj = td[b2];
+            const double2 p0 = yp[0], p1 = yp[NQ2 * YL], p2 = yp[2 * NQ2 * YL], p3 = yp[3 * NQ2 * YL];
+            Z00 += vi * (vj * p0.x + dj * p0.y) + di * (vj * p1.y + dj * p2.y);
+            Z10 += vi * (vj * p2.x + dj * p3.x);
+            Z01 += vj * (vi * p1.x + di * p3.x);
+            Z11 += vi * vj * p3.y;
+          } else {
+            Z00 += vi * vj * yp[0].x;
+          }
+        }
+      }
+      cdptr v3 = uniform_table(kp.t[2].bv) + size_t(g3) * (P + 1);
+      cdptr t3 = uniform_table(kp.t[2].bd) + size_t(g3) * (P + 1);
+#pragma unroll
+      for (int b3 = 0; b3 <= P; ++b3) {
+        double U, V;
+        if constexpr (C::STIFF) {
+          U = v3[b3] * Z00 + t3[b3] * Z01;
+          V = v3[b3] * Z10 + t3[b3] * Z11;
+        } else {
+          U = v3[b3] * Z00;
+          V = 0.0;
+        }
+#pragma unroll
+        for (int a3 = 0; a3 <= P; ++a3) {
+          if constexpr (C::STIFF)
+            acc[a3][b3 - a3 + P] += v3[a3] * U + t3[a3] * V;
+          else
+            acc[a3][b3 - a3 + P] += v3[a3] * U;
+        }
+      }
+    }
+    if (k3 == NQ - 1) {
+      if (e3 < nel3 - 1) {
+        // row e3 is complete: store it and shift the window
+        store_row(e3, 0);
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+#pragma unroll
+          for (int d = 0; d < W; ++d) acc[a][d] = (d < W - 1 - a) ? acc[a + 1][d] : 0.0;
+#pragma unroll
+        for (int d = 0; d < W; ++d) acc[P][d] = 0.0;
+      } else {
+        // last layer of the domain: every row of the window is complete
+#pragma unroll
+        for (int a = 0; a <= P; ++a) store_row(e3 + a, a);
+      }
+    }
+    if (g3 < glast) phase_a(g3 + 1);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------ 3-D single rows -------------
+//
+// One workgroup per isolated row (the surrogate's sample rows): no other row of
+// the workgroup would share its footprint.  The row's support holds at most
+// (P+1)^3 elements; planes of direction 3 are streamed as above, stage 1 uses
+// the same wave-uniform tasks, stage 2 runs one thread per (delta1, delta2),
+// and stage 3 accumulates that thread's W delta3 values (one row: no window).
+
+template <int P, int FORM>
+struct Q3R {
+  static constexpr int NQ = P + 1, W = 2 * P + 1;
+  static constexpr int NQR = (P + 1) * NQ;  // Gauss points of the row's support per direction
+  static constexpr bool STIFF = FORM == IGS_STIFFNESS;
+  static constexpr int NC = STIFF ? 6 : 1;
+  static constexpr int NMODE = STIFF ? 3 : 1;
+  static constexpr int NY = STIFF ? 8 : 1;
+  static constexpr int NSUB = (3 * NQR + 63) / 64;  // waves per stage-1 task
+  static constexpr int CS = (NQR * NQR + 31) / 32 * 32 + NQR % 32;  // component stride of Cs
+  static constexpr int BLOCK = 256;
+  static_assert(W * W <= BLOCK, "stage-2 threads");
+};
+
+template <int P, int FORM, bool VC, typename OutT>
+__global__ void __launch_bounds__(256)
+    quad3d_row_kernel(KProblem kp, const QTile* __restrict__ tiles, OutT* __restrict__ band) {
+  using C = Q3R<P, FORM>;
+  constexpr int NQ = C::NQ, W = C::W, NQR = C::NQR;
+  __shared__ double Cs[C::NC * C::CS];
+  __shared__ double Ys[C::NY][W][NQR];
+
+  const QTile tile = tiles[blockIdx.x];
+  const int b = blockIdx.y;
+  OutT* out = band + size_t(b) * kp.S * kp.ld;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int i1 = tile.i1, i2 = tile.i2, i3 = tile.z0;
+  const int nel1 = kp.nelem[0], nel2 = kp.nelem[1], nel3 = kp.nelem[2];
+  const int E1a = max(0, i1 - P), E1b = min(nel1 - 1, i1);
+  const int E2a = max(0, i2 - P), E2b = min(nel2 - 1, i2);
+  const int E3a = max(0, i3 - P), E3b = min(nel3 - 1, i3);
+  const int nq1 = (E1b - E1a + 1) * NQ, nq2 = (E2b - E2a + 1) * NQ;
+
+  // stage-2/3 identity: column (delta1, delta2)
+  const int d1 = tid % W, d2 = tid / W;
+  const bool active = tid < W * W;
+  const int j2 = i2 + d2 - P;
+  double acc[W];
+#pragma unroll
+  for (int d = 0; d < W; ++d) acc[d] = 0.0;
+
+  auto phase_a = [&](int g3) {
+    for (int t = tid; t < nq1 * nq2; t += C::BLOCK) {
+      const int l1 = t / nq2, l2 = t - l1 * nq2;
+      const int g[3] = {E1a * NQ + l1, E2a * NQ + l2, g3};
+      double v[C::NC];
+      point_data<3, FORM, VC>(kp, b, g, v);
+#pragma unroll
+      for (int c = 0; c < C::NC; ++c) Cs[c * C::CS + l1 * NQR + l2] = v[c];
+    }
+  };
+  auto stage1_task = [&](auto modec, int sub) {
+    constexpr int MODE = decltype(modec)::value;
+    const int idx = sub * 64 + lane;
+    const int cl = idx / NQR, l2 = idx - cl * NQR;
+    bool ok = l2 < nq2;
+    int comp, code0, code1;
+    stage1_slot<MODE, C::STIFF>(cl, &comp, &code0, &code1, &ok);
+    double y0[W], y1[W];
+    stage1_core<P, MODE>(kp, Cs + comp * C::CS + (ok ? l2 : 0), NQR, i1, E1a, y0, y1);
+    if (!ok) return;
+#pragma unroll
+    for (int dd = 0; dd < W; ++dd) {
+      if (code0 >= 0) Ys[code0][dd][l2] = y0[dd];
+      if (MODE == S1_DDV && code1 >= 0) Ys[code1][dd][l2] = y1[dd];
+    }
+  };
+  auto stage1 = [&]() {
+    for (int task = wave; task < C::NMODE * C::NSUB; task += C::BLOCK / 64) {
+      const int mode = task / C::NSUB, sub = task - mode * C::NSUB;
+      if (!C::STIFF || mode == S1_VV)
+        stage1_task(IntC<S1_VV>{}, sub);
+      else if (mode == S1_DDV)
+        stage1_task(IntC<S1_DDV>{}, sub);
+      else
+        stage1_task(IntC<S1_VD>{}, sub);
+    }
+  };
+
+  const int glast = E3b * NQ + NQ - 1;
+  phase_a(E3a * NQ);
+  __syncthreads();
+  for (int g3 = E3a * NQ; g3 <= glast; ++g3) {
+    stage1();
+    __syncthreads();
+    if (active) {
+      double Z00 = 0.0, Z10 = 0.0, Z01 = 0.0, Z11 = 0.0;
+#pragma unroll
+      for (int a2 = 0; a2 <= P; ++a2) {
+        const int e2 = i2 - a2;
+        const int b2 = j2 - e2;
+        if (e2 < 0 || e2 >= nel2 || b2 < 0 || b2 > P) continue;
+#pragma unroll 1
+        for (int k2 = 0; k2 < NQ; ++k2) {
+          const int g2 = e2 * NQ + k2;
+          const int l2 = (e2 - E2a) * NQ + k2;
+          const double* tv = kp.t[1].bv + size_t(g2) * (P + 1);
+          const double* td = kp.t[1].bd + size_t(g2) * (P + 1);
+          const double vi = tv[a2], vj = tv[b2];
+          if constexpr (C::STIFF) {
+            const double di = td[a2], dj = td[b2];
+            Z00 += vi * (vj * Ys[0][d1][l2] + dj * Ys[1][d1][l2]) + di * (vj * Ys[3][d1][l2] + dj * Ys[5][d1][l2]);
+            Z10 += vi * (vj * Ys[4][d1][l2] + dj * Ys[6][d1][l2]);
+            Z01 += vj * (vi * Ys[2][d1][l2] + di * Ys[6][d1][l2]);
+            Z11 += vi * vj * Ys[7][d1][l2];
+          } else {
+            Z00 += vi * vj * Ys[0][d1][l2];
+          }
+        }
+      }
+      // the row's local index in element e3 is uniform: dispatch it at compile time
+      const int a3 = i3 - g3 / NQ;
+      cdptr v3 = uniform_table(kp.t[2].bv) + size_t(g3) * (P + 1);
+      cdptr t3 = uniform_table(kp.t[2].bd) + size_t(g3) * (P + 1);
+      static_for<0, P + 1>([&](auto av) {
+        constexpr int A3 = decltype(av)::value;
+        if (a3 != A3) return;
+        const double va = v3[A3], da = t3[A3];
+#pragma unroll
+        for (int b3 = 0; b3 <= P; ++b3) {
+          if constexpr (C::STIFF)
+            acc[b3 - A3 + P] += va * (v3[b3] * Z00 + t3[b3] * Z01) + da * (v3[b3] * Z10 + t3[b3] * Z11);
+          else
+            acc[b3 - A3 + P] += va * v3[b3] * Z00;
+        }
+      });
+    }
+    if (g3 < glast) phase_a(g3 + 1);
+    __syncthreads();
+  }
+  if (active) {
+    const size_t idx = size_t(i1) + size_t(kp.m[0]) * (i2 + size_t(kp.m[1]) * i3);
+#pragma unroll
+    for (int d3 = 0; d3 < W; ++d3) out[size_t(d1 + W * (d2 + W * d3)) * kp.ld + idx] = static_cast<OutT>(acc[d3]);
   }
 }
 
@@ -792,9 +1256,9 @@ void quad_tile_shape(int n, int p, int* tx, int* ty) {
     return;
   }
   switch (p) {
-    case 1: *tx = Q3Shape<1>::TX; *ty = Q3Shape<1>::TY; break;
-    case 2: *tx = Q3Shape<2>::TX; *ty = Q3Shape<2>::TY; break;
-    case 3: *tx = Q3Shape<3>::TX; *ty = Q3Shape<3>::TY; break;
+    case 1: *tx = Q3B<1, IGS_STIFFNESS>::TX; *ty = Q3B<1, IGS_STIFFNESS>::TY; break;
+    case 2: *tx = Q3B<2, IGS_STIFFNESS>::TX; *ty = Q3B<2, IGS_STIFFNESS>::TY; break;
+    case 3: *tx = Q3B<3, IGS_STIFFNESS>::TX; *ty = Q3B<3, IGS_STIFFNESS>::TY; break;
     default: *tx = Q3Shape<4>::TX; *ty = Q3Shape<4>::TY; break;
   }
 }
@@ -805,11 +1269,28 @@ void rhs_tile_shape(int n, int* tx, int* ty) {
 }
 
 template <int P, int FORM, typename OutT>
-static hipError_t launch_quad_t(const KProblem& kp, const QTile* tiles, int ntiles, OutT* band, hipStream_t s) {
+static hipError_t launch_quad_t(const KProblem& kp, const QTile* tiles, int ntiles, bool rows, OutT* band,
+                                hipStream_t s) {
   if (ntiles == 0) return hipSuccess;
   dim3 grid(ntiles, kp.batch);
-  if (kp.n == 3) {
-    hipLaunchKernelGGL((quad3d_kernel<P, FORM, OutT>), grid, dim3(Q3<P, FORM>::BLOCK), 0, s, kp, tiles, band);
+  const bool vc = kp.coef != IGS_COEF_CONST;
+  if (kp.n == 3 && rows) {
+    if (vc)
+      hipLaunchKernelGGL((quad3d_row_kernel<P, FORM, true, OutT>), grid, dim3(Q3R<P, FORM>::BLOCK), 0, s, kp, tiles,
+                         band);
+    else
+      hipLaunchKernelGGL((quad3d_row_kernel<P, FORM, false, OutT>), grid, dim3(Q3R<P, FORM>::BLOCK), 0, s, kp,
+                         tiles, band);
+  } else if (kp.n == 3) {
+    if constexpr (P <= 3) {
+      if (vc)
+        hipLaunchKernelGGL((quad3d_tile_kernel<P, FORM, true, OutT>), grid, dim3(Q3B<P, FORM>::BLOCK), 0, s, kp,
+                           tiles, band);
+      else
+        hipLaunchKernelGGL((quad3d_tile_kernel<P, FORM, false, OutT>), grid, dim3(Q3B<P, FORM>::BLOCK), 0, s, kp,
+                           tiles, band);
+    } else
+      hipLaunchKernelGGL((quad3d_kernel<P, FORM, OutT>), grid, dim3(Q3<P, FORM>::BLOCK), 0, s, kp, tiles, band);
   } else {
     hipLaunchKernelGGL((quad2d_kernel<P, FORM, OutT>), grid, dim3(Q2<P, FORM>::BLOCK), 0, s, kp, tiles, band);
   }
@@ -817,24 +1298,26 @@ static hipError_t launch_quad_t(const KProblem& kp, const QTile* tiles, int ntil
 }
 
 template <int P, typename OutT>
-static hipError_t launch_quad_p(const KProblem& kp, int form, const QTile* tiles, int ntiles, OutT* band,
+static hipError_t launch_quad_p(const KProblem& kp, int form, const QTile* tiles, int ntiles, bool rows, OutT* band,
                                 hipStream_t s) {
-  return form == IGS_MASS ? launch_quad_t<P, IGS_MASS, OutT>(kp, tiles, ntiles, band, s)
-                          : launch_quad_t<P, IGS_STIFFNESS, OutT>(kp, tiles, ntiles, band, s);
+  return form == IGS_MASS ? launch_quad_t<P, IGS_MASS, OutT>(kp, tiles, ntiles, rows, band, s)
+                          : launch_quad_t<P, IGS_STIFFNESS, OutT>(kp, tiles, ntiles, rows, band, s);
 }
 
+// rows = false: tiles of quad_tile_shape; rows = true: single-row tiles (nx = ny = 1, z1 = z0 + 1)
 template <typename OutT>
-hipError_t launch_quad(const KProblem& kp, int form, const QTile* tiles, int ntiles, OutT* band, hipStream_t s) {
+hipError_t launch_quad(const KProblem& kp, int form, const QTile* tiles, int ntiles, bool rows, OutT* band,
+                       hipStream_t s) {
   switch (kp.p) {
-    case 1: return launch_quad_p<1, OutT>(kp, form, tiles, ntiles, band, s);
-    case 2: return launch_quad_p<2, OutT>(kp, form, tiles, ntiles, band, s);
-    case 3: return launch_quad_p<3, OutT>(kp, form, tiles, ntiles, band, s);
-    default: return launch_quad_p<4, OutT>(kp, form, tiles, ntiles, band, s);
+    case 1: return launch_quad_p<1, OutT>(kp, form, tiles, ntiles, rows, band, s);
+    case 2: return launch_quad_p<2, OutT>(kp, form, tiles, ntiles, rows, band, s);
+    case 3: return launch_quad_p<3, OutT>(kp, form, tiles, ntiles, rows, band, s);
+    default: return launch_quad_p<4, OutT>(kp, form, tiles, ntiles, rows, band, s);
   }
 }
 
-template hipError_t launch_quad<double>(const KProblem&, int, const QTile*, int, double*, hipStream_t);
-template hipError_t launch_quad<float>(const KProblem&, int, const QTile*, int, float*, hipStream_t);
+template hipError_t launch_quad<double>(const KProblem&, int, const QTile*, int, bool, double*, hipStream_t);
+template hipError_t launch_quad<float>(const KProblem&, int, const QTile*, int, bool, float*, hipStream_t);
 
 template <int P>
 static hipError_t launch_rhs_p(const KProblem& kp, const QTile* tiles, int ntiles, int src, double c, double* f,
