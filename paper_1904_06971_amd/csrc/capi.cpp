@@ -54,12 +54,10 @@ static size_t vbytes(const V& v) {
   return padded(v.size() * sizeof(typename V::value_type));
 }
 
+// stages v in the arena; the copy happens at the arena's flush()
 template <typename V>
-static auto* upload(Arena& ar, const V& v, hipStream_t s, igs_status* st) {
-  using E = typename V::value_type;
-  E* p = ar.take<E>(v.size());
-  if (hipMemcpyAsync(p, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice, s) != hipSuccess) *st = IGS_ERR_HIP;
-  return static_cast<const E*>(p);
+static auto* upload(Arena& ar, const V& v, hipStream_t, igs_status*) {
+  return ar.put(v.data(), v.size());
 }
 
 static igs_status prepare(const igs_problem* pb, hipStream_t s, Prepared* P) {
@@ -69,7 +67,7 @@ static igs_status prepare(const igs_problem* pb, hipStream_t s, Prepared* P) {
   size_t bytes = padded(sizeof(int));
   for (int k = 0; k < P->d.n; ++k)
     bytes += vbytes(P->ht.x[k]) + vbytes(P->ht.w[k]) + vbytes(P->ht.bv[k]) + vbytes(P->ht.bd[k]) +
-             vbytes(P->ht.trig[k]) + vbytes(P->ht.cb[k]) + vbytes(P->ht.cf[k]);
+             vbytes(P->ht.bvd[k]) + vbytes(P->ht.trig[k]) + vbytes(P->ht.cb[k]) + vbytes(P->ht.cf[k]);
   st = P->ar.alloc(bytes, s);
   if (st != IGS_OK) return st;
   KProblem& kp = P->kp;
@@ -105,10 +103,12 @@ static igs_status prepare(const igs_problem* pb, hipStream_t s, Prepared* P) {
     kp.t[k].w = upload(P->ar, P->ht.w[k], s, &st);
     kp.t[k].bv = upload(P->ar, P->ht.bv[k], s, &st);
     kp.t[k].bd = upload(P->ar, P->ht.bd[k], s, &st);
+    kp.t[k].bvd = upload(P->ar, P->ht.bvd[k], s, &st);
     kp.t[k].trig = upload(P->ar, P->ht.trig[k], s, &st);
     kp.t[k].cb = upload(P->ar, P->ht.cb[k], s, &st);
     kp.t[k].cf = upload(P->ar, P->ht.cf[k], s, &st);
   }
+  if (st == IGS_OK) st = P->ar.flush();
   return st;
 }
 
@@ -161,6 +161,7 @@ static igs_status exact_t(const igs_problem* pb, int form, OutT* band, hipStream
   st = ta.alloc(padded(tiles.size() * sizeof(QTile)), s);
   if (st != IGS_OK) return st;
   const QTile* dt = upload(ta, tiles, s, &st);
+  if (st == IGS_OK) st = ta.flush();
   if (st != IGS_OK) return st;
   {
     PhaseTimer t("quad_exact", s);
@@ -259,6 +260,7 @@ static igs_status surrogate_t(const igs_problem* pb, int form, int M, int q, Out
   double* tmp0 = ta.take<double>(ncoef);
   double* tmp1 = ta.take<double>(ncoef);
   double* coef = ta.take<double>(ncoef);
+  if (st == IGS_OK) st = ta.flush();
   if (st != IGS_OK) return st;
   if (fill_lds_bytes<OutT>(ipT, fill_npen(d, chunk_rows), d) > 160 * 1024) return IGS_ERR_UNSUPPORTED;
   {
@@ -412,6 +414,7 @@ igs_status igs_assemble_rhs(const igs_problem* pb, int32_t source, double c, dou
   st = ta.alloc(padded(tiles.size() * sizeof(QTile)), s);
   if (st != IGS_OK) return st;
   const QTile* dt = upload(ta, tiles, s, &st);
+  if (st == IGS_OK) st = ta.flush();
   if (st != IGS_OK) return st;
   {
     PhaseTimer t("rhs", s);

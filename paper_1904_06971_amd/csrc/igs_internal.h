@@ -4,7 +4,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <cstring>
 #include <vector>
 
 #include "igs.h"
@@ -22,6 +24,7 @@ struct Tab1D {
   const double* w;     // [Q]       Gauss weight * h/2
   const double* bv;    // [Q][p+1]  b_{e+a}(x_g)
   const double* bd;    // [Q][p+1]  b'_{e+a}(x_g)
+  const double* bvd;   // [Q][p+1][2] (b, b') pairs of the same values
   const double* trig;  // [Q][4]    sin(pi x), pi cos(pi x), sin(2 pi x), 2 pi cos(2 pi x)
   const double* cb;    // [Q][cdeg+1] coefficient-spline basis values (spline kinds)
   const int* cf;       // [Q]       first coefficient-spline function alive at x_g
@@ -81,7 +84,7 @@ igs_status make_dims(const igs_problem* pb, Dims* d);
 
 struct HostTables {
   // per direction, flattened as in Tab1D
-  std::vector<double> x[3], w[3], bv[3], bd[3], trig[3], cb[3];
+  std::vector<double> x[3], w[3], bv[3], bd[3], bvd[3], trig[3], cb[3];
   std::vector<int> cf[3];
 };
 
@@ -109,10 +112,15 @@ std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3]
                                    int groups[3]);
 
 // Device scratch arena: one stream-ordered allocation carved into pieces.
+// put() reserves a piece and stages host data for it; flush() sends every
+// staged piece with a single host-to-device copy (the pieces are contiguous,
+// scratch pieces between them receive zeros before any kernel touches them).
 struct Arena {
   char* base = nullptr;
   size_t size = 0, used = 0;
   hipStream_t stream = nullptr;
+  std::vector<char> stage;
+  size_t dlo = ~size_t(0), dhi = 0;
   igs_status alloc(size_t bytes, hipStream_t s);
   template <typename T>
   T* take(size_t count) {
@@ -120,6 +128,17 @@ struct Arena {
     used = off + count * sizeof(T);
     return reinterpret_cast<T*>(base + off);
   }
+  template <typename T>
+  const T* put(const T* data, size_t count) {
+    T* p = take<T>(count);
+    const size_t off = reinterpret_cast<char*>(p) - base, bytes = count * sizeof(T);
+    if (stage.size() < off + bytes) stage.resize(size);
+    if (bytes) std::memcpy(stage.data() + off, data, bytes);
+    dlo = std::min(dlo, off);
+    dhi = std::max(dhi, off + bytes);
+    return p;
+  }
+  igs_status flush();
   void release();
   ~Arena() { release(); }
 };

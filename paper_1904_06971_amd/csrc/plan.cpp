@@ -199,6 +199,7 @@ void build_tables(const igs_problem* pb, const Dims& d, HostTables* t) {
     t->w[k].resize(Q);
     t->bv[k].resize(size_t(Q) * np1);
     t->bd[k].resize(size_t(Q) * np1);
+    t->bvd[k].resize(size_t(Q) * np1 * 2);
     t->trig[k].resize(size_t(Q) * 4);
     std::vector<double> ck;
     int cne = 0;
@@ -218,6 +219,10 @@ void build_tables(const igs_problem* pb, const Dims& d, HostTables* t) {
         t->x[k][qi] = x;
         t->w[k][qi] = 0.5 * h * gw[g];
         span_basis_d(knots, e + d.p, d.p, x, &t->bv[k][size_t(qi) * np1], &t->bd[k][size_t(qi) * np1]);
+        for (int a = 0; a < np1; ++a) {
+          t->bvd[k][(size_t(qi) * np1 + a) * 2] = t->bv[k][size_t(qi) * np1 + a];
+          t->bvd[k][(size_t(qi) * np1 + a) * 2 + 1] = t->bd[k][size_t(qi) * np1 + a];
+        }
         t->trig[k][qi * 4 + 0] = std::sin(kPi * x);
         t->trig[k][qi * 4 + 1] = kPi * std::cos(kPi * x);
         t->trig[k][qi * 4 + 2] = std::sin(2.0 * kPi * x);
@@ -385,10 +390,21 @@ igs_status Arena::alloc(size_t bytes, hipStream_t s) {
   return IGS_OK;
 }
 
+igs_status Arena::flush() {
+  if (dhi <= dlo) return IGS_OK;
+  const hipError_t e = hipMemcpyAsync(base + dlo, stage.data() + dlo, dhi - dlo, hipMemcpyHostToDevice, stream);
+  dlo = ~size_t(0);
+  dhi = 0;
+  return e == hipSuccess ? IGS_OK : IGS_ERR_HIP;
+}
+
 void Arena::release() {
   if (base) (void)hipFreeAsync(base, stream);
   base = nullptr;
   size = used = 0;
+  stage.clear();
+  dlo = ~size_t(0);
+  dhi = 0;
 }
 
 }  // namespace igs

@@ -505,40 +505,44 @@ struct Q3B {
 // Direction-1 contraction of one component column for one wave-uniform i1.
 // MODE S1_DDV: y0 = dd, y1 = dv;  S1_VD: y0 = vd;  S1_VV: y0 = vv.
 // cb points at the lane's component value at l1 = 0, ls is the l1 stride.
+// Per Gauss point one scalar load brings the (value, derivative) pairs of the
+// p+1 functions alive there; the point loop is unrolled by two so that two
+// points' loads are in flight together.
 template <int P, int MODE>
 __device__ __forceinline__ void stage1_core(const KProblem& kp, const double* cb, int ls, int i1, int E1a,
                                             double* y0, double* y1) {
-  constexpr int NQ = P + 1, W = 2 * P + 1;
+  constexpr int NQ = P + 1, W = 2 * P + 1, NP = P + 1;
 #pragma unroll
   for (int d = 0; d < W; ++d) y0[d] = y1[d] = 0.0;
   const int nel1 = kp.nelem[0];
+  cdptr tab = uniform_table(kp.t[0].bvd);
 #pragma unroll
   for (int a = 0; a <= P; ++a) {
     const int e1 = i1 - a;
     if (e1 < 0 || e1 >= nel1) continue;
-    // a runtime loop over the element's points keeps the scalar basis loads
-    // of one point live at a time
-#pragma unroll 1
+    cdptr row = tab + size_t(e1) * NQ * 2 * NP;
+    const double* cp = cb + (e1 - E1a) * NQ * ls;
+#pragma unroll 2
     for (int k1 = 0; k1 < NQ; ++k1) {
-      const int g1 = e1 * NQ + k1;
-      cdptr tv = uniform_table(kp.t[0].bv) + size_t(g1) * (P + 1);
-      cdptr td = uniform_table(kp.t[0].bd) + size_t(g1) * (P + 1);
-      const double c = cb[((e1 - E1a) * NQ + k1) * ls];
+      double t[2 * NP];
+#pragma unroll
+      for (int q = 0; q < 2 * NP; ++q) t[q] = row[k1 * 2 * NP + q];
+      const double c = cp[k1 * ls];
       if constexpr (MODE == S1_DDV) {
-        const double ud = td[a] * c;
+        const double u = t[2 * a + 1] * c;
 #pragma unroll
         for (int b = 0; b <= P; ++b) {
-          y0[b - a + P] += ud * td[b];
-          y1[b - a + P] += ud * tv[b];
+          y0[b - a + P] += u * t[2 * b + 1];
+          y1[b - a + P] += u * t[2 * b];
         }
       } else if constexpr (MODE == S1_VD) {
-        const double uv = tv[a] * c;
+        const double u = t[2 * a] * c;
 #pragma unroll
-        for (int b = 0; b <= P; ++b) y0[b - a + P] += uv * td[b];
+        for (int b = 0; b <= P; ++b) y0[b - a + P] += u * t[2 * b + 1];
       } else {
-        const double uv = tv[a] * c;
+        const double u = t[2 * a] * c;
 #pragma unroll
-        for (int b = 0; b <= P; ++b) y0[b - a + P] += uv * tv[b];
+        for (int b = 0; b <= P; ++b) y0[b - a + P] += u * t[2 * b];
       }
     }
   }
@@ -696,29 +700,31 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
     stage1();
     __syncthreads();
     if (active) {
+      // the overlap of the supports of i2 and j2 = i2 + delta2: elements
+      // i2 - a2 with partner index b2 = a2 + delta2 in [0, P]; per point two
+      // scalar loads bring (value, derivative) of the functions i2 and j2
       double Z00 = 0.0, Z10 = 0.0, Z01 = 0.0, Z11 = 0.0;
+      cdptr tab2 = uniform_table(kp.t[1].bvd);
 #pragma unroll
       for (int a2 = 0; a2 <= P; ++a2) {
         const int e2 = i2 - a2;
         const int b2 = a2 + d2 - P;
         if (e2 < 0 || e2 >= nel2 || b2 < 0 || b2 > P) continue;
-#pragma unroll 1
+        cdptr row = tab2 + size_t(e2) * NQ * 2 * (P + 1);
+        const double2* yp = Ys + (e2 - E2a) * NQ * YL + lane;
+#pragma unroll 2
         for (int k2 = 0; k2 < NQ; ++k2) {
-          const int g2 = e2 * NQ + k2;
-          const int l2 = (e2 - E2a) * NQ + k2;
-          cdptr tv = uniform_table(kp.t[1].bv) + size_t(g2) * (P + 1);
-          cdptr td = uniform_table(kp.t[1].bd) + size_t(g2) * (P + 1);
-          const double vi = tv[a2], vj = tv[b2];
-          const double2* yp = Ys + l2 * YL + lane;
+          cdptr rk = row + k2 * 2 * (P + 1);
+          const double vi = rk[2 * a2], di = rk[2 * a2 + 1], vj = rk[2 * b2], dj = rk[2 * b2 + 1];
+          const double2* yk = yp + k2 * YL;
           if constexpr (C::STIFF) {
-            const double di = td[a2], dj = td[b2];
-            const double2 p0 = yp[0], p1 = yp[NQ2 * YL], p2 = yp[2 * NQ2 * YL], p3 = yp[3 * NQ2 * YL];
+            const double2 p0 = yk[0], p1 = yk[NQ2 * YL], p2 = yk[2 * NQ2 * YL], p3 = yk[3 * NQ2 * YL];
             Z00 += vi * (vj * p0.x + dj * p0.y) + di * (vj * p1.y + dj * p2.y);
             Z10 += vi * (vj * p2.x + dj * p3.x);
             Z01 += vj * (vi * p1.x + di * p3.x);
             Z11 += vi * vj * p3.y;
           } else {
-            Z00 += vi * vj * yp[0].x;
+            Z00 += vi * vj * yk[0].x;
           }
         }
       }
