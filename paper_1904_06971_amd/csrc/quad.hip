@@ -505,44 +505,66 @@ struct Q3B {
 // Direction-1 contraction of one component column for one wave-uniform i1.
 // MODE S1_DDV: y0 = dd, y1 = dv;  S1_VD: y0 = vd;  S1_VV: y0 = vv.
 // cb points at the lane's component value at l1 = 0, ls is the l1 stride.
-// Per Gauss point one scalar load brings the (value, derivative) pairs of the
-// p+1 functions alive there; the point loop is unrolled by two so that two
-// points' loads are in flight together.
+// The basis values are wave-uniform and come through scalar loads; they are
+// fetched for a batch of NB Gauss points at once (all of an element's points
+// for the vd and vv products, half of them for dd/dv, which need both value
+// and derivative rows) so that one wait covers the whole batch.
 template <int P, int MODE>
 __device__ __forceinline__ void stage1_core(const KProblem& kp, const double* cb, int ls, int i1, int E1a,
                                             double* y0, double* y1) {
   constexpr int NQ = P + 1, W = 2 * P + 1, NP = P + 1;
+  constexpr int NB = MODE == S1_DDV ? (NQ + 1) / 2 : NQ;  // points per batch
 #pragma unroll
   for (int d = 0; d < W; ++d) y0[d] = y1[d] = 0.0;
   const int nel1 = kp.nelem[0];
-  cdptr tab = uniform_table(kp.t[0].bvd);
+  cdptr tv = uniform_table(kp.t[0].bv), td = uniform_table(kp.t[0].bd);
 #pragma unroll
   for (int a = 0; a <= P; ++a) {
     const int e1 = i1 - a;
     if (e1 < 0 || e1 >= nel1) continue;
-    cdptr row = tab + size_t(e1) * NQ * 2 * NP;
+    const size_t g0 = size_t(e1) * NQ;
     const double* cp = cb + (e1 - E1a) * NQ * ls;
-#pragma unroll 2
-    for (int k1 = 0; k1 < NQ; ++k1) {
-      double t[2 * NP];
 #pragma unroll
-      for (int q = 0; q < 2 * NP; ++q) t[q] = row[k1 * 2 * NP + q];
-      const double c = cp[k1 * ls];
-      if constexpr (MODE == S1_DDV) {
-        const double u = t[2 * a + 1] * c;
+    for (int k0 = 0; k0 < NQ; k0 += NB) {
+      // batch loads: TB rows (values or derivatives of the p+1 functions) and ta
+      double tb[NB][NP], tb2[NB][NP], ta[NB], c[NB];
 #pragma unroll
-        for (int b = 0; b <= P; ++b) {
-          y0[b - a + P] += u * t[2 * b + 1];
-          y1[b - a + P] += u * t[2 * b];
+      for (int k = 0; k < NB; ++k) {
+        if (k0 + k >= NQ) break;
+        const size_t g = g0 + k0 + k;
+#pragma unroll
+        for (int b = 0; b < NP; ++b) {
+          if constexpr (MODE == S1_DDV) {
+            tb[k][b] = td[g * NP + b];
+            tb2[k][b] = tv[g * NP + b];
+          } else if constexpr (MODE == S1_VD) {
+            tb[k][b] = td[g * NP + b];
+          } else {
+            tb[k][b] = tv[g * NP + b];
+          }
         }
-      } else if constexpr (MODE == S1_VD) {
-        const double u = t[2 * a] * c;
+        if constexpr (MODE == S1_VD) ta[k] = tv[g * NP + a];
+        c[k] = cp[(k0 + k) * ls];
+      }
 #pragma unroll
-        for (int b = 0; b <= P; ++b) y0[b - a + P] += u * t[2 * b + 1];
-      } else {
-        const double u = t[2 * a] * c;
+      for (int k = 0; k < NB; ++k) {
+        if (k0 + k >= NQ) break;
+        if constexpr (MODE == S1_DDV) {
+          const double u = tb[k][a] * c[k];
 #pragma unroll
-        for (int b = 0; b <= P; ++b) y0[b - a + P] += u * t[2 * b];
+          for (int b = 0; b <= P; ++b) {
+            y0[b - a + P] += u * tb[k][b];
+            y1[b - a + P] += u * tb2[k][b];
+          }
+        } else if constexpr (MODE == S1_VD) {
+          const double u = ta[k] * c[k];
+#pragma unroll
+          for (int b = 0; b <= P; ++b) y0[b - a + P] += u * tb[k][b];
+        } else {
+          const double u = tb[k][a] * c[k];
+#pragma unroll
+          for (int b = 0; b <= P; ++b) y0[b - a + P] += u * tb[k][b];
+        }
       }
     }
   }
