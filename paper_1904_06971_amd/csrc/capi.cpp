@@ -21,9 +21,11 @@ hipError_t launch_fit(const KInterp<double>& ip, int n, int m1, int m2, int64_t 
                       double* tmp0, double* tmp1, double* coef, hipStream_t s);
 template <typename T>
 hipError_t launch_fill(const KInterp<T>& ip, int form, const Dims& d, const int* chunks, int nchunks, int chunk_rows,
-                       const int4* dsl, const double* coef, T* band, hipStream_t s);
+                       int n2max, int n3max, const int4* dsl, const double* coef, T* band, hipStream_t s);
 template <typename T>
-size_t fill_lds_bytes(const KInterp<T>& ip, int npen, const Dims& d);
+size_t fill_lds_bytes(const KInterp<T>& ip, int npen, const Dims& d, int blk);
+void fill_block_dims(const Dims& d, const std::vector<int> ef[3], int q, const std::vector<int>& chunks, int rows,
+                     int* n2max, int* n3max);
 std::vector<int> fill_chunks(const Dims& d, int rows);
 int fill_npen(const Dims& d, int rows);
 int fill_chunk_rows(const Dims& d, int Sd1);
@@ -262,7 +264,9 @@ static igs_status surrogate_t(const igs_problem* pb, int form, int M, int q, Out
   double* coef = ta.take<double>(ncoef);
   if (st == IGS_OK) st = ta.flush();
   if (st != IGS_OK) return st;
-  if (fill_lds_bytes<OutT>(ipT, fill_npen(d, chunk_rows), d) > 160 * 1024) return IGS_ERR_UNSUPPORTED;
+  if (fill_lds_bytes<OutT>(ipT, fill_npen(d, chunk_rows), d, 0) > 160 * 1024) return IGS_ERR_UNSUPPORTED;
+  int n2max = 1, n3max = 1;
+  fill_block_dims(d, hi.ef, q, chunks, chunk_rows, &n2max, &n3max);
   {
     // rows outside the analysis domain: the boundary pencils and the interior
     // pencils' end slabs, tiled
@@ -280,7 +284,8 @@ static igs_status surrogate_t(const igs_problem* pb, int form, int M, int q, Out
   }
   {
     PhaseTimer t("fill", s);
-    HIP_TRY(launch_fill<OutT>(ipT, form, d, dchunks, int(chunks.size()), chunk_rows, ddsl, coef, band, s));
+    HIP_TRY(launch_fill<OutT>(ipT, form, d, dchunks, int(chunks.size()), chunk_rows, n2max, n3max, ddsl, coef, band,
+                              s));
   }
   {
     PhaseTimer t("zero_pad", s);

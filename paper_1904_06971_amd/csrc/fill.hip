@@ -77,6 +77,7 @@ struct FillGeom {
   int npen;           // max pencils a chunk can touch
   int nchunks;
   const int* chunks;  // chunk ids that contain analysis-domain rows
+  int n2max, n3max;   // largest coefficient block (directions 2, 3) a chunk's tasks use
 };
 
 // host-side per-delta table (slot, delta1, delta2, delta3)
@@ -297,7 +298,13 @@ __global__ void __launch_bounds__(kChunk)
 // Requires npen*2*S1 <= kChunk pencil tasks per chunk.
 constexpr int kRows = 3;
 
-template <int ND, int FORM, int Q, typename T>
+// STAGE = true: the coefficient block that the chunk's pencil tasks read for a
+// delta ((directions 2, 3) ranges of the chunk's pencils and their lower
+// partners, all c1) is copied into LDS by coalesced loads two deltas ahead,
+// instead of every task gathering its (q+1)^2 coefficients from memory.
+constexpr int kStage = 4;  // staged coefficients per thread (block <= kStage * kChunk)
+
+template <int ND, int FORM, int Q, typename T, bool STAGE>
 __global__ void __launch_bounds__(kChunk)
     fill_fast_kernel(KInterp<T> ip, FillGeom g, const int4* __restrict__ dsl, const double* __restrict__ coef,
                      T* __restrict__ band) {
@@ -307,7 +314,9 @@ __global__ void __launch_bounds__(kChunk)
   const int S1 = ip.Sd[0], S2 = ip.Sd[1], S3 = (ND == 3) ? ip.Sd[2] : 1;
   const int m3 = (ND == 3) ? g.m3 : 1;
   const int P = g.P;
-  T* Tbuf = reinterpret_cast<T*>(smem_raw);
+  const int blk = STAGE ? g.n3max * g.n2max * S1 : 0;
+  double* Cb = reinterpret_cast<double*>(smem_raw);  // [2][blk]
+  T* Tbuf = reinterpret_cast<T*>(Cb + 2 * blk);
   T* tb1 = Tbuf + size_t(2) * g.npen * 2 * S1;
   T* tb2 = tb1 + size_t(g.m1) * (Q + 1);
   T* tb3 = tb2 + size_t(g.m2) * (Q + 1);
@@ -377,6 +386,57 @@ __global__ void __launch_bounds__(kChunk)
     if (ND == 3) v &= mk >> (18 + d3 + P);
     return (v & 1) != 0;
   };
+  // coefficient block of the chunk: c2 in [c2lo, c2lo + n2), c3 in [c3lo, c3lo + n3)
+  int c2lo = 0, c3lo = 0, n2 = 1, n3 = 1;
+  if constexpr (STAGE) {
+    int i2a = ip.hi[1], i2b = ip.lo[1], i3a = ND == 3 ? ip.hi[2] : 0, i3b = ND == 3 ? ip.lo[2] : 0;
+    for (int k = 0; k < g.npen; ++k) {
+      const int64_t pp = pen0 + k;
+      if (pp * g.m1 >= g.N) break;
+      const int j2 = int(pp % g.m2), j3 = int(pp / g.m2);
+      if (!in_dom(ip, 1, j2) || (ND == 3 && !in_dom(ip, 2, j3))) continue;
+      i2a = min(i2a, j2);
+      i2b = max(i2b, j2);
+      i3a = min(i3a, j3);
+      i3b = max(i3b, j3);
+    }
+    const int j2lo = max(ip.lo[1], i2a - P), j2hi = min(ip.hi[1], i2b + P);
+    c2lo = tf2[j2lo];
+    n2 = tf2[j2hi] + Q + 1 - c2lo;
+    if (ND == 3) {
+      const int j3lo = max(ip.lo[2], i3a - P), j3hi = min(ip.hi[2], i3b + P);
+      c3lo = tf3[j3lo];
+      n3 = tf3[j3hi] + Q + 1 - c3lo;
+    }
+  }
+  const int nblk = n3 * n2 * S1;
+  double cs[kStage];
+  auto stage_load = [&](int u) {
+    const double* cu = coef + (size_t(b) * ip.nup + u) * per;
+#pragma unroll
+    for (int k = 0; k < kStage; ++k) {
+      const int e = tid + k * kChunk;
+      if (e < nblk) {
+        const int c1 = e % S1, r = e / S1;
+        const int l2 = r % n2, l3 = r / n2;
+        cs[k] = cu[(size_t(c3lo + l3) * S2 + c2lo + l2) * S1 + c1];
+      }
+    }
+  };
+  auto stage_store = [&](int u) {
+    double* cb = Cb + (u & 1) * blk;
+#pragma unroll
+    for (int k = 0; k < kStage; ++k) {
+      const int e = tid + k * kChunk;
+      if (e < nblk) cb[e] = cs[k];
+    }
+  };
+  if constexpr (STAGE) {
+    stage_load(0);
+    stage_store(0);
+    if (ip.nup > 1) stage_load(1);
+    __syncthreads();  // block 0 visible
+  }
   // pencil task operands (loaded one delta ahead); every thread loads a valid task
   const int tt = tid % ntask;
   const int tc1 = tt % S1;
@@ -402,12 +462,14 @@ __global__ void __launch_bounds__(kChunk)
     tj3v = j3;
     tf2v = tf2[j2];
     tf3v = ND == 3 ? tf3[j3] : 0;
-    const double* cu = coef + (size_t(b) * ip.nup + u) * per;
+    if constexpr (!STAGE) {
+      const double* cu = coef + (size_t(b) * ip.nup + u) * per;
 #pragma unroll
-    for (int a3 = 0; a3 < (ND == 3 ? Q + 1 : 1); ++a3)
+      for (int a3 = 0; a3 < (ND == 3 ? Q + 1 : 1); ++a3)
 #pragma unroll
-      for (int a2 = 0; a2 <= Q; ++a2)
-        cv[a3 * (Q + 1) + a2] = cu[(size_t(tf3v + a3) * S2 + tf2v + a2) * S1 + tc1];
+        for (int a2 = 0; a2 <= Q; ++a2)
+          cv[a3 * (Q + 1) + a2] = cu[(size_t(tf3v + a3) * S2 + tf2v + a2) * S1 + tc1];
+    }
   };
   auto row_load = [&](int u) {
     const int4 dd = dsl[u];
@@ -440,16 +502,37 @@ __global__ void __launch_bounds__(kChunk)
     {
       const T* b2 = tb2 + tj2v * (Q + 1);
       T v = T(0);
+      if constexpr (STAGE) {
+        // tasks outside the analysis domain read a clamped (valid) block entry
+        // and are zeroed below
+        const int l2 = min(max(tf2v - c2lo, 0), n2 - Q - 1);
+        const int l3 = ND == 3 ? min(max(tf3v - c3lo, 0), n3 - Q - 1) : 0;
+        const double* cb = Cb + (u & 1) * blk + (size_t(l3) * n2 + l2) * S1 + tc1;
 #pragma unroll
-      for (int a3 = 0; a3 < (ND == 3 ? Q + 1 : 1); ++a3) {
-        T r2 = T(0);
+        for (int a3 = 0; a3 < (ND == 3 ? Q + 1 : 1); ++a3) {
+          T r2 = T(0);
 #pragma unroll
-        for (int a2 = 0; a2 <= Q; ++a2) r2 += b2[a2] * T(cv[a3 * (Q + 1) + a2]);
-        v += (ND == 3 ? tb3[tj3v * (Q + 1) + a3] : T(1)) * r2;
+          for (int a2 = 0; a2 <= Q; ++a2) r2 += b2[a2] * T(cb[(a3 * n2 + a2) * S1]);
+          v += (ND == 3 ? tb3[tj3v * (Q + 1) + a3] : T(1)) * r2;
+        }
+      } else {
+#pragma unroll
+        for (int a3 = 0; a3 < (ND == 3 ? Q + 1 : 1); ++a3) {
+          T r2 = T(0);
+#pragma unroll
+          for (int a2 = 0; a2 <= Q; ++a2) r2 += b2[a2] * T(cv[a3 * (Q + 1) + a2]);
+          v += (ND == 3 ? tb3[tj3v * (Q + 1) + a3] : T(1)) * r2;
+        }
       }
       if (tid < ntask) Tu[tid] = tok ? v : T(0);
     }
     task_load(u + 1 < ip.nup ? u + 1 : u);
+    if constexpr (STAGE) {
+      // block u+1 (loaded during the previous delta) into the other buffer, whose
+      // readers finished before the previous barrier; then fetch block u+2
+      if (u + 1 < ip.nup) stage_store(u + 1);
+      if (u + 2 < ip.nup) stage_load(u + 2);
+    }
     __syncthreads();
     const bool has_lo = FORM == IGS_STIFFNESS || s != sc;
     const size_t su = size_t(s) * ld, sl = Sm1ld - size_t(s) * ld;
@@ -565,10 +648,41 @@ int fill_chunk_rows(const Dims& d, int Sd1) {
 }
 
 template <typename T>
-size_t fill_lds_bytes(const KInterp<T>& ip, int npen, const Dims& d) {
+size_t fill_lds_bytes(const KInterp<T>& ip, int npen, const Dims& d, int blk) {
   const size_t msum = size_t(d.m[0]) + d.m[1] + (d.n == 3 ? d.m[2] : 1);
-  return size_t(2) * npen * 2 * ip.Sd[0] * sizeof(T) + msum * (ip.q + 1) * sizeof(T) + (msum + 4) * 4 +
-         size_t(ip.nup) * 16;
+  return size_t(2) * blk * sizeof(double) + size_t(2) * npen * 2 * ip.Sd[0] * sizeof(T) +
+         msum * (ip.q + 1) * sizeof(T) + (msum + 4) * 4 + size_t(ip.nup) * 16;
+}
+
+// Largest coefficient block (extent in directions 2 and 3) that the pencil
+// tasks of one fill chunk read; mirrors the bounds the fast kernel computes.
+void fill_block_dims(const Dims& d, const std::vector<int> ef[3], int q, const std::vector<int>& chunks, int rows,
+                     int* n2max, int* n3max) {
+  const int p = d.p, npen = fill_npen(d, rows);
+  const int lo2 = 2 * p, hi2 = d.m[1] - 2 * p - 1;
+  const int lo3 = d.n == 3 ? 2 * p : 0, hi3 = d.n == 3 ? d.m[2] - 2 * p - 1 : 0;
+  *n2max = 1;
+  *n3max = 1;
+  for (int c : chunks) {
+    const int64_t pen0 = int64_t(c) * rows / d.m[0];
+    int i2a = hi2, i2b = lo2, i3a = hi3, i3b = lo3;
+    for (int k = 0; k < npen; ++k) {
+      const int64_t pp = pen0 + k;
+      if (pp * d.m[0] >= d.N) break;
+      const int j2 = int(pp % d.m[1]), j3 = int(pp / d.m[1]);
+      if (j2 < lo2 || j2 > hi2 || j3 < lo3 || j3 > hi3) continue;
+      i2a = std::min(i2a, j2);
+      i2b = std::max(i2b, j2);
+      i3a = std::min(i3a, j3);
+      i3b = std::max(i3b, j3);
+    }
+    const int j2lo = std::max(lo2, i2a - p), j2hi = std::min(hi2, i2b + p);
+    *n2max = std::max(*n2max, ef[1][j2hi] + q + 1 - ef[1][j2lo]);
+    if (d.n == 3) {
+      const int j3lo = std::max(lo3, i3a - p), j3hi = std::min(hi3, i3b + p);
+      *n3max = std::max(*n3max, ef[2][j3hi] + q + 1 - ef[2][j3lo]);
+    }
+  }
 }
 
 template <int ND, int FORM, typename T, bool MULTI>
@@ -592,21 +706,30 @@ static void launch_fill_m(const KInterp<T>& ip, const FillGeom& g, dim3 grid, si
     launch_fill_q<ND, FORM, T, true>(ip, g, grid, lds, coef, band, s);
 }
 
-template <int ND, int FORM, typename T>
+template <int ND, int FORM, typename T, bool STAGE>
 static void launch_fast_q(const KInterp<T>& ip, const FillGeom& g, dim3 grid, size_t lds, const int4* dsl,
                           const double* coef, T* band, hipStream_t s) {
   switch (ip.q) {
-    case 1: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 1, T>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
-    case 2: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 2, T>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
-    case 3: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 3, T>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
-    case 4: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 4, T>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
-    default: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 5, T>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
+    case 1: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 1, T, STAGE>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
+    case 2: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 2, T, STAGE>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
+    case 3: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 3, T, STAGE>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
+    case 4: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 4, T, STAGE>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
+    default: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 5, T, STAGE>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
   }
+}
+
+template <int ND, int FORM, typename T>
+static void launch_fast_s(const KInterp<T>& ip, const FillGeom& g, bool stage, dim3 grid, size_t lds,
+                          const int4* dsl, const double* coef, T* band, hipStream_t s) {
+  if (stage)
+    launch_fast_q<ND, FORM, T, true>(ip, g, grid, lds, dsl, coef, band, s);
+  else
+    launch_fast_q<ND, FORM, T, false>(ip, g, grid, lds, dsl, coef, band, s);
 }
 
 template <typename T>
 hipError_t launch_fill(const KInterp<T>& ip, int form, const Dims& d, const int* chunks, int nchunks, int chunk_rows,
-                       const int4* dsl, const double* coef, T* band, hipStream_t s) {
+                       int n2max, int n3max, const int4* dsl, const double* coef, T* band, hipStream_t s) {
   FillGeom g;
   g.n = d.n;
   g.P = d.p;
@@ -619,21 +742,27 @@ hipError_t launch_fill(const KInterp<T>& ip, int form, const Dims& d, const int*
   g.npen = fill_npen(d, chunk_rows);
   g.nchunks = nchunks;
   g.chunks = chunks;
-  const size_t lds = fill_lds_bytes<T>(ip, g.npen, d);
+  g.n2max = n2max;
+  g.n3max = n3max;
+  const bool fast = chunk_rows == kChunk * kRows;
+  const int blk = n2max * n3max * ip.Sd[0];
+  const bool stage = fast && blk <= kStage * kChunk &&
+                     fill_lds_bytes<T>(ip, g.npen, d, blk) <= 160 * 1024;
+  const size_t lds = fill_lds_bytes<T>(ip, g.npen, d, stage ? blk : 0);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (nchunks == 0) return hipSuccess;
   dim3 grid(nchunks, d.batch);
-  if (chunk_rows == kChunk * kRows) {
+  if (fast) {
     if (d.n == 3) {
       if (form == IGS_MASS)
-        launch_fast_q<3, IGS_MASS, T>(ip, g, grid, lds, dsl, coef, band, s);
+        launch_fast_s<3, IGS_MASS, T>(ip, g, stage, grid, lds, dsl, coef, band, s);
       else
-        launch_fast_q<3, IGS_STIFFNESS, T>(ip, g, grid, lds, dsl, coef, band, s);
+        launch_fast_s<3, IGS_STIFFNESS, T>(ip, g, stage, grid, lds, dsl, coef, band, s);
     } else {
       if (form == IGS_MASS)
-        launch_fast_q<2, IGS_MASS, T>(ip, g, grid, lds, dsl, coef, band, s);
+        launch_fast_s<2, IGS_MASS, T>(ip, g, stage, grid, lds, dsl, coef, band, s);
       else
-        launch_fast_q<2, IGS_STIFFNESS, T>(ip, g, grid, lds, dsl, coef, band, s);
+        launch_fast_s<2, IGS_STIFFNESS, T>(ip, g, stage, grid, lds, dsl, coef, band, s);
     }
     return hipGetLastError();
   }
@@ -651,12 +780,12 @@ hipError_t launch_fill(const KInterp<T>& ip, int form, const Dims& d, const int*
   return hipGetLastError();
 }
 
-template hipError_t launch_fill<double>(const KInterp<double>&, int, const Dims&, const int*, int, int, const int4*,
-                                        const double*, double*, hipStream_t);
-template hipError_t launch_fill<float>(const KInterp<float>&, int, const Dims&, const int*, int, int, const int4*,
-                                       const double*, float*, hipStream_t);
-template size_t fill_lds_bytes<double>(const KInterp<double>&, int, const Dims&);
-template size_t fill_lds_bytes<float>(const KInterp<float>&, int, const Dims&);
+template hipError_t launch_fill<double>(const KInterp<double>&, int, const Dims&, const int*, int, int, int, int,
+                                        const int4*, const double*, double*, hipStream_t);
+template hipError_t launch_fill<float>(const KInterp<float>&, int, const Dims&, const int*, int, int, int, int,
+                                       const int4*, const double*, float*, hipStream_t);
+template size_t fill_lds_bytes<double>(const KInterp<double>&, int, const Dims&, int);
+template size_t fill_lds_bytes<float>(const KInterp<float>&, int, const Dims&, int);
 
 template <typename T>
 hipError_t launch_zero_pad(T* band, int64_t N, int64_t ld, int slots_total, hipStream_t s) {
