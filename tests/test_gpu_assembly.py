@@ -123,6 +123,55 @@ def test_geometry_fold_reported(igs):
     assert e.value.status == -5
 
 
+# ------------------------------------------------------------------ plans ---
+@pytest.mark.parametrize("prob,form,M,q", [(W.problem(3, 3, (26, 24, 25)), 0, 4, 3), (W.problem(2, 2, 32), 1, 4, 3),
+                                           (W.problem(3, 2, 12), 0, 0, 0)])
+def test_plan_matches_one_shot(igs, prob, form, M, q):
+    """A kept plan runs the same kernels: bitwise equal to the one-shot call,
+    on its first (synchronising) and later (queue-only) executions."""
+    import torch
+
+    ref = igs.assemble_surrogate(prob, form, M=M, q=q) if M else igs.assemble_exact(prob, form)
+    plan = igs.Plan(prob, form, M=M, q=q)
+    for _ in range(3):
+        band = plan.execute()
+        torch.cuda.synchronize()
+        assert torch.equal(band, ref)
+    plan.close()
+
+
+def test_plan_coefficient_swap(igs, oracle):
+    """Executing a plan with new spline control values equals the oracle for
+    those values (the batched exp-spline coefficient of the adjoint workload)."""
+    rng = np.random.default_rng(4)
+    cc0 = rng.normal(0, 0.5, (2, 36))
+    cc1 = rng.normal(0, 0.5, (2, 36))
+    prob0 = W.problem(2, 3, 30, coef="exp_spline", cdeg=3, cn=(6, 6), cc=cc0, batch=2)
+    prob1 = W.problem(2, 3, 30, coef="exp_spline", cdeg=3, cn=(6, 6), cc=cc1, batch=2)
+    import torch
+
+    plan = igs.Plan(prob0, 0, M=4, q=3)
+    band = plan.execute(coef=torch.as_tensor(cc1, device="cuda"))
+    _, N, _ = oracle.dims(prob1)
+    for b in range(2):
+        ref = oracle.surrogate_rows(prob1, 0, 4, 3, b=b)
+        assert rel_maxnorm(_full(igs, band, prob1, b), ref) < TOL64
+    band = plan.execute()  # creation coefficients again
+    ref = oracle.surrogate_rows(prob0, 0, 4, 3, b=1)
+    assert rel_maxnorm(_full(igs, band, prob0, 1), ref) < TOL64
+    plan.close()
+
+
+def test_plan_geometry_fold(igs):
+    prob = W.problem(2, 2, 16, ga=0.5)
+    plan = igs.Plan(prob, 0, M=0, q=0)
+    for _ in range(2):
+        with pytest.raises(igs.IGSError) as e:
+            plan.execute()
+        assert e.value.status == -5
+    plan.close()
+
+
 # ------------------------------------------------------------ full sizes ---
 def _sampled(oracle, prob, M, seed, count=4096):
     _, N, _ = oracle.dims(prob)
