@@ -135,9 +135,9 @@ typedef struct igs_surrogate_info {
 
 typedef struct igs_cg_info {
   int32_t iterations;        /* total CG iterations (inner FP32 ones in mixed mode) */
-  int32_t outer_iterations;  /* inner CG solves between FP64 residual checks
-                                (1 in plain FP64 mode unless the true-residual
-                                check restarts CG) */
+  int32_t outer_iterations;  /* with an FP32 band: FP64 residual replacements;
+                                FP64 only: 1 unless the true-residual check
+                                restarts CG */
   int32_t status;            /* igs_status of the solve */
   double relres;             /* max over batch of ||f_I - A_II u_I||_2 / ||f_I||_2, FP64 */
 } igs_cg_info;
@@ -235,8 +235,11 @@ igs_status igs_apply(const igs_problem* pb, int32_t dtype, const void* band, con
 /* Conjugate gradients for A_II u_I = f_I with homogeneous Dirichlet dofs
  * (Sec. 8, eq. BlockSystem with u_D = 0), per problem of the batch.
  * band64: device FP64 band (required).  band32: optional device FP32 band of
- * the same matrix; when given, FP32 CG runs inside FP64 iterative refinement
- * (residual f - A64 u in FP64, correction from FP32 CG on A32, update in FP64).
+ * the same matrix; when given, CG iterates on A32 with FP32 vectors while the
+ * solution accumulates in FP64, and the FP32 recursive residual is replaced by
+ * the FP64 residual f - A64 u (FP64 band) whenever it has fallen tenfold since
+ * the last replacement or claims convergence: FP64 iterative refinement whose
+ * FP32 correction solves keep their search direction.
  * f: device [batch][N]; u: device [batch][N], in: initial guess (Dirichlet
  * entries ignored), out: solution with u_D = 0.  Stops when the FP64 residual
  * satisfies ||f_I - A_II u_I||_2 <= rtol ||f_I||_2 for every problem, or after

@@ -101,6 +101,139 @@ __global__ void __launch_bounds__(kSpmvBlock)
   }
 }
 
+// Per-problem scalars, kept on the device between kernels.
+struct CgScalars {
+  double rr;      // r^T r
+  double alpha, beta;
+  double tol2;    // stop when rr <= tol2
+  double rr_ref;  // residual replacement: |f - A u|^2 at the last replacement
+  int done;       // converged or broken down
+  int breakdown;
+  int iters;
+  int replace;    // residual replacement due after this iteration
+  int nrep;       // replacements made
+  int pad;
+};
+
+// FP32 band: half the bytes of FP64, so the SpMV would be bound by vector
+// memory instructions (one band and one x load per slot and row) rather than
+// by HBM.  Here each thread owns two consecutive rows (8-byte band loads) and
+// the block's x values are staged in LDS once per (delta2, delta3) run: row
+// r of the block needs x[r + off(delta2, delta3) + delta1], delta1 in [-P, P],
+// i.e. for each run a contiguous window of kS32Rows + 2P values.
+// MODE 0: y = A x, optional Dirichlet mask.  MODE 1: the CG step q = A p with
+// Dirichlet rows zero, skipping finished problems and writing per-block
+// partials of p^T q.
+constexpr int kS32Threads = 128;
+constexpr int kS32Rows = 2 * kS32Threads;
+static_assert(kS32Rows == kSpmvBlock, "CG partial buffers assume kSpmvBlock rows per block");
+
+template <int P, int ND, int MODE>
+__global__ void __launch_bounds__(kS32Threads)
+    spmv32_kernel(SpmvGeom g, const float* __restrict__ band, const float* __restrict__ x, float* __restrict__ y,
+                  int mask, const CgScalars* __restrict__ sc, double* __restrict__ part) {
+  constexpr int W = 2 * P + 1;
+  constexpr int NPL = ND == 3 ? W * W : W;         // (delta2, delta3) runs
+  constexpr int XP = (kS32Rows + 2 * P + 3) & ~3;  // LDS row pitch (floats)
+  __shared__ float xs[NPL * XP];
+  const int b = blockIdx.y;
+  if (MODE == 1 && sc[b].done) return;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t i0 = int64_t(lb) * kS32Rows;
+  const float* xb = x + size_t(b) * g.N;
+  const float* bb = band + size_t(b) * g.S * g.ld;
+  const int64_t m1 = g.m[0], m12 = int64_t(g.m[0]) * g.m[1];
+  const int tid = threadIdx.x;
+  for (int k = 0; k < NPL; ++k) {
+    const int d2 = (ND == 3 ? k % W : k) - P, d3 = ND == 3 ? k / W - P : 0;
+    const int64_t base = i0 + d2 * m1 + d3 * m12 - P;
+    for (int t = tid; t < kS32Rows + 2 * P; t += kS32Threads) {
+      const int64_t j = base + t;
+      xs[k * XP + t] = (j >= 0 && j < g.N) ? xb[j] : 0.0f;
+    }
+  }
+  __syncthreads();
+  const int64_t r0 = i0 + 2 * tid;
+  float a0 = 0.0f, a1 = 0.0f;
+  if (r0 < g.N) {
+    const bool two = r0 + 1 < g.N;
+#pragma unroll 7
+    for (int k = 0; k < NPL; ++k) {
+      float xw[2 * P + 2];
+      const float2* xp = reinterpret_cast<const float2*>(xs + k * XP + 2 * tid);
+#pragma unroll
+      for (int e = 0; e < P + 1; ++e) {
+        const float2 v = xp[e];
+        xw[2 * e] = v.x;
+        xw[2 * e + 1] = v.y;
+      }
+      const float* bk = bb + size_t(k) * W * g.ld + r0;
+#pragma unroll
+      for (int d1 = 0; d1 < W; ++d1) {
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        f2v bv;
+        if (two) {
+          bv = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(bk + size_t(d1) * g.ld));
+        } else {
+          bv.x = bk[size_t(d1) * g.ld];
+          bv.y = 0.0f;
+        }
+        a0 += bv.x * xw[d1];
+        a1 += bv.y * xw[d1 + 1];
+      }
+    }
+  }
+  double dp = 0.0;
+  const int kc = ND == 3 ? P + W * P : P;  // the run with delta2 = delta3 = 0
+  if (r0 < g.N) {
+    if (MODE == 1 || mask) {
+      if (on_dirichlet(g, r0)) a0 = 0.0f;
+      if (r0 + 1 < g.N && on_dirichlet(g, r0 + 1)) a1 = 0.0f;
+    }
+    float* yb = y + size_t(b) * g.N;
+    yb[r0] = a0;
+    if (r0 + 1 < g.N) yb[r0 + 1] = a1;
+    if (MODE == 1) {
+      dp = double(a0) * double(xs[kc * XP + 2 * tid + P]);
+      if (r0 + 1 < g.N) dp += double(a1) * double(xs[kc * XP + 2 * tid + P + 1]);
+    }
+  }
+  if (MODE == 1) {
+    __shared__ double red[kS32Threads];
+    red[tid] = dp;
+    __syncthreads();
+    for (int w = kS32Threads / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0) part[size_t(b) * gridDim.x + lb] = red[0];
+  }
+}
+
+template <int MODE>
+static void launch_spmv32(const SpmvGeom& g, int nblk, int batch, const float* band, const float* x, float* y,
+                          int mask, const CgScalars* sc, double* part, hipStream_t s) {
+  const dim3 grid(nblk, batch), block(kS32Threads);
+#define IGS_SPMV32(PP, NDD) \
+  hipLaunchKernelGGL((spmv32_kernel<PP, NDD, MODE>), grid, block, 0, s, g, band, x, y, mask, sc, part)
+  if (g.n == 3) {
+    switch (g.p) {
+      case 1: IGS_SPMV32(1, 3); break;
+      case 2: IGS_SPMV32(2, 3); break;
+      case 3: IGS_SPMV32(3, 3); break;
+      default: IGS_SPMV32(4, 3); break;
+    }
+  } else {
+    switch (g.p) {
+      case 1: IGS_SPMV32(1, 2); break;
+      case 2: IGS_SPMV32(2, 2); break;
+      case 3: IGS_SPMV32(3, 2); break;
+      default: IGS_SPMV32(4, 2); break;
+    }
+  }
+#undef IGS_SPMV32
+}
+
 // x with its Dirichlet dofs zeroed (the restriction of igs_apply)
 template <typename T>
 __global__ void mask_copy_kernel(SpmvGeom g, int batch, const T* __restrict__ x, T* __restrict__ y) {
@@ -111,16 +244,6 @@ __global__ void mask_copy_kernel(SpmvGeom g, int batch, const T* __restrict__ x,
 
 // --------------------------------------------------------------- CG state --
 
-// Per-problem scalars, kept on the device between kernels.
-struct CgScalars {
-  double rr;      // r^T r
-  double alpha, beta;
-  double tol2;    // stop when rr <= tol2
-  int done;       // converged or broken down
-  int breakdown;
-  int iters;
-  int pad;
-};
 
 template <typename T>
 __device__ __forceinline__ double block_sum(double v) {
@@ -192,6 +315,9 @@ __global__ void cg_setup_kernel(int batch, const double* __restrict__ rr, const 
   s.done = (!active[b] || s.rr <= s.tol2) ? 1 : 0;
   s.breakdown = 0;
   s.iters = 0;
+  s.rr_ref = s.rr;
+  s.replace = 0;
+  s.nrep = 0;
   s.pad = 0;
   sc[b] = s;
 }
@@ -322,8 +448,11 @@ igs_status launch_apply_t(const Dims& d, const T* band, const T* x, T* y, int di
   }
   {
     PhaseTimer t("spmv", s);
-    hipLaunchKernelGGL((spmv_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band, xin, y, dirichlet,
-                       nullptr, nullptr);
+    if constexpr (sizeof(T) == 4)
+      launch_spmv32<0>(g, nblk, d.batch, band, xin, y, dirichlet, nullptr, nullptr, s);
+    else
+      hipLaunchKernelGGL((spmv_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band, xin, y, dirichlet,
+                         nullptr, nullptr);
   }
   HIP_OK(hipGetLastError());
   return IGS_OK;
@@ -403,8 +532,11 @@ static igs_status inner_cg(const Dims& d, const T* band, const SolveBufs& sb, T*
     for (int it = 0; it < k; ++it) {
       {
         PhaseTimer t(sizeof(T) == 8 ? "cg_spmv_f64" : "cg_spmv_f32", s);
-        hipLaunchKernelGGL((cg_spmv_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band, p, q, sb.sc,
-                           sb.part);
+        if constexpr (sizeof(T) == 4)
+          launch_spmv32<1>(g, nblk, d.batch, band, p, q, 1, sb.sc, sb.part, s);
+        else
+          hipLaunchKernelGGL((cg_spmv_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band, p, q, sb.sc,
+                             sb.part);
       }
       PhaseTimer t("cg_vector_ops", s);
       hipLaunchKernelGGL(cg_alpha_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
@@ -523,10 +655,221 @@ static igs_status refine_loop(const Dims& d, const double* band64, const T* band
   return result;
 }
 
+// ---------------------------------- FP32 CG with FP64 residual replacement --
+//
+// Mixed-precision CG that keeps its Krylov space: the iteration runs on the
+// FP32 band with FP32 vectors, the solution u accumulates in FP64, and when
+// the FP32 recursive residual has fallen by kReplace^2 since the last
+// replacement (or claims convergence) it is replaced by the FP64 residual
+// f - A64 u of the FP64 band.  Convergence is decided on those FP64 residuals
+// only.  (An FP64 iterative refinement whose correction solves are not
+// restarted: the search direction survives each correction.)
+constexpr double kReplace = 0.1;
+
+// r32 = float(r64), p = r32
+__global__ void rc_init_kernel(int64_t total, const double* __restrict__ r64, float* __restrict__ r32,
+                               float* __restrict__ p) {
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const float v = float(r64[t]);
+    r32[t] = v;
+    p[t] = v;
+  }
+}
+
+// u += alpha p (FP64), r -= alpha q (FP32), partial |r|^2 (FP64 sums)
+__global__ void __launch_bounds__(kSpmvBlock)
+    rc_update_kernel(int64_t N, const CgScalars* __restrict__ sc, const float* __restrict__ p,
+                     const float* __restrict__ q, double* __restrict__ u, float* __restrict__ r,
+                     double* __restrict__ part) {
+  const int b = blockIdx.y;
+  if (sc[b].done) return;
+  const double alpha = sc[b].alpha;
+  const float af = float(alpha);
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
+  double v = 0.0;
+  if (i < N) {
+    const size_t k = size_t(b) * N + i;
+    u[k] += alpha * double(p[k]);
+    const float rn = r[k] - af * q[k];
+    r[k] = rn;
+    v = double(rn) * double(rn);
+  }
+  v = block_sum<double>(v);
+  if (threadIdx.x == 0) part[size_t(b) * gridDim.x + lb] = v;
+}
+
+// beta = rr_new / rr, or schedule a replacement (beta then comes from the
+// replaced residual)
+__global__ void __launch_bounds__(kRedBlock) rc_beta_kernel(const double* __restrict__ part, int nblk, CgScalars* sc) {
+  const int b = blockIdx.x;
+  if (sc[b].done) return;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += kRedBlock) s += part[size_t(b) * nblk + k];
+  s = block_sum<double>(s);
+  if (threadIdx.x == 0) {
+    if (!isfinite(s)) {
+      sc[b].done = 1;
+      sc[b].breakdown = 1;
+    } else if (s <= kReplace * kReplace * sc[b].rr_ref || s <= sc[b].tol2) {
+      sc[b].replace = 1;
+    } else {
+      sc[b].beta = s / sc[b].rr;
+      sc[b].rr = s;
+      sc[b].iters += 1;
+    }
+  }
+}
+
+// r64 = f - A64 u on problems with a replacement due; r32 = float(r64);
+// partial |r64|^2
+__global__ void __launch_bounds__(kSpmvBlock)
+    rc_residual_kernel(SpmvGeom g, const double* __restrict__ band, const double* __restrict__ f,
+                       const double* __restrict__ u, float* __restrict__ r32, const CgScalars* __restrict__ sc,
+                       double* __restrict__ part) {
+  const int b = blockIdx.y;
+  if (sc[b].done || !sc[b].replace) return;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
+  double rv = 0.0;
+  if (i < g.N && !on_dirichlet(g, i))
+    rv = f[size_t(b) * g.N + i] - row_product<double>(g, band + size_t(b) * g.S * g.ld, u + size_t(b) * g.N, i);
+  if (i < g.N) r32[size_t(b) * g.N + i] = float(rv);
+  const double a = block_sum<double>(rv * rv);
+  if (threadIdx.x == 0) part[size_t(b) * gridDim.x + lb] = a;
+}
+
+__global__ void __launch_bounds__(kRedBlock) rc_replace_kernel(const double* __restrict__ part, int nblk,
+                                                               CgScalars* sc) {
+  const int b = blockIdx.x;
+  if (sc[b].done || !sc[b].replace) return;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += kRedBlock) s += part[size_t(b) * nblk + k];
+  s = block_sum<double>(s);
+  if (threadIdx.x == 0) {
+    sc[b].replace = 0;
+    sc[b].nrep += 1;
+    sc[b].iters += 1;
+    if (!isfinite(s)) {
+      sc[b].done = 1;
+      sc[b].breakdown = 1;
+    } else {
+      sc[b].beta = s / sc[b].rr;
+      sc[b].rr = s;
+      sc[b].rr_ref = s;
+      if (s <= sc[b].tol2) sc[b].done = 1;
+    }
+  }
+}
+
+static igs_status replace_cg(const Dims& d, const double* band64, const float* band32, const double* f, double* u,
+                             double rtol, int maxit, igs_cg_info* info, hipStream_t s) {
+  SpmvGeom g = make_geom(d);
+  const int nblk = int((d.N + kSpmvBlock - 1) / kSpmvBlock);
+  const size_t NB = size_t(d.N) * d.batch;
+  const size_t nb = size_t(d.batch);
+  Arena ar;
+  size_t bytes = padded(sizeof(double) * NB) + 2 * padded(sizeof(double) * nb * nblk) + 4 * padded(sizeof(double) * nb) +
+                 padded(sizeof(int) * nb) + padded(sizeof(CgScalars) * nb) + 3 * padded(sizeof(float) * NB);
+  igs_status st = ar.alloc(bytes, s);
+  if (st != IGS_OK) return st;
+  SolveBufs sb;
+  sb.r64 = ar.take<double>(NB);
+  sb.part = ar.take<double>(nb * nblk);
+  sb.part2 = ar.take<double>(nb * nblk);
+  sb.rr = ar.take<double>(nb);
+  sb.ff = ar.take<double>(nb);
+  sb.scale = ar.take<double>(nb);
+  sb.tol2 = ar.take<double>(nb);
+  sb.active = ar.take<int>(nb);
+  sb.sc = ar.take<CgScalars>(nb);
+  float* r32 = ar.take<float>(NB);
+  float* p = ar.take<float>(NB);
+  float* q = ar.take<float>(NB);
+
+  // initial FP64 residual
+  hipLaunchKernelGGL(zero_dirichlet_kernel, dim3(grid_stride_blocks(NB)), dim3(256), 0, s, g, d.batch, u);
+  auto true_residual = [&](std::vector<double>* rr, std::vector<double>* ff) -> igs_status {
+    {
+      PhaseTimer t("residual_f64", s);
+      hipLaunchKernelGGL(residual_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band64, f, u, sb.r64,
+                         sb.part, sb.part2);
+    }
+    hipLaunchKernelGGL(reduce_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.rr);
+    hipLaunchKernelGGL(reduce_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part2, nblk, sb.ff);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(rr->data(), sb.rr, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(ff->data(), sb.ff, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return IGS_OK;
+  };
+  std::vector<double> rr(nb), ff(nb), tol2(nb);
+  std::vector<int> active(nb);
+  st = true_residual(&rr, &ff);
+  if (st != IGS_OK) return st;
+  for (size_t b = 0; b < nb; ++b) {
+    tol2[b] = rtol * rtol * ff[b];
+    active[b] = rr[b] > tol2[b];
+  }
+  HIP_OK(hipMemcpyAsync(sb.tol2, tol2.data(), sizeof(double) * nb, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(sb.active, active.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(rc_init_kernel, dim3(grid_stride_blocks(NB)), dim3(256), 0, s, int64_t(NB), sb.r64, r32, p);
+  hipLaunchKernelGGL(cg_setup_kernel, dim3(1), dim3(64), 0, s, d.batch, sb.rr, sb.tol2, sb.active, sb.sc);
+  HIP_OK(hipGetLastError());
+
+  std::vector<CgScalars> hsc(nb);
+  const int chunk = 32;
+  int done_iters = 0;
+  while (done_iters < maxit) {
+    const int k = std::min(chunk, maxit - done_iters);
+    for (int it = 0; it < k; ++it) {
+      {
+        PhaseTimer t("cg_spmv_f32", s);
+        launch_spmv32<1>(g, nblk, d.batch, band32, p, q, 1, sb.sc, sb.part, s);
+      }
+      PhaseTimer t("cg_vector_ops", s);
+      hipLaunchKernelGGL(cg_alpha_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
+      hipLaunchKernelGGL(rc_update_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, sb.sc, p, q, u, r32,
+                         sb.part2);
+      hipLaunchKernelGGL(rc_beta_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part2, nblk, sb.sc);
+      hipLaunchKernelGGL(rc_residual_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band64, f, u, r32,
+                         sb.sc, sb.part);
+      hipLaunchKernelGGL(rc_replace_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
+      hipLaunchKernelGGL((cg_pupdate_kernel<float>), dim3(std::min<int64_t>((d.N + 255) / 256, 4096), d.batch),
+                         dim3(256), 0, s, d.N, sb.sc, r32, p);
+    }
+    HIP_OK(hipGetLastError());
+    done_iters += k;
+    HIP_OK(hipMemcpyAsync(hsc.data(), sb.sc, sizeof(CgScalars) * nb, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    bool all = true;
+    for (size_t b = 0; b < nb; ++b) all &= hsc[b].done != 0;
+    if (all) break;
+  }
+  // report the FP64 residual of the returned solution
+  st = true_residual(&rr, &ff);
+  if (st != IGS_OK) return st;
+  double worst = 0.0;
+  bool breakdown = false;
+  int iters = 0, nrep = 0;
+  for (size_t b = 0; b < nb; ++b) {
+    const double rel = ff[b] > 0.0 ? std::sqrt(rr[b] / ff[b]) : 0.0;
+    worst = std::isfinite(rel) ? std::max(worst, rel) : rel;
+    breakdown |= hsc[b].breakdown != 0;
+    iters = std::max(iters, hsc[b].iters);
+    nrep = std::max(nrep, hsc[b].nrep);
+  }
+  info->iterations = iters;
+  info->outer_iterations = nrep;
+  info->relres = worst;
+  igs_status result = (std::isfinite(worst) && worst <= rtol) ? IGS_OK : (breakdown ? IGS_BREAKDOWN : IGS_NOT_CONVERGED);
+  info->status = result;
+  return result;
+}
+
 igs_status solve_cg(const Dims& d, const double* band64, const float* band32, const double* f, double* u, double rtol,
                     int maxit, igs_cg_info* info, hipStream_t s) {
-  if (band32)
-    return refine_loop<float>(d, band64, band32, f, u, rtol, maxit, 1e-4, info, s);
+  if (band32) return replace_cg(d, band64, band32, f, u, rtol, maxit, info, s);
   return refine_loop<double>(d, band64, band64, f, u, rtol, maxit, 0.0, info, s);
 }
 

@@ -30,13 +30,14 @@ def test_rhs(igs, oracle, prob, src, c):
     assert rel_maxnorm(f[0].cpu().numpy(), ref) < 1e-13
 
 
-@pytest.mark.parametrize("prob", [W.problem(2, 3, 41), W.problem(3, 3, (20, 19, 21)), W.problem(3, 2, 17)])
+@pytest.mark.parametrize("prob", [W.problem(2, 3, 41), W.problem(3, 3, (20, 19, 21)), W.problem(3, 2, 17),
+                                  W.problem(2, 1, 50), W.problem(3, 4, 9), W.problem(3, 1, (30, 7, 9))])
 @pytest.mark.parametrize("dirichlet", [False, True])
 def test_apply(igs, oracle, prob, dirichlet):
     import torch
 
     _, N, _ = oracle.dims(prob)
-    band = igs.assemble_surrogate(prob, 0, M=3, q=3)
+    band = igs.assemble_exact(prob, 0)
     rows = igs.band_rows(band, prob)
     x = W.random_vector(N, 9)
     y = igs.apply(prob, band, torch.as_tensor(x, device="cuda"), dirichlet=dirichlet)
@@ -89,6 +90,33 @@ def test_cg_batched(igs, oracle):
         rows = igs.band_rows(band, prob, b)
         uref, _, _ = oracle.cg(prob, rows, f[b].cpu().numpy(), rtol=1e-13)
         assert rel_maxnorm(u[b].cpu().numpy(), uref) < 1e-8
+
+
+def test_cg_mixed_batched(igs, oracle):
+    """FP32 CG with FP64 residual replacement on a batch: every problem reaches
+    the FP64 tolerance and the FP64 solution."""
+    import torch
+
+    prob = W.c5_adjoint2d(nelem=40, batch=3, cn=8)
+    band = igs.assemble_surrogate(prob, 0, M=4, q=3)
+    b32 = igs.assemble_surrogate(prob, 0, M=4, q=3, dtype=torch.float32)
+    f = igs.assemble_rhs(prob, 0, 1.0)
+    u, info = igs.solve_cg(prob, band, f, band32=b32, rtol=1e-11)
+    assert info["status"] == 0 and info["relres"] <= 1e-11
+    for b in range(3):
+        rows = igs.band_rows(band, prob, b)
+        uref, _, _ = oracle.cg(prob, rows, f[b].cpu().numpy(), rtol=1e-13)
+        assert rel_maxnorm(u[b].cpu().numpy(), uref) < 1e-8
+
+
+def test_cg_mixed_not_converged(igs):
+    import torch
+
+    prob = W.c1_poisson2d()
+    band = igs.assemble_exact(prob, 0)
+    f = igs.assemble_rhs(prob, 0, 1.0)
+    u, info = igs.solve_cg(prob, band, f, band32=band.float(), rtol=1e-10, maxit=3, check=False)
+    assert info["status"] == 1 and info["iterations"] <= 3 and info["relres"] > 1e-10
 
 
 def test_cg_not_converged(igs):
