@@ -355,11 +355,15 @@ __global__ void __launch_bounds__(kChunk)
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int64_t i = c0 + tid + int64_t(r) * kChunk;
-    live[r] = i < g.N;
-    const int64_t pen = live[r] ? i / g.m1 : pen0;
-    const int i1 = live[r] ? int(i - pen * g.m1) : 0;
+    const int64_t pen = i < g.N ? i / g.m1 : pen0;
+    const int i1 = i < g.N ? int(i - pen * g.m1) : 0;
     const int i2 = int(pen % g.m2), i3 = int(pen / g.m2);
-    inner[r] = live[r] && in_dom(ip, 0, i1) && in_dom(ip, 1, i2) && (ND == 2 || in_dom(ip, 2, i3));
+    // rows of pencils outside the analysis domain in (i2, i3) are left to the
+    // quadrature (whole pencils: their lines are not shared with domain rows
+    // except at the two ends of a run of domain pencils); rows of domain
+    // pencils outside it in i1 share lines and are stored back
+    live[r] = i < g.N && in_dom(ip, 1, i2) && (ND == 2 || in_dom(ip, 2, i3));
+    inner[r] = live[r] && in_dom(ip, 0, i1);
     i1r[r] = i1;
     kr[r] = int(pen - pen0);
     irow[r] = live[r] ? size_t(i) : size_t(g.ld - 1);

@@ -820,7 +820,7 @@ __global__ void __launch_bounds__(256)
   using C = Q3R<P, FORM>;
   constexpr int NQ = C::NQ, W = C::W, NQR = C::NQR;
   __shared__ double Cs[C::NC * C::CS];
-  __shared__ double Ys[C::NY][W][NQR];
+  __shared__ double Ys[C::NY][W][NQR + 1];  // odd row pitch: the delta1 rows of a stage-2 read use distinct banks
 
   const QTile tile = tiles[blockIdx.x];
   const int b = blockIdx.y;
