@@ -69,7 +69,7 @@ static igs_status prepare(const igs_problem* pb, hipStream_t s, Prepared* P) {
   size_t bytes = padded(sizeof(int));
   for (int k = 0; k < P->d.n; ++k)
     bytes += vbytes(P->ht.x[k]) + vbytes(P->ht.w[k]) + vbytes(P->ht.bv[k]) + vbytes(P->ht.bd[k]) +
-             vbytes(P->ht.bvd[k]) + vbytes(P->ht.trig[k]) + vbytes(P->ht.cb[k]) + vbytes(P->ht.cf[k]);
+             vbytes(P->ht.bpr[k]) + vbytes(P->ht.trig[k]) + vbytes(P->ht.cb[k]) + vbytes(P->ht.cf[k]);
   st = P->ar.alloc(bytes, s);
   if (st != IGS_OK) return st;
   KProblem& kp = P->kp;
@@ -105,7 +105,7 @@ static igs_status prepare(const igs_problem* pb, hipStream_t s, Prepared* P) {
     kp.t[k].w = upload(P->ar, P->ht.w[k], s, &st);
     kp.t[k].bv = upload(P->ar, P->ht.bv[k], s, &st);
     kp.t[k].bd = upload(P->ar, P->ht.bd[k], s, &st);
-    kp.t[k].bvd = upload(P->ar, P->ht.bvd[k], s, &st);
+    kp.t[k].bpr = upload(P->ar, P->ht.bpr[k], s, &st);
     kp.t[k].trig = upload(P->ar, P->ht.trig[k], s, &st);
     kp.t[k].cb = upload(P->ar, P->ht.cb[k], s, &st);
     kp.t[k].cf = upload(P->ar, P->ht.cf[k], s, &st);

@@ -24,7 +24,8 @@ struct Tab1D {
   const double* w;     // [Q]       Gauss weight * h/2
   const double* bv;    // [Q][p+1]  b_{e+a}(x_g)
   const double* bd;    // [Q][p+1]  b'_{e+a}(x_g)
-  const double* bvd;   // [Q][p+1][2] (b, b') pairs of the same values
+  const double* bpr;   // [Q][p+1][p+1][4] products of functions e+a, e+b:
+                       //   b_a b_b, b_a b'_b, b'_a b_b, b'_a b'_b
   const double* trig;  // [Q][4]    sin(pi x), pi cos(pi x), sin(2 pi x), 2 pi cos(2 pi x)
   const double* cb;    // [Q][cdeg+1] coefficient-spline basis values (spline kinds)
   const int* cf;       // [Q]       first coefficient-spline function alive at x_g
@@ -84,7 +85,7 @@ igs_status make_dims(const igs_problem* pb, Dims* d);
 
 struct HostTables {
   // per direction, flattened as in Tab1D
-  std::vector<double> x[3], w[3], bv[3], bd[3], bvd[3], trig[3], cb[3];
+  std::vector<double> x[3], w[3], bv[3], bd[3], bpr[3], trig[3], cb[3];
   std::vector<int> cf[3];
 };
 

@@ -199,7 +199,7 @@ void build_tables(const igs_problem* pb, const Dims& d, HostTables* t) {
     t->w[k].resize(Q);
     t->bv[k].resize(size_t(Q) * np1);
     t->bd[k].resize(size_t(Q) * np1);
-    t->bvd[k].resize(size_t(Q) * np1 * 2);
+    t->bpr[k].resize(size_t(Q) * np1 * np1 * 4);
     t->trig[k].resize(size_t(Q) * 4);
     std::vector<double> ck;
     int cne = 0;
@@ -219,9 +219,17 @@ void build_tables(const igs_problem* pb, const Dims& d, HostTables* t) {
         t->x[k][qi] = x;
         t->w[k][qi] = 0.5 * h * gw[g];
         span_basis_d(knots, e + d.p, d.p, x, &t->bv[k][size_t(qi) * np1], &t->bd[k][size_t(qi) * np1]);
-        for (int a = 0; a < np1; ++a) {
-          t->bvd[k][(size_t(qi) * np1 + a) * 2] = t->bv[k][size_t(qi) * np1 + a];
-          t->bvd[k][(size_t(qi) * np1 + a) * 2 + 1] = t->bd[k][size_t(qi) * np1 + a];
+        {
+          const double* v = &t->bv[k][size_t(qi) * np1];
+          const double* dv = &t->bd[k][size_t(qi) * np1];
+          for (int a = 0; a < np1; ++a)
+            for (int c = 0; c < np1; ++c) {
+              double* o = &t->bpr[k][((size_t(qi) * np1 + a) * np1 + c) * 4];
+              o[0] = v[a] * v[c];
+              o[1] = v[a] * dv[c];
+              o[2] = dv[a] * v[c];
+              o[3] = dv[a] * dv[c];
+            }
         }
         t->trig[k][qi * 4 + 0] = std::sin(kPi * x);
         t->trig[k][qi * 4 + 1] = kPi * std::cos(kPi * x);

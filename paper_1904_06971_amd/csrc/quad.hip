@@ -644,6 +644,11 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
   constexpr int NQ = C::NQ, W = C::W, TX = C::TX, NQ2 = C::NQ2, YL = C::YL;
   __shared__ double Cs[C::NC * C::CS];
   __shared__ double2 Ys[C::NPAIR * NQ2 * YL];
+  // work counters: [0] stage-1 tasks, [1] phase-A passes of 64 points.  Waves
+  // take the next item as they finish one, so that waves with less stage-2
+  // work (large |delta2|) absorb more geometry points and the heavier stage-1
+  // tasks (listed first) do not pile up on one SIMD.
+  __shared__ int qctr[2];
 
   const QTile tile = tiles[blockIdx.x];
   const int b = blockIdx.y;
@@ -673,8 +678,17 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
 #pragma unroll
     for (int d = 0; d < W; ++d) acc[a][d] = 0.0;
 
+  // next item of counter c for the whole wave (lane 0 takes it)
+  auto fetch = [&](int c) {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(&qctr[c], 1);
+    return __builtin_amdgcn_readfirstlane(v);
+  };
   auto phase_a = [&](int g3) {
-    for (int t = tid; t < nq1 * nq2; t += C::BLOCK) {
+    const int npt = nq1 * nq2;
+    for (int pass = fetch(1); pass * 64 < npt; pass = fetch(1)) {
+      const int t = pass * 64 + lane;
+      if (t >= npt) continue;
       const int l1 = t / nq2, l2 = t - l1 * nq2;
       const int g[3] = {E1a * NQ + l1, E2a * NQ + l2, g3};
       double v[C::NC];
@@ -685,7 +699,7 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
   };
   auto stage1 = [&]() {
     double* Ysd = reinterpret_cast<double*>(Ys);
-    for (int task = wave; task < C::NMODE * TX; task += C::NWAVE) {
+    for (int task = fetch(0); task < C::NMODE * TX; task = fetch(0)) {
       const int mode = task / TX, rr1 = task - mode * TX;
       if (rr1 >= tile.nx) continue;
       if (!C::STIFF || mode == S1_VV)
@@ -714,39 +728,47 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
 
   const int Elo = max(0, tile.z0 - P), Ehi = min(nel3 - 1, tile.z1 - 1);
   const int g0 = Elo * NQ, glast = Ehi * NQ + NQ - 1;
+  if (tid == 0) qctr[0] = qctr[1] = 0;
+  __syncthreads();
   phase_a(g0);
   __syncthreads();
 
   for (int g3 = g0; g3 <= glast; ++g3) {
     const int e3 = g3 / NQ, k3 = g3 - e3 * NQ;
     stage1();
+    // the phase-A counter is idle in this interval (its last use ended at the
+    // previous barrier), the stage-1 counter in the next one
+    if (tid == 0) qctr[1] = 0;
     __syncthreads();
+    if (tid == 0) qctr[0] = 0;
     if (active) {
       // the overlap of the supports of i2 and j2 = i2 + delta2: elements
-      // i2 - a2 with partner index b2 = a2 + delta2 in [0, P]; per point two
-      // scalar loads bring (value, derivative) of the functions i2 and j2
+      // i2 - a2 with partner index b2 = a2 + delta2 in [0, P]; per point one
+      // scalar load brings the four products (value/derivative of i2 times
+      // value/derivative of j2), each then a single FMA operand
       double Z00 = 0.0, Z10 = 0.0, Z01 = 0.0, Z11 = 0.0;
-      cdptr tab2 = uniform_table(kp.t[1].bvd);
+      constexpr int PP = (P + 1) * (P + 1) * 4;  // product-table doubles per point
+      cdptr tab2 = uniform_table(kp.t[1].bpr);
 #pragma unroll
       for (int a2 = 0; a2 <= P; ++a2) {
         const int e2 = i2 - a2;
         const int b2 = a2 + d2 - P;
         if (e2 < 0 || e2 >= nel2 || b2 < 0 || b2 > P) continue;
-        cdptr row = tab2 + size_t(e2) * NQ * 2 * (P + 1);
+        cdptr row = tab2 + size_t(e2) * NQ * PP + (a2 * (P + 1) + b2) * 4;
         const double2* yp = Ys + (e2 - E2a) * NQ * YL + lane;
 #pragma unroll 2
         for (int k2 = 0; k2 < NQ; ++k2) {
-          cdptr rk = row + k2 * 2 * (P + 1);
-          const double vi = rk[2 * a2], di = rk[2 * a2 + 1], vj = rk[2 * b2], dj = rk[2 * b2 + 1];
+          cdptr rk = row + k2 * PP;
+          const double vv = rk[0], vd = rk[1], dv = rk[2], dd = rk[3];
           const double2* yk = yp + k2 * YL;
           if constexpr (C::STIFF) {
             const double2 p0 = yk[0], p1 = yk[NQ2 * YL], p2 = yk[2 * NQ2 * YL], p3 = yk[3 * NQ2 * YL];
-            Z00 += vi * (vj * p0.x + dj * p0.y) + di * (vj * p1.y + dj * p2.y);
-            Z10 += vi * (vj * p2.x + dj * p3.x);
-            Z01 += vj * (vi * p1.x + di * p3.x);
-            Z11 += vi * vj * p3.y;
+            Z00 += vv * p0.x + vd * p0.y + dv * p1.y + dd * p2.y;
+            Z10 += vv * p2.x + vd * p3.x;
+            Z01 += vv * p1.x + dv * p3.x;
+            Z11 += vv * p3.y;
           } else {
-            Z00 += vi * vj * yk[0].x;
+            Z00 += vv * yk[0].x;
           }
         }
       }
