@@ -761,14 +761,20 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
           cdptr rk = row + k2 * PP;
           const double vv = rk[0], vd = rk[1], dv = rk[2], dd = rk[3];
           const double2* yk = yp + k2 * YL;
+          // chained FMAs into the accumulators (one instruction per product)
           if constexpr (C::STIFF) {
             const double2 p0 = yk[0], p1 = yk[NQ2 * YL], p2 = yk[2 * NQ2 * YL], p3 = yk[3 * NQ2 * YL];
-            Z00 += vv * p0.x + vd * p0.y + dv * p1.y + dd * p2.y;
-            Z10 += vv * p2.x + vd * p3.x;
-            Z01 += vv * p1.x + dv * p3.x;
-            Z11 += vv * p3.y;
+            Z00 = fma(vv, p0.x, Z00);
+            Z00 = fma(vd, p0.y, Z00);
+            Z00 = fma(dv, p1.y, Z00);
+            Z00 = fma(dd, p2.y, Z00);
+            Z10 = fma(vv, p2.x, Z10);
+            Z10 = fma(vd, p3.x, Z10);
+            Z01 = fma(vv, p1.x, Z01);
+            Z01 = fma(dv, p3.x, Z01);
+            Z11 = fma(vv, p3.y, Z11);
           } else {
-            Z00 += vv * yk[0].x;
+            Z00 = fma(vv, yk[0].x, Z00);
           }
         }
       }
@@ -786,10 +792,9 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
         }
 #pragma unroll
         for (int a3 = 0; a3 <= P; ++a3) {
-          if constexpr (C::STIFF)
-            acc[a3][b3 - a3 + P] += v3[a3] * U + t3[a3] * V;
-          else
-            acc[a3][b3 - a3 + P] += v3[a3] * U;
+          double& w = acc[a3][b3 - a3 + P];
+          w = fma(v3[a3], U, w);
+          if constexpr (C::STIFF) w = fma(t3[a3], V, w);
         }
       }
     }
