@@ -23,6 +23,10 @@
  *   band[b][s][i] = A_{i, i+delta_s}; it is 0 when i+delta_s leaves the index
  *   box.  Padding k in [N, ld) is written as 0.
  * - Vectors are [batch][N], contiguous.
+ * - Band pointers passed to igs_apply and igs_solve_cg are aligned to 16
+ *   bytes (FP64) or 8 bytes (FP32), as every device allocation is: their
+ *   kernels read two consecutive rows of a slot with one load.  Others are
+ *   rejected with IGS_ERR_ARG.
  * - Device memory: every pointer marked "device" must be device memory (or
  *   host-coherent memory visible to the GPU) owned by the caller.  The library
  *   keeps no pointer after a call returns and holds no global mutable state

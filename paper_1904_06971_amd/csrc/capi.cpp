@@ -546,6 +546,7 @@ igs_status igs_apply(const igs_problem* pb, int32_t dtype, const void* band, con
                      void* stream) {
   if (!pb || !band || !x || !y) return IGS_ERR_ARG;
   if (dtype != IGS_F64 && dtype != IGS_F32) return IGS_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(band) % (dtype == IGS_F64 ? 16 : 8) != 0) return IGS_ERR_ARG;
   Dims d;
   igs_status st = make_dims(pb, &d);
   if (st != IGS_OK) return st;
@@ -556,6 +557,8 @@ igs_status igs_solve_cg(const igs_problem* pb, const double* band64, const float
                         double rtol, int32_t maxit, igs_cg_info* info, void* stream) {
   if (!pb || !band64 || !f || !u || !info) return IGS_ERR_ARG;
   if (!(rtol > 0.0) || maxit < 1) return IGS_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(band64) % 16 != 0 || reinterpret_cast<uintptr_t>(band32) % 8 != 0)
+    return IGS_ERR_ARG;
   Dims d;
   igs_status st = make_dims(pb, &d);
   if (st != IGS_OK) return st;

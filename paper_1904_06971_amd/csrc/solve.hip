@@ -1,13 +1,15 @@
 // Banded SpMV and conjugate gradients on the stencil-major band.
 //
 // y_i = sum_s band[s][i] x[i + off_s], off_s = delta_1 + m1 delta_2 + m1 m2
-// delta_3 (the colex offset of the slot's delta).  One thread per row, slots
-// in the outer loop: for a fixed slot the lanes of a wave read consecutive
-// band entries and consecutive x entries, so both streams are coalesced; the
-// band is streamed once (non-temporal), x stays in L2.  Entries whose column
-// leaves the index box are stored as 0, so the column index is only clamped
-// into [0, N) to keep the read in bounds.  Workgroups are remapped so that
-// each XCD walks a contiguous range of rows (its L2 then holds the x halo).
+// delta_3 (the colex offset of the slot's delta).  A thread owns two
+// consecutive rows and walks the slots: for a fixed slot the lanes of a wave
+// read consecutive band entries (one 8- or 16-byte load per slot for the
+// pair) and consecutive x entries, so both streams are coalesced; the band is
+// streamed once (non-temporal), x stays in L2 (FP64) or is staged in LDS per
+// (delta2, delta3) run (FP32).  Entries whose column leaves the index box are
+// stored as 0, so the column index is only clamped into [0, N) to keep the
+// read in bounds.  Workgroups are remapped so that each XCD walks a contiguous
+// range of rows (its L2 then holds the x halo).
 //
 // CG (Dirichlet-restricted, Sec. 8 eq. BlockSystem with u_D = 0) keeps every
 // vector zero on the Dirichlet dofs, so the restriction reduces to zeroing
@@ -49,58 +51,6 @@ __device__ __forceinline__ bool on_dirichlet(const SpmvGeom& g, int64_t i) {
   return d;
 }
 
-template <typename T>
-__device__ __forceinline__ T row_product(const SpmvGeom& g, const T* __restrict__ band, const T* __restrict__ x,
-                                         int64_t i) {
-  const int P = g.p, W = g.W;
-  const int64_t m1 = g.m[0], m12 = int64_t(g.m[0]) * g.m[1];
-  T acc = T(0);
-  int s = 0;
-  const int w3 = (g.n == 3) ? W : 1;
-  for (int a3 = 0; a3 < w3; ++a3) {
-    const int64_t o3 = (g.n == 3) ? (a3 - P) * m12 : 0;
-    for (int a2 = 0; a2 < W; ++a2) {
-      const int64_t o23 = o3 + (a2 - P) * m1;
-      for (int a1 = 0; a1 < W; ++a1, ++s) {
-        int64_t j = i + o23 + (a1 - P);
-        j = j < 0 ? 0 : (j >= g.N ? g.N - 1 : j);
-        acc += __builtin_nontemporal_load(band + size_t(s) * g.ld + i) * x[j];
-      }
-    }
-  }
-  return acc;
-}
-
-// y = A x; with mask, rows on the Dirichlet boundary are written 0.  When
-// `dot` is given, per-block partial sums of x_i y_i go to dot[b][block].
-template <typename T>
-__global__ void __launch_bounds__(kSpmvBlock)
-    spmv_kernel(SpmvGeom g, const T* __restrict__ band, const T* __restrict__ x, T* __restrict__ y, int mask,
-                const int* __restrict__ done, double* __restrict__ dot) {
-  const int b = blockIdx.y;
-  if (done && done[b]) return;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
-  const T* bb = band + size_t(b) * g.S * g.ld;
-  const T* xb = x + size_t(b) * g.N;
-  double part = 0.0;
-  if (i < g.N) {
-    T v = (mask && on_dirichlet(g, i)) ? T(0) : row_product<T>(g, bb, xb, i);
-    y[size_t(b) * g.N + i] = v;
-    part = double(v) * double(xb[i]);
-  }
-  if (dot) {
-    __shared__ double red[kSpmvBlock];
-    red[threadIdx.x] = part;
-    __syncthreads();
-    for (int w = kSpmvBlock / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) dot[size_t(b) * gridDim.x + lb] = red[0];
-  }
-}
-
 // Per-problem scalars, kept on the device between kernels.
 struct CgScalars {
   double rr;      // r^T r
@@ -115,123 +65,211 @@ struct CgScalars {
   int pad;
 };
 
-// FP32 band: half the bytes of FP64, so the SpMV would be bound by vector
-// memory instructions (one band and one x load per slot and row) rather than
-// by HBM.  Here each thread owns two consecutive rows (8-byte band loads) and
-// the block's x values are staged in LDS once per (delta2, delta3) run: row
-// r of the block needs x[r + off(delta2, delta3) + delta1], delta1 in [-P, P],
-// i.e. for each run a contiguous window of kS32Rows + 2P values.
-// MODE 0: y = A x, optional Dirichlet mask.  MODE 1: the CG step q = A p with
-// Dirichlet rows zero, skipping finished problems and writing per-block
-// partials of p^T q.
-constexpr int kS32Threads = 128;
-constexpr int kS32Rows = 2 * kS32Threads;
-static_assert(kS32Rows == kSpmvBlock, "CG partial buffers assume kSpmvBlock rows per block");
+// Banded SpMV for both band types.  A thread owns R consecutive rows, so one
+// 16-byte band load per slot serves all of them (R = 2 for FP64, 4 for FP32):
+// a one-row kernel would issue four (FP32) or two (FP64) times the
+// vector-memory instructions and be bound by them rather than by HBM.  For
+// each (delta2, delta3) run the thread needs the 2P+R values x[r0 + off - P ..]
+// that its rows' delta1 windows cover.  FP64 reads them from L2; FP32 stages
+// the block's windows in LDS one delta3 plane at a time (W windows of
+// kSpmvBlock + 2P values, one per delta2), which keeps the LDS per block small
+// enough for many blocks per CU.  The rows start at a multiple of R and ld is a
+// multiple of 64, so the band load is aligned and stays inside the slot; row
+// indices past N read padding and are not stored.  Modes:
+//   0  y = A x (Dirichlet rows 0 when mask is set)
+//   1  CG step q = A p, Dirichlet rows 0, finished problems skipped,
+//      per-block partials of p^T q
+//   2  (FP64) r = f - A u, Dirichlet rows 0, partials of r^T r and f^T f
+//   3  (FP64) r32 = float(f - A u) on problems with a residual replacement
+//      due, partials of r^T r
+template <int NT>
+__device__ __forceinline__ double block_sum_n(double v) {
+  __shared__ double red[NT];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();  // red is reused by a following call
+  return r;
+}
 
-template <int P, int ND, int MODE>
-__global__ void __launch_bounds__(kS32Threads)
-    spmv32_kernel(SpmvGeom g, const float* __restrict__ band, const float* __restrict__ x, float* __restrict__ y,
-                  int mask, const CgScalars* __restrict__ sc, double* __restrict__ part) {
+template <typename T, int R>
+struct VecR {
+  typedef T v __attribute__((ext_vector_type(R)));
+};
+template <typename T>
+struct Pair2 {
+  typedef T v __attribute__((ext_vector_type(2)));
+};
+
+template <typename T>
+struct SpmvShape {
+  static constexpr int R = 16 / sizeof(T);   // rows per thread: one 16-byte band load per slot
+  static constexpr bool STAGE = sizeof(T) == 4;
+  static constexpr int NT = kSpmvBlock / R;  // threads per block
+};
+
+template <typename T, int P, int ND, int MODE>
+__global__ void __launch_bounds__(SpmvShape<T>::NT)
+    spmv_band_kernel(SpmvGeom g, const T* __restrict__ band, const T* __restrict__ x, const double* __restrict__ f,
+                     T* __restrict__ y, float* __restrict__ y32, int mask, const CgScalars* __restrict__ sc,
+                     double* __restrict__ part, double* __restrict__ part2) {
+  static_assert(MODE < 2 || sizeof(T) == 8, "residual modes take the FP64 band");
+  constexpr int R = SpmvShape<T>::R, NT = SpmvShape<T>::NT;
+  constexpr bool STAGE = SpmvShape<T>::STAGE;
+  typedef typename VecR<T, R>::v VT;
+  typedef typename Pair2<T>::v PT;
   constexpr int W = 2 * P + 1;
-  constexpr int NPL = ND == 3 ? W * W : W;         // (delta2, delta3) runs
-  constexpr int XP = (kS32Rows + 2 * P + 3) & ~3;  // LDS row pitch (floats)
-  __shared__ float xs[NPL * XP];
+  constexpr int NZ = ND == 3 ? W : 1;        // delta3 planes
+  constexpr int NX = 2 * P + R;              // x values per run and thread
+  constexpr int XW = kSpmvBlock + 2 * P;     // staged window length
+  constexpr int XP = (XW + 3) & ~3;          // LDS pitch (elements)
+  __shared__ __align__(16) T xs[STAGE ? W * XP : 1];
   const int b = blockIdx.y;
   if (MODE == 1 && sc[b].done) return;
+  if (MODE == 3 && (sc[b].done || !sc[b].replace)) return;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t i0 = int64_t(lb) * kS32Rows;
-  const float* xb = x + size_t(b) * g.N;
-  const float* bb = band + size_t(b) * g.S * g.ld;
-  const int64_t m1 = g.m[0], m12 = int64_t(g.m[0]) * g.m[1];
+  const int64_t i0 = int64_t(lb) * kSpmvBlock;
   const int tid = threadIdx.x;
-  for (int k = 0; k < NPL; ++k) {
-    const int d2 = (ND == 3 ? k % W : k) - P, d3 = ND == 3 ? k / W - P : 0;
-    const int64_t base = i0 + d2 * m1 + d3 * m12 - P;
-    for (int t = tid; t < kS32Rows + 2 * P; t += kS32Threads) {
-      const int64_t j = base + t;
-      xs[k * XP + t] = (j >= 0 && j < g.N) ? xb[j] : 0.0f;
-    }
-  }
-  __syncthreads();
-  const int64_t r0 = i0 + 2 * tid;
-  float a0 = 0.0f, a1 = 0.0f;
-  if (r0 < g.N) {
-    const bool two = r0 + 1 < g.N;
-#pragma unroll 7
-    for (int k = 0; k < NPL; ++k) {
-      float xw[2 * P + 2];
-      const float2* xp = reinterpret_cast<const float2*>(xs + k * XP + 2 * tid);
+  const int64_t r0 = i0 + R * tid;
+  const T* xb = x + size_t(b) * g.N;
+  const T* bb = band + size_t(b) * g.S * g.ld;
+  const int64_t m1 = g.m[0], m12 = int64_t(g.m[0]) * g.m[1];
+  T acc[R];
 #pragma unroll
-      for (int e = 0; e < P + 1; ++e) {
-        const float2 v = xp[e];
-        xw[2 * e] = v.x;
-        xw[2 * e + 1] = v.y;
-      }
-      const float* bk = bb + size_t(k) * W * g.ld + r0;
+  for (int q = 0; q < R; ++q) acc[q] = T(0);
+  for (int z = 0; z < NZ; ++z) {
+    const int64_t o3 = ND == 3 ? (z - P) * m12 : 0;
+    if constexpr (STAGE) {
+      // one window at a time: its loads go out together, then into LDS
+      constexpr int NS = (XW + NT - 1) / NT;
+      if (z > 0) __syncthreads();  // every thread is done with the previous plane
+      for (int k = 0; k < W; ++k) {
+        const int64_t base = i0 + (k - P) * m1 + o3 - P;
+        T st[NS];
 #pragma unroll
-      for (int d1 = 0; d1 < W; ++d1) {
-        typedef float f2v __attribute__((ext_vector_type(2)));
-        f2v bv;
-        if (two) {
-          bv = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(bk + size_t(d1) * g.ld));
-        } else {
-          bv.x = bk[size_t(d1) * g.ld];
-          bv.y = 0.0f;
+        for (int u = 0; u < NS; ++u) {
+          const int t = tid + u * NT;
+          const int64_t j = base + t;
+          st[u] = (t < XW && j >= 0 && j < g.N) ? xb[j] : T(0);
         }
-        a0 += bv.x * xw[d1];
-        a1 += bv.y * xw[d1 + 1];
+#pragma unroll
+        for (int u = 0; u < NS; ++u)
+          if (tid + u * NT < XW) xs[k * XP + tid + u * NT] = st[u];
       }
-    }
-  }
-  double dp = 0.0;
-  const int kc = ND == 3 ? P + W * P : P;  // the run with delta2 = delta3 = 0
-  if (r0 < g.N) {
-    if (MODE == 1 || mask) {
-      if (on_dirichlet(g, r0)) a0 = 0.0f;
-      if (r0 + 1 < g.N && on_dirichlet(g, r0 + 1)) a1 = 0.0f;
-    }
-    float* yb = y + size_t(b) * g.N;
-    yb[r0] = a0;
-    if (r0 + 1 < g.N) yb[r0 + 1] = a1;
-    if (MODE == 1) {
-      dp = double(a0) * double(xs[kc * XP + 2 * tid + P]);
-      if (r0 + 1 < g.N) dp += double(a1) * double(xs[kc * XP + 2 * tid + P + 1]);
-    }
-  }
-  if (MODE == 1) {
-    __shared__ double red[kS32Threads];
-    red[tid] = dp;
-    __syncthreads();
-    for (int w = kS32Threads / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
       __syncthreads();
     }
-    if (tid == 0) part[size_t(b) * gridDim.x + lb] = red[0];
+    if (r0 < g.N) {
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        T xw[NX];
+        if constexpr (STAGE) {
+          const PT* xp = reinterpret_cast<const PT*>(xs + k * XP + R * tid);
+#pragma unroll
+          for (int e = 0; e < NX / 2; ++e) {
+            const PT v = xp[e];
+            xw[2 * e] = v.x;
+            xw[2 * e + 1] = v.y;
+          }
+        } else {
+          // columns outside [0, N) carry zero band entries: clamp to stay in bounds
+          const int64_t base = r0 + (k - P) * m1 + o3 - P;
+#pragma unroll
+          for (int e = 0; e < NX; ++e) {
+            int64_t j = base + e;
+            j = j < 0 ? 0 : (j >= g.N ? g.N - 1 : j);
+            xw[e] = xb[j];
+          }
+        }
+        // all W band loads of the run go out before their products
+        const T* bk = bb + size_t(z * W + k) * W * g.ld + r0;
+        VT bv[W];
+#pragma unroll
+        for (int d1 = 0; d1 < W; ++d1)
+          bv[d1] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(bk + size_t(d1) * g.ld));
+#pragma unroll
+        for (int d1 = 0; d1 < W; ++d1)
+#pragma unroll
+          for (int q = 0; q < R; ++q) acc[q] = fma(bv[d1][q], xw[d1 + q], acc[q]);
+      }
+    }
   }
+  double sa = 0.0, sf = 0.0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int64_t i = r0 + q;
+    if (i >= g.N) break;
+    const bool dir = on_dirichlet(g, i);
+    const size_t k0 = size_t(b) * g.N + i;
+    T o;
+    double fv = 0.0;
+    if (MODE == 0) {
+      o = (mask && dir) ? T(0) : acc[q];
+    } else if (MODE == 1) {
+      o = dir ? T(0) : acc[q];
+    } else {
+      fv = dir ? 0.0 : f[k0];
+      o = dir ? T(0) : T(fv - double(acc[q]));
+    }
+    if (MODE == 3)
+      y32[k0] = float(o);
+    else
+      y[k0] = o;
+    if (MODE == 1) sa += double(o) * double(xb[i]);
+    if (MODE >= 2) {
+      sa += double(o) * double(o);
+      sf += fv * fv;
+    }
+  }
+  if (MODE == 0) return;
+  const double a = block_sum_n<NT>(sa);
+  if (MODE == 2) {
+    const double c = block_sum_n<NT>(sf);
+    if (threadIdx.x == 0) part2[size_t(b) * gridDim.x + lb] = c;
+  }
+  if (threadIdx.x == 0) part[size_t(b) * gridDim.x + lb] = a;
+}
+
+template <typename T, int MODE>
+static void launch_spmv_band(const SpmvGeom& g, int nblk, int batch, const T* band, const T* x, const double* f,
+                             T* y, float* y32, int mask, const CgScalars* sc, double* part, double* part2,
+                             hipStream_t s) {
+  const dim3 grid(nblk, batch), block(SpmvShape<T>::NT);
+#define IGS_SPMV(PP, NDD)                                                                                         \
+  hipLaunchKernelGGL((spmv_band_kernel<T, PP, NDD, MODE>), grid, block, 0, s, g, band, x, f, y, y32, mask, sc, part, \
+                     part2)
+  if (g.n == 3) {
+    switch (g.p) {
+      case 1: IGS_SPMV(1, 3); break;
+      case 2: IGS_SPMV(2, 3); break;
+      case 3: IGS_SPMV(3, 3); break;
+      default: IGS_SPMV(4, 3); break;
+    }
+  } else {
+    switch (g.p) {
+      case 1: IGS_SPMV(1, 2); break;
+      case 2: IGS_SPMV(2, 2); break;
+      case 3: IGS_SPMV(3, 2); break;
+      default: IGS_SPMV(4, 2); break;
+    }
+  }
+#undef IGS_SPMV
 }
 
 template <int MODE>
 static void launch_spmv32(const SpmvGeom& g, int nblk, int batch, const float* band, const float* x, float* y,
                           int mask, const CgScalars* sc, double* part, hipStream_t s) {
-  const dim3 grid(nblk, batch), block(kS32Threads);
-#define IGS_SPMV32(PP, NDD) \
-  hipLaunchKernelGGL((spmv32_kernel<PP, NDD, MODE>), grid, block, 0, s, g, band, x, y, mask, sc, part)
-  if (g.n == 3) {
-    switch (g.p) {
-      case 1: IGS_SPMV32(1, 3); break;
-      case 2: IGS_SPMV32(2, 3); break;
-      case 3: IGS_SPMV32(3, 3); break;
-      default: IGS_SPMV32(4, 3); break;
-    }
-  } else {
-    switch (g.p) {
-      case 1: IGS_SPMV32(1, 2); break;
-      case 2: IGS_SPMV32(2, 2); break;
-      case 3: IGS_SPMV32(3, 2); break;
-      default: IGS_SPMV32(4, 2); break;
-    }
-  }
-#undef IGS_SPMV32
+  launch_spmv_band<float, MODE>(g, nblk, batch, band, x, nullptr, y, nullptr, mask, sc, part, nullptr, s);
+}
+
+template <int MODE>
+static void launch_spmv64(const SpmvGeom& g, int nblk, int batch, const double* band, const double* x,
+                          const double* f, double* y, float* y32, int mask, const CgScalars* sc, double* part,
+                          double* part2, hipStream_t s) {
+  launch_spmv_band<double, MODE>(g, nblk, batch, band, x, f, y, y32, mask, sc, part, part2, s);
 }
 
 // x with its Dirichlet dofs zeroed (the restriction of igs_apply)
@@ -255,29 +293,6 @@ __device__ __forceinline__ double block_sum(double v) {
     __syncthreads();
   }
   return red[0];
-}
-
-// r = f - A u (FP64, Dirichlet rows 0), partial sums of r^T r and f^T f
-__global__ void __launch_bounds__(kSpmvBlock)
-    residual_kernel(SpmvGeom g, const double* __restrict__ band, const double* __restrict__ f,
-                    const double* __restrict__ u, double* __restrict__ r, double* __restrict__ part_rr,
-                    double* __restrict__ part_ff) {
-  const int b = blockIdx.y;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
-  double rv = 0.0, fv = 0.0;
-  if (i < g.N && !on_dirichlet(g, i)) {
-    fv = f[size_t(b) * g.N + i];
-    rv = fv - row_product<double>(g, band + size_t(b) * g.S * g.ld, u + size_t(b) * g.N, i);
-  }
-  if (i < g.N) r[size_t(b) * g.N + i] = rv;
-  double a = block_sum<double>(rv * rv);
-  __syncthreads();
-  double c = block_sum<double>(fv * fv);
-  if (threadIdx.x == 0) {
-    part_rr[size_t(b) * gridDim.x + lb] = a;
-    part_ff[size_t(b) * gridDim.x + lb] = c;
-  }
 }
 
 // out[b] = sum of part[b][0..nblk) in a fixed order (one block per problem)
@@ -451,8 +466,7 @@ igs_status launch_apply_t(const Dims& d, const T* band, const T* x, T* y, int di
     if constexpr (sizeof(T) == 4)
       launch_spmv32<0>(g, nblk, d.batch, band, xin, y, dirichlet, nullptr, nullptr, s);
     else
-      hipLaunchKernelGGL((spmv_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band, xin, y, dirichlet,
-                         nullptr, nullptr);
+      launch_spmv64<0>(g, nblk, d.batch, band, xin, nullptr, y, nullptr, dirichlet, nullptr, nullptr, nullptr, s);
   }
   HIP_OK(hipGetLastError());
   return IGS_OK;
@@ -476,26 +490,6 @@ __global__ void __launch_bounds__(kRedBlock)
     v += double(a[size_t(b) * N + i]) * double(c[size_t(b) * N + i]);
   v = block_sum<double>(v);
   if (threadIdx.x == 0) part[size_t(b) * gridDim.x + blockIdx.x] = v;
-}
-
-// CG iteration kernels operate on problems whose `done` flag is clear.
-template <typename T>
-__global__ void __launch_bounds__(kSpmvBlock)
-    cg_spmv_kernel(SpmvGeom g, const T* __restrict__ band, const T* __restrict__ p, T* __restrict__ q,
-                   const CgScalars* __restrict__ sc, double* __restrict__ part) {
-  const int b = blockIdx.y;
-  if (sc[b].done) return;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
-  const T* pb = p + size_t(b) * g.N;
-  double v = 0.0;
-  if (i < g.N) {
-    T y = on_dirichlet(g, i) ? T(0) : row_product<T>(g, band + size_t(b) * g.S * g.ld, pb, i);
-    q[size_t(b) * g.N + i] = y;
-    v = double(y) * double(pb[i]);
-  }
-  v = block_sum<double>(v);
-  if (threadIdx.x == 0) part[size_t(b) * gridDim.x + lb] = v;
 }
 
 struct SolveBufs {
@@ -535,8 +529,7 @@ static igs_status inner_cg(const Dims& d, const T* band, const SolveBufs& sb, T*
         if constexpr (sizeof(T) == 4)
           launch_spmv32<1>(g, nblk, d.batch, band, p, q, 1, sb.sc, sb.part, s);
         else
-          hipLaunchKernelGGL((cg_spmv_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band, p, q, sb.sc,
-                             sb.part);
+          launch_spmv64<1>(g, nblk, d.batch, band, p, nullptr, q, nullptr, 1, sb.sc, sb.part, nullptr, s);
       }
       PhaseTimer t("cg_vector_ops", s);
       hipLaunchKernelGGL(cg_alpha_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
@@ -598,8 +591,7 @@ static igs_status refine_loop(const Dims& d, const double* band64, const T* band
   while (true) {
     {
       PhaseTimer t("residual_f64", s);
-      hipLaunchKernelGGL(residual_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band64, f, u, sb.r64,
-                         sb.part, sb.part2);
+      launch_spmv64<2>(g, nblk, d.batch, band64, u, f, sb.r64, nullptr, 1, nullptr, sb.part, sb.part2, s);
     }
     hipLaunchKernelGGL(reduce_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.rr);
     hipLaunchKernelGGL(reduce_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part2, nblk, sb.ff);
@@ -721,24 +713,6 @@ __global__ void __launch_bounds__(kRedBlock) rc_beta_kernel(const double* __rest
   }
 }
 
-// r64 = f - A64 u on problems with a replacement due; r32 = float(r64);
-// partial |r64|^2
-__global__ void __launch_bounds__(kSpmvBlock)
-    rc_residual_kernel(SpmvGeom g, const double* __restrict__ band, const double* __restrict__ f,
-                       const double* __restrict__ u, float* __restrict__ r32, const CgScalars* __restrict__ sc,
-                       double* __restrict__ part) {
-  const int b = blockIdx.y;
-  if (sc[b].done || !sc[b].replace) return;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
-  double rv = 0.0;
-  if (i < g.N && !on_dirichlet(g, i))
-    rv = f[size_t(b) * g.N + i] - row_product<double>(g, band + size_t(b) * g.S * g.ld, u + size_t(b) * g.N, i);
-  if (i < g.N) r32[size_t(b) * g.N + i] = float(rv);
-  const double a = block_sum<double>(rv * rv);
-  if (threadIdx.x == 0) part[size_t(b) * gridDim.x + lb] = a;
-}
-
 __global__ void __launch_bounds__(kRedBlock) rc_replace_kernel(const double* __restrict__ part, int nblk,
                                                                CgScalars* sc) {
   const int b = blockIdx.x;
@@ -792,8 +766,7 @@ static igs_status replace_cg(const Dims& d, const double* band64, const float* b
   auto true_residual = [&](std::vector<double>* rr, std::vector<double>* ff) -> igs_status {
     {
       PhaseTimer t("residual_f64", s);
-      hipLaunchKernelGGL(residual_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band64, f, u, sb.r64,
-                         sb.part, sb.part2);
+      launch_spmv64<2>(g, nblk, d.batch, band64, u, f, sb.r64, nullptr, 1, nullptr, sb.part, sb.part2, s);
     }
     hipLaunchKernelGGL(reduce_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.rr);
     hipLaunchKernelGGL(reduce_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part2, nblk, sb.ff);
@@ -832,8 +805,7 @@ static igs_status replace_cg(const Dims& d, const double* band64, const float* b
       hipLaunchKernelGGL(rc_update_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, sb.sc, p, q, u, r32,
                          sb.part2);
       hipLaunchKernelGGL(rc_beta_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part2, nblk, sb.sc);
-      hipLaunchKernelGGL(rc_residual_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, band64, f, u, r32,
-                         sb.sc, sb.part);
+      launch_spmv64<3>(g, nblk, d.batch, band64, u, f, nullptr, r32, 1, sb.sc, sb.part, nullptr, s);
       hipLaunchKernelGGL(rc_replace_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
       hipLaunchKernelGGL((cg_pupdate_kernel<float>), dim3(std::min<int64_t>((d.N + 255) / 256, 4096), d.batch),
                          dim3(256), 0, s, d.N, sb.sc, r32, p);

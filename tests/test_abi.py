@@ -161,6 +161,20 @@ def test_null_and_enum_arguments():
     assert L.igs_validate(ctypes.byref(sp), 0, 0) == -1
 
 
+def test_band_alignment_rejected():
+    """The SpMV reads a row pair of a slot with one load: a band pointer off
+    the 16-byte (FP64) or 8-byte (FP32) grid is an argument error, reported
+    before any GPU work."""
+    L = igs.lib()
+    pb = igs.make_problem(W.c1_poisson2d())
+    ok, off8, off4 = ctypes.c_void_p(256), ctypes.c_void_p(264), ctypes.c_void_p(260)
+    assert L.igs_apply(ctypes.byref(pb), igs.F64, off8, ok, ok, 0, None) == -1
+    assert L.igs_apply(ctypes.byref(pb), igs.F32, off4, ok, ok, 0, None) == -1
+    info = igs.CgInfo()
+    assert L.igs_solve_cg(ctypes.byref(pb), off8, None, ok, ok, 1e-8, 10, ctypes.byref(info), None) == -1
+    assert L.igs_solve_cg(ctypes.byref(pb), ok, off4, ok, ok, 1e-8, 10, ctypes.byref(info), None) == -1
+
+
 def test_library_resolves_all_symbols():
     """Every symbol the library needs is defined (immediate binding)."""
     ctypes.CDLL(igs.LIB_PATH, mode=os.RTLD_NOW | os.RTLD_LOCAL)
