@@ -30,8 +30,11 @@ def test_rhs(igs, oracle, prob, src, c):
     assert rel_maxnorm(f[0].cpu().numpy(), ref) < 1e-13
 
 
+# every degree in 2D and 3D; N odd or not a multiple of 4 in several cases (the
+# kernels give each thread 2 (FP64) or 4 (FP32) consecutive rows)
 @pytest.mark.parametrize("prob", [W.problem(2, 3, 41), W.problem(3, 3, (20, 19, 21)), W.problem(3, 2, 17),
-                                  W.problem(2, 1, 50), W.problem(3, 4, 9), W.problem(3, 1, (30, 7, 9))])
+                                  W.problem(2, 1, 50), W.problem(3, 4, 9), W.problem(3, 1, (30, 7, 9)),
+                                  W.problem(2, 2, 37), W.problem(2, 4, (23, 30))])
 @pytest.mark.parametrize("dirichlet", [False, True])
 def test_apply(igs, oracle, prob, dirichlet):
     import torch
@@ -46,6 +49,23 @@ def test_apply(igs, oracle, prob, dirichlet):
     b32 = band.float()
     y32 = igs.apply(prob, b32, torch.as_tensor(x, device="cuda", dtype=torch.float32), dirichlet=dirichlet)
     assert rel_maxnorm(y32[0].double().cpu().numpy(), ref) < 1e-5
+
+
+def test_apply_batched(igs, oracle):
+    """A batch of problems with different coefficient fields: each problem's
+    slice of the band applies to its own slice of x."""
+    import torch
+
+    prob = W.c5_adjoint2d(nelem=21, batch=3, cn=8)
+    _, N, _ = oracle.dims(prob)
+    band = igs.assemble_exact(prob, 0)
+    x = np.concatenate([W.random_vector(N, 20 + b) for b in range(3)])
+    y = igs.apply(prob, band, torch.as_tensor(x, device="cuda"))
+    y32 = igs.apply(prob, band.float(), torch.as_tensor(x, device="cuda", dtype=torch.float32))
+    for b in range(3):
+        ref = oracle.apply(prob, igs.band_rows(band, prob, b), x[b])
+        assert rel_maxnorm(y[b].cpu().numpy(), ref) < 1e-13
+        assert rel_maxnorm(y32[b].double().cpu().numpy(), ref) < 1e-5
 
 
 def test_cg_c1(igs, oracle):
