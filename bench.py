@@ -37,22 +37,26 @@ FP64_PEAK_TFLOPS = 78.6
 # reported while the kernel source still hashes to the one measured.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.00, 1.00
 PMC_TRAFFIC = {
-    "quad_boundary_rows": {"source": "quad.hip", "sha256": "4a0b3c1ff8bdbdfb", "fetch_kib": 13876.2,
-                           "write_kib": 2109396.4},
-    "fill": {"source": "fill.hip", "sha256": "846bd0cdc1a4cadd", "fetch_kib": 980295.0, "write_kib": 4972000.0},
+    "quad_boundary_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "", "fetch_kib": 0.0, "write_kib": 0.0},
+    "fill": {"sources": ["fill.hip"], "sha256": "", "fetch_kib": 0.0, "write_kib": 0.0},
+    "copy": {"sources": ["fill.hip"], "sha256": "", "fetch_kib": 0.0, "write_kib": 0.0},
 }
+
+
+def source_hash(sources):
+    import hashlib
+
+    h = hashlib.sha256()
+    for src in sources:
+        h.update(open(os.path.join(ROOT, "paper_1904_06971_amd", "csrc", src), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(phase):
     """Scaled HBM bytes per launch for a phase, or None when not measured for
-    the kernel source as it is now."""
-    import hashlib
-
+    the kernel sources (and tile planner) as they are now."""
     rec = PMC_TRAFFIC.get(phase)
-    if rec is None:
-        return None
-    path = os.path.join(ROOT, "paper_1904_06971_amd", "csrc", rec["source"])
-    if hashlib.sha256(open(path, "rb").read()).hexdigest()[:16] != rec["sha256"]:
+    if rec is None or source_hash(rec["sources"]) != rec["sha256"]:
         return None
     return (rec["fetch_kib"] * PMC_FETCH_SCALE + rec["write_kib"] * PMC_WRITE_SCALE) * 1024.0
 
@@ -73,15 +77,18 @@ def quad_flops_per_row(n, p):
 
 
 def fill_bytes(prob, lay, esize):
-    """Algorithmic HBM bytes of the fill: every slot of every analysis-domain row
-    written once, plus one read per copied exact entry (partner outside the
-    analysis domain)."""
+    """Algorithmic HBM bytes of the fill and copy kernels.  The fill writes
+    every slot of every analysis-domain row once (it reads nothing of the
+    band); the copy kernel reads and writes each copied exact entry (partner
+    outside the analysis domain) once and updates the diagonal of each row
+    that has one."""
     n, p = prob["n"], prob["p"]
     L = [lay.m[d] - 4 * p for d in range(n)]
     rows = math.prod(L)
     both = math.prod(sum(L[d] - abs(dl) for dl in range(-p, p + 1)) for d in range(n))
     copies = rows * lay.slots - both
-    return rows * lay.slots * esize + copies * esize, rows, copies
+    shell = rows - math.prod(max(0, L[d] - 2 * p) for d in range(n))
+    return rows * lay.slots * esize, rows, copies, (2 * copies + 2 * shell) * esize, shell
 
 
 def main():
@@ -154,7 +161,7 @@ def main():
 
     # rooflines of the step's kernels
     fpr = quad_flops_per_row(3, prob["p"])
-    fb, frows, fcopies = fill_bytes(prob, lay, 8)
+    fb, frows, fcopies, cb, cshell = fill_bytes(prob, lay, 8)
     roofs = {}
     for name, rows in (("quad_boundary_rows", info.boundary_rows), ("quad_sample_rows", info.sample_rows)):
         if name in phases:
@@ -167,7 +174,12 @@ def main():
         t = phases["fill"]["avg_ms"] * 1e-3
         roofs["fill"] = {"bound": "hbm", "achieved": fb / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": fb / t / 1e9 / HBM_PEAK_GBS, "traffic": measured_traffic("fill"), "ms": t * 1e3,
-                         "units": f"{frows} analysis-domain rows x {lay.slots} slots, {fcopies} copied entries"}
+                         "units": f"{frows} analysis-domain rows x {lay.slots} slots"}
+    if "copy" in phases:
+        t = phases["copy"]["avg_ms"] * 1e-3
+        roofs["copy"] = {"bound": "hbm", "achieved": cb / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": cb / t / 1e9 / HBM_PEAK_GBS, "traffic": measured_traffic("copy"), "ms": t * 1e3,
+                         "units": f"{fcopies} copied entries read and written, {cshell} diagonals updated"}
     dominant = max(roofs, key=lambda k: roofs[k].get("ms", phases.get(k, {}).get("avg_ms", 0.0)))
     roofline = dict(roofs[dominant])
     roofline["kernel"] = dominant

@@ -31,6 +31,10 @@ int fill_npen(const Dims& d, int rows);
 int fill_chunk_rows(const Dims& d, int Sd1);
 template <typename T>
 hipError_t launch_zero_pad(T* band, int64_t N, int64_t ld, int slots_total, hipStream_t s);
+template <typename T>
+hipError_t launch_copy(const KInterp<T>& ip, int form, const Dims& d, const int* rows, int nrows, T* band,
+                       hipStream_t s);
+std::vector<int> copy_rows(const Dims& d);
 igs_status launch_apply(const Dims& d, int dtype, const void* band, const void* x, void* y, int dirichlet,
                         hipStream_t s);
 igs_status solve_cg(const Dims& d, const double* band64, const float* band32, const double* f, double* u, double rtol,
@@ -210,7 +214,12 @@ struct Plan {
   int nchunks = 0, chunk_rows = 0, n2max = 1, n3max = 1;
   const int4* ddsl = nullptr;
   double *tmp0 = nullptr, *tmp1 = nullptr, *coef = nullptr;
+  const int* dcopy = nullptr;  // analysis-domain rows whose stencil leaves the domain
+  int ncopy = 0;
   int state = 0;  // geometry flag: 0 not read yet, 1 read and clear, 2 set
+  Plan() = default;
+  Plan(const Plan&) = delete;
+  Plan& operator=(const Plan&) = delete;
 };
 
 static igs_status build_exact(const igs_problem* pb, hipStream_t s, Plan* pl) {
@@ -248,6 +257,7 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
   const size_t ncoef = per * hi.upslot.size() * d.batch;
   pl->chunk_rows = fill_chunk_rows(d, int(hi.samp[0].size()));
   std::vector<int> chunks = fill_chunks(d, pl->chunk_rows);
+  std::vector<int> crow = copy_rows(d);
   std::vector<int> dsl;  // (slot, delta1, delta2, delta3) per interpolated slot
   for (int sl : hi.upslot) {
     const int W = d.W;
@@ -257,7 +267,7 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
     dsl.push_back(d.n == 3 ? sl / (W * W) - d.p : 0);
   }
   size_t bytes = padded(tiles.size() * sizeof(QTile)) + 3 * padded(ncoef * sizeof(double)) + vbytes(chunks) +
-                 vbytes(dsl) + padded(hi.upslot.size() * sizeof(int)) * 2;
+                 vbytes(crow) + vbytes(dsl) + padded(hi.upslot.size() * sizeof(int)) * 2;
   for (int k = 0; k < d.n; ++k)
     bytes += 2 * (vbytes(hi.samp[k]) + vbytes(hi.ginv[k]) + vbytes(hi.ef[k]) + vbytes(hi.eb[k]));
   st = pl->ta.alloc(bytes, s);
@@ -272,6 +282,8 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
     pl->ipf = interp_view<float>(hi, d, ta, s, &st, ebf);
   pl->dchunks = upload(ta, chunks, s, &st);
   pl->nchunks = int(chunks.size());
+  pl->dcopy = upload(ta, crow, s, &st);
+  pl->ncopy = int(crow.size());
   pl->ddsl = reinterpret_cast<const int4*>(upload(ta, dsl, s, &st));
   pl->tmp0 = ta.take<double>(ncoef);
   pl->tmp1 = ta.take<double>(ncoef);
@@ -294,16 +306,16 @@ static igs_status run_t(const Plan& pl, const KProblem& kp, const KInterp<OutT>&
       HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt, pl.ntiles, false, band, s));
     }
   } else {
-    {
-      // rows outside the analysis domain: the boundary pencils and the interior
-      // pencils' end slabs, tiled
-      PhaseTimer t("quad_boundary_rows", s);
-      HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt, pl.groups[0] + pl.groups[1], false, band, s));
-    }
+    // Order: sample rows, fit and fill first; the fill writes whole lines of
+    // the analysis-domain pencils, placeholders included, and reads nothing of
+    // the band.  Then the quadrature of every row outside the analysis domain
+    // (overwriting the placeholders) and the copy kernel, which reads the
+    // exact entries of those rows.
+    const QTile* t2 = pl.dt + pl.groups[0] + pl.groups[1];
     {
       // the sample rows: isolated, one workgroup each in 3-D (single-row tiles)
       PhaseTimer t("quad_sample_rows", s);
-      HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt + pl.groups[0] + pl.groups[1], pl.groups[2], d.n == 3, band, s));
+      HIP_TRY(launch_quad<OutT>(kp, pl.form, t2, pl.groups[2], d.n == 3, band, s));
     }
     {
       PhaseTimer t("fit", s);
@@ -313,6 +325,14 @@ static igs_status run_t(const Plan& pl, const KProblem& kp, const KInterp<OutT>&
       PhaseTimer t("fill", s);
       HIP_TRY(launch_fill<OutT>(ipT, pl.form, d, pl.dchunks, pl.nchunks, pl.chunk_rows, pl.n2max, pl.n3max, pl.ddsl,
                                 pl.coef, band, s));
+    }
+    {
+      PhaseTimer t("quad_boundary_rows", s);
+      HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt, pl.groups[0] + pl.groups[1], false, band, s));
+    }
+    {
+      PhaseTimer t("copy", s);
+      HIP_TRY(launch_copy<OutT>(ipT, pl.form, d, pl.dcopy, pl.ncopy, band, s));
     }
   }
   {

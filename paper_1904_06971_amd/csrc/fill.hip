@@ -1,4 +1,4 @@
-// Surrogate interpolation: fit and fill kernels (Secs. 4.1, 5, 8).
+// Surrogate interpolation: fit, fill and copy kernels (Secs. 4.1, 5, 8).
 //
 // fit:  for every interpolated ("upper") stencil delta, the sample values
 //       V_delta[k] = A_{s(k), s(k)+delta} (read from the band rows that the
@@ -6,12 +6,19 @@
 //       c_delta = (G_n^-1 x ... x G_1^-1) V_delta, one direction per pass.
 // fill: every analysis-domain row gets, for each upper delta, Phi~_delta at
 //       its own index (upper entry) and at the index of its lower partner
-//       (lower entry, eq. 5.1b/5.1c copy rule), or the exact entry of the
-//       boundary row when the partner leaves the analysis domain; the
-//       stiffness diagonal is minus the sum of the row (eq. 5.1c).  A
-//       workgroup evaluates the interpolant separably on its tile (plus the
-//       halo that the lower entries need) through two LDS stages and writes
-//       each band slot of its rows exactly once, stencil-major and coalesced.
+//       (lower entry, eq. 5.1b/5.1c copy rule).  A workgroup evaluates the
+//       interpolant separably on its chunk of rows through two LDS stages and
+//       writes every slot of every row of the analysis-domain pencils (rows
+//       with (i2, i3) inside the analysis domain), whole 128-byte lines, with
+//       no reads of the band.  Slots it cannot know yet hold placeholders:
+//       the rows of those pencils outside the domain in i1 (their quadrature
+//       runs afterwards and overwrites them) and the entries whose partner
+//       leaves the domain.  The stiffness diagonal holds minus the sum of the
+//       interpolated entries.
+// copy: afterwards, the domain rows whose stencil leaves the domain take the
+//       exact entries of their partners (A_ij = A_ji, row j from quadrature)
+//       and subtract them from the diagonal, which then closes the row sum
+//       over every off-diagonal entry (eq. 5.1c).
 #include <algorithm>
 
 #include "igs_internal.h"
@@ -58,15 +65,13 @@ __global__ void fit_pass_kernel(KInterp<double> ip, int d, int n, int m1, int m2
 //
 // A workgroup owns an aligned chunk of kChunk consecutive rows of the flat
 // (colex) index, one row per thread, and writes every slot of every row of the
-// chunk: analysis-domain rows get the interpolated/copied/diagonal values,
-// boundary rows (already assembled by quadrature) are read and stored back
-// unchanged.  Each store instruction of a wave therefore covers whole 128-byte
-// lines, which the HBM write path needs to stream at full rate.  Per
-// interpolated delta the chunk's pencils (rows with the same (i2, i3)) get the
-// partial contraction T[c1] = sum_{c2,c3} beta2 beta3 c_delta[c3][c2][c1] in
-// LDS (for the pencil itself and for the pencil of the lower partners); each
-// row then finishes with its q+1 direction-1 weights.  LDS is double-buffered
-// so one barrier per delta suffices.
+// chunk that lies in an analysis-domain pencil, so each store instruction of
+// a wave covers whole 128-byte lines (the HBM write path streams those at full
+// rate).  Per interpolated delta the chunk's pencils (rows with the same
+// (i2, i3)) get the partial contraction T[c1] = sum_{c2,c3} beta2 beta3
+// c_delta[c3][c2][c1] in LDS (for the pencil itself and for the pencil of the
+// lower partners); each row then finishes with its q+1 direction-1 weights.
+// LDS is double-buffered so one barrier per delta suffices.
 
 constexpr int kChunk = 256;
 
@@ -131,18 +136,20 @@ __global__ void __launch_bounds__(kChunk)
     dsl[u] = make_int4(s, s % W - g.P, (s / W) % W - g.P, (ND == 3) ? s / (W * W) - g.P : 0);
   }
   const int64_t i = c0 + tid;
-  const bool live = i < g.N;
   const int64_t pen0 = c0 / g.m1;
   int i1 = 0, i2 = 0, i3 = 0;
-  int64_t pen = 0;
-  if (live) {
+  int64_t pen = pen0;
+  if (i < g.N) {
     pen = i / g.m1;
     i1 = int(i - pen * g.m1);
     i2 = int(pen % g.m2);
     i3 = int(pen / g.m2);
   }
   const int k = int(pen - pen0);  // this row's pencil slot in the chunk
-  const bool inner = live && in_dom(ip, 0, i1) && in_dom(ip, 1, i2) && (ND == 2 || in_dom(ip, 2, i3));
+  // rows of pencils outside the analysis domain in (i2, i3) belong to the
+  // quadrature alone (it may run concurrently): they are not written here
+  const bool live = i < g.N && in_dom(ip, 1, i2) && (ND == 2 || in_dom(ip, 2, i3));
+  const bool inner = live && in_dom(ip, 0, i1);
   T* bnd = band + size_t(b) * g.S * g.ld;
   const size_t per = size_t(S1) * S2 * S3;
   const int sc = (g.S - 1) / 2;
@@ -189,32 +196,6 @@ __global__ void __launch_bounds__(kChunk)
       }
     }
   };
-  // per-row operands read from the band: a boundary row's own entries, or the
-  // exact partner entries an analysis-domain row copies; lanes that need
-  // neither read the first band entry (one cached line)
-  auto row_load = [&](int u, T* pu, T* pl) {
-    const int4 dd = dsl[u];
-    const int s = dd.x;
-    const int64_t off = dd.y + int64_t(g.m1) * (dd.z + int64_t(g.m2) * dd.w);
-    const bool has_lo = FORM == IGS_STIFFNESS || s != sc;
-    size_t au = 0, al = 0;
-    if (live) {
-      if (!inner) {
-        au = size_t(s) * g.ld + size_t(i);
-        if (has_lo) al = size_t(g.S - 1 - s) * g.ld + size_t(i);
-      } else {
-        const bool up = in_dom(ip, 0, i1 + dd.y) && in_dom(ip, 1, i2 + dd.z) && (ND == 2 || in_dom(ip, 2, i3 + dd.w));
-        if (!up) au = size_t(g.S - 1 - s) * g.ld + size_t(i + off);  // exact A_ji, row j = i + delta
-        if (has_lo) {
-          const bool lo = in_dom(ip, 0, i1 - dd.y) && in_dom(ip, 1, i2 - dd.z) && (ND == 2 || in_dom(ip, 2, i3 - dd.w));
-          if (!lo) al = size_t(s) * g.ld + size_t(i - off);  // exact A_{j,j+delta}, row j = i - delta
-        }
-      }
-    }
-    *pu = bnd[au];
-    *pl = bnd[al];
-  };
-
   T wgt[MULTI ? 1 : NC];
   double cv[MULTI ? 1 : NC];
   // The steady-state loop issues the same global loads and stores on every
@@ -224,8 +205,6 @@ __global__ void __launch_bounds__(kChunk)
   // operands prefetched one delta ahead are not drained early.
   const int tt = MULTI ? 0 : tid % ntask;
   if constexpr (!MULTI) task_load(0, tt, wgt, cv);
-  T pu, pl;
-  row_load(0, &pu, &pl);
   T dsum = T(0);
   // dead rows (beyond N in the last chunk) write into the padding of slot 0,
   // which zero_pad clears afterwards
@@ -255,41 +234,35 @@ __global__ void __launch_bounds__(kChunk)
     }
     __syncthreads();
     const bool has_lo = FORM == IGS_STIFFNESS || s != sc;
-    T vu = pu, vl = pl;
+    // placeholders (0) where the entry is not interpolated: the quadrature of
+    // boundary rows and the copy kernel overwrite them
+    T vu = T(0), vl = T(0);
     if (inner) {
       const T* Tk = Tu + size_t(k) * 2 * S1;
       const bool up = in_dom(ip, 0, i1 + dl1) && in_dom(ip, 1, i2 + dl2) && (ND == 2 || in_dom(ip, 2, i3 + dl3));
       if (up) {
         const int f1 = tf1[i1];
         const T* bb = tb1 + i1 * (Q + 1);
-        vu = T(0);
 #pragma unroll
         for (int a = 0; a <= Q; ++a) vu += bb[a] * Tk[f1 + a];
       }
-      if (FORM == IGS_STIFFNESS) dsum += vu;
       if (has_lo) {
         const int j1 = i1 - dl1;
         const bool lo = in_dom(ip, 0, j1) && in_dom(ip, 1, i2 - dl2) && (ND == 2 || in_dom(ip, 2, i3 - dl3));
         if (lo) {
           const int f1 = tf1[j1];
           const T* bb = tb1 + j1 * (Q + 1);
-          vl = T(0);
 #pragma unroll
           for (int a = 0; a <= Q; ++a) vl += bb[a] * Tk[S1 + f1 + a];
         }
-        if (FORM == IGS_STIFFNESS) dsum += vl;
       }
+      if (FORM == IGS_STIFFNESS) dsum += vu + vl;
     }
-    // boundary rows store back their exact values with the same instruction,
-    // so every line of the chunk is written whole
     bnd[live ? size_t(s) * g.ld + irow : irow] = vu;
     if (has_lo) bnd[live ? size_t(g.S - 1 - s) * g.ld + irow : irow] = vl;
-    row_load(u + 1 < ip.nup ? u + 1 : u, &pu, &pl);  // prefetch for the next delta
   }
-  if (FORM == IGS_STIFFNESS && live) {
-    const size_t ic = size_t(sc) * g.ld + size_t(i);
-    bnd[ic] = inner ? -dsum : bnd[ic];
-  }
+  // diagonal of the interpolated part (the copy kernel subtracts the copies)
+  if (FORM == IGS_STIFFNESS) bnd[live ? size_t(sc) * g.ld + irow : irow] = inner ? -dsum : T(0);
 }
 
 // Fast path: R rows per thread (chunks of R*kChunk rows), per-delta metadata
@@ -351,17 +324,18 @@ __global__ void __launch_bounds__(kChunk)
   bool live[R], inner[R];
   int i1r[R], kr[R], mask[R], f1u[R];
   size_t irow[R];
-  T bu[R][Q + 1], dsum[R], pu[R], pl[R];
+  T bu[R][Q + 1], dsum[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int64_t i = c0 + tid + int64_t(r) * kChunk;
     const int64_t pen = i < g.N ? i / g.m1 : pen0;
     const int i1 = i < g.N ? int(i - pen * g.m1) : 0;
     const int i2 = int(pen % g.m2), i3 = int(pen / g.m2);
-    // rows of pencils outside the analysis domain in (i2, i3) are left to the
-    // quadrature (whole pencils: their lines are not shared with domain rows
-    // except at the two ends of a run of domain pencils); rows of domain
-    // pencils outside it in i1 share lines and are stored back
+    // rows of pencils outside the analysis domain in (i2, i3) belong to the
+    // quadrature alone (whole pencils: their lines are not shared with domain
+    // rows except at the two ends of a run of domain pencils) and are not
+    // written here; rows of domain pencils outside it in i1 share lines with
+    // domain rows and get placeholders that their quadrature overwrites later
     live[r] = i < g.N && in_dom(ip, 1, i2) && (ND == 2 || in_dom(ip, 2, i3));
     inner[r] = live[r] && in_dom(ip, 0, i1);
     i1r[r] = i1;
@@ -415,25 +389,27 @@ __global__ void __launch_bounds__(kChunk)
   }
   const int nblk = n3 * n2 * S1;
   double cs[kStage];
+  // this thread's staged block entries: offsets into a delta's coefficient
+  // array (loop-invariant; -1 for entries beyond the block)
+  int soff[kStage];
+#pragma unroll
+  for (int k = 0; k < kStage; ++k) {
+    const int e = tid + k * kChunk;
+    const int c1 = e % S1, r = e / S1;
+    const int l2 = r % n2, l3 = r / n2;
+    soff[k] = (STAGE && e < nblk) ? int((size_t(c3lo + l3) * S2 + c2lo + l2) * S1 + c1) : -1;
+  }
   auto stage_load = [&](int u) {
     const double* cu = coef + (size_t(b) * ip.nup + u) * per;
 #pragma unroll
-    for (int k = 0; k < kStage; ++k) {
-      const int e = tid + k * kChunk;
-      if (e < nblk) {
-        const int c1 = e % S1, r = e / S1;
-        const int l2 = r % n2, l3 = r / n2;
-        cs[k] = cu[(size_t(c3lo + l3) * S2 + c2lo + l2) * S1 + c1];
-      }
-    }
+    for (int k = 0; k < kStage; ++k)
+      if (soff[k] >= 0) cs[k] = cu[soff[k]];
   };
   auto stage_store = [&](int u) {
     double* cb = Cb + (u & 1) * blk;
 #pragma unroll
-    for (int k = 0; k < kStage; ++k) {
-      const int e = tid + k * kChunk;
-      if (e < nblk) cb[e] = cs[k];
-    }
+    for (int k = 0; k < kStage; ++k)
+      if (soff[k] >= 0) cb[tid + k * kChunk] = cs[k];
   };
   if constexpr (STAGE) {
     stage_load(0);
@@ -475,29 +451,7 @@ __global__ void __launch_bounds__(kChunk)
           cv[a3 * (Q + 1) + a2] = cu[(size_t(tf3v + a3) * S2 + tf2v + a2) * S1 + tc1];
     }
   };
-  auto row_load = [&](int u) {
-    const int4 dd = dsl[u];
-    const int s = dd.x;
-    const int64_t off = dd.y + int64_t(g.m1) * (dd.z + int64_t(g.m2) * dd.w);
-    const bool has_lo = FORM == IGS_STIFFNESS || s != sc;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      size_t au = 0, al = 0;
-      if (live[r]) {
-        if (!inner[r]) {
-          au = size_t(s) * ld + irow[r];
-          if (has_lo) al = Sm1ld - size_t(s) * ld + irow[r];
-        } else {
-          if (!inside(mask[r], dd.y, dd.z, dd.w)) au = Sm1ld - size_t(s) * ld + size_t(int64_t(irow[r]) + off);
-          if (has_lo && !inside(mask[r], -dd.y, -dd.z, -dd.w)) al = size_t(s) * ld + size_t(int64_t(irow[r]) - off);
-        }
-      }
-      pu[r] = bnd[au];
-      pl[r] = bnd[al];
-    }
-  };
   task_load(0);
-  row_load(0);
 
   for (int u = 0; u < ip.nup; ++u) {
     const int4 dd = dsl[u];
@@ -542,39 +496,32 @@ __global__ void __launch_bounds__(kChunk)
     const size_t su = size_t(s) * ld, sl = Sm1ld - size_t(s) * ld;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      T vu = pu[r], vl = pl[r];
-      if (inner[r]) {
-        const T* Tk = Tu + size_t(kr[r]) * 2 * S1;
-        if (inside(mask[r], dl1, dl2, dl3)) {
-          vu = T(0);
+      // placeholders (0) where the entry is not interpolated: the quadrature of
+      // boundary rows and the copy kernel overwrite them
+      // branch-free: every row evaluates both (its table reads stay in range:
+      // rows outside the domain have zero weights and first function 0) and
+      // the domain tests select
+      const T* Tk = Tu + size_t(kr[r]) * 2 * S1;
+      T vu = T(0), vl = T(0);
 #pragma unroll
-          for (int a = 0; a <= Q; ++a) vu += bu[r][a] * Tk[f1u[r] + a];
-        }
-        if (FORM == IGS_STIFFNESS) dsum[r] += vu;
-        if (has_lo) {
-          if (inside(mask[r], -dl1, -dl2, -dl3)) {
-            const int j1 = i1r[r] - dl1;
-            const int f1 = tf1[j1];
-            vl = T(0);
+      for (int a = 0; a <= Q; ++a) vu += bu[r][a] * Tk[f1u[r] + a];
+      vu = (inner[r] && inside(mask[r], dl1, dl2, dl3)) ? vu : T(0);
+      if (has_lo) {
+        const int j1 = min(max(i1r[r] - dl1, 0), g.m1 - 1);
+        const int f1 = tf1[j1];
 #pragma unroll
-            for (int a = 0; a <= Q; ++a) vl += tb1[a * g.m1 + j1] * Tk[S1 + f1 + a];
-          }
-          if (FORM == IGS_STIFFNESS) dsum[r] += vl;
-        }
+        for (int a = 0; a <= Q; ++a) vl += tb1[a * g.m1 + j1] * Tk[S1 + f1 + a];
+        vl = (inner[r] && inside(mask[r], -dl1, -dl2, -dl3)) ? vl : T(0);
       }
-      // boundary rows store back their exact values with the same instruction
+      if (FORM == IGS_STIFFNESS) dsum[r] += vu + vl;
       bnd[live[r] ? su + irow[r] : irow[r]] = vu;
       if (has_lo) bnd[live[r] ? sl + irow[r] : irow[r]] = vl;
     }
-    row_load(u + 1 < ip.nup ? u + 1 : u);
   }
+  // diagonal of the interpolated part (the copy kernel subtracts the copies)
   if (FORM == IGS_STIFFNESS) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (!live[r]) continue;
-      const size_t ic = size_t(sc) * ld + irow[r];
-      bnd[ic] = inner[r] ? -dsum[r] : bnd[ic];
-    }
+    for (int r = 0; r < R; ++r) bnd[live[r] ? size_t(sc) * ld + irow[r] : irow[r]] = inner[r] ? -dsum[r] : T(0);
   }
 }
 
@@ -586,6 +533,72 @@ __global__ void zero_pad_kernel(T* band, int64_t N, int64_t ld, int slots_total)
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
     const int64_t s = t / pad;
     band[s * ld + N + (t - s * pad)] = T(0);
+  }
+}
+
+// ------------------------------------------------------------------ copy ----
+//
+// Analysis-domain rows whose stencil leaves the analysis domain (listed on the
+// host in flat order): every slot whose partner j = i + delta lies outside
+// takes the exact entry A_ij, read as A_ji from slot -delta of row j (a row
+// assembled by quadrature; the form is symmetric), and the stiffness
+// diagonal, which the fill left at minus the sum of the interpolated entries,
+// loses these entries too (eq. 5.1c).  Runs after the fill and every
+// quadrature launch of the assembly.
+//
+// A workgroup takes 64 rows (one per lane); its four waves split the rows'
+// (delta2, delta3) lines, so each wave waits on memory about a quarter as
+// often, and the 2p+1 loads of a line are issued before any is used.  The
+// waves' partial sums meet in LDS in a fixed order.
+constexpr int kCopyWaves = 4;
+
+template <int ND, int FORM, int P, typename T>
+__global__ void __launch_bounds__(64 * kCopyWaves)
+    copy_kernel(KInterp<T> ip, int m1, int m2, int64_t ld, int S, const int* __restrict__ rows, int nrows,
+                T* __restrict__ band) {
+  constexpr int W = 2 * P + 1, NL = ND == 3 ? W * W : W;
+  __shared__ T part[kCopyWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int t = blockIdx.x * 64 + lane;
+  const bool ok = t < nrows;
+  const int64_t i = rows[ok ? t : 0];
+  const int64_t pen = i / m1;
+  const int i1 = int(i - pen * m1), i2 = int(pen % m2), i3 = ND == 3 ? int(pen / m2) : 0;
+  T* bnd = band + size_t(blockIdx.y) * S * ld;
+  const size_t Sm1ld = size_t(S - 1) * ld;
+  int o1 = 0;  // bit d1 + P: i1 + d1 leaves the domain
+#pragma unroll
+  for (int d1 = -P; d1 <= P; ++d1) o1 |= in_dom(ip, 0, i1 + d1) ? 0 : 1 << (d1 + P);
+  T csum = T(0);
+  for (int L = w; L < NL; L += kCopyWaves) {
+    const int d2 = L % W - P, d3 = ND == 3 ? L / W - P : 0;
+    const bool out23 = !in_dom(ip, 1, i2 + d2) || (ND == 3 && !in_dom(ip, 2, i3 + d3));
+    const int om = ok ? (out23 ? (1 << W) - 1 : o1) : 0;
+    const int s0 = W * L;
+    const int64_t off0 = int64_t(m1) * (d2 + int64_t(m2) * d3);
+    T v[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      v[k] = T(0);
+      if (om >> k & 1) v[k] = bnd[Sm1ld - size_t(s0 + k) * ld + size_t(i + off0 + (k - P))];
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+      if (om >> k & 1) {
+        bnd[size_t(s0 + k) * ld + size_t(i)] = v[k];
+        csum += v[k];
+      }
+  }
+  if (FORM == IGS_STIFFNESS) {
+    part[w][lane] = csum;
+    __syncthreads();
+    if (w == 0 && ok) {
+      T c = part[0][lane];
+#pragma unroll
+      for (int k = 1; k < kCopyWaves; ++k) c += part[k][lane];
+      const size_t ic = size_t((S - 1) / 2) * ld + size_t(i);
+      bnd[ic] = bnd[ic] - c;
+    }
   }
 }
 
@@ -790,6 +803,66 @@ template hipError_t launch_fill<float>(const KInterp<float>&, int, const Dims&, 
                                        const int4*, const double*, float*, hipStream_t);
 template size_t fill_lds_bytes<double>(const KInterp<double>&, int, const Dims&, int);
 template size_t fill_lds_bytes<float>(const KInterp<float>&, int, const Dims&, int);
+
+// analysis-domain rows within p-1 of the domain's edge in some direction: the
+// rows whose stencil reaches outside the analysis domain, in flat order
+std::vector<int> copy_rows(const Dims& d) {
+  const int p = d.p;
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int k = 0; k < d.n; ++k) {
+    lo[k] = 2 * p;
+    hi[k] = d.m[k] - 2 * p - 1;
+  }
+  auto edge = [&](int k, int i) { return k < d.n && (i < lo[k] + p || i > hi[k] - p); };
+  std::vector<int> out;
+  for (int i3 = lo[2]; i3 <= hi[2]; ++i3)
+    for (int i2 = lo[1]; i2 <= hi[1]; ++i2) {
+      const int64_t base = int64_t(d.m[0]) * (i2 + int64_t(d.m[1]) * i3);
+      if (edge(1, i2) || edge(2, i3)) {
+        for (int i1 = lo[0]; i1 <= hi[0]; ++i1) out.push_back(int(base + i1));
+      } else {
+        // only the rows near the two ends of the pencil's domain range
+        for (int i1 = lo[0]; i1 <= hi[0]; ++i1) {
+          if (!edge(0, i1)) i1 = std::max(i1, hi[0] - p + 1);
+          if (i1 <= hi[0]) out.push_back(int(base + i1));
+        }
+      }
+    }
+  return out;
+}
+
+template <int ND, int FORM, typename T>
+static void launch_copy_p(const KInterp<T>& ip, const Dims& d, const int* rows, int nrows, T* band, hipStream_t s) {
+  dim3 grid((nrows + 63) / 64, d.batch);
+  switch (d.p) {
+    case 1: hipLaunchKernelGGL((copy_kernel<ND, FORM, 1, T>), grid, dim3(64 * kCopyWaves), 0, s, ip, d.m[0], d.m[1], d.ld, d.S, rows, nrows, band); break;
+    case 2: hipLaunchKernelGGL((copy_kernel<ND, FORM, 2, T>), grid, dim3(64 * kCopyWaves), 0, s, ip, d.m[0], d.m[1], d.ld, d.S, rows, nrows, band); break;
+    case 3: hipLaunchKernelGGL((copy_kernel<ND, FORM, 3, T>), grid, dim3(64 * kCopyWaves), 0, s, ip, d.m[0], d.m[1], d.ld, d.S, rows, nrows, band); break;
+    default: hipLaunchKernelGGL((copy_kernel<ND, FORM, 4, T>), grid, dim3(64 * kCopyWaves), 0, s, ip, d.m[0], d.m[1], d.ld, d.S, rows, nrows, band); break;
+  }
+}
+
+template <typename T>
+hipError_t launch_copy(const KInterp<T>& ip, int form, const Dims& d, const int* rows, int nrows, T* band,
+                       hipStream_t s) {
+  if (nrows == 0) return hipSuccess;
+  if (d.n == 3) {
+    if (form == IGS_MASS)
+      launch_copy_p<3, IGS_MASS, T>(ip, d, rows, nrows, band, s);
+    else
+      launch_copy_p<3, IGS_STIFFNESS, T>(ip, d, rows, nrows, band, s);
+  } else {
+    if (form == IGS_MASS)
+      launch_copy_p<2, IGS_MASS, T>(ip, d, rows, nrows, band, s);
+    else
+      launch_copy_p<2, IGS_STIFFNESS, T>(ip, d, rows, nrows, band, s);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_copy<double>(const KInterp<double>&, int, const Dims&, const int*, int, double*,
+                                        hipStream_t);
+template hipError_t launch_copy<float>(const KInterp<float>&, int, const Dims&, const int*, int, float*, hipStream_t);
 
 template <typename T>
 hipError_t launch_zero_pad(T* band, int64_t N, int64_t ld, int slots_total, hipStream_t s) {

@@ -107,8 +107,9 @@ igs_status build_interp(const Dims& d, int form, int M, int q, int boxlen[3], Ho
 
 // Tile lists.
 std::vector<QTile> tiles_all(const Dims& d, int tx, int ty, int zchunk);
-// groups[0..2] = tile counts of the boundary pencils, the end slabs of the
-// interior pencils, and the sample rows (in that order in the list)
+// groups[0..2] = tile counts of the rows of the analysis-domain pencils
+// (pencils along i1) outside the domain in i1, the rows of the other pencils,
+// and the sample rows (in that order in the list)
 std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3], int tx, int ty, int zchunk,
                                    int groups[3]);
 

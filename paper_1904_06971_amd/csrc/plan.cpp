@@ -349,34 +349,39 @@ void tile_rect(std::vector<QTile>* out, int x0, int x1, int y0, int y1, int tx, 
 }  // namespace
 
 // Rows assembled by quadrature in the surrogate: every row outside the
-// analysis domain [2p, m-2p-1]^n plus the sample lattice.
+// analysis domain [2p, m-2p-1]^n plus the sample lattice, in three groups.
+// Group 0: rows of the analysis-domain pencils (pencils along i1, the flat
+// index's fastest direction) outside the domain in i1.  Group 1: rows of the
+// pencils outside the analysis domain in (i2, i3).  Group 2: the sample rows,
+// single-row tiles.  Groups 0 and 1 run as one launch; the list puts the long
+// tiles (whole columns, chunked along the streamed direction) before the short
+// end slabs so that the short ones fill the launch's tail.
 std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3], int tx, int ty, int zchunk,
                                    int groups[3]) {
   std::vector<QTile> out;
   const int p = d.p;
+  const int lo1 = 2 * p, hi1 = d.m[0] - 2 * p, lo2 = 2 * p, hi2 = d.m[1] - 2 * p;
   if (d.n == 3) {
-    const int lo1 = 2 * p, hi1 = d.m[0] - 2 * p, lo2 = 2 * p, hi2 = d.m[1] - 2 * p;
     const int lo3 = 2 * p, hi3 = d.m[2] - 2 * p;
-    // (i1, i2) frame: whole pencils
+    // tiles are (i1, i2) rectangles streamed along i3
+    tile_rect(&out, 0, lo1, lo2, hi2, tx, ty, lo3, hi3, zchunk);
+    tile_rect(&out, hi1, d.m[0], lo2, hi2, tx, ty, lo3, hi3, zchunk);
+    groups[0] = int(out.size());
     tile_rect(&out, 0, d.m[0], 0, lo2, tx, ty, 0, d.m[2], zchunk);
     tile_rect(&out, 0, d.m[0], hi2, d.m[1], tx, ty, 0, d.m[2], zchunk);
-    tile_rect(&out, 0, lo1, lo2, hi2, tx, ty, 0, d.m[2], zchunk);
-    tile_rect(&out, hi1, d.m[0], lo2, hi2, tx, ty, 0, d.m[2], zchunk);
-    groups[0] = int(out.size());
-    // interior pencils: the two end slabs in i3
-    tile_rect(&out, lo1, hi1, lo2, hi2, tx, ty, 0, lo3, zchunk);
-    tile_rect(&out, lo1, hi1, lo2, hi2, tx, ty, hi3, d.m[2], zchunk);
+    tile_rect(&out, 0, d.m[0], lo2, hi2, tx, ty, 0, lo3, zchunk);
+    tile_rect(&out, 0, d.m[0], lo2, hi2, tx, ty, hi3, d.m[2], zchunk);
     groups[1] = int(out.size()) - groups[0];
     for (int s3 : samp[2])
       for (int s2 : samp[1])
         for (int s1 : samp[0]) out.push_back(QTile{s1, s2, 1, 1, s3, s3 + 1});
   } else {
-    const int lo1 = 2 * p, hi1 = d.m[0] - 2 * p, lo2 = 2 * p, hi2 = d.m[1] - 2 * p;
-    tile_rect(&out, 0, lo1, 0, 1, tx, 1, 0, d.m[1], zchunk);
-    tile_rect(&out, hi1, d.m[0], 0, 1, tx, 1, 0, d.m[1], zchunk);
+    // tiles are i1 ranges streamed along i2
+    tile_rect(&out, 0, lo1, 0, 1, tx, 1, lo2, hi2, zchunk);
+    tile_rect(&out, hi1, d.m[0], 0, 1, tx, 1, lo2, hi2, zchunk);
     groups[0] = int(out.size());
-    tile_rect(&out, lo1, hi1, 0, 1, tx, 1, 0, lo2, zchunk);
-    tile_rect(&out, lo1, hi1, 0, 1, tx, 1, hi2, d.m[1], zchunk);
+    tile_rect(&out, 0, d.m[0], 0, 1, tx, 1, 0, lo2, zchunk);
+    tile_rect(&out, 0, d.m[0], 0, 1, tx, 1, hi2, d.m[1], zchunk);
     groups[1] = int(out.size()) - groups[0];
     for (int s2 : samp[1])
       for (int s1 : samp[0]) out.push_back(QTile{s1, 0, 1, 1, s2, s2 + 1});
