@@ -37,9 +37,10 @@ FP64_PEAK_TFLOPS = 78.6
 # reported while the kernel source still hashes to the one measured.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.00, 1.00
 PMC_TRAFFIC = {
-    "quad_boundary_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "", "fetch_kib": 0.0, "write_kib": 0.0},
-    "fill": {"sources": ["fill.hip"], "sha256": "", "fetch_kib": 0.0, "write_kib": 0.0},
-    "copy": {"sources": ["fill.hip"], "sha256": "", "fetch_kib": 0.0, "write_kib": 0.0},
+    "quad_boundary_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "d60326ae688793a7", "fetch_kib": 13949.2,
+                           "write_kib": 2097916.6},
+    "fill": {"sources": ["fill.hip"], "sha256": "18e111884bf86bdd", "fetch_kib": 142574.9, "write_kib": 4971999.7},
+    "copy": {"sources": ["fill.hip"], "sha256": "18e111884bf86bdd", "fetch_kib": 360706.5, "write_kib": 301085.9},
 }
 
 
