@@ -63,6 +63,9 @@ struct CgScalars {
   int replace;    // residual replacement due after this iteration
   int nrep;       // replacements made
   int pad;
+  // plain CG: r^T r of iterations k (rrv[k & 1]) and k + 1 (rrv[(k + 1) & 1]);
+  // the fused kernels of iteration k read one and write the other
+  double rrv[2];
 };
 
 // Banded SpMV for both band types.  A thread owns R consecutive rows, so one
@@ -334,6 +337,8 @@ __global__ void cg_setup_kernel(int batch, const double* __restrict__ rr, const 
   s.replace = 0;
   s.nrep = 0;
   s.pad = 0;
+  s.rrv[0] = s.rr;
+  s.rrv[1] = 0.0;
   sc[b] = s;
 }
 
@@ -405,6 +410,74 @@ __global__ void cg_pupdate_kernel(int64_t N, const CgScalars* __restrict__ sc, c
   if (sc[b].done) return;
   const T beta = T(sc[b].beta);
   for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+    const size_t k = size_t(b) * N + i;
+    p[k] = r[k] + beta * p[k];
+  }
+}
+
+// Fused plain-CG steps.  Every workgroup reduces the same per-block partial
+// sums in the same order, so all of them hold the same scalar and none waits
+// for another; only workgroup 0 records it.  Iteration k reads r^T r from
+// rrv[k & 1] and the next one's from rrv[(k + 1) & 1].
+__device__ __forceinline__ double sum_parts(const double* __restrict__ part, int b, int nparts) {
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += kRedBlock) s += part[size_t(b) * nparts + k];
+  return block_sum<double>(s);
+}
+
+// alpha = rr / (p^T A p); d += alpha p, r -= alpha q, partial r^T r
+template <typename T>
+__global__ void __launch_bounds__(kSpmvBlock)
+    cg_step_kernel(int64_t N, int par, CgScalars* __restrict__ sc, const double* __restrict__ pap,
+                   const T* __restrict__ p, const T* __restrict__ q, T* __restrict__ d, T* __restrict__ r,
+                   double* __restrict__ part) {
+  const int b = blockIdx.y;
+  if (sc[b].done) return;
+  const double s = sum_parts(pap, b, gridDim.x);
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  if (!(s > 0.0) || !isfinite(s)) {
+    if (lb == 0 && threadIdx.x == 0) {
+      sc[b].done = 1;
+      sc[b].breakdown = 1;
+    }
+    return;
+  }
+  const T alpha = T(sc[b].rrv[par] / s);
+  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
+  double v = 0.0;
+  if (i < N) {
+    const size_t k = size_t(b) * N + i;
+    d[k] += alpha * p[k];
+    const T rn = r[k] - alpha * q[k];
+    r[k] = rn;
+    v = double(rn) * double(rn);
+  }
+  v = block_sum<double>(v);
+  if (threadIdx.x == 0) part[size_t(b) * gridDim.x + lb] = v;
+}
+
+// beta = rr_new / rr, p = r + beta p; convergence on the recursive residual
+template <typename T>
+__global__ void __launch_bounds__(kSpmvBlock)
+    cg_dir_kernel(int64_t N, int par, CgScalars* __restrict__ sc, const double* __restrict__ rrp,
+                  const T* __restrict__ r, T* __restrict__ p) {
+  const int b = blockIdx.y;
+  if (sc[b].done) return;
+  const double s = sum_parts(rrp, b, gridDim.x);
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  if (lb == 0 && threadIdx.x == 0) {
+    sc[b].rrv[par ^ 1] = s;
+    sc[b].iters += 1;
+    if (!isfinite(s)) {
+      sc[b].done = 1;
+      sc[b].breakdown = 1;
+    } else if (s <= sc[b].tol2) {
+      sc[b].done = 1;
+    }
+  }
+  const T beta = T(s / sc[b].rrv[par]);
+  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
+  if (i < N) {
     const size_t k = size_t(b) * N + i;
     p[k] = r[k] + beta * p[k];
   }
@@ -532,12 +605,11 @@ static igs_status inner_cg(const Dims& d, const T* band, const SolveBufs& sb, T*
           launch_spmv64<1>(g, nblk, d.batch, band, p, nullptr, q, nullptr, 1, sb.sc, sb.part, nullptr, s);
       }
       PhaseTimer t("cg_vector_ops", s);
-      hipLaunchKernelGGL(cg_alpha_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
-      hipLaunchKernelGGL((cg_update_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, sb.sc, p, q, dv,
-                         rh, sb.part2);
-      hipLaunchKernelGGL(cg_beta_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part2, nblk, sb.sc);
-      hipLaunchKernelGGL((cg_pupdate_kernel<T>), dim3(std::min<int64_t>((d.N + 255) / 256, 4096), d.batch),
-                         dim3(256), 0, s, d.N, sb.sc, rh, p);
+      const int par = (done_iters + it) & 1;
+      hipLaunchKernelGGL((cg_step_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, par, sb.sc,
+                         sb.part, p, q, dv, rh, sb.part2);
+      hipLaunchKernelGGL((cg_dir_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, par, sb.sc,
+                         sb.part2, rh, p);
     }
     HIP_OK(hipGetLastError());
     done_iters += k;
