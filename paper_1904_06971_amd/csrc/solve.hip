@@ -360,48 +360,6 @@ __global__ void __launch_bounds__(kRedBlock) cg_alpha_kernel(const double* __res
   }
 }
 
-// d += alpha p, r -= alpha q, partial r^T r
-template <typename T>
-__global__ void __launch_bounds__(kSpmvBlock)
-    cg_update_kernel(int64_t N, const CgScalars* __restrict__ sc, const T* __restrict__ p, const T* __restrict__ q,
-                     T* __restrict__ d, T* __restrict__ r, double* __restrict__ part) {
-  const int b = blockIdx.y;
-  if (sc[b].done) return;
-  const T alpha = T(sc[b].alpha);
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
-  double v = 0.0;
-  if (i < N) {
-    const size_t k = size_t(b) * N + i;
-    d[k] += alpha * p[k];
-    const T rn = r[k] - alpha * q[k];
-    r[k] = rn;
-    v = double(rn) * double(rn);
-  }
-  v = block_sum<double>(v);
-  if (threadIdx.x == 0) part[size_t(b) * gridDim.x + lb] = v;
-}
-
-// beta = rr_new / rr; convergence on the recursive residual
-__global__ void __launch_bounds__(kRedBlock) cg_beta_kernel(const double* __restrict__ part, int nblk, CgScalars* sc) {
-  const int b = blockIdx.x;
-  if (sc[b].done) return;
-  double s = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += kRedBlock) s += part[size_t(b) * nblk + k];
-  s = block_sum<double>(s);
-  if (threadIdx.x == 0) {
-    sc[b].beta = s / sc[b].rr;
-    sc[b].rr = s;
-    sc[b].iters += 1;
-    if (!isfinite(s)) {
-      sc[b].done = 1;
-      sc[b].breakdown = 1;
-    } else if (s <= sc[b].tol2) {
-      sc[b].done = 1;
-    }
-  }
-}
-
 // p = r + beta p
 template <typename T>
 __global__ void cg_pupdate_kernel(int64_t N, const CgScalars* __restrict__ sc, const T* __restrict__ r,
