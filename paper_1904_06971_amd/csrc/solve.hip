@@ -360,6 +360,48 @@ __global__ void __launch_bounds__(kRedBlock) cg_alpha_kernel(const double* __res
   }
 }
 
+// d += alpha p, r -= alpha q, partial r^T r
+template <typename T>
+__global__ void __launch_bounds__(kSpmvBlock)
+    cg_update_kernel(int64_t N, const CgScalars* __restrict__ sc, const T* __restrict__ p, const T* __restrict__ q,
+                     T* __restrict__ d, T* __restrict__ r, double* __restrict__ part) {
+  const int b = blockIdx.y;
+  if (sc[b].done) return;
+  const T alpha = T(sc[b].alpha);
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
+  double v = 0.0;
+  if (i < N) {
+    const size_t k = size_t(b) * N + i;
+    d[k] += alpha * p[k];
+    const T rn = r[k] - alpha * q[k];
+    r[k] = rn;
+    v = double(rn) * double(rn);
+  }
+  v = block_sum<double>(v);
+  if (threadIdx.x == 0) part[size_t(b) * gridDim.x + lb] = v;
+}
+
+// beta = rr_new / rr; convergence on the recursive residual
+__global__ void __launch_bounds__(kRedBlock) cg_beta_kernel(const double* __restrict__ part, int nblk, CgScalars* sc) {
+  const int b = blockIdx.x;
+  if (sc[b].done) return;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += kRedBlock) s += part[size_t(b) * nblk + k];
+  s = block_sum<double>(s);
+  if (threadIdx.x == 0) {
+    sc[b].beta = s / sc[b].rr;
+    sc[b].rr = s;
+    sc[b].iters += 1;
+    if (!isfinite(s)) {
+      sc[b].done = 1;
+      sc[b].breakdown = 1;
+    } else if (s <= sc[b].tol2) {
+      sc[b].done = 1;
+    }
+  }
+}
+
 // p = r + beta p
 template <typename T>
 __global__ void cg_pupdate_kernel(int64_t N, const CgScalars* __restrict__ sc, const T* __restrict__ r,
@@ -373,10 +415,13 @@ __global__ void cg_pupdate_kernel(int64_t N, const CgScalars* __restrict__ sc, c
   }
 }
 
-// Fused plain-CG steps.  Every workgroup reduces the same per-block partial
-// sums in the same order, so all of them hold the same scalar and none waits
-// for another; only workgroup 0 records it.  Iteration k reads r^T r from
-// rrv[k & 1] and the next one's from rrv[(k + 1) & 1].
+// Fused plain-CG steps, for problems with at most kFuseParts partial sums per
+// problem (each workgroup reads all of them, so the cost grows with their
+// square).  Every workgroup reduces the same per-block partial sums in the
+// same order, so all of them hold the same scalar and none waits for another;
+// only workgroup 0 records it.  Iteration k reads r^T r from rrv[k & 1] and
+// the next one's from rrv[(k + 1) & 1].
+constexpr int kFuseParts = 1024;
 __device__ __forceinline__ double sum_parts(const double* __restrict__ part, int b, int nparts) {
   double s = 0.0;
   for (int k = threadIdx.x; k < nparts; k += kRedBlock) s += part[size_t(b) * nparts + k];
@@ -563,11 +608,20 @@ static igs_status inner_cg(const Dims& d, const T* band, const SolveBufs& sb, T*
           launch_spmv64<1>(g, nblk, d.batch, band, p, nullptr, q, nullptr, 1, sb.sc, sb.part, nullptr, s);
       }
       PhaseTimer t("cg_vector_ops", s);
-      const int par = (done_iters + it) & 1;
-      hipLaunchKernelGGL((cg_step_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, par, sb.sc,
-                         sb.part, p, q, dv, rh, sb.part2);
-      hipLaunchKernelGGL((cg_dir_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, par, sb.sc,
-                         sb.part2, rh, p);
+      if (nblk <= kFuseParts) {
+        const int par = (done_iters + it) & 1;
+        hipLaunchKernelGGL((cg_step_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, par, sb.sc,
+                           sb.part, p, q, dv, rh, sb.part2);
+        hipLaunchKernelGGL((cg_dir_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, par, sb.sc,
+                           sb.part2, rh, p);
+      } else {
+        hipLaunchKernelGGL(cg_alpha_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
+        hipLaunchKernelGGL((cg_update_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, sb.sc, p, q,
+                           dv, rh, sb.part2);
+        hipLaunchKernelGGL(cg_beta_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part2, nblk, sb.sc);
+        hipLaunchKernelGGL((cg_pupdate_kernel<T>), dim3(std::min<int64_t>((d.N + 255) / 256, 4096), d.batch),
+                           dim3(256), 0, s, d.N, sb.sc, rh, p);
+      }
     }
     HIP_OK(hipGetLastError());
     done_iters += k;

@@ -145,3 +145,27 @@ def test_cg_not_converged(igs):
     f = igs.assemble_rhs(prob, 0, 1.0)
     u, info = igs.solve_cg(prob, band, f, rtol=1e-10, maxit=3, check=False)
     assert info["status"] == 1 and info["iterations"] <= 3 + 32
+
+
+def test_cg_large(igs, oracle):
+    """A problem with more than 1024 SpMV workgroups per problem (373,248 dofs),
+    where the CG scalars are reduced by separate kernels: the returned solution
+    meets the tolerance on the FP64 residual recomputed by igs_apply, and agrees
+    with the FP32 solve with FP64 residual replacement (other kernels)."""
+    import torch
+
+    prob = W.problem(3, 2, 70)
+    band = igs.assemble_surrogate(prob, 0, M=8, q=3)
+    f = igs.assemble_rhs(prob, 1, 3 * math.pi ** 2)
+    u, info = igs.solve_cg(prob, band, f, rtol=1e-10)
+    assert info["status"] == 0 and info["relres"] <= 1e-10
+    # f restricted to the free dofs (no index on the boundary), minus A_II u_I
+    m, N, _ = oracle.dims(prob)
+    idx = oracle.multi_index(prob, np.arange(N))
+    free = torch.as_tensor(np.all((idx > 0) & (idx < np.asarray(m) - 1), axis=1), device="cuda")[None, :]
+    r = torch.where(free, f - igs.apply(prob, band, u, dirichlet=True), torch.zeros_like(f))
+    fn = torch.where(free, f, torch.zeros_like(f)).norm()
+    assert float(r.norm() / fn) <= 1e-10
+    umx, imx = igs.solve_cg(prob, band, f, band32=band.float(), rtol=1e-10)
+    assert imx["status"] == 0
+    assert float((umx - u).abs().max() / u.abs().max()) < 1e-7
