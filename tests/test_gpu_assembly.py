@@ -228,3 +228,40 @@ def test_c3_surrogate_sampled(igs, oracle):
     sur = oracle.Surrogate(prob, 0, 8, 3)
     rows = np.unique(np.concatenate([sur.sample_rows, rnd]))
     assert rel_maxnorm(gather_rows(band, rows), sur.rows(rows)) < TOL64
+
+
+# ------------------------------------------------- more surrogate cases ---
+def test_surrogate_batched_spline_3d(igs, oracle):
+    """3D surrogate of a batch of two exp-spline coefficient fields: the fill,
+    copy and quadrature kernels index the batch through the grid."""
+    rng = np.random.default_rng(11)
+    cc = rng.normal(0, 0.3, (2, 5 * 5 * 5))
+    prob = W.problem(3, 2, (18, 16, 17), coef="exp_spline", cdeg=2, cn=(5, 5, 5), cc=cc, batch=2)
+    band = igs.assemble_surrogate(prob, 0, M=4, q=3)
+    for b in range(2):
+        ref = oracle.surrogate_rows(prob, 0, 4, 3, b=b)
+        assert rel_maxnorm(_full(igs, band, prob, b), ref) < TOL64
+
+
+@pytest.mark.parametrize("prob,form,M,q", [(W.problem(2, 3, 70), 0, 5, 3), (W.problem(3, 3, 24), 1, 4, 3),
+                                           (W.problem(2, 2, 50), 1, 4, 3)])
+def test_surrogate_fp32_more(igs, oracle, prob, form, M, q):
+    """FP32 storage (fill in FP32 with FP32 accumulation) in 2D and for the
+    mass form, against the FP64 oracle at FP32 resolution."""
+    import torch
+
+    band = igs.assemble_surrogate(prob, form, M=M, q=q, dtype=torch.float32)
+    ref = oracle.surrogate_rows(prob, form, M, q)
+    assert rel_maxnorm(_full(igs, band, prob), ref) < 2e-6
+
+
+@pytest.mark.parametrize("prob,M,q", [(W.problem(3, 2, 19), 5, 3), (W.problem(2, 3, 40), 11, 3),
+                                      (W.problem(3, 1, 14), 10, 1)])
+def test_surrogate_few_samples(igs, oracle, prob, M, q):
+    """Sampling steps that leave exactly q+1 samples in a direction (the
+    smallest lattice the interpolant accepts), with a shorter last interval."""
+    m, N, _ = oracle.dims(prob)
+    assert min(len(oracle.lattice(m[d], prob["p"], M)) for d in range(prob["n"])) == q + 1
+    band = igs.assemble_surrogate(prob, 0, M=M, q=q)
+    ref = oracle.surrogate_rows(prob, 0, M, q)
+    assert rel_maxnorm(_full(igs, band, prob), ref) < TOL64
