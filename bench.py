@@ -221,6 +221,27 @@ def main():
         # -------------------------------------------------------- SpMV / CG
         plan.execute(out=band)
         b32 = igs.assemble_surrogate(prob, igs.STIFFNESS, M, q, dtype=torch.float32)
+        # precision form: the same surrogate assembly into FP32 storage (fill and
+        # interpolation in FP32), kept plan, timed like the FP64 step
+        plan32 = igs.Plan(prob, igs.STIFFNESS, M=M, q=q, dtype=torch.float32)
+        plan32.execute(out=b32)
+        igs.profile_enable(True)
+        igs.profile_read()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            plan32.execute(out=b32)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        p32 = igs.profile_read()
+        igs.profile_enable(False)
+        ms32 = e0.elapsed_time(e1) / 5
+        extra["fp32_assembly"] = {"ms": ms32, "slots_per_s": slots / (ms32 * 1e-3),
+                                  "phases_ms": {k: v[1] / v[0] for k, v in p32.items()},
+                                  "fill_GBps": fb / 2 / (p32["fill"][1] / p32["fill"][0] * 1e-3) / 1e9}
+        plan32.close()
+        log(f"fp32 assembly: {extra['fp32_assembly']}")
         x = torch.randn(1, lay.N, dtype=torch.float64, device=dev)
         x32 = x.float()
         y64, y32 = torch.empty_like(x), torch.empty_like(x32)
