@@ -146,8 +146,9 @@ __global__ void __launch_bounds__(kChunk)
     i3 = int(pen / g.m2);
   }
   const int k = int(pen - pen0);  // this row's pencil slot in the chunk
-  // rows of pencils outside the analysis domain in (i2, i3) belong to the
-  // quadrature alone (it may run concurrently): they are not written here
+  // rows of pencils outside the analysis domain in (i2, i3) are left to the
+  // quadrature (their lines are not shared with domain rows except at the two
+  // ends of a run of domain pencils)
   const bool live = i < g.N && in_dom(ip, 1, i2) && (ND == 2 || in_dom(ip, 2, i3));
   const bool inner = live && in_dom(ip, 0, i1);
   T* bnd = band + size_t(b) * g.S * g.ld;
