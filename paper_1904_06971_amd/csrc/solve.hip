@@ -85,18 +85,22 @@ struct CgScalars {
 //   2  (FP64) r = f - A u, Dirichlet rows 0, partials of r^T r and f^T f
 //   3  (FP64) r32 = float(f - A u) on problems with a residual replacement
 //      due, partials of r^T r
+// Sum over a workgroup of NT threads (a multiple of 64), returned to every
+// thread: a butterfly within each wavefront (lane exchanges, no LDS), then the
+// wavefronts' sums added in wavefront order.  Fixed order: deterministic.
 template <int NT>
 __device__ __forceinline__ double block_sum_n(double v) {
-  __shared__ double red[NT];
-  red[threadIdx.x] = v;
+  static_assert(NT % 64 == 0, "whole wavefronts");
+  __shared__ double red[NT / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int w = NT / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double r = red[0];
+  double s = red[0];
+#pragma unroll
+  for (int k = 1; k < NT / 64; ++k) s += red[k];
   __syncthreads();  // red is reused by a following call
-  return r;
+  return s;
 }
 
 template <typename T, int R>
@@ -288,14 +292,7 @@ __global__ void mask_copy_kernel(SpmvGeom g, int batch, const T* __restrict__ x,
 
 template <typename T>
 __device__ __forceinline__ double block_sum(double v) {
-  __shared__ double red[kRedBlock];
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = kRedBlock / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  return red[0];
+  return block_sum_n<kRedBlock>(v);
 }
 
 // out[b] = sum of part[b][0..nblk) in a fixed order (one block per problem)
