@@ -313,7 +313,8 @@ static igs_status run_t(const Plan& pl, const KProblem& kp, const KInterp<OutT>&
     // exact entries of those rows.
     const QTile* t2 = pl.dt + pl.groups[0] + pl.groups[1];
     {
-      // the sample rows: isolated, one workgroup each in 3-D (single-row tiles)
+      // the sample rows: isolated, one workgroup each in 3-D (single-row
+      // tiles); whole lattice lines in 2-D
       PhaseTimer t("quad_sample_rows", s);
       HIP_TRY(launch_quad<OutT>(kp, pl.form, t2, pl.groups[2], d.n == 3, band, s));
     }

@@ -352,10 +352,11 @@ void tile_rect(std::vector<QTile>* out, int x0, int x1, int y0, int y1, int tx, 
 // analysis domain [2p, m-2p-1]^n plus the sample lattice, in three groups.
 // Group 0: rows of the analysis-domain pencils (pencils along i1, the flat
 // index's fastest direction) outside the domain in i1.  Group 1: rows of the
-// pencils outside the analysis domain in (i2, i3).  Group 2: the sample rows,
-// single-row tiles.  Groups 0 and 1 run as one launch; the list puts the long
-// tiles (whole columns, chunked along the streamed direction) before the short
-// end slabs so that the short ones fill the launch's tail.
+// pencils outside the analysis domain in (i2, i3).  Group 2: the sample rows
+// (single-row tiles in 3-D, line tiles in 2-D).  Groups 0 and 1 run as one
+// launch; the list puts the long tiles (whole columns, chunked along the
+// streamed direction) before the short end slabs so that the short ones fill
+// the launch's tail.
 std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3], int tx, int ty, int zchunk,
                                    int groups[3]) {
   std::vector<QTile> out;
@@ -383,8 +384,12 @@ std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3]
     tile_rect(&out, 0, d.m[0], 0, 1, tx, 1, 0, lo2, zchunk);
     tile_rect(&out, 0, d.m[0], 0, 1, tx, 1, hi2, d.m[1], zchunk);
     groups[1] = int(out.size()) - groups[0];
-    for (int s2 : samp[1])
-      for (int s1 : samp[0]) out.push_back(QTile{s1, 0, 1, 1, s2, s2 + 1});
+    // a 2-D tile computes tx consecutive i1 for every i2 it streams: the
+    // sample rows of a lattice line i2 = s2 come from tiles over the line's
+    // analysis range (its other rows are domain rows that the fill, which runs
+    // later, overwrites), not from single-row tiles that would leave all but
+    // one of a tile's tx lanes idle
+    for (int s2 : samp[1]) tile_rect(&out, samp[0].front(), samp[0].back() + 1, 0, 1, tx, 1, s2, s2 + 1, 1);
   }
   groups[2] = int(out.size()) - groups[0] - groups[1];
   return out;
