@@ -268,7 +268,9 @@ __global__ void __launch_bounds__(kChunk)
 
 // Fast path: R rows per thread (chunks of R*kChunk rows), per-delta metadata
 // read from a host-built table through the scalar cache, per-row domain tests
-// as bitmasks, direction-1 weights of the upper entries kept in registers.
+// as bitmasks.  The direction-1 weights are read from LDS for every delta:
+// keeping a row's q+1 weights in registers costs the VGPRs that separate 4
+// from 5 waves per SIMD, and the extra wave hides more of the stores.
 // Requires npen*2*S1 <= kChunk pencil tasks per chunk.
 constexpr int kRows = 3;
 
@@ -325,7 +327,7 @@ __global__ void __launch_bounds__(kChunk)
   bool live[R], inner[R];
   int i1r[R], kr[R], mask[R], f1u[R];
   size_t irow[R];
-  T bu[R][Q + 1], dsum[R];
+  T dsum[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int64_t i = c0 + tid + int64_t(r) * kChunk;
@@ -356,8 +358,6 @@ __global__ void __launch_bounds__(kChunk)
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     f1u[r] = tf1[i1r[r]];
-#pragma unroll
-    for (int a = 0; a <= Q; ++a) bu[r][a] = tb1[a * g.m1 + i1r[r]];
   }
 
   auto inside = [&](int mk, int d1, int d2, int d3) {
@@ -505,7 +505,7 @@ __global__ void __launch_bounds__(kChunk)
       const T* Tk = Tu + size_t(kr[r]) * 2 * S1;
       T vu = T(0), vl = T(0);
 #pragma unroll
-      for (int a = 0; a <= Q; ++a) vu += bu[r][a] * Tk[f1u[r] + a];
+      for (int a = 0; a <= Q; ++a) vu += tb1[a * g.m1 + i1r[r]] * Tk[f1u[r] + a];
       vu = (inner[r] && inside(mask[r], dl1, dl2, dl3)) ? vu : T(0);
       if (has_lo) {
         const int j1 = min(max(i1r[r] - dl1, 0), g.m1 - 1);
