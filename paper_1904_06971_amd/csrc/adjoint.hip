@@ -327,6 +327,340 @@ __global__ void adj_red2_kernel(KProblem kp, const int* __restrict__ qlo, const 
   }
 }
 
+// ------------------------------------------------------------------ 3-D ----
+//
+// The same construction for n = 3 (p <= 3: an element's weight matrix of
+// (p+1)^3 x (p+1)^3 entries is held in LDS).
+
+struct AdjGeom3 {
+  int P, W, S, m1, m2, m3;
+  int64_t N, ld;
+  int lo, hi1, hi2, hi3;  // analysis range [lo, hi_d]
+  int form;
+  int surrogate;
+  const unsigned char *is_s1, *is_s2, *is_s3;
+};
+
+__device__ __forceinline__ bool interior3(const AdjGeom3& g, int i1, int i2, int i3) {
+  return i1 >= g.lo && i1 <= g.hi1 && i2 >= g.lo && i2 <= g.hi2 && i3 >= g.lo && i3 <= g.hi3;
+}
+
+__device__ __forceinline__ bool quad_row3(const AdjGeom3& g, int i1, int i2, int i3) {
+  if (!g.surrogate) return true;
+  if (!interior3(g, i1, i2, i3)) return true;
+  return g.is_s1[i1] && g.is_s2[i2] && g.is_s3[i3];
+}
+
+__device__ __forceinline__ double moved_weight3(const AdjGeom3& g, double yj, double xj, double xb) {
+  return g.form == IGS_STIFFNESS ? yj * (xb - xj) : yj * xb;
+}
+
+__global__ void adj_weights3_kernel(AdjGeom3 g, const double* __restrict__ x, const double* __restrict__ yb,
+                                    double* __restrict__ wbar) {
+  const int b = blockIdx.y;
+  const int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (i >= g.N) return;
+  const int i1 = int(i % g.m1);
+  const int64_t r = i / g.m1;
+  const int i2 = int(r % g.m2), i3 = int(r / g.m2);
+  const double* xb = x + size_t(b) * g.N;
+  const double* yy = yb + size_t(b) * g.N;
+  double* w = wbar + size_t(b) * g.S * g.ld;
+  const bool inner = g.surrogate && interior3(g, i1, i2, i3);
+  if (inner) {
+    if (g.is_s1[i1] && g.is_s2[i2] && g.is_s3[i3])
+      for (int s = 0; s < g.S; ++s) w[size_t(s) * g.ld + i] = 0.0;
+    return;
+  }
+  const double yi = yy[i];
+  for (int s = 0; s < g.S; ++s) {
+    const int d1 = s % g.W - g.P, d2 = (s / g.W) % g.W - g.P, d3 = s / (g.W * g.W) - g.P;
+    const int j1 = i1 + d1, j2 = i2 + d2, j3 = i3 + d3;
+    double v = 0.0;
+    if (j1 >= 0 && j1 < g.m1 && j2 >= 0 && j2 < g.m2 && j3 >= 0 && j3 < g.m3) {
+      const int64_t j = i + d1 + int64_t(g.m1) * (d2 + int64_t(g.m2) * d3);
+      v = yi * xb[j];
+      if (g.surrogate && s != (g.S - 1) / 2 && interior3(g, j1, j2, j3)) v += moved_weight3(g, yy[j], xb[j], xb[i]);
+    }
+    w[size_t(s) * g.ld + i] = v;
+  }
+}
+
+__device__ __forceinline__ double interp_weight3(const AdjGeom3& g, const double* xb, const double* yy, int p1,
+                                                 int p2, int p3, int d1, int d2, int d3) {
+  const int j1 = p1 + d1, j2 = p2 + d2, j3 = p3 + d3;
+  if (!interior3(g, j1, j2, j3)) return 0.0;
+  const int64_t p = p1 + int64_t(g.m1) * (p2 + int64_t(g.m2) * p3);
+  const int64_t j = j1 + int64_t(g.m1) * (j2 + int64_t(g.m2) * j3);
+  if (g.form == IGS_STIFFNESS) return (xb[j] - xb[p]) * (yy[p] - yy[j]);
+  if (d1 == 0 && d2 == 0 && d3 == 0) return yy[p] * xb[p];
+  return yy[p] * xb[j] + yy[j] * xb[p];
+}
+
+// H1[b][u][p3][p2][c1] = sum_{p1} E1[p1][c1] G_u(p1, p2, p3)
+__global__ void adj_h1_3_kernel(AdjGeom3 g, KInterp<double> ip, const int* __restrict__ plo1,
+                                const int* __restrict__ phi1, const double* __restrict__ x,
+                                const double* __restrict__ yb, double* __restrict__ H1) {
+  const int S1 = ip.Sd[0];
+  const int L2 = g.hi2 - g.lo + 1, L3 = g.hi3 - g.lo + 1;
+  const int64_t total = int64_t(ip.nup) * L3 * L2 * S1;
+  const int b = blockIdx.y;
+  const double* xb = x + size_t(b) * g.N;
+  const double* yy = yb + size_t(b) * g.N;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int c1 = int(t % S1);
+    int64_t r = t / S1;
+    const int p2 = g.lo + int(r % L2);
+    r /= L2;
+    const int p3 = g.lo + int(r % L3);
+    const int u = int(r / L3);
+    const int s = ip.upslot[u];
+    const int d1 = s % g.W - g.P, d2 = (s / g.W) % g.W - g.P, d3 = s / (g.W * g.W) - g.P;
+    double acc = 0.0;
+    for (int p1 = plo1[c1]; p1 <= phi1[c1]; ++p1) {
+      const int a = c1 - ip.ef[0][p1];
+      if (a < 0 || a > ip.q) continue;
+      acc += ip.eb[0][size_t(p1) * (ip.q + 1) + a] * interp_weight3(g, xb, yy, p1, p2, p3, d1, d2, d3);
+    }
+    H1[size_t(b) * total + t] = acc;
+  }
+}
+
+// out[bu][outer][c][inner] = sum_{p} E_d[p][c] in[bu][outer][p - lo][inner]
+// (direction d = 1: outer = p3, inner = c1; d = 2: outer = 1, inner = (c2, c1))
+__global__ void adj_contract3_kernel(KInterp<double> ip, int d, int lo, int L, int nouter, int ninner, int64_t nbu,
+                                     const int* __restrict__ plo, const int* __restrict__ phi,
+                                     const double* __restrict__ in, double* __restrict__ out) {
+  const int Sd = ip.Sd[d];
+  const int64_t total = nbu * nouter * Sd * ninner;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int inner = int(t % ninner);
+    int64_t r = t / ninner;
+    const int c = int(r % Sd);
+    r /= Sd;  // bu * nouter + outer
+    const double* src = in + size_t(r) * L * ninner + inner;
+    double acc = 0.0;
+    for (int pp = plo[c]; pp <= phi[c]; ++pp) {
+      const int a = c - ip.ef[d][pp];
+      if (a < 0 || a > ip.q) continue;
+      acc += ip.eb[d][size_t(pp) * (ip.q + 1) + a] * src[size_t(pp - lo) * ninner];
+    }
+    out[t] = acc;
+  }
+}
+
+__global__ void adj_scatter3_kernel(AdjGeom3 g, KInterp<double> ip, int batch, const double* __restrict__ Vbar,
+                                    double* __restrict__ wbar) {
+  const int S1 = ip.Sd[0], S2 = ip.Sd[1], S3 = ip.Sd[2];
+  const int64_t total = int64_t(batch) * ip.nup * S3 * S2 * S1;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int k1 = int(t % S1);
+    int64_t r = t / S1;
+    const int k2 = int(r % S2);
+    r /= S2;
+    const int k3 = int(r % S3);
+    r /= S3;
+    const int u = int(r % ip.nup);
+    const int b = int(r / ip.nup);
+    const int64_t row = ip.samp[0][k1] + int64_t(g.m1) * (ip.samp[1][k2] + int64_t(g.m2) * ip.samp[2][k3]);
+    wbar[(size_t(b) * g.S + ip.upslot[u]) * g.ld + row] = Vbar[t];
+  }
+}
+
+// Reverse quadrature, one workgroup per element: the element's weight matrix
+// W[i][j] = wbar_{i, j-i} (quadrature rows only) contracted with the basis
+// values/derivatives at the element's Gauss points, direction 3, then 2,
+// then 1, into Ghat_ab(q) = sum W[i][j] d_a B_i(q) d_b B_j(q) for the nine
+// (a, b); each point stores (dkappa/dc factor) * sum_ab Khat_ab Ghat_ab.
+template <int P>
+__global__ void __launch_bounds__(256)
+    adj_elem3_kernel(KProblem kp, AdjGeom3 g, const int4* __restrict__ elems, const double* __restrict__ wbar,
+                     double* __restrict__ pv) {
+  constexpr int NP = P + 1, NL = NP * NP * NP, NQ = P + 1, NP2 = NP * NP, NP4 = NP2 * NP2;
+  __shared__ double Wl[NL * NL];
+  __shared__ double T3[4 * NP4 * NQ];        // [code3][i1 + NP j1 + NP^2 i2 + NP^3 j2][k3]
+  __shared__ double T2[9 * NP2 * NQ * NQ];   // [(a,b)][i1 + NP j1][k2 + NQ k3]
+  const int tid = threadIdx.x;
+  const int b = blockIdx.y;
+  const int4 e = elems[blockIdx.x];
+  const double* w = wbar + size_t(b) * g.S * g.ld;
+  for (int t = tid; t < NL * NL; t += 256) {
+    const int il = t / NL, jl = t % NL;
+    const int a1 = il % NP, a2 = (il / NP) % NP, a3 = il / NP2;
+    const int b1 = jl % NP, b2 = (jl / NP) % NP, b3 = jl / NP2;
+    const int i1 = e.x + a1, i2 = e.y + a2, i3 = e.z + a3;
+    const int s = (b1 - a1 + P) + g.W * ((b2 - a2 + P) + g.W * (b3 - a3 + P));
+    double v = 0.0;
+    if (quad_row3(g, i1, i2, i3)) v = w[size_t(s) * g.ld + i1 + size_t(g.m1) * (i2 + size_t(g.m2) * i3)];
+    Wl[t] = v;
+  }
+  __syncthreads();
+  // direction 3: code3 = (alpha3, beta3) selects value (0) or derivative (1)
+  const double* bv3 = kp.t[2].bv;
+  const double* bd3 = kp.t[2].bd;
+  for (int t = tid; t < 4 * NP4 * NQ; t += 256) {
+    const int k3 = t % NQ;
+    const int r = (t / NQ) % NP4;
+    const int code = t / (NQ * NP4);
+    const int i1 = r % NP, j1 = (r / NP) % NP, i2 = (r / NP2) % NP, j2 = r / (NP2 * NP);
+    const size_t gq = size_t(e.z * NQ + k3) * NP;
+    double acc = 0.0;
+    for (int a3 = 0; a3 < NP; ++a3) {
+      const double fa = (code & 2) ? bd3[gq + a3] : bv3[gq + a3];
+      for (int b3 = 0; b3 < NP; ++b3) {
+        const double fb = (code & 1) ? bd3[gq + b3] : bv3[gq + b3];
+        acc += fa * fb * Wl[(i1 + NP * i2 + NP2 * a3) * NL + (j1 + NP * j2 + NP2 * b3)];
+      }
+    }
+    T3[t] = acc;
+  }
+  __syncthreads();
+  // direction 2, for the nine (a, b): alpha_d = [a == d], beta_d = [b == d]
+  const double* bv2 = kp.t[1].bv;
+  const double* bd2 = kp.t[1].bd;
+  for (int t = tid; t < 9 * NP2 * NQ * NQ; t += 256) {
+    const int k23 = t % (NQ * NQ);
+    const int k2 = k23 % NQ, k3 = k23 / NQ;
+    const int ij1 = (t / (NQ * NQ)) % NP2;
+    const int ab = t / (NQ * NQ * NP2);
+    const int a = ab / 3, bb = ab % 3;
+    const int al2 = a == 1, be2 = bb == 1;
+    const int code3 = ((a == 2) << 1) | (bb == 2);
+    const size_t gq = size_t(e.y * NQ + k2) * NP;
+    double acc = 0.0;
+    for (int a2 = 0; a2 < NP; ++a2) {
+      const double fa = al2 ? bd2[gq + a2] : bv2[gq + a2];
+      for (int b2 = 0; b2 < NP; ++b2) {
+        const double fb = be2 ? bd2[gq + b2] : bv2[gq + b2];
+        acc += fa * fb * T3[(code3 * NP4 + ij1 + NP2 * a2 + NP2 * NP * b2) * NQ + k3];
+      }
+    }
+    T2[t] = acc;
+  }
+  __syncthreads();
+  // direction 1 and the point values: one thread per Gauss point of the element
+  if (tid < NQ * NQ * NQ) {
+    const int k1 = tid % NQ, k2 = (tid / NQ) % NQ, k3 = tid / (NQ * NQ);
+    const int g1 = e.x * NQ + k1, g2 = e.y * NQ + k2, g3 = e.z * NQ + k3;
+    const double* bv1 = kp.t[0].bv + size_t(g1) * NP;
+    const double* bd1 = kp.t[0].bd + size_t(g1) * NP;
+    double G[9];
+    for (int ab = 0; ab < 9; ++ab) {
+      const int a = ab / 3, bb = ab % 3;
+      double acc = 0.0;
+      for (int a1 = 0; a1 < NP; ++a1) {
+        const double fa = a == 0 ? bd1[a1] : bv1[a1];
+        for (int b1 = 0; b1 < NP; ++b1) {
+          const double fb = bb == 0 ? bd1[b1] : bv1[b1];
+          acc += fa * fb * T2[(ab * NP2 + a1 + NP * b1) * NQ * NQ + k2 + NQ * k3];
+        }
+      }
+      G[ab] = acc;
+    }
+    // Khat = w adj adj^T / |det J| at the point
+    const int gg[3] = {g1, g2, g3};
+    double xi[3], tr[3][4], J[3][3];
+    double wq = 1.0;
+    for (int d = 0; d < 3; ++d) {
+      xi[d] = kp.t[d].x[gg[d]];
+      wq *= kp.t[d].w[gg[d]];
+      for (int k = 0; k < 4; ++k) tr[d][k] = kp.t[d].trig[4 * gg[d] + k];
+    }
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) J[r][c] = r == c ? 1.0 : 0.0;
+    const double ga = kp.ga;
+    if (kp.geom == IGS_GEOM_SINE) {
+      // F = xi + a (sin pi x1 sin 2pi x2 sin pi x3, sin 2pi x1 sin pi x2 sin pi x3,
+      //             sin pi x1 sin pi x2 sin 2pi x3); tr = sin pi x, pi cos pi x, sin 2pi x, 2pi cos 2pi x
+      J[0][0] += ga * tr[0][1] * tr[1][2] * tr[2][0];
+      J[0][1] += ga * tr[0][0] * tr[1][3] * tr[2][0];
+      J[0][2] += ga * tr[0][0] * tr[1][2] * tr[2][1];
+      J[1][0] += ga * tr[0][3] * tr[1][0] * tr[2][0];
+      J[1][1] += ga * tr[0][2] * tr[1][1] * tr[2][0];
+      J[1][2] += ga * tr[0][2] * tr[1][0] * tr[2][1];
+      J[2][0] += ga * tr[0][1] * tr[1][0] * tr[2][2];
+      J[2][1] += ga * tr[0][0] * tr[1][1] * tr[2][2];
+      J[2][2] += ga * tr[0][0] * tr[1][0] * tr[2][3];
+    } else if (kp.geom == IGS_GEOM_POLY2) {
+      double qd[3], dq[3];
+      for (int d = 0; d < 3; ++d) {
+        qd[d] = xi[d] * (1.0 - xi[d]);
+        dq[d] = 1.0 - 2.0 * xi[d];
+      }
+      for (int c = 0; c < 3; ++c) {
+        double dprod = dq[c];
+        for (int d = 0; d < 3; ++d)
+          if (d != c) dprod *= qd[d];
+        for (int r = 0; r < 3; ++r) J[r][c] += ga * (r + 1) * dprod;
+      }
+    }
+    double adj[3][3];
+    adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+    if (!(det > 0.0)) atomicOr(kp.flag, 1);
+    const double sc = wq / fabs(det);
+    double val = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int bb = 0; bb < 3; ++bb) {
+        double k = 0.0;
+        for (int c = 0; c < 3; ++c) k += adj[a][c] * adj[bb][c];
+        val += sc * k * G[a * 3 + bb];
+      }
+    if (kp.coef == IGS_COEF_EXP_SPLINE) {
+      const double* cc = kp.cc + b * kp.cstride;
+      const int nd = kp.cdeg + 1;
+      const double* c0 = kp.t[0].cb + size_t(g1) * nd;
+      const double* c1 = kp.t[1].cb + size_t(g2) * nd;
+      const double* c2 = kp.t[2].cb + size_t(g3) * nd;
+      const int f0 = kp.t[0].cf[g1], f1 = kp.t[1].cf[g2], f2 = kp.t[2].cf[g3];
+      double gsum = 0.0;
+      for (int r3 = 0; r3 < nd; ++r3) {
+        double s2 = 0.0;
+        for (int r2 = 0; r2 < nd; ++r2) {
+          double s1 = 0.0;
+          for (int r1 = 0; r1 < nd; ++r1)
+            s1 += c0[r1] * cc[(size_t(f2 + r3) * kp.cn[1] + f1 + r2) * kp.cn[0] + f0 + r1];
+          s2 += c1[r2] * s1;
+        }
+        gsum += c2[r3] * s2;
+      }
+      val *= exp(gsum);
+    }
+    const size_t Q1 = size_t(kp.nelem[0]) * NQ, Q2 = size_t(kp.nelem[1]) * NQ, Q3 = size_t(kp.nelem[2]) * NQ;
+    pv[size_t(b) * Q1 * Q2 * Q3 + (size_t(g3) * Q2 + g2) * Q1 + g1] = val;
+  }
+}
+
+// out[bo][k][inner] = sum_{q} N_k(q) in[bo][q][inner] along coefficient
+// direction d (bo: the slower indices, inner: the faster ones)
+__global__ void adj_cred3_kernel(KProblem kp, int d, int nq, int64_t nbo, int ninner, const int* __restrict__ qlo,
+                                 const int* __restrict__ qhi, const double* __restrict__ in, double* __restrict__ out) {
+  const int cn = kp.cn[d], nd = kp.cdeg + 1;
+  const int64_t total = nbo * cn * ninner;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int inner = int(t % ninner);
+    int64_t r = t / ninner;
+    const int k = int(r % cn);
+    const int64_t bo = r / cn;
+    const double* src = in + size_t(bo) * nq * ninner + inner;
+    double acc = 0.0;
+    for (int qq = qlo[k]; qq <= qhi[k]; ++qq) {
+      const int a = k - kp.t[d].cf[qq];
+      if (a < 0 || a >= nd) continue;
+      acc += kp.t[d].cb[size_t(qq) * nd + a] * src[size_t(qq) * ninner];
+    }
+    out[t] = acc;
+  }
+}
+
 __global__ void fill_zero_kernel(double* p, int64_t n) {
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x) p[t] = 0.0;
 }
@@ -379,6 +713,10 @@ static void ranges(const std::vector<int>& first, int deg, int nk, int qa, int q
     }
 }
 
+static igs_status vjp3(const igs_problem* pb, const Dims& d, const KProblem& kp, const HostTables& ht, int M, int q,
+                       const double* band64, const double* x, const double* ybar, double* xbar, double* cbar,
+                       bool negate_y, hipStream_t s);
+
 static igs_status vjp(const igs_problem* pb, int M, int q, const double* band64, const double* x, const double* ybar,
                       double* xbar, double* cbar, bool negate_y, hipStream_t s) {
   Dims d;
@@ -387,7 +725,7 @@ static igs_status vjp(const igs_problem* pb, int M, int q, const double* band64,
   HostTables ht;
   igs_status st = prepare_problem(pb, s, &d, &kp, &ar, &ht);
   if (st != IGS_OK) return st;
-  if (d.n != 2) return IGS_ERR_UNSUPPORTED;
+  if (d.n == 3) return vjp3(pb, d, kp, ht, M, q, band64, x, ybar, xbar, cbar, negate_y, s);
   const bool want_c = cbar != nullptr;
   if (want_c && pb->coef.kind != IGS_COEF_SPLINE && pb->coef.kind != IGS_COEF_EXP_SPLINE) return IGS_ERR_ARG;
   const int form = IGS_STIFFNESS;
@@ -549,6 +887,205 @@ static igs_status vjp(const igs_problem* pb, int M, int q, const double* band64,
                        dq[0], dq[1], pv, R);
     hipLaunchKernelGGL(adj_red2_kernel, dim3(gs_blocks(int64_t(d.batch) * kp.cstride)), dim3(256), 0, s, kp, dq[2],
                        dq[3], R, cbar);
+  }
+  ADJ_TRY(hipGetLastError());
+  return finish_problem(kp, s);
+}
+
+// n = 3: the same steps with a third direction (p <= 3)
+static igs_status vjp3(const igs_problem* pb, const Dims& d, const KProblem& kp, const HostTables& ht, int M, int q,
+                       const double* band64, const double* x, const double* ybar, double* xbar, double* cbar,
+                       bool negate_y, hipStream_t s) {
+  const bool want_c = cbar != nullptr;
+  if (want_c && pb->coef.kind != IGS_COEF_SPLINE && pb->coef.kind != IGS_COEF_EXP_SPLINE) return IGS_ERR_ARG;
+  if (want_c && d.p > 3) return IGS_ERR_UNSUPPORTED;
+  if (xbar && !band64) return IGS_ERR_ARG;
+  const int form = IGS_STIFFNESS;
+  const bool sur = M >= 1;
+  igs_status st = IGS_OK;
+  HostInterp hi;
+  if (sur) {
+    int box[3] = {1, 1, 1};
+    st = build_interp(d, form, M, q, box, &hi);
+    if (st != IGS_OK) return st;
+  }
+  const size_t NB = size_t(d.N) * d.batch;
+  const int P = d.p, NQ = d.nq;
+  const int lo = 2 * P;
+  int hiv[3], L[3], Sd[3] = {1, 1, 1}, Qd[3];
+  for (int k = 0; k < 3; ++k) {
+    hiv[k] = d.m[k] - 2 * P - 1;
+    L[k] = hiv[k] - lo + 1;
+    if (sur) Sd[k] = int(hi.samp[k].size());
+    Qd[k] = d.nelem[k] * NQ;
+  }
+  const int nup = sur ? int(hi.upslot.size()) : 0;
+  std::vector<unsigned char> is[3];
+  for (int k = 0; k < 3; ++k) {
+    is[k].assign(d.m[k], 0);
+    if (sur)
+      for (int v : hi.samp[k]) is[k][v] = 1;
+  }
+  auto quad_row = [&](int i1, int i2, int i3) {
+    if (!sur) return true;
+    const bool inner = i1 >= lo && i1 <= hiv[0] && i2 >= lo && i2 <= hiv[1] && i3 >= lo && i3 <= hiv[2];
+    return !inner || (is[0][i1] && is[1][i2] && is[2][i3]);
+  };
+  // elements whose (p+1)^3 rows include a quadrature row
+  std::vector<int> elems;
+  for (int e3 = 0; e3 < d.nelem[2]; ++e3)
+    for (int e2 = 0; e2 < d.nelem[1]; ++e2)
+      for (int e1 = 0; e1 < d.nelem[0]; ++e1) {
+        bool any = false;
+        for (int a3 = 0; a3 <= P && !any; ++a3)
+          for (int a2 = 0; a2 <= P && !any; ++a2)
+            for (int a1 = 0; a1 <= P && !any; ++a1) any = quad_row(e1 + a1, e2 + a2, e3 + a3);
+        if (any) {
+          elems.push_back(e1);
+          elems.push_back(e2);
+          elems.push_back(e3);
+          elems.push_back(0);
+        }
+      }
+  std::vector<int> pr[3][2], qr[3][2];
+  std::vector<double> gT[3];
+  if (sur)
+    for (int k = 0; k < 3; ++k) {
+      ranges(hi.ef[k], q, Sd[k], lo, hiv[k], &pr[k][0], &pr[k][1]);
+      gT[k].resize(size_t(Sd[k]) * Sd[k]);
+      for (int r = 0; r < Sd[k]; ++r)
+        for (int c = 0; c < Sd[k]; ++c) gT[k][size_t(r) * Sd[k] + c] = hi.ginv[k][size_t(c) * Sd[k] + r];
+    }
+  if (want_c)
+    for (int k = 0; k < 3; ++k) ranges(ht.cf[k], pb->coef.degree, pb->coef.ncoef[k], 0, Qd[k] - 1, &qr[k][0], &qr[k][1]);
+  const size_t nQ = size_t(Qd[0]) * Qd[1] * Qd[2];
+  const int cn1 = want_c ? pb->coef.ncoef[0] : 0, cn2 = want_c ? pb->coef.ncoef[1] : 0;
+  const size_t nH1 = size_t(d.batch) * nup * L[2] * L[1] * Sd[0];
+  const size_t nH2 = size_t(d.batch) * nup * L[2] * Sd[1] * Sd[0];
+  const size_t nG = size_t(d.batch) * nup * Sd[2] * Sd[1] * Sd[0];
+  size_t bytes = padded(NB * sizeof(double));
+  if (want_c) {
+    bytes += padded(size_t(d.batch) * d.S * d.ld * 8) + padded(size_t(d.batch) * nQ * 8);
+    bytes += padded(size_t(d.batch) * Qd[2] * Qd[1] * cn1 * 8) + padded(size_t(d.batch) * Qd[2] * cn2 * cn1 * 8);
+    bytes += vb(elems);
+    for (int k = 0; k < 3; ++k) bytes += vb(is[k]) + vb(qr[k][0]) + vb(qr[k][1]);
+    if (sur) {
+      bytes += padded(nH1 * 8) + padded(nH2 * 8) + 3 * padded(nG * 8) + vb(hi.upslot);
+      for (int k = 0; k < 3; ++k)
+        bytes += vb(pr[k][0]) + vb(pr[k][1]) + vb(gT[k]) + vb(hi.samp[k]) + vb(hi.ef[k]) + vb(hi.eb[k]);
+    }
+  }
+  Arena wa;
+  st = wa.alloc(bytes, s);
+  if (st != IGS_OK) return st;
+  const double* yv = ybar;
+  if (negate_y) {
+    double* yn = wa.take<double>(NB);
+    hipLaunchKernelGGL(negate_copy_kernel, dim3(gs_blocks(NB)), dim3(256), 0, s, ybar, yn, int64_t(NB));
+    yv = yn;
+  }
+  if (xbar) {
+    PhaseTimer t("adj_xbar_spmv", s);
+    st = launch_apply(d, IGS_F64, band64, yv, xbar, 0, s);
+    if (st != IGS_OK) return st;
+  }
+  if (!want_c) return finish_problem(kp, s);
+
+  AdjGeom3 g;
+  g.P = P;
+  g.W = d.W;
+  g.S = d.S;
+  g.m1 = d.m[0];
+  g.m2 = d.m[1];
+  g.m3 = d.m[2];
+  g.N = d.N;
+  g.ld = d.ld;
+  g.lo = lo;
+  g.hi1 = hiv[0];
+  g.hi2 = hiv[1];
+  g.hi3 = hiv[2];
+  g.form = form;
+  g.surrogate = sur ? 1 : 0;
+  double* wbar = wa.take<double>(size_t(d.batch) * d.S * d.ld);
+  double* pv = wa.take<double>(size_t(d.batch) * nQ);
+  double* R1 = wa.take<double>(size_t(d.batch) * Qd[2] * Qd[1] * cn1);
+  double* R2 = wa.take<double>(size_t(d.batch) * Qd[2] * cn2 * cn1);
+  const int4* delems = reinterpret_cast<const int4*>(up(wa, elems, s, &st));
+  g.is_s1 = up(wa, is[0], s, &st);
+  g.is_s2 = up(wa, is[1], s, &st);
+  g.is_s3 = up(wa, is[2], s, &st);
+  const int* dq[3][2];
+  for (int k = 0; k < 3; ++k) {
+    dq[k][0] = up(wa, qr[k][0], s, &st);
+    dq[k][1] = up(wa, qr[k][1], s, &st);
+  }
+  if (st != IGS_OK) return st;
+  {
+    PhaseTimer t("adj_weights", s);
+    hipLaunchKernelGGL(adj_weights3_kernel, dim3(int((d.N + 255) / 256), d.batch), dim3(256), 0, s, g, x, yv, wbar);
+  }
+  if (sur) {
+    KInterp<double> ip;
+    std::memset(&ip, 0, sizeof(ip));
+    ip.q = q;
+    for (int k = 0; k < 3; ++k) {
+      ip.Sd[k] = Sd[k];
+      ip.lo[k] = lo;
+      ip.hi[k] = hiv[k];
+      ip.samp[k] = up(wa, hi.samp[k], s, &st);
+      ip.ef[k] = up(wa, hi.ef[k], s, &st);
+      ip.eb[k] = up(wa, hi.eb[k], s, &st);
+      ip.ginv[k] = up(wa, gT[k], s, &st);
+    }
+    ip.nup = nup;
+    ip.upslot = up(wa, hi.upslot, s, &st);
+    const int* pl[3][2];
+    for (int k = 0; k < 3; ++k) {
+      pl[k][0] = up(wa, pr[k][0], s, &st);
+      pl[k][1] = up(wa, pr[k][1], s, &st);
+    }
+    double* H1 = wa.take<double>(nH1);
+    double* H2 = wa.take<double>(nH2);
+    double* Gc = wa.take<double>(nG);
+    double* A = wa.take<double>(nG);
+    double* Vb = wa.take<double>(nG);
+    if (st != IGS_OK) return st;
+    PhaseTimer t("adj_interp", s);
+    const int64_t nbu = int64_t(d.batch) * nup;
+    hipLaunchKernelGGL(adj_h1_3_kernel, dim3(gs_blocks(int64_t(nup) * L[2] * L[1] * Sd[0]), d.batch), dim3(256), 0, s,
+                       g, ip, pl[0][0], pl[0][1], x, yv, H1);
+    hipLaunchKernelGGL(adj_contract3_kernel, dim3(gs_blocks(int64_t(nH2))), dim3(256), 0, s, ip, 1, lo, L[1], L[2],
+                       Sd[0], nbu, pl[1][0], pl[1][1], H1, H2);
+    hipLaunchKernelGGL(adj_contract3_kernel, dim3(gs_blocks(int64_t(nG))), dim3(256), 0, s, ip, 2, lo, L[2], 1,
+                       Sd[1] * Sd[0], nbu, pl[2][0], pl[2][1], H2, Gc);
+    ADJ_TRY(launch_fit_pass_plain<double>(ip, 0, 3, d.batch, Gc, A, s));
+    ADJ_TRY(launch_fit_pass_plain<double>(ip, 1, 3, d.batch, A, Vb, s));
+    ADJ_TRY(launch_fit_pass_plain<double>(ip, 2, 3, d.batch, Vb, A, s));
+    hipLaunchKernelGGL(adj_scatter3_kernel, dim3(gs_blocks(int64_t(nG))), dim3(256), 0, s, g, ip, d.batch, A, wbar);
+  }
+  {
+    PhaseTimer t("adj_elements", s);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(gs_blocks(int64_t(d.batch) * nQ)), dim3(256), 0, s, pv,
+                       int64_t(d.batch) * nQ);
+    const int ne = int(elems.size() / 4);
+    if (ne > 0) {
+      dim3 grid(ne, d.batch);
+      switch (d.p) {
+        case 1: hipLaunchKernelGGL((adj_elem3_kernel<1>), grid, dim3(256), 0, s, kp, g, delems, wbar, pv); break;
+        case 2: hipLaunchKernelGGL((adj_elem3_kernel<2>), grid, dim3(256), 0, s, kp, g, delems, wbar, pv); break;
+        default: hipLaunchKernelGGL((adj_elem3_kernel<3>), grid, dim3(256), 0, s, kp, g, delems, wbar, pv); break;
+      }
+    }
+  }
+  {
+    PhaseTimer t("adj_coef_reduce", s);
+    const int64_t b = d.batch;
+    hipLaunchKernelGGL(adj_cred3_kernel, dim3(gs_blocks(b * Qd[2] * Qd[1] * cn1)), dim3(256), 0, s, kp, 0, Qd[0],
+                       b * Qd[2] * Qd[1], 1, dq[0][0], dq[0][1], pv, R1);
+    hipLaunchKernelGGL(adj_cred3_kernel, dim3(gs_blocks(b * Qd[2] * cn2 * cn1)), dim3(256), 0, s, kp, 1, Qd[1],
+                       b * Qd[2], cn1, dq[1][0], dq[1][1], R1, R2);
+    hipLaunchKernelGGL(adj_cred3_kernel, dim3(gs_blocks(b * kp.cstride)), dim3(256), 0, s, kp, 2, Qd[2], b,
+                       cn2 * cn1, dq[2][0], dq[2][1], R2, cbar);
   }
   ADJ_TRY(hipGetLastError());
   return finish_problem(kp, s);

@@ -173,3 +173,58 @@ def test_adjoint_workload_fd(igs):
             worst = max(worst, abs(fd[t, b] - g[b][picks[b][t]]) / np.abs(g[b]).max())
     print(f"max |fd - adjoint| / max|g| = {worst:.3e}")
     assert worst <= 1e-6, worst
+
+
+# ------------------------------------------------------------------ 3-D ----
+def _prob3(cc, batch, ne, p, cn=4, cdeg=2):
+    return W.problem(3, p, ne, coef="exp_spline", cdeg=cdeg, cn=(cn, cn, cn), cc=cc, batch=batch)
+
+
+@pytest.mark.parametrize("p,ne,M", [(2, 16, 3), (1, 14, 3), (3, 7, 0), (2, 8, 0)])
+def test_vjp3_matches_oracle(igs, oracle, p, ne, M):
+    """3D adjoint of y = A~(c) x (surrogate M = 3, q = 3, or exact) against the
+    oracle's FP64 gradient on a batch of two exp-spline coefficient fields."""
+    import torch
+
+    rng = np.random.default_rng(21 + p)
+    batch = 2
+    cc = rng.normal(0, 0.4, (batch, 64))
+    prob = _prob3(cc, batch, ne, p)
+    _, N, _ = oracle.dims(prob)
+    x = rng.standard_normal((batch, N))
+    yb = rng.standard_normal((batch, N))
+    xt, yt = torch.as_tensor(x, device="cuda"), torch.as_tensor(yb, device="cuda")
+    band = igs.assemble_surrogate(prob, 0, M=M, q=3) if M else igs.assemble_exact(prob, 0)
+    xbar, cbar = igs.apply_vjp(prob, M, 3, band, xt, yt)
+    ks = [0, 21, 42, 63]
+    for b in range(batch):
+        ref = oracle.bilinear_grad(prob, M, 3, yb[b], x[b], ks, b=b, surrogate=M > 0)
+        got = cbar[b].cpu().numpy()[ks]
+        assert rel_maxnorm(got, ref) < 1e-11, (b, got, ref)
+        rows = igs.band_rows(band, prob, b)
+        assert rel_maxnorm(xbar[b].cpu().numpy(), oracle.apply(prob, rows, yb[b])) < 1e-13
+
+
+def test_compliance3_fd(igs):
+    """3D compliance gradient against central differences (step 1e-6) of the
+    GPU's own compliance, surrogate M = 3, q = 3."""
+    rng = np.random.default_rng(31)
+    cc = rng.normal(0, 0.4, (1, 64))
+    prob = _prob3(cc, 1, 16, 2)
+    f = igs.assemble_rhs(prob, 0, 1.0)
+    band = igs.assemble_surrogate(prob, 0, M=3, q=3)
+    u, info = igs.solve_cg(prob, band, f, rtol=1e-14)
+    g = igs.compliance_grad(prob, 3, 3, u)[0].cpu().numpy()
+
+    def J(c):
+        p = _prob3(c, 1, 16, 2)
+        bd = igs.assemble_surrogate(p, 0, M=3, q=3)
+        uu, _ = igs.solve_cg(p, bd, f, rtol=1e-14)
+        return float((f * uu).sum())
+
+    for k in (5, 27, 50):
+        cp, cm = cc.copy(), cc.copy()
+        cp[0, k] += 1e-6
+        cm[0, k] -= 1e-6
+        fd = (J(cp) - J(cm)) / 2e-6
+        assert abs(fd - g[k]) <= 1e-6 * np.abs(g).max(), (k, fd, g[k])
