@@ -228,3 +228,22 @@ def test_compliance3_fd(igs):
         cm[0, k] -= 1e-6
         fd = (J(cp) - J(cm)) / 2e-6
         assert abs(fd - g[k]) <= 1e-6 * np.abs(g).max(), (k, fd, g[k])
+
+
+def test_vjp3_p3_surrogate(igs, oracle):
+    """3D p = 3 surrogate (M = 3, q = 3, 19^3 elements, 4 samples per
+    direction): cbar on two coefficients against the oracle."""
+    import torch
+
+    rng = np.random.default_rng(27)
+    cc = rng.normal(0, 0.4, (1, 64))
+    prob = _prob3(cc, 1, 19, 3)
+    _, N, _ = oracle.dims(prob)
+    x = rng.standard_normal((1, N))
+    yb = rng.standard_normal((1, N))
+    band = igs.assemble_surrogate(prob, 0, M=3, q=3)
+    _, cbar = igs.apply_vjp(prob, 3, 3, band, torch.as_tensor(x, device="cuda"), torch.as_tensor(yb, device="cuda"),
+                            want_x=False)
+    ks = [13, 50]
+    ref = oracle.bilinear_grad(prob, 3, 3, yb[0], x[0], ks, b=0, surrogate=True)
+    assert rel_maxnorm(cbar[0].cpu().numpy()[ks], ref) < 1e-11
