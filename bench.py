@@ -10,8 +10,9 @@ is the assembly's GPU work; the one-shot call (plan built and freed per call,
 synchronising) is timed separately.  value = band slots assembled per second
 (N * S / step time).  The same run also measures, each with its own timing,
 full quadrature assembly of the same matrix, the banded SpMV, CG in FP64 and
-FP32-inside-FP64-refinement to 1e-10, and the batched 2D compliance solve +
-adjoint; those figures go into the same JSON line.
+FP32-inside-FP64-refinement to 1e-10, the batched 2D compliance solve +
+adjoint, and the 2D p = 2, q = 5 timing study with mesh-dependent sampling
+lengths; those figures go into the same JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra] [--copy-probe]
 """
@@ -37,10 +38,10 @@ FP64_PEAK_TFLOPS = 78.6
 # reported while the kernel source still hashes to the one measured.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.00, 1.00
 PMC_TRAFFIC = {
-    "quad_boundary_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "bcb09694516b9cce", "fetch_kib": 14090.6,
+    "quad_boundary_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "bcb09694516b9cce", "fetch_kib": 14016.6,
                            "write_kib": 2097916.6},
-    "fill": {"sources": ["fill.hip"], "sha256": "873db5dfacf25025", "fetch_kib": 151441.2, "write_kib": 4971999.6},
-    "copy": {"sources": ["fill.hip"], "sha256": "873db5dfacf25025", "fetch_kib": 360716.1, "write_kib": 301085.9},
+    "fill": {"sources": ["fill.hip"], "sha256": "6116744f722c5260", "fetch_kib": 156705.2, "write_kib": 4971999.7},
+    "copy": {"sources": ["fill.hip"], "sha256": "6116744f722c5260", "fetch_kib": 360712.9, "write_kib": 301085.9},
 }
 
 
@@ -305,6 +306,8 @@ def main():
             extra["compliance_2d_batch8"] = {"error": str(e)}
         log(f"c5: {extra['compliance_2d_batch8']}")
 
+        extra["mesh_dependent_2d_p2_q5"] = mesh_dependent_study(stream)
+
     # ------------------------------------------------------------ CPU oracle
     cpu = None
     if not args.no_cpu:
@@ -334,6 +337,62 @@ def main():
         **extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def mesh_dependent_study(stream):
+    """The paper's 2D timing study with mesh-dependent sampling lengths
+    (Sec. 7.3.3): p = 2, q = 5, M(h) = max{1, floor(c h^((p-q+1/2)/(q+1)))} for
+    c in 0.25..4, on the 2D sine map up to about 2.1e6 dofs.  Per mesh: the
+    full quadrature assembly and each surrogate assembly, each a kept plan
+    timed over 5 executions on the launch stream; speed-up as the paper
+    defines it, t_std / t_surr - 1 (in %); the share of rows assembled by
+    quadrature (boundary rows plus the sample lattice)."""
+    import torch
+
+    from paper_1904_06971_amd import igs
+    from paper_1904_06971_amd import workloads as W
+
+    cs = [0.25, 0.5, 0.75, 1.0, 2.0, 3.0, 4.0]
+    rows = []
+
+    def timed(pl, band, reps=5):
+        pl.execute(out=band)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            pl.execute(out=band)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for ne in (64, 128, 256, 512, 1024, 1448):
+        prob = W.problem(2, 2, ne)
+        lay = igs.layout(prob)
+        band = igs.empty_band(prob, torch.float64)
+        xp = igs.Plan(prob, igs.STIFFNESS, M=0, q=0)
+        t_std = timed(xp, band)
+        xp.close()
+        row = {"nelem": ne, "dofs": lay.N, "std_ms": t_std, "surrogate": {}}
+        for c in cs:
+            M = igs.sampling_length(ne, 2, 5, c, 0.5)
+            st = igs.validate(prob, M, 5)
+            if st != 0:
+                row["surrogate"][str(c)] = {"M": M, "status": igs.STATUS.get(st, st)}
+                continue
+            info, _ = igs.surrogate_layout(prob, M, 5)
+            sp = igs.Plan(prob, igs.STIFFNESS, M=M, q=5)
+            t = timed(sp, band)
+            sp.close()
+            row["surrogate"][str(c)] = {"M": M, "ms": t, "speedup_pct": (t_std / t - 1) * 100,
+                                        "quadrature_rows_pct": 100.0 * info.quadrature_rows / lay.N}
+        rows.append(row)
+        del band
+        log(f"mesh-dependent M, 2D p=2 q=5, nelem {ne}: std {t_std:.3f} ms, " + ", ".join(
+            f"c={c}: M={v['M']} " + (f"{v['ms']:.3f} ms" if "ms" in v else v["status"])
+            for c, v in row["surrogate"].items()))
+    return {"workload": "2D Poisson stiffness, p=2, q=5, sine map a=0.05, kappa=1, M(h) with beta=1/2",
+            "rows": rows}
 
 
 def cpu_baseline(prob, M, q, lay):

@@ -154,12 +154,23 @@ igs_status igs_band_layout(const igs_problem* pb, igs_layout* out);
 /* Validate a problem (and, for M >= 1, the sampling M, q).  Host only. */
 igs_status igs_validate(const igs_problem* pb, int32_t M, int32_t q);
 
-/* Sample lattice (Sec. 8): in each direction start at the first analysis-domain
+/* Sample lattice (Sec. 6): in each direction start at the first analysis-domain
  * index 2p, take every M-th index and append the last one, m-2p-1, if M does
  * not land on it.  `indices` (host, optional) receives the concatenated sample
  * indices per direction.  Host only. */
 igs_status igs_surrogate_layout(const igs_problem* pb, int32_t M, int32_t q, igs_surrogate_info* out,
                                 int32_t* indices, int32_t capacity);
+
+/* Mesh-dependent sampling length (Sec. 7.3.3): M(h) = max{1, floor(c h^e)}
+ * with h = 1/nelem and e = (p - q + beta)/(q + 1), so that H = M h obeys
+ * H^(q+1) <= c^(q+1) h^(p+1+beta) and, for beta > 0, the consistency error
+ * falls faster than the discretisation error under refinement.  c >= 0 is
+ * calibrated per problem; the paper uses beta = 1/2.  Evaluated in FP64 as
+ * c * nelem^(-e), scaled by (1 + 1e-12) before the floor so that a value that
+ * is an integer in exact arithmetic is not rounded down; clamped to 2^30.
+ * Returns M >= 1, or IGS_ERR_ARG for nelem < 1, p < 1, q < 1, or c or beta
+ * negative or not finite.  Host only. */
+int32_t igs_sampling_length(int32_t nelem, int32_t p, int32_t q, double c, double beta);
 
 const char* igs_status_string(int32_t status);
 const char* igs_version(void);
@@ -174,7 +185,7 @@ const char* igs_version(void);
  * Arithmetic is FP64; IGS_F32 rounds on store.  Synchronous on return. */
 igs_status igs_assemble_exact(const igs_problem* pb, int32_t form, int32_t dtype, void* band, void* stream);
 
-/* Surrogate assembly (Secs. 4, 5, 8).  Rows outside the analysis domain
+/* Surrogate assembly (Secs. 4, 5, 6).  Rows outside the analysis domain
  * [2p, m-2p-1]^n and the rows of the sample lattice (igs_surrogate_layout) are
  * assembled by quadrature; for every upper stencil delta the sample values are
  * interpolated by the tensor-product degree-q spline whose knots are the
@@ -221,7 +232,7 @@ igs_status igs_plan_create(const igs_problem* pb, int32_t form, int32_t M, int32
 igs_status igs_plan_execute(igs_plan plan, const double* coef, void* band, void* stream);
 igs_status igs_plan_destroy(igs_plan plan);
 
-/* Load vector F(B_i) = int_Omega f B_i dx (Sec. 6, eq. PoissonWeakForm) by
+/* Load vector F(B_i) = int_Omega f B_i dx (Sec. 7, eq. PoissonWeakForm) by
  * the same quadrature; source 0: f = c, source 1: f = c prod_d sin(pi x_d),
  * x = F(xi).  f: device [batch][N] FP64.  Synchronous on return. */
 igs_status igs_assemble_rhs(const igs_problem* pb, int32_t source, double c, double* f, void* stream);
@@ -229,7 +240,7 @@ igs_status igs_assemble_rhs(const igs_problem* pb, int32_t source, double c, dou
 /* ---------------------------------------------------------------- solve */
 
 /* y = A x with the band of `dtype` (x, y of the same type, device [batch][N]).
- * dirichlet != 0 applies the Dirichlet restriction of Sec. 8 (remark on
+ * dirichlet != 0 applies the Dirichlet restriction of Sec. 6 (remark on
  * boundary conditions, eq. BlockSystem): x is read as 0 and y is written 0 on
  * dofs with some i_d in {0, m_d-1}.  FP32 bands accumulate in FP32.
  * Asynchronous. */
@@ -237,7 +248,7 @@ igs_status igs_apply(const igs_problem* pb, int32_t dtype, const void* band, con
                      int32_t dirichlet, void* stream);
 
 /* Conjugate gradients for A_II u_I = f_I with homogeneous Dirichlet dofs
- * (Sec. 8, eq. BlockSystem with u_D = 0), per problem of the batch.
+ * (Sec. 6, eq. BlockSystem with u_D = 0), per problem of the batch.
  * band64: device FP64 band (required).  band32: optional device FP32 band of
  * the same matrix; when given, CG iterates on A32 with FP32 vectors while the
  * solution accumulates in FP64, and the FP32 recursive residual is replaced by

@@ -12,10 +12,10 @@
  *     (Sec. 2.2, eq. NURBS with all weights 1);
  *   - the stiffness entries A_ij = a(B_j, B_i) through the pull-back tensor
  *     K = kappa |det J| J^{-1} J^{-T} (Sec. 3.2, eq. BilinearFormPoissonTensor)
- *     and the mass entries M_ij = int B_i B_j |det J| (Sec. 7, membrane
+ *     and the mass entries M_ij = int B_i B_j |det J| (Sec. 8, membrane
  *     problem), each row computed by element-wise Gauss quadrature over the
  *     support of B_i, entry (i, i+delta) stored at stencil slot delta;
- *   - the load vector F(B_i) = int f B_i (Sec. 6, eq. PoissonWeakForm);
+ *   - the load vector F(B_i) = int f B_i (Sec. 7, eq. PoissonWeakForm);
  *   - the derivative of the stiffness entries with respect to one B-spline
  *     control coefficient of the diffusion coefficient (adjoint checks).
  *
@@ -406,7 +406,7 @@ int or_rows(const int32_t* ip, const double* dp, const double* cc, int form, int
 }
 
 /* Load vector F(B_i) = int f(x) B_i(x) dx with f = c (src 0) or
- * f = c prod_d sin(pi x_d) (src 1), x = F(xi) (Sec. 6, eq. PoissonWeakForm). */
+ * f = c prod_d sin(pi x_d) (src 1), x = F(xi) (Sec. 7, eq. PoissonWeakForm). */
 int or_rhs(const int32_t* ip, const double* dp, const double* cc, int src, double c,
            const int64_t* rows, int64_t nrows, double* out) {
   oprob P;

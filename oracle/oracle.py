@@ -11,11 +11,11 @@ Low-cost assembly for isogeometric analysis":
 * exact rows and the load vector come from ``igs_oracle.c`` (row-wise Gauss
   quadrature of eq. BilinearFormPoissonTensor, Sec. 3.2, and of the mass form);
 * the surrogate follows Sec. 4.1 (tensor B-spline interpolation of every
-  stencil function on the sample lattice, Sec. 8 / Appendix on existing IGA
+  stencil function on the sample lattice, Sec. 6 on existing IGA
   codes) and Sec. 5: eq. DefinitionOfSurrogateMatrixSymmetricKernel (5.1c)
   for stiffness, eq. DefinitionOfSurrogateMatrixSymmetric (5.1b) for mass;
 * the solve eliminates Dirichlet dofs as in the remark on Dirichlet boundary
-  conditions (Sec. 8, eq. BlockSystem) and runs plain conjugate gradients;
+  conditions (Sec. 6, eq. BlockSystem) and runs plain conjugate gradients;
 * the compliance gradient is -u^T (dA~/dc_k) u, with dA~/dc_k obtained by
   pushing the derivative of the exact entries through the same (linear)
   surrogate construction.
@@ -204,7 +204,7 @@ def interior_mask(prob, idx):
 
 
 def lattice(m, p, M):
-    """Sample indices along one direction (Sec. 8): start at the first analysis
+    """Sample indices along one direction (Sec. 6): start at the first analysis
     index 2p, take every M-th index, and append the last index m-2p-1 when M
     does not land on it (the last interval may then be shorter than M)."""
     lo, hi = 2 * p, m - 2 * p - 1
@@ -214,6 +214,38 @@ def lattice(m, p, M):
     if s[-1] != hi:
         s.append(hi)
     return np.array(s, dtype=np.int64)
+
+
+def sampling_length(nelem, p, q, c, beta=0.5):
+    """Mesh-dependent sampling length of Sec. 7.3.3:
+    M(h) = max{1, floor(c h^((p - q + beta)/(q + 1)))}, h = 1/nelem.
+
+    Evaluated exactly in rational arithmetic on the given (binary) values of c
+    and beta: M is the largest integer k >= 1 with k <= c' nelem^e',
+    e' = (q - p - beta)/(q + 1), c' = c (1 + 1e-12) (the reading: a value
+    within 1e-12 relative below an integer counts as that integer).  With
+    beta = a/b both sides are raised to the power (q+1) b, which leaves only
+    integer powers: k^((q+1)b) <= c'^((q+1)b) nelem^((q-p)b - a)."""
+    from fractions import Fraction
+
+    if nelem < 1 or p < 1 or q < 1 or c < 0 or beta < 0:
+        raise ValueError("sampling_length: invalid argument")
+    fb = Fraction(beta)
+    if fb.denominator > 64:
+        raise ValueError("sampling_length: beta must have a small binary denominator")
+    a, b = fb.numerator, fb.denominator
+    power = (q + 1) * b
+    cc = Fraction(c) * Fraction(10**12 + 1, 10**12)
+    ex = (q - p) * b - a
+    rhs = cc**power * (Fraction(nelem) ** ex)
+
+    def fits(k):
+        return Fraction(k) ** power <= rhs
+
+    k = 1
+    while fits(k + 1):
+        k += 1
+    return k
 
 
 def interp_knots(s, q):

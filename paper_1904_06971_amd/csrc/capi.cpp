@@ -18,7 +18,7 @@ void quad_tile_shape(int n, int p, int* tx, int* ty);
 void rhs_tile_shape(int n, int* tx, int* ty);
 template <typename BT>
 hipError_t launch_fit(const KInterp<double>& ip, int n, int m1, int m2, int64_t ld, int S, int batch, const BT* band,
-                      double* tmp0, double* tmp1, double* coef, hipStream_t s);
+                      double* tmp0, double* tmp1, double* coef, const double* g0T, hipStream_t s);
 template <typename T>
 hipError_t launch_fill(const KInterp<T>& ip, int form, const Dims& d, const int* chunks, int nchunks, int chunk_rows,
                        int n2max, int n3max, const int4* dsl, const double* coef, T* band, hipStream_t s);
@@ -28,6 +28,7 @@ void fill_block_dims(const Dims& d, const std::vector<int> ef[3], int q, const s
                      int* n2max, int* n3max);
 std::vector<int> fill_chunks(const Dims& d, int rows);
 int fill_npen(const Dims& d, int rows);
+bool fill_is_2d(const Dims& d);
 int fill_chunk_rows(const Dims& d, int Sd1);
 template <typename T>
 hipError_t launch_zero_pad(T* band, int64_t N, int64_t ld, int slots_total, hipStream_t s);
@@ -214,6 +215,7 @@ struct Plan {
   int nchunks = 0, chunk_rows = 0, n2max = 1, n3max = 1;
   const int4* ddsl = nullptr;
   double *tmp0 = nullptr, *tmp1 = nullptr, *coef = nullptr;
+  const double* g0T = nullptr;  // direction-1 inverse collocation matrix, transposed
   const int* dcopy = nullptr;  // analysis-domain rows whose stencil leaves the domain
   int ncopy = 0;
   int state = 0;  // geometry flag: 0 not read yet, 1 read and clear, 2 set
@@ -251,7 +253,15 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
   for (int k = 0; k < d.n; ++k) ebf[k].assign(hi.eb[k].begin(), hi.eb[k].end());
   int tx, ty;
   quad_tile_shape(d.n, d.p, &tx, &ty);
-  std::vector<QTile> tiles = tiles_surrogate(d, hi.samp, tx, ty, pick_zchunk(d, tx, ty), pl->groups);
+  int zchunk = pick_zchunk(d, tx, ty);
+  if (d.n == 2) {
+    // the 2-D boundary columns are 2p rows wide, so a launch holds only two
+    // tiles per z-chunk: shorter chunks (about 1024 tiles in all, at least
+    // p+1 long) trade p halo element rows per chunk for parallelism
+    const int64_t want = (int64_t(2) * (d.m[1] - 4 * d.p) * d.batch + 1023) / 1024;
+    zchunk = int(std::min<int64_t>(zchunk, std::max<int64_t>(d.p + 1, want)));
+  }
+  std::vector<QTile> tiles = tiles_surrogate(d, hi.samp, tx, ty, zchunk, pl->groups);
   size_t per = 1;
   for (int k = 0; k < d.n; ++k) per *= hi.samp[k].size();
   const size_t ncoef = per * hi.upslot.size() * d.batch;
@@ -266,8 +276,12 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
     dsl.push_back((sl / W) % W - d.p);
     dsl.push_back(d.n == 3 ? sl / (W * W) - d.p : 0);
   }
+  const size_t S1 = hi.samp[0].size();
+  std::vector<double> g0t(S1 * S1);
+  for (size_t r = 0; r < S1; ++r)
+    for (size_t c = 0; c < S1; ++c) g0t[c * S1 + r] = hi.ginv[0][r * S1 + c];
   size_t bytes = padded(tiles.size() * sizeof(QTile)) + 3 * padded(ncoef * sizeof(double)) + vbytes(chunks) +
-                 vbytes(crow) + vbytes(dsl) + padded(hi.upslot.size() * sizeof(int)) * 2;
+                 vbytes(crow) + vbytes(dsl) + padded(hi.upslot.size() * sizeof(int)) * 2 + vbytes(g0t);
   for (int k = 0; k < d.n; ++k)
     bytes += 2 * (vbytes(hi.samp[k]) + vbytes(hi.ginv[k]) + vbytes(hi.ef[k]) + vbytes(hi.eb[k]));
   st = pl->ta.alloc(bytes, s);
@@ -285,6 +299,7 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
   pl->dcopy = upload(ta, crow, s, &st);
   pl->ncopy = int(crow.size());
   pl->ddsl = reinterpret_cast<const int4*>(upload(ta, dsl, s, &st));
+  pl->g0T = upload(ta, g0t, s, &st);
   pl->tmp0 = ta.take<double>(ncoef);
   pl->tmp1 = ta.take<double>(ncoef);
   pl->coef = ta.take<double>(ncoef);
@@ -292,7 +307,7 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
   if (st != IGS_OK) return st;
   const size_t lds = pl->dtype == IGS_F64 ? fill_lds_bytes<double>(pl->ipd, fill_npen(d, pl->chunk_rows), d, 0)
                                           : fill_lds_bytes<float>(pl->ipf, fill_npen(d, pl->chunk_rows), d, 0);
-  if (lds > 160 * 1024) return IGS_ERR_UNSUPPORTED;
+  if (!fill_is_2d(d) && lds > 160 * 1024) return IGS_ERR_UNSUPPORTED;
   fill_block_dims(d, hi.ef, q, chunks, pl->chunk_rows, &pl->n2max, &pl->n3max);
   return IGS_OK;
 }
@@ -320,7 +335,8 @@ static igs_status run_t(const Plan& pl, const KProblem& kp, const KInterp<OutT>&
     }
     {
       PhaseTimer t("fit", s);
-      HIP_TRY(launch_fit<OutT>(pl.ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, pl.tmp0, pl.tmp1, pl.coef, s));
+      HIP_TRY(launch_fit<OutT>(pl.ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, pl.tmp0, pl.tmp1, pl.coef,
+                               pl.g0T, s));
     }
     {
       PhaseTimer t("fill", s);
@@ -439,6 +455,18 @@ igs_status igs_surrogate_layout(const igs_problem* pb, int32_t M, int32_t q, igs
   out->boundary_rows = d.N - interior;
   out->quadrature_rows = out->boundary_rows + samples;
   return IGS_OK;
+}
+
+int32_t igs_sampling_length(int32_t nelem, int32_t p, int32_t q, double c, double beta) {
+  if (nelem < 1 || p < 1 || q < 1 || !std::isfinite(c) || !std::isfinite(beta) || c < 0.0 || beta < 0.0)
+    return IGS_ERR_ARG;
+  // h^((p - q + beta) / (q + 1)) with h = 1/nelem, written as a power of nelem.
+  const double v = c * std::pow(double(nelem), (double(q) - double(p) - beta) / double(q + 1));
+  // A value that is an integer in exact arithmetic may come out a few ulps
+  // below it; the relative nudge keeps floor() on that integer.
+  const double f = std::floor(v * (1.0 + 1e-12));
+  if (!(f >= 1.0)) return 1;
+  return f >= double(1 << 30) ? int32_t(1 << 30) : int32_t(f);
 }
 
 const char* igs_status_string(int32_t status) {

@@ -1,4 +1,4 @@
-// Surrogate interpolation: fit, fill and copy kernels (Secs. 4.1, 5, 8).
+// Surrogate interpolation: fit, fill and copy kernels (Secs. 4.1, 5, 6).
 //
 // fit:  for every interpolated ("upper") stencil delta, the sample values
 //       V_delta[k] = A_{s(k), s(k)+delta} (read from the band rows that the
@@ -28,10 +28,14 @@ namespace igs {
 // ------------------------------------------------------------------ fit ----
 
 // out[b][u][..k_d..] = sum_j ginv_d[k_d][j] in[b][u][..j..]; pass 0 gathers
-// `in` from the band at the sample rows.
+// `in` from the band at the sample rows.  gT (optional) is ginv_d transposed:
+// in direction 1 consecutive threads have consecutive k_d, so reading
+// gT[j][k_d] is one coalesced load per j where ginv_d[k_d][j] would touch a
+// separate cache line per lane.
 template <typename BT, bool GATHER>
 __global__ void fit_pass_kernel(KInterp<double> ip, int d, int n, int m1, int m2, int64_t ld, int S, int batch,
-                                const BT* __restrict__ band, const double* __restrict__ in, double* __restrict__ out) {
+                                const BT* __restrict__ band, const double* __restrict__ in, double* __restrict__ out,
+                                const double* __restrict__ gT) {
   const int S1 = ip.Sd[0], S2 = ip.Sd[1], S3 = (n == 3) ? ip.Sd[2] : 1;
   const int64_t per = int64_t(S1) * S2 * S3;
   const int64_t total = per * ip.nup * batch;
@@ -44,20 +48,36 @@ __global__ void fit_pass_kernel(KInterp<double> ip, int d, int n, int m1, int m2
     const int b = r / ip.nup;
     const int kd = (d == 0) ? k1 : (d == 1 ? k2 : k3);
     const int Sd = ip.Sd[d];
-    const double* g = ip.ginv[d] + size_t(kd) * Sd;
-    double acc = 0.0;
+    const double* g = gT ? gT + kd : ip.ginv[d] + size_t(kd) * Sd;
+    const size_t gs = gT ? size_t(Sd) : 1;
+    // four independent partial sums over j = 4l + e keep several loads in
+    // flight per thread (a single chain waits on each load in turn)
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const int J4 = Sd & ~3;
     if constexpr (GATHER) {
       const BT* bs = band + (size_t(b) * S + ip.upslot[u]) * ld;
       const size_t rowbase = size_t(m1) * (ip.samp[1][k2] + size_t(m2) * (n == 3 ? ip.samp[2][k3] : 0));
-      for (int j = 0; j < Sd; ++j) acc += g[j] * double(bs[rowbase + ip.samp[0][j]]);
+      const int* s1 = ip.samp[0];
+      for (int j = 0; j < J4; j += 4) {
+        a0 += g[j * gs] * double(bs[rowbase + s1[j]]);
+        a1 += g[(j + 1) * gs] * double(bs[rowbase + s1[j + 1]]);
+        a2 += g[(j + 2) * gs] * double(bs[rowbase + s1[j + 2]]);
+        a3 += g[(j + 3) * gs] * double(bs[rowbase + s1[j + 3]]);
+      }
+      for (int j = J4; j < Sd; ++j) a0 += g[j * gs] * double(bs[rowbase + s1[j]]);
     } else {
       const double* src = in + (size_t(b) * ip.nup + u) * per;
-      for (int j = 0; j < Sd; ++j) {
-        const int a1 = (d == 0) ? j : k1, a2 = (d == 1) ? j : k2, a3 = (d == 2) ? j : k3;
-        acc += g[j] * src[(size_t(a3) * S2 + a2) * S1 + a1];
+      const size_t stride = d == 0 ? 1 : (d == 1 ? size_t(S1) : size_t(S1) * S2);
+      const double* sp = src + (size_t(d == 2 ? 0 : k3) * S2 + (d == 1 ? 0 : k2)) * S1 + (d == 0 ? 0 : k1);
+      for (int j = 0; j < J4; j += 4) {
+        a0 += g[j * gs] * sp[j * stride];
+        a1 += g[(j + 1) * gs] * sp[(j + 1) * stride];
+        a2 += g[(j + 2) * gs] * sp[(j + 2) * stride];
+        a3 += g[(j + 3) * gs] * sp[(j + 3) * stride];
       }
+      for (int j = J4; j < Sd; ++j) a0 += g[j * gs] * sp[j * stride];
     }
-    out[t] = acc;
+    out[t] = (a0 + a1) + (a2 + a3);
   }
 }
 
@@ -72,6 +92,11 @@ __global__ void fit_pass_kernel(KInterp<double> ip, int d, int n, int m1, int m2
 // c_delta[c3][c2][c1] in LDS (for the pencil itself and for the pencil of the
 // lower partners); each row then finishes with its q+1 direction-1 weights.
 // LDS is double-buffered so one barrier per delta suffices.
+
+bool fill_is_2d(const Dims& d);
+template <typename T>
+hipError_t launch_fill2d(const KInterp<T>& ip, int form, const Dims& d, const int4* dsl, const double* coef, T* band,
+                         hipStream_t s);
 
 constexpr int kChunk = 256;
 
@@ -607,7 +632,7 @@ __global__ void __launch_bounds__(64 * kCopyWaves)
 
 template <typename BT>
 hipError_t launch_fit(const KInterp<double>& ip, int n, int m1, int m2, int64_t ld, int S, int batch, const BT* band,
-                      double* tmp0, double* tmp1, double* coef, hipStream_t s) {
+                      double* tmp0, double* tmp1, double* coef, const double* g0T, hipStream_t s) {
   int64_t total = int64_t(ip.Sd[0]) * ip.Sd[1] * (n == 3 ? ip.Sd[2] : 1) * ip.nup * batch;
   int blocks = int(std::min<int64_t>((total + 255) / 256, 65535));
   double* bufs[3];
@@ -617,10 +642,10 @@ hipError_t launch_fit(const KInterp<double>& ip, int n, int m1, int m2, int64_t 
     bufs[0] = tmp0; bufs[1] = coef; bufs[2] = nullptr;
   }
   hipLaunchKernelGGL((fit_pass_kernel<BT, true>), dim3(blocks), dim3(256), 0, s, ip, 0, n, m1, m2, ld, S, batch, band,
-                     nullptr, bufs[0]);
+                     nullptr, bufs[0], g0T);
   for (int d = 1; d < n; ++d)
     hipLaunchKernelGGL((fit_pass_kernel<BT, false>), dim3(blocks), dim3(256), 0, s, ip, d, n, m1, m2, ld, S, batch,
-                       band, bufs[d - 1], bufs[d]);
+                       band, bufs[d - 1], bufs[d], static_cast<const double*>(nullptr));
   return hipGetLastError();
 }
 
@@ -631,16 +656,16 @@ hipError_t launch_fit_pass_plain(const KInterp<double>& ip, int d, int n, int ba
   int64_t total = int64_t(ip.Sd[0]) * ip.Sd[1] * (n == 3 ? ip.Sd[2] : 1) * ip.nup * batch;
   int blocks = int(std::min<int64_t>((total + 255) / 256, 65535));
   hipLaunchKernelGGL((fit_pass_kernel<T, false>), dim3(blocks), dim3(256), 0, s, ip, d, n, 0, 0, int64_t(0), 0, batch,
-                     static_cast<const T*>(nullptr), in, out);
+                     static_cast<const T*>(nullptr), in, out, static_cast<const double*>(nullptr));
   return hipGetLastError();
 }
 template hipError_t launch_fit_pass_plain<double>(const KInterp<double>&, int, int, int, const double*, double*,
                                                   hipStream_t);
 
 template hipError_t launch_fit<double>(const KInterp<double>&, int, int, int, int64_t, int, int, const double*,
-                                       double*, double*, double*, hipStream_t);
+                                       double*, double*, double*, const double*, hipStream_t);
 template hipError_t launch_fit<float>(const KInterp<double>&, int, int, int, int64_t, int, int, const float*,
-                                      double*, double*, double*, hipStream_t);
+                                      double*, double*, double*, const double*, hipStream_t);
 
 // chunk ids (of `rows` rows) that contain at least one analysis-domain row
 std::vector<int> fill_chunks(const Dims& d, int rows) {
@@ -748,6 +773,7 @@ static void launch_fast_s(const KInterp<T>& ip, const FillGeom& g, bool stage, d
 template <typename T>
 hipError_t launch_fill(const KInterp<T>& ip, int form, const Dims& d, const int* chunks, int nchunks, int chunk_rows,
                        int n2max, int n3max, const int4* dsl, const double* coef, T* band, hipStream_t s) {
+  if (fill_is_2d(d)) return launch_fill2d<T>(ip, form, d, dsl, coef, band, s);
   FillGeom g;
   g.n = d.n;
   g.P = d.p;

@@ -1,0 +1,158 @@
+// 2-D fill of the surrogate band (Sec. 5, eqs. 5.1b and 5.1c): the
+// interpolated entries of every analysis-domain row, evaluated separably from
+// the tensor spline coefficients of each upper stencil function.
+#include <algorithm>
+
+#include "igs_internal.h"
+
+namespace igs {
+
+// 2D fill: one workgroup per analysis-domain pencil (fixed i2), its threads
+// striding over the whole pencil (R rows each, consecutive threads on
+// consecutive rows, so each store instruction covers a contiguous run).  Per
+// interpolated delta u = (d1, d2):
+//   A  the pencil's line contractions in direction 2 for pencils i2 (upper
+//      entries) and i2 - d2 (lower ones): T[side][c1] = sum_a2 beta2 c_u[f2+a2][c1];
+//   B  each row i1 finishes both with its own q+1 direction-1 weights (kept in
+//      registers): the upper entry Phi~_u(i1, i2) and the value Phi~_u(i1, i2-d2),
+//      which is the lower entry of row i1 + d1; the latter goes to LDS;
+//   C  each row reads its lower entry Phi~_u(i1 - d1, i2 - d2) from LDS.
+// Nothing is staged but the two contraction lines and one pencil of values, so
+// the LDS footprint is (2 S1 + m1) values whatever the mesh.  Entries that are
+// not interpolated get placeholders (0) and rows outside the analysis domain
+// zeros; the boundary-row quadrature and the copy kernel overwrite them as in
+// the other fill kernels.
+template <int FORM, int Q, int R, typename T>
+__global__ void __launch_bounds__(1024)
+    fill2d_kernel(KInterp<T> ip, int m1, int64_t ld, int S, const int4* __restrict__ dsl,
+                  const double* __restrict__ coef, T* __restrict__ band) {
+  extern __shared__ char smem_raw[];
+  const int S1 = ip.Sd[0], S2 = ip.Sd[1];
+  T* Tl = reinterpret_cast<T*>(smem_raw);  // [2][S1]
+  T* Lb = Tl + 2 * S1;                     // [m1]
+  const int nt = blockDim.x, tid = threadIdx.x;
+  const int i2 = ip.lo[1] + blockIdx.x;
+  const int b = blockIdx.y;
+  const int sc = (S - 1) / 2;
+  T* bnd = band + size_t(b) * S * ld + size_t(i2) * m1;
+  const double* cb = coef + size_t(b) * ip.nup * S1 * S2;
+
+  T w1[R][Q + 1];
+  int f1[R];
+  bool in1[R];
+  T dsum[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i1 = tid + r * nt;
+    in1[r] = i1 < m1 && i1 >= ip.lo[0] && i1 <= ip.hi[0];
+    f1[r] = in1[r] ? ip.ef[0][i1] : 0;
+#pragma unroll
+    for (int a = 0; a <= Q; ++a) w1[r][a] = in1[r] ? ip.eb[0][size_t(i1) * (Q + 1) + a] : T(0);
+    dsum[r] = T(0);
+  }
+
+  for (int u = 0; u < ip.nup; ++u) {
+    const int4 dd = dsl[u];
+    const int s = dd.x, d1 = dd.y, d2 = dd.z;
+    const bool has_lo = FORM == IGS_STIFFNESS || s != sc;
+    const bool up2 = i2 + d2 <= ip.hi[1];          // d2 >= 0 for upper deltas
+    const int j2 = i2 - d2;
+    const bool lo2 = has_lo && j2 >= ip.lo[1];
+    // A: direction-2 contractions of the two pencils
+    const double* cu = cb + size_t(u) * S1 * S2;
+    for (int t = tid; t < 2 * S1; t += nt) {
+      const int side = t >= S1;
+      const int c1 = side ? t - S1 : t;
+      const int p2 = side ? j2 : i2;
+      T v = T(0);
+      if (side ? lo2 : up2) {
+        const int f2 = ip.ef[1][p2];
+        const T* w2 = ip.eb[1] + size_t(p2) * (Q + 1);
+#pragma unroll
+        for (int a = 0; a <= Q; ++a) v += w2[a] * T(cu[size_t(f2 + a) * S1 + c1]);
+      }
+      Tl[t] = v;
+    }
+    __syncthreads();
+    // B: upper entries; values at pencil i2 - d2 for the lower partners
+    T vu[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i1 = tid + r * nt;
+      vu[r] = T(0);
+      T vl = T(0);
+      if (in1[r]) {
+#pragma unroll
+        for (int a = 0; a <= Q; ++a) {
+          vu[r] += w1[r][a] * Tl[f1[r] + a];
+          vl += w1[r][a] * Tl[S1 + f1[r] + a];
+        }
+        if (!(up2 && i1 + d1 >= ip.lo[0] && i1 + d1 <= ip.hi[0])) vu[r] = T(0);
+      }
+      if (i1 < m1) Lb[i1] = vl;
+    }
+    __syncthreads();
+    // C: lower entries, stores
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i1 = tid + r * nt;
+      if (i1 >= m1) continue;
+      T vl = T(0);
+      if (in1[r] && lo2) {
+        const int k1 = i1 - d1;
+        if (k1 >= ip.lo[0] && k1 <= ip.hi[0]) vl = Lb[k1];
+      }
+      bnd[size_t(s) * ld + i1] = vu[r];
+      if (has_lo) bnd[size_t(S - 1 - s) * ld + i1] = vl;
+      if (FORM == IGS_STIFFNESS) dsum[r] += vu[r] + vl;
+    }
+  }
+  if (FORM == IGS_STIFFNESS) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i1 = tid + r * nt;
+      if (i1 < m1) bnd[size_t(sc) * ld + i1] = in1[r] ? -dsum[r] : T(0);
+    }
+  }
+}
+
+template <int FORM, int R, typename T>
+static void launch_fill2d_q(const KInterp<T>& ip, const Dims& d, int nt, size_t lds, const int4* dsl,
+                            const double* coef, T* band, hipStream_t s) {
+  dim3 grid(d.m[1] - 4 * d.p, d.batch);
+  switch (ip.q) {
+    case 1: hipLaunchKernelGGL((fill2d_kernel<FORM, 1, R, T>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
+    case 2: hipLaunchKernelGGL((fill2d_kernel<FORM, 2, R, T>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
+    case 3: hipLaunchKernelGGL((fill2d_kernel<FORM, 3, R, T>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
+    case 4: hipLaunchKernelGGL((fill2d_kernel<FORM, 4, R, T>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
+    default: hipLaunchKernelGGL((fill2d_kernel<FORM, 5, R, T>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
+  }
+}
+
+// 2D pencils of up to kFill2dRows rows take fill2d_kernel
+constexpr int kFill2dR = 4;
+constexpr int kFill2dRows = 1024 * kFill2dR;
+
+bool fill_is_2d(const Dims& d) { return d.n == 2 && d.m[0] <= kFill2dRows; }
+
+template <typename T>
+hipError_t launch_fill2d(const KInterp<T>& ip, int form, const Dims& d, const int4* dsl, const double* coef, T* band,
+                         hipStream_t s) {
+  const int rows_per = (d.m[0] + kFill2dR - 1) / kFill2dR;
+  const int nt = std::min(1024, (rows_per + 63) / 64 * 64);
+  const size_t lds = (size_t(2) * ip.Sd[0] + d.m[0]) * sizeof(T);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (d.m[1] - 4 * d.p < 1) return hipSuccess;
+  if (form == IGS_MASS)
+    launch_fill2d_q<IGS_MASS, kFill2dR, T>(ip, d, nt, lds, dsl, coef, band, s);
+  else
+    launch_fill2d_q<IGS_STIFFNESS, kFill2dR, T>(ip, d, nt, lds, dsl, coef, band, s);
+  return hipGetLastError();
+}
+
+template hipError_t launch_fill2d<double>(const KInterp<double>&, int, const Dims&, const int4*, const double*,
+                                          double*, hipStream_t);
+template hipError_t launch_fill2d<float>(const KInterp<float>&, int, const Dims&, const int4*, const double*, float*,
+                                         hipStream_t);
+
+}  // namespace igs

@@ -11,7 +11,7 @@
 // read in bounds.  Workgroups are remapped so that each XCD walks a contiguous
 // range of rows (its L2 then holds the x halo).
 //
-// CG (Dirichlet-restricted, Sec. 8 eq. BlockSystem with u_D = 0) keeps every
+// CG (Dirichlet-restricted, Sec. 6, eq. BlockSystem with u_D = 0) keeps every
 // vector zero on the Dirichlet dofs, so the restriction reduces to zeroing
 // those rows of A p.  Reductions are two-stage and deterministic (per-block
 // partials, then one block in a fixed order): no floating-point atomics.

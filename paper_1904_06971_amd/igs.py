@@ -24,7 +24,8 @@ F64, F32 = 0, 1
 GEOM = {"identity": 0, "sine": 1, "poly2": 2}
 COEF = {"const": 0, "sine3": 1, "spline": 2, "exp_spline": 3}
 SRC_CONST, SRC_SINE = 0, 1
-EXPORTS = ["igs_band_layout", "igs_validate", "igs_surrogate_layout", "igs_status_string", "igs_version",
+EXPORTS = ["igs_band_layout", "igs_validate", "igs_surrogate_layout", "igs_sampling_length", "igs_status_string",
+           "igs_version",
            "igs_assemble_exact", "igs_assemble_surrogate", "igs_plan_create", "igs_plan_execute", "igs_plan_destroy",
            "igs_assemble_rhs", "igs_apply", "igs_solve_cg", "igs_apply_vjp", "igs_compliance_grad",
            "igs_profile_enable", "igs_profile_read"]
@@ -90,6 +91,7 @@ def lib():
             "igs_band_layout": [P, ctypes.POINTER(Layout)],
             "igs_validate": [P, i32, i32],
             "igs_surrogate_layout": [P, i32, i32, ctypes.POINTER(SurrogateInfo), ctypes.POINTER(ctypes.c_int32), i32],
+            "igs_sampling_length": [i32, i32, i32, f64, f64],
             "igs_assemble_exact": [P, i32, i32, vp, vp],
             "igs_assemble_surrogate": [P, i32, i32, i32, i32, vp, vp],
             "igs_plan_create": [P, i32, i32, i32, i32, vp, ctypes.POINTER(vp)],
@@ -190,6 +192,14 @@ def surrogate_layout(prob, M, q):
         idx.append(np.array(buf[pos:pos + info.samples[d]], dtype=np.int64))
         pos += info.samples[d]
     return info, idx
+
+
+def sampling_length(nelem, p, q, c, beta=0.5):
+    """Mesh-dependent sampling length M(h) = max{1, floor(c h^((p-q+beta)/(q+1)))}, h = 1/nelem."""
+    M = lib().igs_sampling_length(int(nelem), int(p), int(q), float(c), float(beta))
+    if M < 1:
+        raise IGSError(M, "igs_sampling_length")
+    return M
 
 
 def validate(prob, M=0, q=0):

@@ -17,7 +17,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 
 def _declared():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:igs_status|const char\*)\s+(igs_\w+)\(", txt, flags=re.M)))
+    return sorted(set(re.findall(r"^(?:igs_status|int32_t|const char\*)\s+(igs_\w+)\(", txt, flags=re.M)))
 
 
 def test_exports_every_declared_symbol():
@@ -123,6 +123,25 @@ def test_sampling_errors():
     pb = igs.make_problem(W.problem(2, 2, 14))
     assert L.igs_plan_create(ctypes.byref(pb), 0, 4, 3, 0, None, ctypes.byref(h)) == -4
     assert L.igs_plan_create(ctypes.byref(pb), 0, 2, 6, 0, None, ctypes.byref(h)) == -2
+
+
+@pytest.mark.parametrize("p,q", [(2, 5), (1, 3), (3, 5), (2, 4), (4, 3)])
+@pytest.mark.parametrize("beta", [0.0, 0.25, 0.5, 1.0])
+def test_sampling_length_matches_oracle(oracle, p, q, beta):
+    """igs_sampling_length against the oracle's exact rational evaluation, on
+    a grid of meshes and calibrations that includes exact-integer cases
+    (nelem = 4096 with beta = 1/2, p = 2, q = 5: c * 32)."""
+    for nelem in (1, 7, 16, 64, 100, 128, 333, 1000, 1024, 1448, 4096):
+        for c in (0.0, 0.25, 0.5, 0.75, 1.0, 2.0, 3.0, 4.0):
+            assert igs.sampling_length(nelem, p, q, c, beta) == oracle.sampling_length(nelem, p, q, c, beta), \
+                (nelem, c)
+
+
+def test_sampling_length_rejects():
+    L = igs.lib()
+    for args in [(0, 2, 5, 1.0, 0.5), (10, 0, 5, 1.0, 0.5), (10, 2, 0, 1.0, 0.5), (10, 2, 5, -1.0, 0.5),
+                 (10, 2, 5, 1.0, -0.5), (10, 2, 5, float("nan"), 0.5), (10, 2, 5, 1.0, float("inf"))]:
+        assert L.igs_sampling_length(*args) == -1, args
 
 
 def test_knot_validation():

@@ -87,6 +87,20 @@ def test_surrogate_small(igs, oracle, prob, form, M, q):
     assert rel_maxnorm(_full(igs, band, prob), ref) < TOL64
 
 
+@pytest.mark.parametrize("ne,c", [(96, 0.75), (96, 3.0), (200, 0.75), (200, 3.0)])
+def test_surrogate_mesh_dependent_q5(igs, oracle, ne, c):
+    """2D p = 2, q = 5 with the mesh-dependent sampling length M(h) (beta = 1/2)
+    of the paper's timing study: the library's M equals the oracle's and the
+    band matches the oracle's surrogate."""
+    M = oracle.sampling_length(ne, 2, 5, c, 0.5)
+    assert igs.sampling_length(ne, 2, 5, c, 0.5) == M
+    prob = W.problem(2, 2, ne)
+    print(f"nelem {ne} c {c}: M = {M}")
+    band = igs.assemble_surrogate(prob, 0, M=M, q=5)
+    ref = oracle.surrogate_rows(prob, 0, M, 5)
+    assert rel_maxnorm(_full(igs, band, prob), ref) < TOL64
+
+
 @pytest.mark.parametrize("prob,form", [(W.problem(2, 3, 30), 0), (W.problem(3, 2, 14), 0), (W.problem(3, 2, 14), 1)])
 def test_surrogate_m1_equals_exact(igs, oracle, prob, form):
     a = igs.band_rows(igs.assemble_exact(prob, form), prob)

@@ -1,6 +1,6 @@
 """Pins for the oracle's solve and gradient:
 
-* CG on the Dirichlet-reduced system (Sec. 8, eq. BlockSystem) against a
+* CG on the Dirichlet-reduced system (Sec. 6, eq. BlockSystem) against a
   direct sparse solve;
 * L2 error of the discrete solution against the manufactured one decays like
   h^{p+1} (Thm. APrioriBounds) for the exact and surrogate matrices;

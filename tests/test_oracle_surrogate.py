@@ -1,6 +1,6 @@
-"""Pins for the oracle's surrogate construction (Secs. 4-5, 8):
+"""Pins for the oracle's surrogate construction (Secs. 4-6):
 
-* M = 1 samples every analysis-domain row, so A~ = A (Sec. 8);
+* M = 1 samples every analysis-domain row, so A~ = A (Sec. 6);
 * polynomial reproduction: identity map with kappa in Q_q gives A~ = A
   (Remark PolynomialReproduction, Prop. PolynomialReproduction); a Q_2 map
   with q >= np-1 gives M~ = M (Corollary MassMatrixReproduction);

@@ -1,7 +1,7 @@
 """Pins for the oracle's 1-D building blocks against independent libraries:
 Gauss-Legendre (numpy), B-spline values/derivatives (scipy BSpline) and the
 interpolating spline of the surrogate (scipy make_interp_spline and
-RectBivariateSpline, the tool the paper's 2D implementation used, Sec. 8)."""
+RectBivariateSpline, the tool the paper's 2D implementation used, Sec. 6)."""
 import numpy as np
 import pytest
 from scipy.interpolate import BSpline, RectBivariateSpline, make_interp_spline
@@ -70,7 +70,7 @@ def test_tensor_interpolant_matches_rect_bivariate_spline(oracle, q):
 
 
 def test_lattice_end_rule(oracle):
-    # m = 131, p = 3: analysis indices 6..124, every 8th plus the last (Sec. 8)
+    # m = 131, p = 3: analysis indices 6..124, every 8th plus the last (Sec. 6)
     s = oracle.lattice(131, 3, 8)
     assert s[0] == 6 and s[-1] == 124 and len(s) == 16
     assert np.all(np.diff(s)[:-1] == 8) and np.diff(s)[-1] == 6
