@@ -971,18 +971,24 @@ __global__ void __launch_bounds__(256)
 template <int P, int FORM>
 struct Q2 {
   static constexpr int NQ = P + 1, W = 2 * P + 1;
-  static constexpr int TX = 64;
+  static constexpr int TX = P == 4 ? 32 : 64;  // LDS: two element rows of point data
   static constexpr int NQ1 = (TX + P) * NQ;
   static constexpr int NC = FORM == IGS_STIFFNESS ? 3 : 1;
   static constexpr int BLOCK = (TX * W + 63) / 64 * 64;
 };
 
+// A workgroup owns TX consecutive i1 of a tile and streams its element rows
+// e2 (direction 2); thread (r1, d1) accumulates the column delta1 = d1 - P of
+// row i1 for every delta2, over a ring of the P+1 rows the current element row
+// touches.  The pulled-back coefficients of a whole element row (all NQ Gauss
+// lines, the tile's direction-1 footprint) are computed into one LDS buffer
+// while the rows consume the other, so an element row costs one barrier.
 template <int P, int FORM, typename OutT>
 __global__ void __launch_bounds__((Q2<P, FORM>::BLOCK))
     quad2d_kernel(KProblem kp, const QTile* __restrict__ tiles, OutT* __restrict__ band) {
   using C = Q2<P, FORM>;
   constexpr int NQ = C::NQ, W = C::W, TX = C::TX, NQ1 = C::NQ1;
-  __shared__ double Cs[C::NC][NQ1];
+  __shared__ double Cs[2][C::NC][NQ][NQ1];
   __shared__ double T1v[P + 1][NQ1], T1d[P + 1][NQ1];
 
   const QTile tile = tiles[blockIdx.x];
@@ -1007,32 +1013,49 @@ __global__ void __launch_bounds__((Q2<P, FORM>::BLOCK))
     for (int d = 0; d < W; ++d) acc[s][d] = 0.0;
 
   const int Elo = max(0, tile.z0 - P), Ehi = min(nel2 - 1, tile.z1 - 1);
-  __syncthreads();
 
-  auto write_row = [&](int i2, const double* row) {
-    if (active && i2 >= tile.z0 && i2 < tile.z1) {
-      const size_t idx = size_t(i1) + size_t(kp.m[0]) * i2;
+  // point data of element row e2 (all NQ Gauss lines) into buffer `buf`
+  auto phase_a = [&](int e2, int buf) __attribute__((always_inline)) {
+    for (int t = tid; t < nq1 * NQ; t += C::BLOCK) {
+      const int k2 = t / nq1, l = t - k2 * nq1;
+      const int g[2] = {E1a * NQ + l, e2 * NQ + k2};
+      double v[C::NC];
+      point_data<2, FORM>(kp, b, g, v);
 #pragma unroll
-      for (int dd = 0; dd < W; ++dd) out[size_t(d1 + W * dd) * kp.ld + idx] = static_cast<OutT>(row[dd]);
+      for (int c = 0; c < C::NC; ++c) Cs[buf][c][k2][l] = v[c];
     }
   };
 
+  // the ring entry is selected by comparison with a slot that is a
+  // compile-time constant after inlining, so acc stays in registers
+  auto write_row = [&](int i2, int slot) __attribute__((always_inline)) {
+    if (active && i2 >= tile.z0 && i2 < tile.z1) {
+      const size_t idx = size_t(i1) + size_t(kp.m[0]) * i2;
+#pragma unroll
+      for (int dd = 0; dd < W; ++dd) {
+        double v = 0.0;
+#pragma unroll
+        for (int r = 0; r <= P; ++r)
+          if (r == slot) v = acc[r][dd];
+        out[size_t(d1 + W * dd) * kp.ld + idx] = static_cast<OutT>(v);
+      }
+    }
+  };
+
+  if (Elo <= Ehi) phase_a(Elo, 0);
+  __syncthreads();
+
   for (int e0 = Elo; e0 <= Ehi; e0 += P + 1) {
-    static_for<0, P + 1>([&](auto ph) {
+    static_for<0, P + 1>([&](auto ph) __attribute__((always_inline)) {
       constexpr int PH = decltype(ph)::value;
       const int e2 = e0 + PH;
       if (e2 > Ehi) return;
-      for (int k2 = 0; k2 < NQ; ++k2) {
-        const int g2 = e2 * NQ + k2;
-        for (int t = tid; t < nq1; t += C::BLOCK) {
-          const int g[2] = {E1a * NQ + t, g2};
-          double v[C::NC];
-          point_data<2, FORM>(kp, b, g, v);
-#pragma unroll
-          for (int c = 0; c < C::NC; ++c) Cs[c][t] = v[c];
-        }
-        __syncthreads();
-        if (active) {
+      const int buf = (e2 - Elo) & 1;
+      if (e2 < Ehi) phase_a(e2 + 1, buf ^ 1);
+      if (active) {
+#pragma unroll 1
+        for (int k2 = 0; k2 < NQ; ++k2) {
+          const int g2 = e2 * NQ + k2;
           double Y0 = 0.0, Y1 = 0.0, Y2 = 0.0, Y3 = 0.0;
 #pragma unroll
           for (int a = 0; a <= P; ++a) {
@@ -1045,13 +1068,13 @@ __global__ void __launch_bounds__((Q2<P, FORM>::BLOCK))
               const int l1 = le + k1;
               const double vi = T1v[a][l1], vj = T1v[bb][l1];
               if constexpr (FORM == IGS_MASS) {
-                Y0 += vi * vj * Cs[0][l1];
+                Y0 += vi * vj * Cs[buf][0][k2][l1];
               } else {
                 const double di = T1d[a][l1], dj = T1d[bb][l1];
-                Y0 += di * dj * Cs[0][l1];  // (1,1): K11, dd
-                Y1 += di * vj * Cs[1][l1];  // (1,2): K12, dv
-                Y2 += vi * dj * Cs[1][l1];  // (2,1): K12, vd
-                Y3 += vi * vj * Cs[2][l1];  // (2,2): K22, vv
+                Y0 += di * dj * Cs[buf][0][k2][l1];  // (1,1): K11, dd
+                Y1 += di * vj * Cs[buf][1][k2][l1];  // (1,2): K12, dv
+                Y2 += vi * dj * Cs[buf][1][k2][l1];  // (2,1): K12, vd
+                Y3 += vi * vj * Cs[buf][2][k2][l1];  // (2,2): K22, vv
               }
             }
           }
@@ -1082,20 +1105,20 @@ __global__ void __launch_bounds__((Q2<P, FORM>::BLOCK))
             }
           }
         }
-        __syncthreads();
       }
       if (e2 < nel2 - 1) {
-        write_row(e2, acc[PH]);
+        write_row(e2, PH);
 #pragma unroll
         for (int d = 0; d < W; ++d) acc[PH][d] = 0.0;
       } else {
 #pragma unroll
         for (int a = 0; a <= P; ++a) {
-          write_row(e2 + a, acc[(PH + a) % (P + 1)]);
+          write_row(e2 + a, (PH + a) % (P + 1));
 #pragma unroll
           for (int d = 0; d < W; ++d) acc[(PH + a) % (P + 1)][d] = 0.0;
         }
       }
+      __syncthreads();
     });
   }
 }
@@ -1306,7 +1329,7 @@ __global__ void __launch_bounds__(256)
 
 void quad_tile_shape(int n, int p, int* tx, int* ty) {
   if (n == 2) {
-    *tx = 64;
+    *tx = p == 4 ? Q2<4, IGS_STIFFNESS>::TX : Q2<1, IGS_STIFFNESS>::TX;
     *ty = 1;
     return;
   }
