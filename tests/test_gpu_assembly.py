@@ -129,6 +129,29 @@ def test_surrogate_fp32(igs, oracle):
     assert rel_maxnorm(got, ref) < 2e-6
 
 
+@pytest.mark.parametrize("prob,form,M,q", [
+    (W.problem(2, 3, (70, 41)), 0, 5, 5), (W.problem(2, 2, (37, 66)), 1, 4, 2),
+    (W.problem(2, 4, (60, 47), coef="sine3", camp=0.5), 0, 6, 3), (W.problem(2, 1, (300, 23)), 0, 7, 1),
+])
+def test_surrogate_2d_rectangular(igs, oracle, prob, form, M, q):
+    """2D fill on meshes with m1 != m2 (pencils of one direction, lattices of
+    the other), stiffness and mass, even and odd q."""
+    band = igs.assemble_surrogate(prob, form, M=M, q=q)
+    ref = oracle.surrogate_rows(prob, form, M, q)
+    assert rel_maxnorm(_full(igs, band, prob), ref) < TOL64
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_surrogate_2d_fp32(igs, oracle, form):
+    """2D precision form (FP32 fill from FP64-fitted coefficients)."""
+    import torch
+
+    prob = W.problem(2, 3, (90, 77))
+    band = igs.assemble_surrogate(prob, form, M=6, q=3, dtype=torch.float32)
+    ref = oracle.surrogate_rows(prob, form, 6, 3)
+    assert rel_maxnorm(_full(igs, band, prob), ref) < 2e-6
+
+
 def test_geometry_fold_reported(igs):
     """A sine map with amplitude 0.5 folds (det J < 0 somewhere)."""
     prob = W.problem(2, 2, 16, ga=0.5)
