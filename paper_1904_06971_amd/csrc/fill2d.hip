@@ -22,7 +22,9 @@ namespace igs {
 // not interpolated get placeholders (0) and rows outside the analysis domain
 // zeros; the boundary-row quadrature and the copy kernel overwrite them as in
 // the other fill kernels.
-template <int FORM, int Q, int R, typename T>
+// PF: every direction-2 task has its own thread (2 S1 <= blockDim.x); its
+// operands for the next delta are loaded while the rows finish this one.
+template <int FORM, int Q, int R, typename T, bool PF>
 __global__ void __launch_bounds__(1024)
     fill2d_kernel(KInterp<T> ip, int m1, int64_t ld, int S, const int4* __restrict__ dsl,
                   const double* __restrict__ coef, T* __restrict__ band) {
@@ -51,6 +53,30 @@ __global__ void __launch_bounds__(1024)
     dsum[r] = T(0);
   }
 
+  // operands of this thread's direction-2 task for delta u (PF only): every
+  // lane loads (tasks past 2 S1 repeat the last one, tasks of a pencil outside
+  // the domain read pencil i2 with zero weights)
+  double cv[PF ? Q + 1 : 1];
+  T wv[PF ? Q + 1 : 1];
+  auto task_load = [&](int u) {
+    const int4 dd = dsl[u];
+    const bool hl = FORM == IGS_STIFFNESS || dd.x != sc;
+    const int t = min(tid, 2 * S1 - 1);
+    const int side = t >= S1;
+    const int c1 = side ? t - S1 : t;
+    const bool ok = side ? (hl && i2 - dd.z >= ip.lo[1]) : (i2 + dd.z <= ip.hi[1]);
+    const int p2 = (ok && side) ? i2 - dd.z : i2;
+    const int f2 = ip.ef[1][p2];
+    const double* cu = cb + size_t(u) * S1 * S2 + c1;
+    const T z = ok ? T(1) : T(0);
+#pragma unroll
+    for (int a = 0; a < (PF ? Q + 1 : 1); ++a) {
+      cv[a] = cu[size_t(f2 + a) * S1];
+      wv[a] = z * ip.eb[1][size_t(p2) * (Q + 1) + a];
+    }
+  };
+  if constexpr (PF) task_load(0);
+
   for (int u = 0; u < ip.nup; ++u) {
     const int4 dd = dsl[u];
     const int s = dd.x, d1 = dd.y, d2 = dd.z;
@@ -59,19 +85,27 @@ __global__ void __launch_bounds__(1024)
     const int j2 = i2 - d2;
     const bool lo2 = has_lo && j2 >= ip.lo[1];
     // A: direction-2 contractions of the two pencils
-    const double* cu = cb + size_t(u) * S1 * S2;
-    for (int t = tid; t < 2 * S1; t += nt) {
-      const int side = t >= S1;
-      const int c1 = side ? t - S1 : t;
-      const int p2 = side ? j2 : i2;
+    if constexpr (PF) {
       T v = T(0);
-      if (side ? lo2 : up2) {
-        const int f2 = ip.ef[1][p2];
-        const T* w2 = ip.eb[1] + size_t(p2) * (Q + 1);
 #pragma unroll
-        for (int a = 0; a <= Q; ++a) v += w2[a] * T(cu[size_t(f2 + a) * S1 + c1]);
+      for (int a = 0; a <= Q; ++a) v += wv[a] * T(cv[a]);
+      if (tid < 2 * S1) Tl[tid] = v;
+      if (u + 1 < ip.nup) task_load(u + 1);
+    } else {
+      const double* cu = cb + size_t(u) * S1 * S2;
+      for (int t = tid; t < 2 * S1; t += nt) {
+        const int side = t >= S1;
+        const int c1 = side ? t - S1 : t;
+        const int p2 = side ? j2 : i2;
+        T v = T(0);
+        if (side ? lo2 : up2) {
+          const int f2 = ip.ef[1][p2];
+          const T* w2 = ip.eb[1] + size_t(p2) * (Q + 1);
+#pragma unroll
+          for (int a = 0; a <= Q; ++a) v += w2[a] * T(cu[size_t(f2 + a) * S1 + c1]);
+        }
+        Tl[t] = v;
       }
-      Tl[t] = v;
     }
     __syncthreads();
     // B: upper entries; values at pencil i2 - d2 for the lower partners
@@ -116,17 +150,28 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
-template <int FORM, int R, typename T>
+template <int FORM, int R, typename T, bool PF>
 static void launch_fill2d_q(const KInterp<T>& ip, const Dims& d, int nt, size_t lds, const int4* dsl,
                             const double* coef, T* band, hipStream_t s) {
   dim3 grid(d.m[1] - 4 * d.p, d.batch);
   switch (ip.q) {
-    case 1: hipLaunchKernelGGL((fill2d_kernel<FORM, 1, R, T>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
-    case 2: hipLaunchKernelGGL((fill2d_kernel<FORM, 2, R, T>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
-    case 3: hipLaunchKernelGGL((fill2d_kernel<FORM, 3, R, T>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
-    case 4: hipLaunchKernelGGL((fill2d_kernel<FORM, 4, R, T>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
-    default: hipLaunchKernelGGL((fill2d_kernel<FORM, 5, R, T>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
+    case 1: hipLaunchKernelGGL((fill2d_kernel<FORM, 1, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
+    case 2: hipLaunchKernelGGL((fill2d_kernel<FORM, 2, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
+    case 3: hipLaunchKernelGGL((fill2d_kernel<FORM, 3, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
+    case 4: hipLaunchKernelGGL((fill2d_kernel<FORM, 4, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
+    default: hipLaunchKernelGGL((fill2d_kernel<FORM, 5, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
   }
+}
+
+template <int FORM, int R, typename T>
+static void launch_fill2d_pf(const KInterp<T>& ip, const Dims& d, int nt, size_t lds, const int4* dsl,
+                             const double* coef, T* band, hipStream_t s) {
+  // prefetching needs one thread per task; at q = 5 its registers beside the
+  // rows' weights spill, and the plain loop is faster there
+  if (2 * ip.Sd[0] <= nt && ip.q <= 4)
+    launch_fill2d_q<FORM, R, T, true>(ip, d, nt, lds, dsl, coef, band, s);
+  else
+    launch_fill2d_q<FORM, R, T, false>(ip, d, nt, lds, dsl, coef, band, s);
 }
 
 // 2D pencils of up to kFill2dRows rows take fill2d_kernel
@@ -144,9 +189,9 @@ hipError_t launch_fill2d(const KInterp<T>& ip, int form, const Dims& d, const in
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (d.m[1] - 4 * d.p < 1) return hipSuccess;
   if (form == IGS_MASS)
-    launch_fill2d_q<IGS_MASS, kFill2dR, T>(ip, d, nt, lds, dsl, coef, band, s);
+    launch_fill2d_pf<IGS_MASS, kFill2dR, T>(ip, d, nt, lds, dsl, coef, band, s);
   else
-    launch_fill2d_q<IGS_STIFFNESS, kFill2dR, T>(ip, d, nt, lds, dsl, coef, band, s);
+    launch_fill2d_pf<IGS_STIFFNESS, kFill2dR, T>(ip, d, nt, lds, dsl, coef, band, s);
   return hipGetLastError();
 }
 
