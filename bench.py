@@ -70,11 +70,11 @@ def log(msg):
 def quad_flops_per_row(n, p):
     """Algorithmic flops of sum-factorised row quadrature (stiffness): per
     (a, b) component (p+1)^5 + (2p+1)(p+1)^4 + (2p+1)^2(p+1)^3 FMA in 3D,
-    (p+1)^3 + (2p+1)(p+1)^2 in 2D; n^2 components; 2 flops per FMA."""
+    (p+1)^4 + (2p+1)(p+1)^3 in 2D; n^2 components; 2 flops per FMA."""
     if n == 3:
         fma = (p + 1) ** 5 + (2 * p + 1) * (p + 1) ** 4 + (2 * p + 1) ** 2 * (p + 1) ** 3
     else:
-        fma = (p + 1) ** 3 + (2 * p + 1) * (p + 1) ** 2
+        fma = (p + 1) ** 4 + (2 * p + 1) * (p + 1) ** 3
     return 2 * n * n * fma
 
 
@@ -325,6 +325,39 @@ def main():
         except igs.IGSError as e:
             extra["compliance_2d_batch8"] = {"error": str(e)}
         log(f"c5: {extra['compliance_2d_batch8']}")
+
+        # ---------------- 3D p=4 128^3, variable coefficient (kept plans, 2 executions each)
+        try:
+            p3 = W.c3_varcoef3d()
+            lay3 = igs.layout(p3)
+            b3 = igs.empty_band(p3, torch.float64)
+            c3 = {}
+            for name, M3, q3 in (("surrogate", M, q), ("exact", 0, 0)):
+                pl3 = igs.Plan(p3, igs.STIFFNESS, M=M3, q=q3)
+                pl3.execute(out=b3)
+                igs.profile_enable(True)
+                igs.profile_read()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(2):
+                    pl3.execute(out=b3)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                pr3 = igs.profile_read()
+                igs.profile_enable(False)
+                pl3.close()
+                ms3 = e0.elapsed_time(e1) / 2
+                c3[name] = {"ms": ms3, "slots_per_s": lay3.N * lay3.slots / (ms3 * 1e-3),
+                            "phases_ms": {k: v[1] / v[0] for k, v in pr3.items()}}
+            fl3 = quad_flops_per_row(3, 4) * lay3.N
+            c3["exact"]["quad_kernel_tflops"] = fl3 / (c3["exact"]["phases_ms"]["quad_exact"] * 1e-3) / 1e12
+            c3["workload"] = "3D p=4 stiffness, 128^3 elements, sine map, kappa = 1 + 0.5 sin 2pi x1 cos 2pi x2 sin 2pi x3"
+            extra["varcoef_3d_p4_128"] = c3
+            del b3
+        except igs.IGSError as e:
+            extra["varcoef_3d_p4_128"] = {"error": str(e)}
+        log(f"3D p=4: {extra['varcoef_3d_p4_128']}")
 
         extra["mesh_dependent_2d_p2_q5"] = mesh_dependent_study(stream)
 
