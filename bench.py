@@ -476,10 +476,36 @@ def cpu_baseline(prob, M, q, lay):
     nb = N - math.prod(m[d] - 4 * prob["p"] for d in range(3))
     ni = N - nb
     total = t_setup + t_b * nb / len(rb) + t_i * ni / len(ri)
-    return {"value": N * S / total, "unit": "band slots/s", "cores": O.threads(), "kind": "oracle",
-            "sample": (f"sample-row quadrature + fit in full ({len(sur.sample_rows)} rows, {t_setup:.1f} s), "
-                       f"{len(rb)} random boundary rows ({t_b:.1f} s) and {len(ri)} random analysis-domain rows "
-                       f"({t_i:.1f} s), extrapolated to {nb} + {ni} rows: {total:.0f} s for the full band")}
+    nthreads = O.threads()
+    out = {"value": N * S / total, "unit": "band slots/s", "cores": nthreads, "kind": "oracle",
+           "sample": (f"sample-row quadrature + fit in full ({len(sur.sample_rows)} rows, {t_setup:.1f} s), "
+                      f"{len(rb)} random boundary rows ({t_b:.1f} s) and {len(ri)} random analysis-domain rows "
+                      f"({t_i:.1f} s), extrapolated to {nb} + {ni} rows: {total:.0f} s for the full band")}
+    # the same oracle on one thread (OpenMP of the oracle's C half set to 1):
+    # per-row costs of smaller samples, sample rows costed as exact rows
+    try:
+        import ctypes
+
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        try:
+            rb1, ri1 = rb[:300], ri[:1000]
+            t0 = time.perf_counter()
+            O.exact_rows(prob, 0, rb1)
+            tb1 = (time.perf_counter() - t0) / len(rb1)
+            t0 = time.perf_counter()
+            sur.rows(ri1)
+            ti1 = (time.perf_counter() - t0) / len(ri1)
+        finally:
+            gomp.omp_set_num_threads(nthreads)
+        total1 = tb1 * (nb + len(sur.sample_rows)) + ti1 * ni
+        out["single_thread"] = {"value": N * S / total1, "unit": "band slots/s", "cores": 1,
+                                "sample": (f"{len(rb1)} boundary rows ({tb1 * 1e3:.2f} ms/row) and {len(ri1)} "
+                                           f"analysis-domain rows ({ti1 * 1e3:.3f} ms/row) on one thread, "
+                                           f"sample rows costed as boundary rows: {total1:.0f} s for the full band")}
+    except OSError:
+        pass
+    return out
 
 
 if __name__ == "__main__":
