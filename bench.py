@@ -160,6 +160,18 @@ def main():
     value = slots / (ms_step * 1e-3)
     phases = {k: {"launches": v[0], "avg_ms": v[1] / v[0]} for k, v in prof.items()}
     log(f"surrogate: {ms_step:.3f} ms/step (wall {wall / args.steps * 1e3:.3f}), {value:.3e} slots/s, phases {phases}")
+    # the same number of steps again, each between its own events: median and spread
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record(stream)
+    for k in range(args.steps):
+        plan.execute(out=band)
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    per_step = sorted(evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps))
+    step_stats = {"median_ms": per_step[len(per_step) // 2] if len(per_step) % 2 else
+                  0.5 * (per_step[len(per_step) // 2 - 1] + per_step[len(per_step) // 2]),
+                  "min_ms": per_step[0], "max_ms": per_step[-1], "steps": args.steps}
+    log(f"per-step: {step_stats}")
 
     # rooflines of the step's kernels
     fpr = quad_flops_per_row(3, prob["p"])
@@ -383,6 +395,7 @@ def main():
         "config": {"workload": "3D Poisson stiffness, p=3, 128^3 elements, sine map a=0.05, kappa=1, surrogate M=8 q=3",
                    "dofs": lay.N, "slots": slots, "true_nnz": true_nnz, "parallelism": "single GPU"},
         "true_nnz_per_s": true_nnz / (ms_step * 1e-3),
+        "step_ms_separately_timed": step_stats,
         "phases_ms": {k: v["avg_ms"] for k, v in phases.items()},
         "roofline": roofline,
         "rooflines": roofs,
