@@ -132,12 +132,27 @@ def test_surrogate_fp32(igs, oracle):
 @pytest.mark.parametrize("prob,form,M,q", [
     (W.problem(2, 3, (70, 41)), 0, 5, 5), (W.problem(2, 2, (37, 66)), 1, 4, 2),
     (W.problem(2, 4, (60, 47), coef="sine3", camp=0.5), 0, 6, 3), (W.problem(2, 1, (300, 23)), 0, 7, 1),
+    # m1 = 4096, the widest pencil of the per-pencil 2D fill (1024 threads x 4 rows)
+    (W.problem(2, 1, (4095, 8)), 0, 2, 1),
 ])
 def test_surrogate_2d_rectangular(igs, oracle, prob, form, M, q):
     """2D fill on meshes with m1 != m2 (pencils of one direction, lattices of
     the other), stiffness and mass, even and odd q."""
     band = igs.assemble_surrogate(prob, form, M=M, q=q)
     ref = oracle.surrogate_rows(prob, form, M, q)
+    assert rel_maxnorm(_full(igs, band, prob), ref) < TOL64
+
+
+def test_surrogate_2d_too_wide(igs, oracle):
+    """Past 4096 functions in direction 1 the 2D fill falls back to the chunked
+    kernel, whose per-chunk tables outgrow LDS at small sampling steps: a clean
+    IGS_ERR_UNSUPPORTED, while a larger step still assembles."""
+    prob = W.problem(2, 1, (4200, 8))
+    with pytest.raises(igs.IGSError) as e:
+        igs.assemble_surrogate(prob, 0, M=2, q=1)
+    assert e.value.status == -2
+    band = igs.assemble_surrogate(prob, 0, M=16, q=1)
+    ref = oracle.surrogate_rows(prob, 0, 16, 1)
     assert rel_maxnorm(_full(igs, band, prob), ref) < TOL64
 
 
