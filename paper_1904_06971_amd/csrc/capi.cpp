@@ -29,6 +29,10 @@ void fill_block_dims(const Dims& d, const std::vector<int> ef[3], int q, const s
 std::vector<int> fill_chunks(const Dims& d, int rows);
 int fill_npen(const Dims& d, int rows);
 bool fill_is_2d(const Dims& d);
+bool fit_use_gemm(const KInterp<double>& ip, int n, int batch);
+template <typename BT>
+hipError_t launch_fit_gemm(const KInterp<double>& ip, int n, int m1, int m2, int64_t ld, int S, int batch,
+                           const BT* band, double* tmp0, double* tmp1, double* coef, hipStream_t s);
 int fill_chunk_rows(const Dims& d, int Sd1);
 template <typename T>
 hipError_t launch_zero_pad(T* band, int64_t N, int64_t ld, int slots_total, hipStream_t s);
@@ -335,8 +339,12 @@ static igs_status run_t(const Plan& pl, const KProblem& kp, const KInterp<OutT>&
     }
     {
       PhaseTimer t("fit", s);
-      HIP_TRY(launch_fit<OutT>(pl.ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, pl.tmp0, pl.tmp1, pl.coef,
-                               pl.g0T, s));
+      if (fit_use_gemm(pl.ip64, d.n, d.batch))
+        HIP_TRY(launch_fit_gemm<OutT>(pl.ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, pl.tmp0, pl.tmp1,
+                                      pl.coef, s));
+      else
+        HIP_TRY(launch_fit<OutT>(pl.ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, pl.tmp0, pl.tmp1, pl.coef,
+                                 pl.g0T, s));
     }
     {
       PhaseTimer t("fill", s);

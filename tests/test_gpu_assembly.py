@@ -143,6 +143,29 @@ def test_surrogate_2d_rectangular(igs, oracle, prob, form, M, q):
     assert rel_maxnorm(_full(igs, band, prob), ref) < TOL64
 
 
+@pytest.mark.parametrize("prob,form,M,q", [
+    (W.problem(3, 1, (200, 5, 5)), 0, 1, 1), (W.problem(3, 1, (5, 200, 5)), 1, 1, 1),
+    (W.problem(3, 1, (5, 5, 200)), 0, 1, 1), (W.problem(2, 2, 230), 0, 1, 5), (W.problem(2, 2, (60, 230)), 1, 1, 3),
+])
+def test_surrogate_fit_tiled(igs, oracle, prob, form, M, q):
+    """At least 192 samples in a direction: the fit runs as tiled products
+    (each direction long in turn in 3D; 2D stiffness and mass)."""
+    band = igs.assemble_surrogate(prob, form, M=M, q=q)
+    ref = oracle.surrogate_rows(prob, form, M, q)
+    assert rel_maxnorm(_full(igs, band, prob), ref) < TOL64
+
+
+def test_surrogate_fit_tiled_batch(igs, oracle):
+    """Tiled fit over a batch of two coefficient fields (2D, 197 x 197 samples)."""
+    rng = np.random.default_rng(41)
+    cc = rng.normal(0, 0.4, (2, 25))
+    prob = W.problem(2, 1, 200, coef="exp_spline", cdeg=2, cn=(5, 5), cc=cc, batch=2)
+    band = igs.assemble_surrogate(prob, 0, M=1, q=3)
+    for b in range(2):
+        ref = oracle.surrogate_rows(prob, 0, 1, 3, b=b)
+        assert rel_maxnorm(igs.band_rows(band, prob, b), ref) < TOL64
+
+
 def test_surrogate_2d_too_wide(igs, oracle):
     """Past 4096 functions in direction 1 the 2D fill falls back to the chunked
     kernel, whose per-chunk tables outgrow LDS at small sampling steps: a clean
