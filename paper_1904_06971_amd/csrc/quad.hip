@@ -975,6 +975,9 @@ struct Q2 {
   static constexpr int NQ1 = (TX + P) * NQ;
   static constexpr int NC = FORM == IGS_STIFFNESS ? 3 : 1;
   static constexpr int BLOCK = (TX * W + 63) / 64 * 64;
+  // p <= 2: ask for 4 waves per SIMD (128 VGPRs, a few spills at p = 2);
+  // larger p would spill heavily
+  static constexpr int MINW = P <= 2 ? 4 : 1;
 };
 
 // A workgroup owns TX consecutive i1 of a tile and streams its element rows
@@ -984,7 +987,7 @@ struct Q2 {
 // lines, the tile's direction-1 footprint) are computed into one LDS buffer
 // while the rows consume the other, so an element row costs one barrier.
 template <int P, int FORM, typename OutT>
-__global__ void __launch_bounds__((Q2<P, FORM>::BLOCK))
+__global__ void __launch_bounds__((Q2<P, FORM>::BLOCK), (Q2<P, FORM>::MINW))
     quad2d_kernel(KProblem kp, const QTile* __restrict__ tiles, OutT* __restrict__ band) {
   using C = Q2<P, FORM>;
   constexpr int NQ = C::NQ, W = C::W, TX = C::TX, NQ1 = C::NQ1;
