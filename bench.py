@@ -197,6 +197,13 @@ def main():
     dominant = max(roofs, key=lambda k: roofs[k].get("ms", phases.get(k, {}).get("avg_ms", 0.0)))
     roofline = dict(roofs[dominant])
     roofline["kernel"] = dominant
+    # the whole step against the HBM roofline: the band it must write, over the
+    # step time (the target reading of ">= 60% of HBM peak" for the assembly)
+    band_bytes = slots * 8
+    step_hbm = {"bound": "hbm", "achieved": band_bytes / (ms_step * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": band_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "units": f"{slots} band slots x 8 bytes written once", "target_frac": 0.60}
+    log(f"whole step: {step_hbm['achieved']:.0f} GB/s algorithmic, {100 * step_hbm['frac']:.1f}% of HBM peak")
 
     extra = {}
     if not args.no_extra:
@@ -398,6 +405,7 @@ def main():
         "step_ms_separately_timed": step_stats,
         "phases_ms": {k: v["avg_ms"] for k, v in phases.items()},
         "roofline": roofline,
+        "step_hbm": step_hbm,
         "rooflines": roofs,
         "cpu_baseline": cpu,
         **extra,
@@ -461,6 +469,18 @@ def mesh_dependent_study(stream):
             "rows": rows}
 
 
+def cpu_model():
+    """The host CPU's model name (first /proc/cpuinfo entry), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(prob, M, q, lay):
     """The oracle timed on the host: sample-row quadrature and fit in full, then
     seeded random samples of boundary rows (exact) and analysis-domain rows
@@ -491,6 +511,7 @@ def cpu_baseline(prob, M, q, lay):
     total = t_setup + t_b * nb / len(rb) + t_i * ni / len(ri)
     nthreads = O.threads()
     out = {"value": N * S / total, "unit": "band slots/s", "cores": nthreads, "kind": "oracle",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
            "sample": (f"sample-row quadrature + fit in full ({len(sur.sample_rows)} rows, {t_setup:.1f} s), "
                       f"{len(rb)} random boundary rows ({t_b:.1f} s) and {len(ri)} random analysis-domain rows "
                       f"({t_i:.1f} s), extrapolated to {nb} + {ni} rows: {total:.0f} s for the full band")}

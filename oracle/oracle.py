@@ -403,10 +403,186 @@ class Surrogate:
         return out
 
 
+def layer_classes(prob):
+    """Row classes of the face/edge stencil functions (Sec. 3.6 reading).
+
+    In direction d an index is "free" when it lies in the analysis range
+    [2p, m_d - 2p - 1] (there b_{i_d} and every partner b_{i_d + delta_d} are
+    translates of one cardinal B-spline) and otherwise sits in one of the 4p
+    boundary layers [0, 2p) u [m_d - 2p, m_d).  The class of row i is the tuple
+    key_d = -1 (free) or i_d (its layer); rows of one class are translates of
+    each other along the free directions, so every stencil function
+    Phi^key_delta is a function of the free coordinates alone.  Returns the
+    keys with at least one free direction (interior, faces, edges); the
+    classes without one are the corner rows."""
+    n, p = prob["n"], prob["p"]
+    m, _, _ = dims(prob)
+    opts = []
+    for d in range(n):
+        opts.append([-1] + list(range(2 * p)) + list(range(m[d] - 2 * p, m[d])))
+    keys = []
+    for key in np.ndindex(*[len(o) for o in opts]):
+        k = tuple(opts[d][key[d]] for d in range(n))
+        if any(v < 0 for v in k):
+            keys.append(k)
+    return keys
+
+
+def row_class(prob, idx):
+    """Class keys [npts, n] of multi-indices idx (-1 in free directions)."""
+    m, _, _ = dims(prob)
+    p = prob["p"]
+    key = idx.copy()
+    for d in range(prob["n"]):
+        free = (idx[:, d] >= 2 * p) & (idx[:, d] <= m[d] - 2 * p - 1)
+        key[free, d] = -1
+    return key
+
+
+class SurrogateFE:
+    """Surrogate with face- and edge-based stencil functions (Sec. 3.6: a
+    family of stencil functions for each face and edge, exploiting the
+    translation invariance that remains parallel to them).
+
+    Reading (the paper states the idea only):
+      * classes as in ``layer_classes``; each class with at least one free
+        direction has, for every upper delta (colex offset > 0; also delta = 0
+        for the mass form), its own stencil function over its free
+        coordinates, sampled on the tensor lattice of the free directions
+        (the same 1-D lattice as the analysis domain, Sec. 6) at the class's
+        fixed layers, and interpolated by the degree-q tensor spline of
+        ``interp_knots`` (Sec. 4.1) along the free directions only;
+      * rows with no free direction (corners) are exact (quadrature);
+      * entries, extending eq. 5.1c to the classes: for i < j the value is
+        decided by the smaller index i, Phi~^{c(i)}_delta(i) when row i has a
+        free direction, else the exact A_ij; for i > j it is the value of
+        the pair (j, i) (symmetry); entries whose partner leaves the index box
+        are 0;
+      * stiffness: every diagonal is -sum_{k != i} A~_ik (eq. 5.1c as stated,
+        for every row); mass: the diagonal is interpolated (delta = 0 is an
+        upper stencil, eq. 5.1b), exact on corner rows.
+    Lower entries whose smaller partner is a corner row take row i's own
+    quadrature here; the GPU copies A_ji from the partner (equal to rounding).
+    """
+
+    def __init__(self, prob, form, M, q, b=0, exact=None):
+        self.prob, self.form, self.M, self.q, self.b = prob, form, M, q, b
+        self.exact = exact if exact is not None else (lambda rows: exact_rows(prob, form, rows, b))
+        n, p = prob["n"], prob["p"]
+        m, N, S = dims(prob)
+        self.m, self.N, self.S = m, N, S
+        self.sc = (S - 1) // 2
+        self.off = stencil_offsets(prob)
+        self.samples = [lattice(m[d], p, M) for d in range(n)]
+        for d in range(n):
+            if len(self.samples[d]) < q + 1:
+                raise ValueError("fewer samples than q+1 in a direction")
+        knots = [interp_knots(self.samples[d], q) for d in range(n)]
+        self.G = [bspline_matrix(knots[d], q, self.samples[d]) for d in range(n)]
+        self.E = []
+        for d in range(n):
+            x = np.clip(np.arange(m[d], dtype=np.float64), self.samples[d][0], self.samples[d][-1])
+            self.E.append(bspline_matrix(knots[d], q, x))
+        self.upper = [s for s in range(S) if s > self.sc or (form == MASS and s == self.sc)]
+        self.keys = layer_classes(prob)
+        # sample rows of every class, then one batch of exact rows for all
+        srows, spans = [], {}
+        for key in self.keys:
+            sets = [self.samples[d] if key[d] < 0 else np.array([key[d]]) for d in range(n)]
+            g = np.meshgrid(*sets[::-1], indexing="ij")
+            r = flat_index(prob, np.stack([x.ravel() for x in g[::-1]], axis=1))
+            spans[key] = (sum(len(x) for x in srows), len(r), tuple(len(x) for x in sets)[::-1])
+            srows.append(r)
+        self.sample_rows = np.concatenate(srows)
+        V = self.exact(self.sample_rows)
+        self.coef = {}
+        for key in self.keys:
+            start, cnt, shape = spans[key]
+            free = [d for d in range(n) if key[d] < 0]
+            for s in self.upper:
+                c = V[start:start + cnt, s].reshape(shape)
+                for d in free:                                    # solve along each free direction
+                    ax = n - 1 - d
+                    c = np.moveaxis(c, ax, 0)
+                    sh = c.shape
+                    c = np.linalg.solve(self.G[d], c.reshape(sh[0], -1)).reshape(sh)
+                    c = np.moveaxis(c, 0, ax)
+                self.coef[(key, s)] = c
+
+    def phi(self, key, s, idx):
+        """Phi~^key for upper slot s at multi-indices idx [npts, n] of rows of
+        class key (only their free coordinates enter)."""
+        n = self.prob["n"]
+        c = self.coef[(key, s)]
+        v = c.reshape(c.shape + (1,)) * np.ones(len(idx))             # [..., npts]
+        for d in range(n):                                            # contract the last axis first (direction 1)
+            ax = n - 1 - d
+            if key[d] < 0:
+                w = self.E[d][idx[:, d]]                                  # [npts, S_d]
+                v = np.einsum("...jn,nj->...n", np.moveaxis(v, ax, -2), w)
+            else:
+                v = np.moveaxis(v, ax, -2)[..., 0, :]
+        return v.reshape(len(idx))
+
+    def rows(self, rows):
+        prob = self.prob
+        n = prob["n"]
+        rows = np.asarray(rows, dtype=np.int64)
+        idx = multi_index(prob, rows)
+        key = row_class(prob, idx)
+        corner = np.all(key >= 0, axis=1)
+        mvec = np.array(self.m)
+        out = np.zeros((len(rows), self.S))
+        ex = self.exact(rows)                       # exact values: corner rows and corner partners
+        for s in range(self.S):
+            jidx = idx + self.off[s]
+            inbox = np.all((jidx >= 0) & (jidx < mvec), axis=1)
+            if s == self.sc and self.form == STIFFNESS:
+                continue
+            if s in self.upper:
+                own, part = ~corner & inbox, None
+                sel, src_idx, src_key, slot = own, idx, key, s
+            else:
+                jkey = row_class(prob, np.where(inbox[:, None], jidx, 0))
+                jcorner = np.all(jkey >= 0, axis=1)
+                sel, src_idx, src_key, slot = inbox & ~jcorner, jidx, jkey, self.S - 1 - s
+            val = np.where(inbox, ex[:, s], 0.0)
+            ii = np.nonzero(sel)[0]
+            if len(ii):
+                ks = src_key[ii]
+                for kk in np.unique(ks, axis=0):
+                    grp = ii[np.all(ks == kk, axis=1)]
+                    val[grp] = self.phi(tuple(int(v) for v in kk), slot, src_idx[grp])
+            out[:, s] = val
+        if self.form == STIFFNESS:
+            out[:, self.sc] = -(out.sum(axis=1) - out[:, self.sc])
+        return out
+
+
 def surrogate_rows(prob, form, M, q, rows=None, b=0):
     _, N, _ = dims(prob)
     rows = np.arange(N) if rows is None else rows
     return Surrogate(prob, form, M, q, b).rows(rows)
+
+
+def surrogate_fe_rows(prob, form, M, q, rows=None, b=0):
+    _, N, _ = dims(prob)
+    rows = np.arange(N) if rows is None else rows
+    return SurrogateFE(prob, form, M, q, b).rows(rows)
+
+
+def quadrature_rows_fe(prob, M):
+    """Rows the face/edge surrogate assembles by quadrature: the sample rows of
+    every class with a free direction, plus the corner rows."""
+    m, N, _ = dims(prob)
+    p = prob["p"]
+    idx = multi_index(prob, np.arange(N))
+    key = row_class(prob, idx)
+    out = np.all(key >= 0, axis=1)
+    samp = np.ones(N, dtype=bool)
+    for d in range(prob["n"]):
+        samp &= (key[:, d] >= 0) | np.isin(idx[:, d], lattice(m[d], p, M))
+    return out | samp
 
 
 def quadrature_rows(prob, M):

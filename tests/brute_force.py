@@ -55,6 +55,30 @@ def sine_map(xi, a):
     return F, J
 
 
+def poly2_map(xi, a):
+    """F and J of the Q_2 map F_r = xi_r + a (r+1) prod_d xi_d (1 - xi_d)
+    (r 0-based).  J is not transcribed: it comes from complex-step
+    differentiation of F, dF/dxi_c = Im F(xi + i t e_c) / t, which is exact
+    to rounding for a polynomial map and shares no formula with the oracle's
+    hand-written Jacobian."""
+    n = len(xi)
+
+    def F(z):
+        prod = 1.0 + 0.0j
+        for d in range(n):
+            prod *= z[d] * (1.0 - z[d])
+        return np.array([z[r] + a * (r + 1) * prod for r in range(n)])
+
+    x0 = np.array(xi, dtype=complex)
+    t = 1e-30
+    J = np.zeros((n, n))
+    for c in range(n):
+        z = x0.copy()
+        z[c] += 1j * t
+        J[:, c] = F(z).imag / t
+    return F(x0).real, J
+
+
 def coefficient(prob, xi, F):
     kind = prob["coef"]
     if kind == "const":
@@ -114,6 +138,8 @@ def assemble_dense(prob, form):
             w = np.prod([wts[d][k[d]] for d in range(n)])
             if prob["geom"] == "identity":
                 F, J = np.array(xi), np.eye(n)
+            elif prob["geom"] == "poly2":
+                F, J = poly2_map(xi, prob["ga"])
             else:
                 F, J = sine_map(xi, prob["ga"])
             det = np.linalg.det(J)

@@ -155,6 +155,18 @@ def test_surrogate_fit_tiled(igs, oracle, prob, form, M, q):
     assert rel_maxnorm(_full(igs, band, prob), ref) < TOL64
 
 
+def test_surrogate_fit_tiled_fp32(igs, oracle):
+    """The FP32 form of the tiled fit (FP32 sample rows gathered into the FP64
+    products): 2D p = 2, 230^2 elements, M = 1, q = 5 (226 samples per
+    direction), at FP32 resolution."""
+    import torch
+
+    prob = W.problem(2, 2, 230)
+    band = igs.assemble_surrogate(prob, 0, M=1, q=5, dtype=torch.float32)
+    ref = oracle.surrogate_rows(prob, 0, 1, 5)
+    assert rel_maxnorm(_full(igs, band, prob), ref) < 2e-6
+
+
 def test_surrogate_fit_tiled_batch(igs, oracle):
     """Tiled fit over a batch of two coefficient fields (2D, 197 x 197 samples)."""
     rng = np.random.default_rng(41)

@@ -134,11 +134,31 @@ def test_linear_functions_in_kernel_identity(oracle, n, p, ne):
     (W.problem(3, 2, 3), 1),
     (W.problem(2, 3, 5, coef="exp_spline", cdeg=3, cn=(5, 6), cc=np.random.default_rng(7).normal(0, .5, 30)), 0),
     (W.problem(2, 2, 4, coef="spline", cdeg=2, cn=(3, 3), cc=np.arange(9.0) + 1.0), 0),
+    (W.problem(2, 2, 5, geom="poly2", ga=0.3), 0), (W.problem(2, 3, 4, geom="poly2", ga=0.3), 1),
+    (W.problem(3, 2, 3, geom="poly2", ga=0.2), 0), (W.problem(3, 2, 3, geom="poly2", ga=0.2), 1),
+    (W.problem(2, 2, 4, geom="poly2", ga=0.3, coef="sine3", camp=0.5), 0),
 ])
 def test_rows_match_brute_force(oracle, prob, form):
     ref = assemble_dense(prob, form)
     A = _full(oracle, prob, form)
     assert np.abs(A - ref).max() < 1e-14 * max(1.0, np.abs(ref).max()) * 10
+
+
+@pytest.mark.parametrize("prob", [W.problem(2, 2, 7, geom="poly2", ga=0.3), W.problem(2, 3, 6, geom="poly2", ga=0.3),
+                                  W.problem(3, 3, 4, geom="poly2", ga=0.2)])
+def test_poly2_total_mass(oracle, prob):
+    """The Q_2 map fixes the boundary of the unit box (a factor xi_d (1 - xi_d)
+    vanishes there) and folds nowhere at these amplitudes, so it maps the box
+    onto itself and sum_ij M_ij = int det J = |Omega| = 1 (partition of unity,
+    Sec. 2.2).  Every entry of J has degree <= 2 in each variable, so det J
+    has degree <= 2n in each variable (4 in 2D, 6 in 3D), which (p+1)-point
+    Gauss integrates exactly for p >= 2 (2D) and p >= 3 (3D): the sum is 1 to
+    rounding, not just to quadrature accuracy."""
+    Mm = _full(oracle, prob, 1)
+    assert abs(Mm.sum() - 1.0) < 1e-13
+    A = _full(oracle, prob, 0)
+    assert np.abs(A - A.T).max() < 1e-13 * np.abs(A).max()
+    assert np.abs(A.sum(axis=1)).max() < 1e-13 * np.abs(A).max()
 
 
 def test_rhs_identity_constant(oracle):
