@@ -30,7 +30,8 @@
  * - Device memory: every pointer marked "device" must be device memory (or
  *   host-coherent memory visible to the GPU) owned by the caller.  The library
  *   keeps no pointer after a call returns and holds no global mutable state
- *   besides the opt-in, thread-local profiling record (igs_profile_enable);
+ *   besides the opt-in, thread-local profiling record (igs_profile_enable)
+ *   and the static scratch array of igs_assemble_noalloc;
  *   scratch memory is taken stream-ordered from the default memory pool and
  *   returned before the call returns.  Plans (igs_plan_*) are the exception:
  *   they own device memory from igs_plan_create to igs_plan_destroy.
@@ -59,6 +60,8 @@ typedef enum igs_status {
   IGS_ERR_GEOMETRY = -5,    /* det J <= 0 at a quadrature point */
   IGS_ERR_HIP = -6,         /* a HIP runtime call failed */
   IGS_ERR_NOMEM = -7,       /* scratch allocation failed */
+  IGS_ERR_SCRATCH = -8,     /* igs_assemble_noalloc: the problem needs more
+                               scratch than IGS_NOALLOC_SCRATCH_BYTES */
   IGS_NOT_CONVERGED = 1,    /* solver stopped at maxit */
   IGS_BREAKDOWN = 2         /* CG: p^T A p <= 0 or a non-finite value */
 } igs_status;
@@ -205,6 +208,27 @@ igs_status igs_assemble_exact(const igs_problem* pb, int32_t form, int32_t dtype
  * not (small M on such meshes) the call returns IGS_ERR_UNSUPPORTED. */
 igs_status igs_assemble_surrogate(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype,
                                   void* band, void* stream);
+
+/* Allocation-free assembly, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  M = 0: as igs_assemble_exact; M >= 1: as
+ * igs_assemble_surrogate with sampling step M and degree q.  Same arguments,
+ * validation, results and errors as those calls, and synchronous on return
+ * like them; the caller still passes the band (device, igs_layout.band_elems
+ * elements of dtype).  The scratch the kernels use (the 1-D tables, tile and
+ * chunk lists, interpolation tables, spline coefficients and the error word)
+ * lives in one static device array of IGS_NOALLOC_SCRATCH_BYTES per GPU,
+ * held from the first call on that GPU until the process ends; the call makes
+ * no hipMalloc, hipMallocAsync or hipFree.  A problem whose scratch exceeds
+ * the array returns IGS_ERR_SCRATCH before any GPU work is queued (the 3-D
+ * p = 3, 128^3 surrogate with M = 8 needs about 20 MB).  Calls share their
+ * GPU's array: calls that overlap in time on one GPU (other host threads,
+ * other streams) race and must be serialised by the caller.  Host-side set-up
+ * uses ordinary host memory.  IGS_ERR_HIP if the array's device address cannot
+ * be obtained. */
+#define IGS_NOALLOC_SCRATCH_BYTES (32u << 20)
+igs_status igs_assemble_noalloc(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* band,
+                                void* stream);
 
 /* ---------------------------------------------------------------- plans */
 

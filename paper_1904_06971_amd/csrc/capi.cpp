@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "igs_internal.h"
@@ -107,8 +108,9 @@ static igs_status prepare(const igs_problem* pb, hipStream_t s, Prepared* P) {
     kp.cstride *= kp.cn[k];
   }
   kp.cc = spline ? pb->coef.coef : nullptr;
-  kp.flag = P->ar.take<int>(1);
-  HIP_TRY(hipMemsetAsync(kp.flag, 0, sizeof(int), s));
+  // the error word starts at 0: it is sent with the tables (no memset node)
+  const int zero = 0;
+  kp.flag = const_cast<int*>(P->ar.put(&zero, 1));
   for (int k = 0; k < kp.n; ++k) {
     kp.t[k].x = upload(P->ar, P->ht.x[k], s, &st);
     kp.t[k].w = upload(P->ar, P->ht.w[k], s, &st);
@@ -388,8 +390,10 @@ static igs_status check_plan(Plan* pl, hipStream_t s, bool always) {
 }
 
 static igs_status one_shot(const igs_problem* pb, int kind, int form, int M, int q, int dtype, void* band,
-                           hipStream_t s) {
+                           hipStream_t s, ScratchPool* pool = nullptr) {
   Plan pl;
+  pl.P.ar.pool = pool;
+  pl.ta.pool = pool;
   pl.kind = kind;
   pl.form = form;
   pl.dtype = dtype;
@@ -400,6 +404,31 @@ static igs_status one_shot(const igs_problem* pb, int kind, int form, int M, int
   st = run_plan(pl, nullptr, band, s);
   if (st != IGS_OK) return st;
   return check_plan(&pl, s, true);
+}
+
+// ------------------------------------------------------ allocation-free path
+//
+// The scratch of igs_assemble_noalloc: one array per GPU for the life of the
+// process.  Its name is a host-side stand-in, not a device address: host code
+// uses only the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) char scratch[IGS_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::vector<char*> g_scratch_ptr;  // per device ordinal; null until looked up
+
+static igs_status scratch_address(char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0) return IGS_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (size_t(dev) >= g_scratch_ptr.size()) g_scratch_ptr.resize(size_t(dev) + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return IGS_ERR_HIP;
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return IGS_OK;
 }
 
 }  // namespace igs
@@ -487,6 +516,7 @@ const char* igs_status_string(int32_t status) {
     case IGS_ERR_GEOMETRY: return "geometry map folds (det J <= 0 at a quadrature point)";
     case IGS_ERR_HIP: return "HIP runtime error";
     case IGS_ERR_NOMEM: return "out of device memory";
+    case IGS_ERR_SCRATCH: return "problem needs more scratch than the allocation-free entry point holds";
     case IGS_NOT_CONVERGED: return "not converged within maxit";
     case IGS_BREAKDOWN: return "CG breakdown";
     default: return "unknown status";
@@ -516,6 +546,26 @@ igs_status igs_assemble_surrogate(const igs_problem* pb, int32_t form, int32_t M
   st = check_sampling(d, M, q);
   if (st != IGS_OK) return st;
   return one_shot(pb, 1, form, M, q, dtype, band, static_cast<hipStream_t>(stream));
+}
+
+igs_status igs_assemble_noalloc(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* band,
+                                void* stream) {
+  if (!pb || !band) return IGS_ERR_ARG;
+  if (form != IGS_STIFFNESS && form != IGS_MASS) return IGS_ERR_ARG;
+  if (dtype != IGS_F64 && dtype != IGS_F32) return IGS_ERR_ARG;
+  if (M < 0) return IGS_ERR_ARG;
+  Dims d;
+  igs_status st = make_dims(pb, &d);
+  if (st != IGS_OK) return st;
+  if (M >= 1) {
+    st = check_sampling(d, M, q);
+    if (st != IGS_OK) return st;
+  }
+  ScratchPool pool;
+  st = scratch_address(&pool.base);
+  if (st != IGS_OK) return st;
+  pool.cap = IGS_NOALLOC_SCRATCH_BYTES;
+  return one_shot(pb, M == 0 ? 0 : 1, form, M, q, dtype, band, static_cast<hipStream_t>(stream), &pool);
 }
 
 struct igs_plan_s {

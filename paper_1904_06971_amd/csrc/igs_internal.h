@@ -113,6 +113,15 @@ std::vector<QTile> tiles_all(const Dims& d, int tx, int ty, int zchunk);
 std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3], int tx, int ty, int zchunk,
                                    int groups[3]);
 
+// Caller-provided device memory that arenas carve their pieces from instead
+// of allocating (the allocation-free entry point): every arena attached to a
+// pool takes the next 256-byte aligned range, and fails with
+// IGS_ERR_SCRATCH when the pool is exhausted.
+struct ScratchPool {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+};
+
 // Device scratch arena: one stream-ordered allocation carved into pieces.
 // put() reserves a piece and stages host data for it; flush() sends every
 // staged piece with a single host-to-device copy (the pieces are contiguous,
@@ -122,6 +131,7 @@ struct Arena {
   size_t size = 0, used = 0;
   hipStream_t stream = nullptr;
   bool persistent = false;  // plain hipMalloc/hipFree (outlives the stream it was made on)
+  ScratchPool* pool = nullptr;  // when set: carve from the pool, never allocate or free
   std::vector<char> stage;
   size_t dlo = ~size_t(0), dhi = 0;
   igs_status alloc(size_t bytes, hipStream_t s);

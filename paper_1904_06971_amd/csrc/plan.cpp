@@ -401,6 +401,13 @@ igs_status Arena::alloc(size_t bytes, hipStream_t s) {
   size = bytes;
   used = 0;
   if (bytes == 0) return IGS_OK;
+  if (pool) {
+    const size_t off = padded(pool->used);
+    if (off > pool->cap || bytes > pool->cap - off) return IGS_ERR_SCRATCH;
+    base = pool->base + off;
+    pool->used = off + bytes;
+    return IGS_OK;
+  }
   const hipError_t e = persistent ? hipMalloc(reinterpret_cast<void**>(&base), bytes)
                                   : hipMallocAsync(reinterpret_cast<void**>(&base), bytes, s);
   if (e != hipSuccess) {
@@ -419,7 +426,7 @@ igs_status Arena::flush() {
 }
 
 void Arena::release() {
-  if (base) (void)(persistent ? hipFree(base) : hipFreeAsync(base, stream));
+  if (base && !pool) (void)(persistent ? hipFree(base) : hipFreeAsync(base, stream));
   base = nullptr;
   size = used = 0;
   stage.clear();

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libigs.so")
 
 IGS_OK = 0
 STATUS = {0: "IGS_OK", -1: "IGS_ERR_ARG", -2: "IGS_ERR_UNSUPPORTED", -3: "IGS_ERR_KNOTS", -4: "IGS_ERR_SAMPLES",
-          -5: "IGS_ERR_GEOMETRY", -6: "IGS_ERR_HIP", -7: "IGS_ERR_NOMEM", 1: "IGS_NOT_CONVERGED", 2: "IGS_BREAKDOWN"}
+          -5: "IGS_ERR_GEOMETRY", -6: "IGS_ERR_HIP", -7: "IGS_ERR_NOMEM",
+          -8: "IGS_ERR_SCRATCH", 1: "IGS_NOT_CONVERGED", 2: "IGS_BREAKDOWN"}
 STIFFNESS, MASS = 0, 1
 F64, F32 = 0, 1
 GEOM = {"identity": 0, "sine": 1, "poly2": 2}
@@ -26,7 +27,7 @@ COEF = {"const": 0, "sine3": 1, "spline": 2, "exp_spline": 3}
 SRC_CONST, SRC_SINE = 0, 1
 EXPORTS = ["igs_band_layout", "igs_validate", "igs_surrogate_layout", "igs_sampling_length", "igs_status_string",
            "igs_version",
-           "igs_assemble_exact", "igs_assemble_surrogate", "igs_plan_create", "igs_plan_execute", "igs_plan_destroy",
+           "igs_assemble_exact", "igs_assemble_surrogate", "igs_assemble_noalloc", "igs_plan_create", "igs_plan_execute", "igs_plan_destroy",
            "igs_assemble_rhs", "igs_apply", "igs_solve_cg", "igs_apply_vjp", "igs_compliance_grad",
            "igs_profile_enable", "igs_profile_read"]
 
@@ -94,6 +95,7 @@ def lib():
             "igs_sampling_length": [i32, i32, i32, f64, f64],
             "igs_assemble_exact": [P, i32, i32, vp, vp],
             "igs_assemble_surrogate": [P, i32, i32, i32, i32, vp, vp],
+            "igs_assemble_noalloc": [P, i32, i32, i32, i32, vp, vp],
             "igs_plan_create": [P, i32, i32, i32, i32, vp, ctypes.POINTER(vp)],
             "igs_plan_execute": [vp, vp, vp, vp],
             "igs_plan_destroy": [vp],
@@ -259,6 +261,20 @@ def assemble_surrogate(prob, form=STIFFNESS, M=8, q=3, dtype=None, out=None, dev
     pb = make_problem(prob, None if cc is None else cc.data_ptr())
     _check(lib().igs_assemble_surrogate(ctypes.byref(pb), form, M, q, cdt, band.data_ptr(), _stream()),
            "igs_assemble_surrogate")
+    return band
+
+
+def assemble_noalloc(prob, form=STIFFNESS, M=0, q=3, dtype=None, out=None, device="cuda"):
+    """igs_assemble_noalloc: M = 0 full assembly, M >= 1 surrogate, with the
+    library's static scratch instead of device allocations (the band is the
+    caller's: pass ``out`` to keep the call free of allocations)."""
+    torch = _torch()
+    tdt, cdt = _dt(dtype if dtype is not None else torch.float64)
+    band = out if out is not None else empty_band(prob, tdt, device)
+    cc = _coef_tensor(prob, band.device)
+    pb = make_problem(prob, None if cc is None else cc.data_ptr())
+    _check(lib().igs_assemble_noalloc(ctypes.byref(pb), form, M, q, cdt, band.data_ptr(), _stream()),
+           "igs_assemble_noalloc")
     return band
 
 
