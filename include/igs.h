@@ -140,6 +140,16 @@ typedef struct igs_surrogate_info {
   int64_t quadrature_rows;   /* boundary_rows + sample_rows */
 } igs_surrogate_info;
 
+/* Face/edge surrogate sampling (host-only, igs_surrogate_fe_layout). */
+typedef struct igs_fe_info {
+  int32_t samples[3];        /* per direction: the 4p boundary layers plus the
+                                lattice samples (1 for unused directions) */
+  int64_t classes;           /* row classes with a stencil-function family:
+                                (4p+1)^n - (4p)^n */
+  int64_t corner_rows;       /* (4p)^n rows with no free direction (exact) */
+  int64_t quadrature_rows;   /* prod samples[d]: every row assembled by quadrature */
+} igs_fe_info;
+
 typedef struct igs_cg_info {
   int32_t iterations;        /* total CG iterations (inner FP32 ones in mixed mode) */
   int32_t outer_iterations;  /* with an FP32 band: FP64 residual replacements;
@@ -163,6 +173,9 @@ igs_status igs_validate(const igs_problem* pb, int32_t M, int32_t q);
  * indices per direction.  Host only. */
 igs_status igs_surrogate_layout(const igs_problem* pb, int32_t M, int32_t q, igs_surrogate_info* out,
                                 int32_t* indices, int32_t capacity);
+
+/* Sampling of the face/edge surrogate (igs_assemble_surrogate_fe).  Host only. */
+igs_status igs_surrogate_fe_layout(const igs_problem* pb, int32_t M, int32_t q, igs_fe_info* out);
 
 /* Mesh-dependent sampling length (Sec. 7.3.3): M(h) = max{1, floor(c h^e)}
  * with h = 1/nelem and e = (p - q + beta)/(q + 1), so that H = M h obeys
@@ -208,6 +221,29 @@ igs_status igs_assemble_exact(const igs_problem* pb, int32_t form, int32_t dtype
  * not (small M on such meshes) the call returns IGS_ERR_UNSUPPORTED. */
 igs_status igs_assemble_surrogate(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype,
                                   void* band, void* stream);
+
+/* Surrogate assembly with face- and edge-based stencil functions (Sec. 3.6:
+ * besides the stencil functions of the analysis domain, a family for each face
+ * and edge layer, exploiting the translation invariance left parallel to it).
+ * Row classes: in direction d an index is free in [2p, m_d-2p-1] and
+ * otherwise one of the 4p boundary layers; a row's class fixes its layers.
+ * Every class with a free direction has, for each upper stencil delta (and
+ * delta = 0 for mass), its own stencil function of the free coordinates,
+ * sampled on the same lattice as the analysis domain (igs_surrogate_layout)
+ * at the class's layers and interpolated by the degree-q tensor spline along
+ * the free directions only.  Rows with no free direction (corners, (4p)^n of
+ * them) keep their quadrature.  Entries, eq. 5.1c extended to the classes:
+ * for i < j the class of i decides (its interpolant at i, exact for a corner
+ * row); A~_ji = A~_ij; entries whose partner leaves the index box are 0; the
+ * stiffness diagonal is -sum_{k!=i} A~_ik in every row, the mass diagonal is
+ * interpolated (exact on corners).  Quadrature runs only on the rows of the
+ * tensor product of the per-direction sets layers + lattice
+ * (igs_surrogate_fe_layout: 28^3 = 21,952 rows at p = 3, 128^3, M = 8, against
+ * 567,028 for igs_assemble_surrogate).  M = 1 reproduces igs_assemble_exact to
+ * rounding.  Same arguments, dtype semantics, errors and synchronisation as
+ * igs_assemble_surrogate. */
+igs_status igs_assemble_surrogate_fe(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype,
+                                     void* band, void* stream);
 
 /* Allocation-free assembly, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
@@ -256,6 +292,10 @@ igs_status igs_assemble_noalloc(const igs_problem* pb, int32_t form, int32_t M, 
 typedef struct igs_plan_s* igs_plan;
 igs_status igs_plan_create(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
                            igs_plan* out);
+/* igs_plan_create_fe: as igs_plan_create for the face/edge surrogate
+ * (igs_assemble_surrogate_fe); M >= 1. */
+igs_status igs_plan_create_fe(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
+                              igs_plan* out);
 igs_status igs_plan_execute(igs_plan plan, const double* coef, void* band, void* stream);
 igs_status igs_plan_destroy(igs_plan plan);
 

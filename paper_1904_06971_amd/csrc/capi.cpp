@@ -26,8 +26,8 @@ hipError_t launch_fill(const KInterp<T>& ip, int form, const Dims& d, const int*
 template <typename T>
 size_t fill_lds_bytes(const KInterp<T>& ip, int npen, const Dims& d, int blk);
 void fill_block_dims(const Dims& d, const std::vector<int> ef[3], int q, const std::vector<int>& chunks, int rows,
-                     int* n2max, int* n3max);
-std::vector<int> fill_chunks(const Dims& d, int rows);
+                     const int lo[3], const int hi[3], int* n2max, int* n3max);
+std::vector<int> fill_chunks(const Dims& d, int rows, const int lo[3], const int hi[3]);
 int fill_npen(const Dims& d, int rows);
 bool fill_is_2d(const Dims& d);
 bool fit_use_gemm(const KInterp<double>& ip, int n, int batch);
@@ -169,10 +169,12 @@ static KInterp<T> interp_view(const HostInterp& hi, const Dims& d, Arena& ar, hi
   std::memset(&ip, 0, sizeof(ip));
   ip.q = hi.q;
   for (int k = 0; k < 3; ++k) {
+    ip.flo[k] = hi.flo[k];
+    ip.fhi[k] = hi.fhi[k];
     if (k < d.n) {
       ip.Sd[k] = int(hi.samp[k].size());
-      ip.lo[k] = 2 * d.p;
-      ip.hi[k] = d.m[k] - 2 * d.p - 1;
+      ip.lo[k] = hi.lo[k];
+      ip.hi[k] = hi.hi[k];
       ip.samp[k] = upload(ar, hi.samp[k], s, st);
       ip.ginv[k] = upload(ar, hi.ginv[k], s, st);
       ip.ef[k] = upload(ar, hi.ef[k], s, st);
@@ -209,7 +211,7 @@ static igs_status check_sampling(const Dims& d, int M, int q) {
 // free it; igs_plan_* keep it for repeated runs.
 
 struct Plan {
-  int kind = 0;  // 0 exact, 1 surrogate
+  int kind = 0;  // 0 exact, 1 surrogate, 2 face/edge surrogate
   int form = 0, dtype = 0, M = 0, q = 0;
   Prepared P;
   Arena ta;
@@ -251,9 +253,10 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
   const int form = pl->form, M = pl->M, q = pl->q;
   st = check_sampling(d, M, q);
   if (st != IGS_OK) return st;
+  const bool fe = pl->kind == 2;
   HostInterp hi;
   int box[3] = {1, 1, 1};
-  st = build_interp(d, form, M, q, box, &hi);
+  st = fe ? build_interp_fe(d, form, M, q, box, &hi) : build_interp(d, form, M, q, box, &hi);
   if (st != IGS_OK) return st;
   std::vector<float> ebf[3];
   for (int k = 0; k < d.n; ++k) ebf[k].assign(hi.eb[k].begin(), hi.eb[k].end());
@@ -267,13 +270,23 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
     const int64_t want = (int64_t(2) * (d.m[1] - 4 * d.p) * d.batch + 1023) / 1024;
     zchunk = int(std::min<int64_t>(zchunk, std::max<int64_t>(d.p + 1, want)));
   }
-  std::vector<QTile> tiles = tiles_surrogate(d, hi.samp, tx, ty, zchunk, pl->groups);
+  std::vector<QTile> tiles;
+  if (fe) {
+    // every quadrature row of the face/edge surrogate runs in the sample-row launch
+    tiles = tiles_fe(d, hi.samp, tx, zchunk);
+    pl->groups[0] = pl->groups[1] = 0;
+    pl->groups[2] = int(tiles.size());
+  } else {
+    tiles = tiles_surrogate(d, hi.samp, tx, ty, zchunk, pl->groups);
+  }
   size_t per = 1;
   for (int k = 0; k < d.n; ++k) per *= hi.samp[k].size();
   const size_t ncoef = per * hi.upslot.size() * d.batch;
   pl->chunk_rows = fill_chunk_rows(d, int(hi.samp[0].size()));
-  std::vector<int> chunks = fill_chunks(d, pl->chunk_rows);
-  std::vector<int> crow = copy_rows(d);
+  std::vector<int> chunks = fill_chunks(d, pl->chunk_rows, hi.lo, hi.hi);
+  // face/edge: every entry is interpolated or (corners) copied by the identity
+  // part of the fit, so no entry is left for the copy kernel
+  std::vector<int> crow = fe ? std::vector<int>() : copy_rows(d);
   std::vector<int> dsl;  // (slot, delta1, delta2, delta3) per interpolated slot
   for (int sl : hi.upslot) {
     const int W = d.W;
@@ -314,7 +327,7 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
   const size_t lds = pl->dtype == IGS_F64 ? fill_lds_bytes<double>(pl->ipd, fill_npen(d, pl->chunk_rows), d, 0)
                                           : fill_lds_bytes<float>(pl->ipf, fill_npen(d, pl->chunk_rows), d, 0);
   if (!fill_is_2d(d) && lds > 160 * 1024) return IGS_ERR_UNSUPPORTED;
-  fill_block_dims(d, hi.ef, q, chunks, pl->chunk_rows, &pl->n2max, &pl->n3max);
+  fill_block_dims(d, hi.ef, q, chunks, pl->chunk_rows, hi.lo, hi.hi, &pl->n2max, &pl->n3max);
   return IGS_OK;
 }
 
@@ -325,6 +338,28 @@ static igs_status run_t(const Plan& pl, const KProblem& kp, const KInterp<OutT>&
     {
       PhaseTimer t("quad_exact", s);
       HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt, pl.ntiles, false, band, s));
+    }
+  } else if (pl.kind == 2) {
+    // face/edge: the quadrature rows (every sample row of every class, and the
+    // corner rows), the fit over the augmented sample sets, and one fill over
+    // every row of the band
+    {
+      PhaseTimer t("quad_fe_rows", s);
+      HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt, pl.groups[2], d.n == 3, band, s));
+    }
+    {
+      PhaseTimer t("fit", s);
+      if (fit_use_gemm(pl.ip64, d.n, d.batch))
+        HIP_TRY(launch_fit_gemm<OutT>(pl.ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, pl.tmp0, pl.tmp1,
+                                      pl.coef, s));
+      else
+        HIP_TRY(launch_fit<OutT>(pl.ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, pl.tmp0, pl.tmp1, pl.coef,
+                                 pl.g0T, s));
+    }
+    {
+      PhaseTimer t("fill", s);
+      HIP_TRY(launch_fill<OutT>(ipT, pl.form, d, pl.dchunks, pl.nchunks, pl.chunk_rows, pl.n2max, pl.n3max, pl.ddsl,
+                                pl.coef, band, s));
     }
   } else {
     // Order: sample rows, fit and fill first; the fill writes whole lines of
@@ -568,14 +603,58 @@ igs_status igs_assemble_noalloc(const igs_problem* pb, int32_t form, int32_t M, 
   return one_shot(pb, M == 0 ? 0 : 1, form, M, q, dtype, band, static_cast<hipStream_t>(stream), &pool);
 }
 
+igs_status igs_assemble_surrogate_fe(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype,
+                                     void* band, void* stream) {
+  if (!pb || !band) return IGS_ERR_ARG;
+  if (form != IGS_STIFFNESS && form != IGS_MASS) return IGS_ERR_ARG;
+  if (dtype != IGS_F64 && dtype != IGS_F32) return IGS_ERR_ARG;
+  Dims d;
+  igs_status st = make_dims(pb, &d);
+  if (st != IGS_OK) return st;
+  st = check_sampling(d, M, q);
+  if (st != IGS_OK) return st;
+  return one_shot(pb, 2, form, M, q, dtype, band, static_cast<hipStream_t>(stream));
+}
+
+igs_status igs_surrogate_fe_layout(const igs_problem* pb, int32_t M, int32_t q, igs_fe_info* out) {
+  if (!out) return IGS_ERR_ARG;
+  Dims d;
+  igs_status st = make_dims(pb, &d);
+  if (st != IGS_OK) return st;
+  st = check_sampling(d, M, q);
+  if (st != IGS_OK) return st;
+  std::memset(out, 0, sizeof(*out));
+  int64_t all = 1, layers = 1, free_or_layer = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (k >= d.n) {
+      out->samples[k] = 1;
+      continue;
+    }
+    std::vector<int> s;
+    sample_lattice(d.m[k], d.p, M, &s);
+    out->samples[k] = int(s.size()) + 4 * d.p;
+    all *= out->samples[k];
+    layers *= 4 * d.p;
+    free_or_layer *= 4 * d.p + 1;
+  }
+  out->classes = free_or_layer - layers;
+  out->corner_rows = layers;
+  out->quadrature_rows = all;
+  return IGS_OK;
+}
+
 struct igs_plan_s {
   igs::Plan pl;
   hipStream_t last = nullptr;
 };
 
-igs_status igs_plan_create(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
-                           igs_plan* out) {
+static igs_status plan_create(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
+                              igs_plan* out, bool fe) {
   if (!pb || !out) return IGS_ERR_ARG;
+  if (fe && M < 1) {
+    *out = nullptr;
+    return IGS_ERR_ARG;
+  }
   *out = nullptr;
   if (form != IGS_STIFFNESS && form != IGS_MASS) return IGS_ERR_ARG;
   if (dtype != IGS_F64 && dtype != IGS_F32) return IGS_ERR_ARG;
@@ -590,7 +669,7 @@ igs_status igs_plan_create(const igs_problem* pb, int32_t form, int32_t M, int32
   igs_plan_s* h = new igs_plan_s;
   h->pl.P.ar.persistent = true;
   h->pl.ta.persistent = true;
-  h->pl.kind = M == 0 ? 0 : 1;
+  h->pl.kind = M == 0 ? 0 : (fe ? 2 : 1);
   h->pl.form = form;
   h->pl.dtype = dtype;
   h->pl.M = M;
@@ -605,6 +684,16 @@ igs_status igs_plan_create(const igs_problem* pb, int32_t form, int32_t M, int32
   h->last = s;
   *out = h;
   return IGS_OK;
+}
+
+igs_status igs_plan_create(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
+                           igs_plan* out) {
+  return plan_create(pb, form, M, q, dtype, stream, out, false);
+}
+
+igs_status igs_plan_create_fe(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
+                              igs_plan* out) {
+  return plan_create(pb, form, M, q, dtype, stream, out, true);
 }
 
 igs_status igs_plan_execute(igs_plan plan, const double* coef, void* band, void* stream) {

@@ -50,32 +50,45 @@ __global__ void fit_pass_kernel(KInterp<double> ip, int d, int n, int m1, int m2
     const int Sd = ip.Sd[d];
     const double* g = gT ? gT + kd : ip.ginv[d] + size_t(kd) * Sd;
     const size_t gs = gT ? size_t(Sd) : 1;
-    // four independent partial sums over j = 4l + e keep several loads in
+    // the spline block [flo, fhi) of the matrix; outside it the matrix is
+    // the identity (face/edge layers) and the value is copied
+    const int flo = ip.flo[d], fhi = ip.fhi[d];
+    const bool copy = kd < flo || kd >= fhi;
+    const int ja = copy ? kd : flo, jb = copy ? kd + 1 : fhi;
+    // four independent partial sums over j = ja + 4l + e keep several loads in
     // flight per thread (a single chain waits on each load in turn)
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    const int J4 = Sd & ~3;
+    const int J4 = copy ? ja : ja + ((jb - ja) & ~3);
     if constexpr (GATHER) {
       const BT* bs = band + (size_t(b) * S + ip.upslot[u]) * ld;
       const size_t rowbase = size_t(m1) * (ip.samp[1][k2] + size_t(m2) * (n == 3 ? ip.samp[2][k3] : 0));
       const int* s1 = ip.samp[0];
-      for (int j = 0; j < J4; j += 4) {
+      if (copy) {
+        out[t] = double(bs[rowbase + s1[kd]]);
+        continue;
+      }
+      for (int j = ja; j < J4; j += 4) {
         a0 += g[j * gs] * double(bs[rowbase + s1[j]]);
         a1 += g[(j + 1) * gs] * double(bs[rowbase + s1[j + 1]]);
         a2 += g[(j + 2) * gs] * double(bs[rowbase + s1[j + 2]]);
         a3 += g[(j + 3) * gs] * double(bs[rowbase + s1[j + 3]]);
       }
-      for (int j = J4; j < Sd; ++j) a0 += g[j * gs] * double(bs[rowbase + s1[j]]);
+      for (int j = J4; j < jb; ++j) a0 += g[j * gs] * double(bs[rowbase + s1[j]]);
     } else {
       const double* src = in + (size_t(b) * ip.nup + u) * per;
       const size_t stride = d == 0 ? 1 : (d == 1 ? size_t(S1) : size_t(S1) * S2);
       const double* sp = src + (size_t(d == 2 ? 0 : k3) * S2 + (d == 1 ? 0 : k2)) * S1 + (d == 0 ? 0 : k1);
-      for (int j = 0; j < J4; j += 4) {
+      if (copy) {
+        out[t] = sp[kd * stride];
+        continue;
+      }
+      for (int j = ja; j < J4; j += 4) {
         a0 += g[j * gs] * sp[j * stride];
         a1 += g[(j + 1) * gs] * sp[(j + 1) * stride];
         a2 += g[(j + 2) * gs] * sp[(j + 2) * stride];
         a3 += g[(j + 3) * gs] * sp[(j + 3) * stride];
       }
-      for (int j = J4; j < Sd; ++j) a0 += g[j * gs] * sp[j * stride];
+      for (int j = J4; j < jb; ++j) a0 += g[j * gs] * sp[j * stride];
     }
     out[t] = (a0 + a1) + (a2 + a3);
   }
@@ -667,15 +680,15 @@ template hipError_t launch_fit<double>(const KInterp<double>&, int, int, int, in
 template hipError_t launch_fit<float>(const KInterp<double>&, int, int, int, int64_t, int, int, const float*,
                                       double*, double*, double*, const double*, hipStream_t);
 
-// chunk ids (of `rows` rows) that contain at least one analysis-domain row
-std::vector<int> fill_chunks(const Dims& d, int rows) {
-  const int p = d.p;
+// chunk ids (of `rows` rows) that contain at least one row the fill
+// evaluates: rows with every i_d in [lo[d], hi[d]]
+std::vector<int> fill_chunks(const Dims& d, int rows, const int lo[3], const int hi[3]) {
   std::vector<int> out;
-  const int lo3 = (d.n == 3) ? 2 * p : 0, hi3 = (d.n == 3) ? d.m[2] - 2 * p - 1 : 0;
+  const int lo3 = (d.n == 3) ? lo[2] : 0, hi3 = (d.n == 3) ? hi[2] : 0;
   for (int i3 = lo3; i3 <= hi3; ++i3)
-    for (int i2 = 2 * p; i2 <= d.m[1] - 2 * p - 1; ++i2) {
+    for (int i2 = lo[1]; i2 <= hi[1]; ++i2) {
       const int64_t base = int64_t(d.m[0]) * (i2 + int64_t(d.m[1]) * i3);
-      const int a = int((base + 2 * p) / rows), z = int((base + d.m[0] - 2 * p - 1) / rows);
+      const int a = int((base + lo[0]) / rows), z = int((base + hi[0]) / rows);
       for (int c = a; c <= z; ++c)
         if (out.empty() || out.back() < c) out.push_back(c);
     }
@@ -700,10 +713,10 @@ size_t fill_lds_bytes(const KInterp<T>& ip, int npen, const Dims& d, int blk) {
 // Largest coefficient block (extent in directions 2 and 3) that the pencil
 // tasks of one fill chunk read; mirrors the bounds the fast kernel computes.
 void fill_block_dims(const Dims& d, const std::vector<int> ef[3], int q, const std::vector<int>& chunks, int rows,
-                     int* n2max, int* n3max) {
+                     const int lo[3], const int hi[3], int* n2max, int* n3max) {
   const int p = d.p, npen = fill_npen(d, rows);
-  const int lo2 = 2 * p, hi2 = d.m[1] - 2 * p - 1;
-  const int lo3 = d.n == 3 ? 2 * p : 0, hi3 = d.n == 3 ? d.m[2] - 2 * p - 1 : 0;
+  const int lo2 = lo[1], hi2 = hi[1];
+  const int lo3 = d.n == 3 ? lo[2] : 0, hi3 = d.n == 3 ? hi[2] : 0;
   *n2max = 1;
   *n3max = 1;
   for (int c : chunks) {

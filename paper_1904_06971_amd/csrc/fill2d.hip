@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(1024)
 template <int FORM, int R, typename T, bool PF>
 static void launch_fill2d_q(const KInterp<T>& ip, const Dims& d, int nt, size_t lds, const int4* dsl,
                             const double* coef, T* band, hipStream_t s) {
-  dim3 grid(d.m[1] - 4 * d.p, d.batch);
+  dim3 grid(ip.hi[1] - ip.lo[1] + 1, d.batch);
   switch (ip.q) {
     case 1: hipLaunchKernelGGL((fill2d_kernel<FORM, 1, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
     case 2: hipLaunchKernelGGL((fill2d_kernel<FORM, 2, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
@@ -187,7 +187,7 @@ hipError_t launch_fill2d(const KInterp<T>& ip, int form, const Dims& d, const in
   const int nt = std::min(1024, (rows_per + 63) / 64 * 64);
   const size_t lds = (size_t(2) * ip.Sd[0] + d.m[0]) * sizeof(T);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (d.m[1] - 4 * d.p < 1) return hipSuccess;
+  if (ip.hi[1] < ip.lo[1]) return hipSuccess;
   if (form == IGS_MASS)
     launch_fill2d_pf<IGS_MASS, kFill2dR, T>(ip, d, nt, lds, dsl, coef, band, s);
   else

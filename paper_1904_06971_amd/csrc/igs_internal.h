@@ -70,6 +70,8 @@ struct KInterp {
   int nup;               // number of interpolated (upper) slots
   const int* upslot;     // [nup] band slot of each interpolated delta
   int nc[3];             // max coefficient span of a fill box, per direction
+  int flo[3], fhi[3];    // coefficient range of the spline part per direction;
+                         // outside it ginv is the identity (face/edge layers)
 };
 
 // ---------------------------------------------------------------- host plan
@@ -99,11 +101,19 @@ struct HostInterp {
   std::vector<double> eb[3];
   std::vector<int> upslot;
   int nc[3];
+  int lo[3], hi[3];      // rows the fill evaluates per direction (the analysis
+                         // range, or the whole index range for face/edge)
+  int flo[3], fhi[3];    // spline part of the coefficient range (see KInterp)
 };
 
 // samples per direction; IGS_ERR_SAMPLES when the lattice is too small
 igs_status sample_lattice(int m, int p, int M, std::vector<int>* s);
 igs_status build_interp(const Dims& d, int form, int M, int q, int boxlen[3], HostInterp* hi);
+// Face/edge stencil functions (Sec. 3.6): per direction the sample set is the
+// 4p boundary layers plus the lattice, in index order; the interpolation is
+// the degree-q spline on the lattice part and the identity on the layers, and
+// the fill covers every index.  samp[d] then lists every quadrature index.
+igs_status build_interp_fe(const Dims& d, int form, int M, int q, int boxlen[3], HostInterp* hi);
 
 // Tile lists.
 std::vector<QTile> tiles_all(const Dims& d, int tx, int ty, int zchunk);
@@ -112,6 +122,10 @@ std::vector<QTile> tiles_all(const Dims& d, int tx, int ty, int zchunk);
 // and the sample rows (in that order in the list)
 std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3], int tx, int ty, int zchunk,
                                    int groups[3]);
+
+// Face/edge surrogate: the quadrature rows of the tensor sample set (3-D:
+// single-row tiles; 2-D: line tiles of tx rows streamed over runs of i2).
+std::vector<QTile> tiles_fe(const Dims& d, const std::vector<int> samp[3], int tx, int zchunk);
 
 // Caller-provided device memory that arenas carve their pieces from instead
 // of allocating (the allocation-free entry point): every arena attached to a

@@ -304,10 +304,76 @@ igs_status build_interp(const Dims& d, int form, int M, int q, int boxlen[3], Ho
     hi->nc[k] = std::min(nc, S);
   }
   for (int k = d.n; k < 3; ++k) hi->nc[k] = 1;
+  for (int k = 0; k < 3; ++k) {
+    hi->lo[k] = k < d.n ? 2 * d.p : 0;
+    hi->hi[k] = k < d.n ? d.m[k] - 2 * d.p - 1 : 0;
+    hi->flo[k] = 0;
+    hi->fhi[k] = k < d.n ? int(hi->samp[k].size()) : 1;
+  }
   hi->upslot.clear();
   const int sc = (d.S - 1) / 2;
   for (int s = 0; s < d.S; ++s)
     if (s > sc || (form == IGS_MASS && s == sc)) hi->upslot.push_back(s);
+  return IGS_OK;
+}
+
+igs_status build_interp_fe(const Dims& d, int form, int M, int q, int boxlen[3], HostInterp* hi) {
+  // the lattice spline of each direction, as for the analysis-domain surrogate
+  int one[3] = {1, 1, 1};
+  HostInterp base;
+  igs_status st = build_interp(d, form, M, q, one, &base);
+  if (st != IGS_OK) return st;
+  const int p = d.p;
+  hi->q = q;
+  hi->upslot = base.upslot;
+  for (int k = 0; k < d.n; ++k) {
+    const int m = d.m[k], S = int(base.samp[k].size()), Sx = S + 4 * p;
+    // augmented coefficient index: low layers 0..2p-1, lattice 2p..2p+S-1,
+    // high layers after; increasing with the fine index
+    hi->samp[k].clear();
+    for (int i = 0; i < 2 * p; ++i) hi->samp[k].push_back(i);
+    for (int v : base.samp[k]) hi->samp[k].push_back(v);
+    for (int i = m - 2 * p; i < m; ++i) hi->samp[k].push_back(i);
+    hi->ginv[k].assign(size_t(Sx) * Sx, 0.0);
+    for (int r = 0; r < Sx; ++r) {
+      if (r < 2 * p || r >= 2 * p + S) {
+        hi->ginv[k][size_t(r) * Sx + r] = 1.0;
+      } else {
+        for (int c = 0; c < S; ++c)
+          hi->ginv[k][size_t(r) * Sx + 2 * p + c] = base.ginv[k][size_t(r - 2 * p) * S + c];
+      }
+    }
+    hi->ef[k].assign(m, 0);
+    hi->eb[k].assign(size_t(m) * (q + 1), 0.0);
+    for (int i = 0; i < m; ++i) {
+      if (i >= 2 * p && i <= m - 2 * p - 1) {
+        hi->ef[k][i] = 2 * p + base.ef[k][i];
+        for (int c = 0; c <= q; ++c) hi->eb[k][size_t(i) * (q + 1) + c] = base.eb[k][size_t(i) * (q + 1) + c];
+      } else {
+        // a layer: weight 1 at its own coefficient, inside a window of q+1
+        const int pos = i < 2 * p ? i : 2 * p + S + (i - (m - 2 * p));
+        const int f = std::min(pos, Sx - q - 1);
+        hi->ef[k][i] = f;
+        hi->eb[k][size_t(i) * (q + 1) + (pos - f)] = 1.0;
+      }
+    }
+    int nc = 0;
+    for (int i = 0; i < m; ++i) {
+      const int j = std::min(m - 1, i + boxlen[k] - 1);
+      nc = std::max(nc, hi->ef[k][j] - hi->ef[k][i] + q + 1);
+    }
+    hi->nc[k] = std::min(nc, Sx);
+    hi->lo[k] = 0;
+    hi->hi[k] = m - 1;
+    hi->flo[k] = 2 * p;
+    hi->fhi[k] = 2 * p + S;
+  }
+  for (int k = d.n; k < 3; ++k) {
+    hi->nc[k] = 1;
+    hi->lo[k] = hi->hi[k] = 0;
+    hi->flo[k] = 0;
+    hi->fhi[k] = 1;
+  }
   return IGS_OK;
 }
 
@@ -392,6 +458,29 @@ std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3]
     for (int s2 : samp[1]) tile_rect(&out, samp[0].front(), samp[0].back() + 1, 0, 1, tx, 1, s2, s2 + 1, 1);
   }
   groups[2] = int(out.size()) - groups[0] - groups[1];
+  return out;
+}
+
+// Rows the face/edge surrogate assembles by quadrature: the tensor product of
+// the per-direction sample sets (layers and lattice; samp from
+// build_interp_fe).  3-D: single-row tiles (the rows are isolated in at least
+// one direction except near the corners); 2-D: whole i1 lines over each run of
+// consecutive i2 in the set (the extra rows are evaluated again by the fill).
+std::vector<QTile> tiles_fe(const Dims& d, const std::vector<int> samp[3], int tx, int zchunk) {
+  std::vector<QTile> out;
+  if (d.n == 3) {
+    for (int s3 : samp[2])
+      for (int s2 : samp[1])
+        for (int s1 : samp[0]) out.push_back(QTile{s1, s2, 1, 1, s3, s3 + 1});
+    return out;
+  }
+  const std::vector<int>& t = samp[1];
+  for (size_t a = 0; a < t.size();) {
+    size_t b = a + 1;
+    while (b < t.size() && t[b] == t[b - 1] + 1) ++b;
+    tile_rect(&out, 0, d.m[0], 0, 1, tx, 1, t[a], t[b - 1] + 1, zchunk);
+    a = b;
+  }
   return out;
 }
 

@@ -27,7 +27,8 @@ COEF = {"const": 0, "sine3": 1, "spline": 2, "exp_spline": 3}
 SRC_CONST, SRC_SINE = 0, 1
 EXPORTS = ["igs_band_layout", "igs_validate", "igs_surrogate_layout", "igs_sampling_length", "igs_status_string",
            "igs_version",
-           "igs_assemble_exact", "igs_assemble_surrogate", "igs_assemble_noalloc", "igs_plan_create", "igs_plan_execute", "igs_plan_destroy",
+           "igs_assemble_exact", "igs_assemble_surrogate", "igs_assemble_noalloc", "igs_assemble_surrogate_fe",
+           "igs_surrogate_fe_layout", "igs_plan_create", "igs_plan_create_fe", "igs_plan_execute", "igs_plan_destroy",
            "igs_assemble_rhs", "igs_apply", "igs_solve_cg", "igs_apply_vjp", "igs_compliance_grad",
            "igs_profile_enable", "igs_profile_read"]
 
@@ -63,6 +64,11 @@ class SurrogateInfo(ctypes.Structure):
                 ("boundary_rows", ctypes.c_int64), ("quadrature_rows", ctypes.c_int64)]
 
 
+class FEInfo(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_int32 * 3), ("classes", ctypes.c_int64), ("corner_rows", ctypes.c_int64),
+                ("quadrature_rows", ctypes.c_int64)]
+
+
 class ProfilePhase(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int32), ("ms", ctypes.c_double)]
 
@@ -96,6 +102,9 @@ def lib():
             "igs_assemble_exact": [P, i32, i32, vp, vp],
             "igs_assemble_surrogate": [P, i32, i32, i32, i32, vp, vp],
             "igs_assemble_noalloc": [P, i32, i32, i32, i32, vp, vp],
+            "igs_assemble_surrogate_fe": [P, i32, i32, i32, i32, vp, vp],
+            "igs_surrogate_fe_layout": [P, i32, i32, ctypes.POINTER(FEInfo)],
+            "igs_plan_create_fe": [P, i32, i32, i32, i32, vp, ctypes.POINTER(vp)],
             "igs_plan_create": [P, i32, i32, i32, i32, vp, ctypes.POINTER(vp)],
             "igs_plan_execute": [vp, vp, vp, vp],
             "igs_plan_destroy": [vp],
@@ -196,6 +205,13 @@ def surrogate_layout(prob, M, q):
     return info, idx
 
 
+def surrogate_fe_layout(prob, M, q):
+    info = FEInfo()
+    _check(lib().igs_surrogate_fe_layout(ctypes.byref(make_problem(prob, coef_ptr=1)), M, q, ctypes.byref(info)),
+           "igs_surrogate_fe_layout")
+    return info
+
+
 def sampling_length(nelem, p, q, c, beta=0.5):
     """Mesh-dependent sampling length M(h) = max{1, floor(c h^((p-q+beta)/(q+1)))}, h = 1/nelem."""
     M = lib().igs_sampling_length(int(nelem), int(p), int(q), float(c), float(beta))
@@ -264,6 +280,18 @@ def assemble_surrogate(prob, form=STIFFNESS, M=8, q=3, dtype=None, out=None, dev
     return band
 
 
+def assemble_surrogate_fe(prob, form=STIFFNESS, M=8, q=3, dtype=None, out=None, device="cuda"):
+    """igs_assemble_surrogate_fe: surrogate with face/edge stencil functions."""
+    torch = _torch()
+    tdt, cdt = _dt(dtype if dtype is not None else torch.float64)
+    band = out if out is not None else empty_band(prob, tdt, device)
+    cc = _coef_tensor(prob, band.device)
+    pb = make_problem(prob, None if cc is None else cc.data_ptr())
+    _check(lib().igs_assemble_surrogate_fe(ctypes.byref(pb), form, M, q, cdt, band.data_ptr(), _stream()),
+           "igs_assemble_surrogate_fe")
+    return band
+
+
 def assemble_noalloc(prob, form=STIFFNESS, M=0, q=3, dtype=None, out=None, device="cuda"):
     """igs_assemble_noalloc: M = 0 full assembly, M >= 1 surrogate, with the
     library's static scratch instead of device allocations (the band is the
@@ -279,11 +307,12 @@ def assemble_noalloc(prob, form=STIFFNESS, M=0, q=3, dtype=None, out=None, devic
 
 
 class Plan:
-    """A kept assembly plan (igs_plan_*): M = 0 full assembly, M >= 1 surrogate.
-    execute() queues the assembly on torch's current stream; the first call
-    synchronises and checks the geometry, later calls only queue."""
+    """A kept assembly plan (igs_plan_*): M = 0 full assembly, M >= 1 surrogate
+    (face_edge=True: igs_plan_create_fe).  execute() queues the assembly on
+    torch's current stream; the first call synchronises and checks the
+    geometry, later calls only queue."""
 
-    def __init__(self, prob, form=STIFFNESS, M=8, q=3, dtype=None, device="cuda"):
+    def __init__(self, prob, form=STIFFNESS, M=8, q=3, dtype=None, device="cuda", face_edge=False):
         torch = _torch()
         self.prob = prob
         self.tdt, self.cdt = _dt(dtype if dtype is not None else torch.float64)
@@ -291,8 +320,9 @@ class Plan:
         self._cc = _coef_tensor(prob, device)
         pb = make_problem(prob, None if self._cc is None else self._cc.data_ptr())
         h = ctypes.c_void_p()
-        _check(lib().igs_plan_create(ctypes.byref(pb), form, M, q, self.cdt, _stream(), ctypes.byref(h)),
-               "igs_plan_create")
+        create = lib().igs_plan_create_fe if face_edge else lib().igs_plan_create
+        _check(create(ctypes.byref(pb), form, M, q, self.cdt, _stream(), ctypes.byref(h)),
+               "igs_plan_create_fe" if face_edge else "igs_plan_create")
         self._h = h
 
     def execute(self, out=None, coef=None):

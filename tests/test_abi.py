@@ -62,6 +62,25 @@ def test_surrogate_layout_matches_oracle(oracle, prob, M, q):
     assert info.sample_rows == np.prod([len(i) for i in idx])
 
 
+@pytest.mark.parametrize("prob,M,q", [(W.problem(2, 2, 32), 4, 3), (W.problem(2, 3, (70, 41)), 5, 3),
+                                      (W.problem(3, 2, (22, 19, 25)), 4, 2), (W.c4_precision3d(), 8, 3)])
+def test_surrogate_fe_layout_matches_oracle(oracle, prob, M, q):
+    """Face/edge sampling: per-direction sample sets (4p layers + lattice), the
+    class count (4p+1)^n - (4p)^n, and the quadrature row count against the
+    oracle's own class enumeration."""
+    info = igs.surrogate_fe_layout(prob, M, q)
+    m, N, _ = oracle.dims(prob)
+    p, n = prob["p"], prob["n"]
+    for d in range(n):
+        assert info.samples[d] == len(oracle.lattice(m[d], p, M)) + 4 * p
+    assert info.classes == len(oracle.layer_classes(prob))
+    assert info.corner_rows == (4 * p) ** n
+    if N < 400000:
+        assert info.quadrature_rows == int(oracle.quadrature_rows_fe(prob, M).sum())
+    else:
+        assert info.quadrature_rows == np.prod([info.samples[d] for d in range(n)])
+
+
 def test_published_sizes():
     """Sizes quoted for the workloads: 34^2 = 1156 dofs; 67^3 = 300,763 dofs with
     343-entry stencils; 132^3 with 729-entry stencils; 131^3 ~ 2.25M dofs; 259^2."""
@@ -101,6 +120,8 @@ def test_validation_errors(mutate, expected):
     assert L.igs_assemble_surrogate(ctypes.byref(pb), 0, 4, 3, 0, dummy, None) == expected
     assert L.igs_assemble_noalloc(ctypes.byref(pb), 0, 0, 0, 0, dummy, None) == expected
     assert L.igs_assemble_noalloc(ctypes.byref(pb), 0, 4, 3, 0, dummy, None) == expected
+    assert L.igs_assemble_surrogate_fe(ctypes.byref(pb), 0, 4, 3, 0, dummy, None) == expected
+    assert L.igs_plan_create_fe(ctypes.byref(pb), 0, 4, 3, 0, None, ctypes.byref(ctypes.c_void_p())) == expected
     assert L.igs_assemble_rhs(ctypes.byref(pb), 0, 1.0, dummy, None) == expected
     assert L.igs_apply(ctypes.byref(pb), 0, dummy, dummy, dummy, 0, None) == expected
     h = ctypes.c_void_p(16)
@@ -120,6 +141,7 @@ def test_sampling_errors():
     assert L.igs_validate(ctypes.byref(pb), 1, 1) == -4
     dummy = ctypes.c_void_p(16)
     assert L.igs_assemble_surrogate(ctypes.byref(pb), 0, 1, 1, 0, dummy, None) == -4
+    assert L.igs_assemble_surrogate_fe(ctypes.byref(pb), 0, 1, 1, 0, dummy, None) == -4
     h = ctypes.c_void_p()
     assert L.igs_plan_create(ctypes.byref(pb), 0, 1, 1, 0, None, ctypes.byref(h)) == -4
     pb = igs.make_problem(W.problem(2, 2, 14))
