@@ -34,7 +34,7 @@ bool fit_use_gemm(const KInterp<double>& ip, int n, int batch);
 template <typename BT>
 hipError_t launch_fit_gemm(const KInterp<double>& ip, int n, int m1, int m2, int64_t ld, int S, int batch,
                            const BT* band, double* tmp0, double* tmp1, double* coef, hipStream_t s);
-int fill_chunk_rows(const Dims& d, int Sd1);
+int fill_chunk_rows(const Dims& d, int Sd1, int q, int nup);
 template <typename T>
 hipError_t launch_zero_pad(T* band, int64_t N, int64_t ld, int slots_total, hipStream_t s);
 template <typename T>
@@ -282,7 +282,7 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
   size_t per = 1;
   for (int k = 0; k < d.n; ++k) per *= hi.samp[k].size();
   const size_t ncoef = per * hi.upslot.size() * d.batch;
-  pl->chunk_rows = fill_chunk_rows(d, int(hi.samp[0].size()));
+  pl->chunk_rows = fill_chunk_rows(d, int(hi.samp[0].size()), q, int(hi.upslot.size()));
   std::vector<int> chunks = fill_chunks(d, pl->chunk_rows, hi.lo, hi.hi);
   // face/edge: every entry is interpolated or (corners) copied by the identity
   // part of the fit, so no entry is left for the copy kernel

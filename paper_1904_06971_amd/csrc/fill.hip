@@ -309,16 +309,20 @@ __global__ void __launch_bounds__(kChunk)
 // as bitmasks.  The direction-1 weights are read from LDS for every delta:
 // keeping a row's q+1 weights in registers costs the VGPRs that separate 4
 // from 5 waves per SIMD, and the extra wave hides more of the stores.
-// Requires npen*2*S1 <= kChunk pencil tasks per chunk.
+// A thread carries NT pencil tasks: npen*2*S1 <= NT*kChunk (NT = 2 for the
+// face/edge surrogate, whose lines carry the 4p layer coefficients too).
 constexpr int kRows = 3;
 
 // STAGE = true: the coefficient block that the chunk's pencil tasks read for a
 // delta ((directions 2, 3) ranges of the chunk's pencils and their lower
 // partners, all c1) is copied into LDS by coalesced loads two deltas ahead,
 // instead of every task gathering its (q+1)^2 coefficients from memory.
+// Chunks whose block exceeds kStage*kChunk values (face/edge chunks next to
+// the boundary layers, where every layer has a coefficient of its own) gather
+// instead; the choice is uniform per workgroup.
 constexpr int kStage = 4;  // staged coefficients per thread (block <= kStage * kChunk)
 
-template <int ND, int FORM, int Q, typename T, bool STAGE>
+template <int ND, int FORM, int Q, typename T, bool STAGE, int NT>
 __global__ void __launch_bounds__(kChunk)
     fill_fast_kernel(KInterp<T> ip, FillGeom g, const int4* __restrict__ dsl, const double* __restrict__ coef,
                      T* __restrict__ band) {
@@ -328,7 +332,8 @@ __global__ void __launch_bounds__(kChunk)
   const int S1 = ip.Sd[0], S2 = ip.Sd[1], S3 = (ND == 3) ? ip.Sd[2] : 1;
   const int m3 = (ND == 3) ? g.m3 : 1;
   const int P = g.P;
-  const int blk = STAGE ? g.n3max * g.n2max * S1 : 0;
+  static_assert(STAGE || NT == 1, "the prefetching path carries one task per thread");
+  const int blk = STAGE ? min(g.n3max * g.n2max * S1, kStage * kChunk) : 0;
   double* Cb = reinterpret_cast<double*>(smem_raw);  // [2][blk]
   T* Tbuf = reinterpret_cast<T*>(Cb + 2 * blk);
   T* tb1 = Tbuf + size_t(2) * g.npen * 2 * S1;
@@ -427,6 +432,10 @@ __global__ void __launch_bounds__(kChunk)
     }
   }
   const int nblk = n3 * n2 * S1;
+  // this chunk stages its blocks (uniform per workgroup); with one task per
+  // thread the host has checked that every block fits
+  constexpr bool MIXED = NT > 1;
+  const bool stg = STAGE && (!MIXED || nblk <= kStage * kChunk);
   double cs[kStage];
   // this thread's staged block entries: offsets into a delta's coefficient
   // array (loop-invariant; -1 for entries beyond the block)
@@ -436,7 +445,7 @@ __global__ void __launch_bounds__(kChunk)
     const int e = tid + k * kChunk;
     const int c1 = e % S1, r = e / S1;
     const int l2 = r % n2, l3 = r / n2;
-    soff[k] = (STAGE && e < nblk) ? int((size_t(c3lo + l3) * S2 + c2lo + l2) * S1 + c1) : -1;
+    soff[k] = (stg && e < nblk) ? int((size_t(c3lo + l3) * S2 + c2lo + l2) * S1 + c1) : -1;
   }
   auto stage_load = [&](int u) {
     const double* cu = coef + (size_t(b) * ip.nup + u) * per;
@@ -450,44 +459,53 @@ __global__ void __launch_bounds__(kChunk)
     for (int k = 0; k < kStage; ++k)
       if (soff[k] >= 0) cb[tid + k * kChunk] = cs[k];
   };
-  if constexpr (STAGE) {
+  if (stg) {
     stage_load(0);
     stage_store(0);
     if (ip.nup > 1) stage_load(1);
-    __syncthreads();  // block 0 visible
   }
+  __syncthreads();  // block 0 visible
   // pencil task operands (loaded one delta ahead); every thread loads a valid task
-  const int tt = tid % ntask;
-  const int tc1 = tt % S1;
-  const int tside = (tt / S1) & 1;
-  const int64_t tpp = pen0 + tt / (2 * S1);
-  const int tj2 = int(tpp % g.m2), tj3 = int(tpp / g.m2);
-  double cv[NC];
-  bool tok = false;
-  int tf2v = 0, tf3v = 0, tj2v = 0, tj3v = 0;
+  int tc1[NT], tside[NT], tj2[NT], tj3[NT];
+  int64_t tpp[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const int tt = (tid + k * kChunk) % ntask;
+    tc1[k] = tt % S1;
+    tside[k] = (tt / S1) & 1;
+    tpp[k] = pen0 + tt / (2 * S1);
+    tj2[k] = int(tpp[k] % g.m2);
+    tj3[k] = int(tpp[k] / g.m2);
+  }
+  double cv[STAGE ? 1 : NC];
+  bool tok[NT];
+  int tf2v[NT], tf3v[NT], tj2v[NT], tj3v[NT];
   auto task_load = [&](int u) {
     const int4 dd = dsl[u];
-    int j2 = tj2, j3 = tj3;
-    if (tside) {
-      j2 -= dd.z;
-      j3 -= dd.w;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      int j2 = tj2[k], j3 = tj3[k];
+      if (tside[k]) {
+        j2 -= dd.z;
+        j3 -= dd.w;
+      }
+      tok[k] = in_dom(ip, 1, j2) && (ND == 2 || in_dom(ip, 2, j3)) && tpp[k] * g.m1 < g.N;
+      if (!tok[k]) {
+        j2 = ip.lo[1];
+        j3 = ND == 3 ? ip.lo[2] : 0;
+      }
+      tj2v[k] = j2;
+      tj3v[k] = j3;
+      tf2v[k] = tf2[j2];
+      tf3v[k] = ND == 3 ? tf3[j3] : 0;
     }
-    tok = in_dom(ip, 1, j2) && (ND == 2 || in_dom(ip, 2, j3)) && tpp * g.m1 < g.N;
-    if (!tok) {
-      j2 = ip.lo[1];
-      j3 = ND == 3 ? ip.lo[2] : 0;
-    }
-    tj2v = j2;
-    tj3v = j3;
-    tf2v = tf2[j2];
-    tf3v = ND == 3 ? tf3[j3] : 0;
     if constexpr (!STAGE) {
       const double* cu = coef + (size_t(b) * ip.nup + u) * per;
 #pragma unroll
       for (int a3 = 0; a3 < (ND == 3 ? Q + 1 : 1); ++a3)
 #pragma unroll
         for (int a2 = 0; a2 <= Q; ++a2)
-          cv[a3 * (Q + 1) + a2] = cu[(size_t(tf3v + a3) * S2 + tf2v + a2) * S1 + tc1];
+          cv[a3 * (Q + 1) + a2] = cu[(size_t(tf3v[0] + a3) * S2 + tf2v[0] + a2) * S1 + tc1[0]];
     }
   };
   task_load(0);
@@ -496,21 +514,36 @@ __global__ void __launch_bounds__(kChunk)
     const int4 dd = dsl[u];
     const int s = dd.x, dl1 = dd.y, dl2 = dd.z, dl3 = dd.w;
     T* Tu = Tbuf + size_t(u & 1) * ntask;
-    {
-      const T* b2 = tb2 + tj2v * (Q + 1);
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      const int task = tid + k * kChunk;
+      if (NT > 1 && task >= ntask) break;
+      const T* b2 = tb2 + tj2v[k] * (Q + 1);
       T v = T(0);
       if constexpr (STAGE) {
-        // tasks outside the analysis domain read a clamped (valid) block entry
-        // and are zeroed below
-        const int l2 = min(max(tf2v - c2lo, 0), n2 - Q - 1);
-        const int l3 = ND == 3 ? min(max(tf3v - c3lo, 0), n3 - Q - 1) : 0;
-        const double* cb = Cb + (u & 1) * blk + (size_t(l3) * n2 + l2) * S1 + tc1;
+        if (!MIXED || stg) {
+          // tasks outside the evaluated range read a clamped (valid) block
+          // entry and are zeroed below
+          const int l2 = min(max(tf2v[k] - c2lo, 0), n2 - Q - 1);
+          const int l3 = ND == 3 ? min(max(tf3v[k] - c3lo, 0), n3 - Q - 1) : 0;
+          const double* cb = Cb + (u & 1) * blk + (size_t(l3) * n2 + l2) * S1 + tc1[k];
 #pragma unroll
-        for (int a3 = 0; a3 < (ND == 3 ? Q + 1 : 1); ++a3) {
-          T r2 = T(0);
+          for (int a3 = 0; a3 < (ND == 3 ? Q + 1 : 1); ++a3) {
+            T r2 = T(0);
 #pragma unroll
-          for (int a2 = 0; a2 <= Q; ++a2) r2 += b2[a2] * T(cb[(a3 * n2 + a2) * S1]);
-          v += (ND == 3 ? tb3[tj3v * (Q + 1) + a3] : T(1)) * r2;
+            for (int a2 = 0; a2 <= Q; ++a2) r2 += b2[a2] * T(cb[(a3 * n2 + a2) * S1]);
+            v += (ND == 3 ? tb3[tj3v[k] * (Q + 1) + a3] : T(1)) * r2;
+          }
+        } else if constexpr (MIXED) {
+          // the same contraction from memory
+          const double* cb = coef + (size_t(b) * ip.nup + u) * per + (size_t(tf3v[k]) * S2 + tf2v[k]) * S1 + tc1[k];
+#pragma unroll
+          for (int a3 = 0; a3 < (ND == 3 ? Q + 1 : 1); ++a3) {
+            T r2 = T(0);
+#pragma unroll
+            for (int a2 = 0; a2 <= Q; ++a2) r2 += b2[a2] * T(cb[(size_t(a3) * S2 + a2) * S1]);
+            v += (ND == 3 ? tb3[tj3v[k] * (Q + 1) + a3] : T(1)) * r2;
+          }
         }
       } else {
 #pragma unroll
@@ -518,13 +551,13 @@ __global__ void __launch_bounds__(kChunk)
           T r2 = T(0);
 #pragma unroll
           for (int a2 = 0; a2 <= Q; ++a2) r2 += b2[a2] * T(cv[a3 * (Q + 1) + a2]);
-          v += (ND == 3 ? tb3[tj3v * (Q + 1) + a3] : T(1)) * r2;
+          v += (ND == 3 ? tb3[tj3v[k] * (Q + 1) + a3] : T(1)) * r2;
         }
       }
-      if (tid < ntask) Tu[tid] = tok ? v : T(0);
+      if (task < ntask) Tu[task] = tok[k] ? v : T(0);
     }
     task_load(u + 1 < ip.nup ? u + 1 : u);
-    if constexpr (STAGE) {
+    if (stg) {
       // block u+1 (loaded during the previous delta) into the other buffer, whose
       // readers finished before the previous barrier; then fetch block u+2
       if (u + 1 < ip.nup) stage_store(u + 1);
@@ -698,9 +731,15 @@ std::vector<int> fill_chunks(const Dims& d, int rows, const int lo[3], const int
 int fill_npen(const Dims& d, int rows) { return (rows - 1) / d.m[0] + 2; }
 
 // rows per chunk of the fill launch: the fast kernel when its pencil tasks fit
-// one workgroup, else the generic one
-int fill_chunk_rows(const Dims& d, int Sd1) {
-  return fill_npen(d, kChunk * kRows) * 2 * Sd1 <= kChunk ? kChunk * kRows : kChunk;
+// one per thread, or two per thread with a staged block of kStage*kChunk
+// values that fits LDS with the tables; else the generic one
+int fill_chunk_rows(const Dims& d, int Sd1, int q, int nup) {
+  const int npen = fill_npen(d, kChunk * kRows), ntask = npen * 2 * Sd1;
+  if (ntask <= kChunk) return kChunk * kRows;
+  const size_t msum = size_t(d.m[0]) + d.m[1] + (d.n == 3 ? d.m[2] : 1);
+  const size_t lds = size_t(2) * kStage * kChunk * sizeof(double) + size_t(2) * ntask * sizeof(double) +
+                     msum * (q + 1) * sizeof(double) + (msum + 4) * 4 + size_t(nup) * 16;
+  return ntask <= 2 * kChunk && lds <= 160 * 1024 ? kChunk * kRows : kChunk;
 }
 
 template <typename T>
@@ -762,25 +801,30 @@ static void launch_fill_m(const KInterp<T>& ip, const FillGeom& g, dim3 grid, si
     launch_fill_q<ND, FORM, T, true>(ip, g, grid, lds, coef, band, s);
 }
 
-template <int ND, int FORM, typename T, bool STAGE>
+template <int ND, int FORM, typename T, bool STAGE, int NT>
 static void launch_fast_q(const KInterp<T>& ip, const FillGeom& g, dim3 grid, size_t lds, const int4* dsl,
                           const double* coef, T* band, hipStream_t s) {
   switch (ip.q) {
-    case 1: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 1, T, STAGE>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
-    case 2: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 2, T, STAGE>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
-    case 3: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 3, T, STAGE>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
-    case 4: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 4, T, STAGE>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
-    default: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 5, T, STAGE>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
+    case 1: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 1, T, STAGE, NT>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
+    case 2: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 2, T, STAGE, NT>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
+    case 3: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 3, T, STAGE, NT>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
+    case 4: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 4, T, STAGE, NT>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
+    default: hipLaunchKernelGGL((fill_fast_kernel<ND, FORM, 5, T, STAGE, NT>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef, band); break;
   }
 }
 
+// stage: coefficient blocks staged in LDS where they fit (else the one-task,
+// prefetching form); two tasks per thread need staging
 template <int ND, int FORM, typename T>
 static void launch_fast_s(const KInterp<T>& ip, const FillGeom& g, bool stage, dim3 grid, size_t lds,
                           const int4* dsl, const double* coef, T* band, hipStream_t s) {
-  if (stage)
-    launch_fast_q<ND, FORM, T, true>(ip, g, grid, lds, dsl, coef, band, s);
+  const bool two = g.npen * 2 * ip.Sd[0] > kChunk;
+  if (stage && two)
+    launch_fast_q<ND, FORM, T, true, 2>(ip, g, grid, lds, dsl, coef, band, s);
+  else if (stage)
+    launch_fast_q<ND, FORM, T, true, 1>(ip, g, grid, lds, dsl, coef, band, s);
   else
-    launch_fast_q<ND, FORM, T, false>(ip, g, grid, lds, dsl, coef, band, s);
+    launch_fast_q<ND, FORM, T, false, 1>(ip, g, grid, lds, dsl, coef, band, s);
 }
 
 template <typename T>
@@ -802,9 +846,12 @@ hipError_t launch_fill(const KInterp<T>& ip, int form, const Dims& d, const int*
   g.n2max = n2max;
   g.n3max = n3max;
   const bool fast = chunk_rows == kChunk * kRows;
-  const int blk = n2max * n3max * ip.Sd[0];
-  const bool stage = fast && blk <= kStage * kChunk &&
-                     fill_lds_bytes<T>(ip, g.npen, d, blk) <= 160 * 1024;
+  const bool two = g.npen * 2 * ip.Sd[0] > kChunk;
+  // one task per thread: stage when every block fits (else prefetch); two
+  // tasks: blocks capped at kStage*kChunk, larger ones gathered from memory
+  const int blk = two ? std::min(n2max * n3max * ip.Sd[0], kStage * kChunk) : n2max * n3max * ip.Sd[0];
+  const bool stage = fast && (two || blk <= kStage * kChunk) && fill_lds_bytes<T>(ip, g.npen, d, blk) <= 160 * 1024;
+  if (fast && two && !stage) return hipErrorInvalidValue;
   const size_t lds = fill_lds_bytes<T>(ip, g.npen, d, stage ? blk : 0);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (nchunks == 0) return hipSuccess;
