@@ -272,10 +272,7 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
   }
   std::vector<QTile> tiles;
   if (fe) {
-    // every quadrature row of the face/edge surrogate runs in the sample-row launch
-    tiles = tiles_fe(d, hi.samp, tx, zchunk);
-    pl->groups[0] = pl->groups[1] = 0;
-    pl->groups[2] = int(tiles.size());
+    tiles = tiles_fe(d, hi.samp, tx, ty, zchunk, pl->groups);
   } else {
     tiles = tiles_surrogate(d, hi.samp, tx, ty, zchunk, pl->groups);
   }
@@ -344,8 +341,12 @@ static igs_status run_t(const Plan& pl, const KProblem& kp, const KInterp<OutT>&
     // corner rows), the fit over the augmented sample sets, and one fill over
     // every row of the band
     {
+      PhaseTimer t("quad_fe_tiles", s);
+      HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt, pl.groups[0], false, band, s));
+    }
+    if (pl.groups[2] > 0) {
       PhaseTimer t("quad_fe_rows", s);
-      HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt, pl.groups[2], d.n == 3, band, s));
+      HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt + pl.groups[0], pl.groups[2], true, band, s));
     }
     {
       PhaseTimer t("fit", s);

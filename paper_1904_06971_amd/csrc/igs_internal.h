@@ -123,9 +123,11 @@ std::vector<QTile> tiles_all(const Dims& d, int tx, int ty, int zchunk);
 std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3], int tx, int ty, int zchunk,
                                    int groups[3]);
 
-// Face/edge surrogate: the quadrature rows of the tensor sample set (3-D:
-// single-row tiles; 2-D: line tiles of tx rows streamed over runs of i2).
-std::vector<QTile> tiles_fe(const Dims& d, const std::vector<int> samp[3], int tx, int zchunk);
+// Face/edge surrogate: the quadrature rows of the tensor sample set; groups[0]
+// tiles of quad_tile_shape (runs of the set), groups[2] single-row tiles
+// (3-D rows with an isolated i1), groups[1] = 0.
+std::vector<QTile> tiles_fe(const Dims& d, const std::vector<int> samp[3], int tx, int ty, int zchunk,
+                            int groups[3]);
 
 // Caller-provided device memory that arenas carve their pieces from instead
 // of allocating (the allocation-free entry point): every arena attached to a

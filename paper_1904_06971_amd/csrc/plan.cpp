@@ -461,26 +461,49 @@ std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3]
   return out;
 }
 
-// Rows the face/edge surrogate assembles by quadrature: the tensor product of
-// the per-direction sample sets (layers and lattice; samp from
-// build_interp_fe).  3-D: single-row tiles (the rows are isolated in at least
-// one direction except near the corners); 2-D: whole i1 lines over each run of
-// consecutive i2 in the set (the extra rows are evaluated again by the fill).
-std::vector<QTile> tiles_fe(const Dims& d, const std::vector<int> samp[3], int tx, int zchunk) {
-  std::vector<QTile> out;
-  if (d.n == 3) {
-    for (int s3 : samp[2])
-      for (int s2 : samp[1])
-        for (int s1 : samp[0]) out.push_back(QTile{s1, s2, 1, 1, s3, s3 + 1});
-    return out;
-  }
-  const std::vector<int>& t = samp[1];
+namespace {
+// maximal runs [first, first + len) of consecutive values in a sorted set
+std::vector<std::pair<int, int>> index_runs(const std::vector<int>& t) {
+  std::vector<std::pair<int, int>> out;
   for (size_t a = 0; a < t.size();) {
     size_t b = a + 1;
     while (b < t.size() && t[b] == t[b - 1] + 1) ++b;
-    tile_rect(&out, 0, d.m[0], 0, 1, tx, 1, t[a], t[b - 1] + 1, zchunk);
+    out.push_back({t[a], int(b - a)});
     a = b;
   }
+  return out;
+}
+}  // namespace
+
+// Rows the face/edge surrogate assembles by quadrature: the tensor product of
+// the per-direction sample sets (layers and lattice; samp from
+// build_interp_fe).  3-D: the rows whose i1 lies in a run of the set (the 2p+1
+// indices at each end) as tiles over (i1 run) x (i2 run or single index),
+// streamed over each i3 run or single index -> groups[0]; the rows with an
+// isolated i1 (a lattice index) as single-row tiles -> groups[2].  2-D: whole
+// i1 lines over each run of consecutive i2 in the set (the extra rows are
+// evaluated again by the fill) -> groups[0].
+std::vector<QTile> tiles_fe(const Dims& d, const std::vector<int> samp[3], int tx, int ty, int zchunk,
+                            int groups[3]) {
+  std::vector<QTile> out;
+  groups[0] = groups[1] = groups[2] = 0;
+  if (d.n == 3) {
+    const auto r1 = index_runs(samp[0]), r2 = index_runs(samp[1]), r3 = index_runs(samp[2]);
+    for (const auto& z : r3)
+      for (const auto& y : r2)
+        for (const auto& x : r1)
+          if (x.second > 1) tile_rect(&out, x.first, x.first + x.second, y.first, y.first + y.second, tx, ty, z.first,
+                                      z.first + z.second, z.second);
+    groups[0] = int(out.size());
+    for (int s3 : samp[2])
+      for (int s2 : samp[1])
+        for (const auto& x : r1)
+          if (x.second == 1) out.push_back(QTile{x.first, s2, 1, 1, s3, s3 + 1});
+    groups[2] = int(out.size()) - groups[0];
+    return out;
+  }
+  for (const auto& z : index_runs(samp[1])) tile_rect(&out, 0, d.m[0], 0, 1, tx, 1, z.first, z.first + z.second, zchunk);
+  groups[0] = int(out.size());
   return out;
 }
 
