@@ -239,6 +239,30 @@ def main():
         log(f"exact: {ms_ex:.3f} ms; surrogate speed-up {ms_ex / ms_step:.2f}x")
         xplan.close()
 
+        # ------------------------ face/edge stencil functions (Sec. 3.6), same workload
+        info_fe = igs.surrogate_fe_layout(prob, M, q)
+        fe = {"quadrature_rows": info_fe.quadrature_rows, "domain_surrogate_quadrature_rows": info.quadrature_rows,
+              "classes": info_fe.classes}
+        for name, tdt, esize in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+            bfe = band if tdt == torch.float64 else igs.empty_band(prob, tdt)
+            pfe = igs.Plan(prob, igs.STIFFNESS, M=M, q=q, dtype=tdt, face_edge=True)
+            ms_fe, ph_fe = timed_plan(pfe, bfe, stream, args.steps)
+            pfe.close()
+            leg = {"ms": ms_fe, "slots_per_s": slots / (ms_fe * 1e-3), "phases_ms": ph_fe,
+                   "step_hbm_frac": slots * esize / (ms_fe * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                   "fill_hbm_frac": slots * esize / (ph_fe["fill"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            if name == "f64":
+                leg["speedup_vs_domain_surrogate"] = ms_step / ms_fe
+                leg["speedup_vs_exact"] = ms_ex / ms_fe
+            fe[name] = leg
+            del bfe
+        extra["face_edge"] = fe
+        log(f"face/edge: {fe}")
+
+        # ------------- 3D p=3 64^3 stiffness and mass, exact vs surrogate M in {4, 8, 16}
+        extra["poisson3d_p3_64"] = c2_study(stream, args.steps)
+        log(f"3D p=3 64^3: {extra['poisson3d_p3_64']}")
+
         # -------------------------------------------------------- SpMV / CG
         plan.execute(out=band)
         b32 = igs.assemble_surrogate(prob, igs.STIFFNESS, M, q, dtype=torch.float32)
@@ -411,6 +435,70 @@ def main():
         **extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def timed_plan(plan, band, stream, reps):
+    """Average step time (HIP events on the launch stream around reps
+    back-to-back executions, after one warm execution) and per-phase kernel
+    times of a kept plan."""
+    import torch
+
+    from paper_1904_06971_amd import igs
+
+    plan.execute(out=band)
+    torch.cuda.synchronize()
+    igs.profile_enable(True)
+    igs.profile_read()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        plan.execute(out=band)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    pr = igs.profile_read()
+    igs.profile_enable(False)
+    return e0.elapsed_time(e1) / reps, {k: v[1] / v[0] for k, v in pr.items()}
+
+
+def c2_study(stream, reps):
+    """3D Poisson stiffness and mass, p = 3, 64^3 elements on the sine map:
+    full quadrature assembly against the surrogate (and its face/edge form) at
+    M = 4, 8, 16, q = 3 -- band slots per second, the entry error
+    ||A - A~||_max / ||A||_max per M, and the fitted log2 rate of that error
+    over M (Thm. RegularityOfStencilFunctions: ~ H^(q+1), slope q+1 = 4)."""
+    import torch
+
+    from paper_1904_06971_amd import igs
+    from paper_1904_06971_amd import workloads as W
+
+    prob = W.c2_poisson3d()
+    lay = igs.layout(prob)
+    slots = lay.N * lay.slots
+    out = {"workload": "3D Poisson, p=3, 64^3 elements, sine map a=0.05, kappa=1, q=3", "dofs": lay.N, "slots": slots}
+    ex = igs.empty_band(prob, torch.float64)
+    sb = igs.empty_band(prob, torch.float64)
+    for form, fname in ((igs.STIFFNESS, "stiffness"), (igs.MASS, "mass")):
+        pe = igs.Plan(prob, form, M=0, q=0)
+        ms_ex, _ = timed_plan(pe, ex, stream, reps)
+        pe.close()
+        scale = float(ex[:, :, :lay.N].abs().max())
+        leg = {"exact": {"ms": ms_ex, "slots_per_s": slots / (ms_ex * 1e-3)}}
+        for fe in (False, True):
+            errs = {}
+            for M in (4, 8, 16):
+                ps = igs.Plan(prob, form, M=M, q=3, face_edge=fe)
+                ms_s, ph = timed_plan(ps, sb, stream, reps)
+                ps.close()
+                err = float((sb[:, :, :lay.N] - ex[:, :, :lay.N]).abs().max()) / scale
+                errs[M] = err
+                leg[("face_edge_M%d" if fe else "surrogate_M%d") % M] = {
+                    "ms": ms_s, "slots_per_s": slots / (ms_s * 1e-3), "speedup_vs_exact": ms_ex / ms_s,
+                    "rel_max_err": err, "phases_ms": ph}
+            leg["face_edge_rate" if fe else "rate"] = {
+                "log2_slope_M4_M8": math.log2(errs[8] / errs[4]), "log2_slope_M8_M16": math.log2(errs[16] / errs[8])}
+        out[fname] = leg
+    del ex, sb
+    return out
 
 
 def mesh_dependent_study(stream):
