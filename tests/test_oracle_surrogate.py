@@ -79,6 +79,25 @@ def test_entry_error_rate(oracle, q, rate):
     assert errs[2] > errs[1] > errs[0]
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("form,q,rate", [(0, 3, 4.0), (1, 3, 4.0), (0, 1, 2.0)])
+def test_entry_error_rate_3d(oracle, form, q, rate):
+    """The same rate in 3D (Thm. RegularityOfStencilFunctions holds in any
+    dimension): stiffness and mass on the 3D sine map, p = 2, 44^3 elements,
+    off-diagonal entries of every 23rd analysis-domain row, M = 4 -> 8."""
+    prob = W.problem(3, 2, 44)
+    m, N, _ = oracle.dims(prob)
+    idx = oracle.multi_index(prob, np.arange(N))
+    rows = np.nonzero(oracle.interior_mask(prob, idx))[0][::23]
+    A = oracle.exact_rows(prob, form, rows)
+    off = np.ones(A.shape[1], dtype=bool)
+    off[A.shape[1] // 2] = False
+    errs = [np.abs(A - oracle.Surrogate(prob, form, M, q).rows(rows))[:, off].max() for M in (4, 8, 16)]
+    slope = np.log2(errs[1] / errs[0])
+    assert abs(slope - rate) < 0.5, (errs, slope)
+    assert errs[2] > errs[1] > errs[0]
+
+
 @pytest.mark.parametrize("form", [0, 1])
 def test_structure(oracle, form):
     prob = W.problem(2, 3, 30, coef="sine3", camp=0.5)
