@@ -297,6 +297,29 @@ igs_status igs_plan_create(const igs_problem* pb, int32_t form, int32_t M, int32
 igs_status igs_plan_create_fe(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
                               igs_plan* out);
 igs_status igs_plan_execute(igs_plan plan, const double* coef, void* band, void* stream);
+
+/* Matrix-free surrogate operator (Sec. 1 names the surrogate's cheap
+ * matrix-free application as the goal; remark after eq. 5.1c).  A plan from
+ * igs_plan_create_mf (3-D, FP64; same validation as igs_plan_create with
+ * M >= 1) executes only what the operator needs: the sample rows, the tensor
+ * spline coefficients of every upper stencil function (kept in the plan) and
+ * the exact rows outside the analysis domain, written into `band` (the full
+ * igs_layout band; its analysis-domain rows are neither written nor read).
+ * igs_apply_mf: y = A~ x for the surrogate of eq. 5.1c (5.1b for mass) -- the
+ *   analysis-domain rows evaluate Phi~_delta from the coefficients on the fly
+ *   (their copied exact entries and the rows outside the domain come from
+ *   `band`, which must hold the plan's last execution); dirichlet as in
+ *   igs_apply.  x, y: device [batch][N] FP64.  Asynchronous.  2-D plans
+ *   (at creation) and meshes whose analysis-domain pencils are too short for
+ *   the chunked evaluation (a 768-row chunk touching more than 256 / (S1)
+ *   pencils, e.g. 18-row pencils with 6 samples) return IGS_ERR_UNSUPPORTED.
+ * igs_solve_cg_mf: FP64 CG with that operator, arguments and stopping rule
+ *   as igs_solve_cg without an FP32 band (x0 = u on entry).  Synchronous. */
+igs_status igs_plan_create_mf(const igs_problem* pb, int32_t form, int32_t M, int32_t q, void* stream, igs_plan* out);
+igs_status igs_apply_mf(igs_plan plan, const double* band, const double* x, double* y, int32_t dirichlet,
+                        void* stream);
+igs_status igs_solve_cg_mf(igs_plan plan, const double* band, const double* f, double* u, double rtol, int32_t maxit,
+                           igs_cg_info* info, void* stream);
 igs_status igs_plan_destroy(igs_plan plan);
 
 /* Load vector F(B_i) = int_Omega f B_i dx (Sec. 7, eq. PoissonWeakForm) by

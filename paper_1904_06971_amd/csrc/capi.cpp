@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <vector>
 
@@ -45,6 +46,14 @@ igs_status launch_apply(const Dims& d, int dtype, const void* band, const void* 
                         hipStream_t s);
 igs_status solve_cg(const Dims& d, const double* band64, const float* band32, const double* f, double* u, double rtol,
                     int maxit, igs_cg_info* info, hipStream_t s);
+template <typename T>
+hipError_t launch_apply_mf(const KInterp<T>& ip, int form, const Dims& d, const int* chunks, int nchunks,
+                           int chunk_rows, int n2max, int n3max, const int4* dsl, const double* coef, const T* band,
+                           const int* crow, int ncopy, const int* brow, int nbrow, const T* x, T* y, T* xm,
+                           int dirichlet, bool x_masked, hipStream_t s);
+std::vector<int> boundary_rows(const Dims& d);
+igs_status solve_cg_op(const Dims& d, const std::function<igs_status(const double*, double*)>& A, const double* f,
+                       double* u, double rtol, int maxit, igs_cg_info* info, hipStream_t s);
 igs_status adjoint_weights_grad(const igs_problem* pb, const Dims& d, const KProblem& kp, int M, int q,
                                 const double* x, const double* ybar, double* cbar, hipStream_t s);
 
@@ -211,7 +220,7 @@ static igs_status check_sampling(const Dims& d, int M, int q) {
 // free it; igs_plan_* keep it for repeated runs.
 
 struct Plan {
-  int kind = 0;  // 0 exact, 1 surrogate, 2 face/edge surrogate
+  int kind = 0;  // 0 exact, 1 surrogate, 2 face/edge surrogate, 3 matrix-free surrogate
   int form = 0, dtype = 0, M = 0, q = 0;
   Prepared P;
   Arena ta;
@@ -226,6 +235,9 @@ struct Plan {
   const double* g0T = nullptr;  // direction-1 inverse collocation matrix, transposed
   const int* dcopy = nullptr;  // analysis-domain rows whose stencil leaves the domain
   int ncopy = 0;
+  const int* dbrow = nullptr;  // matrix-free: rows outside the analysis domain
+  int nbrow = 0;
+  double* xm = nullptr;        // matrix-free: Dirichlet-masked copy of x
   int state = 0;  // geometry flag: 0 not read yet, 1 read and clear, 2 set
   Plan() = default;
   Plan(const Plan&) = delete;
@@ -292,6 +304,8 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
     dsl.push_back((sl / W) % W - d.p);
     dsl.push_back(d.n == 3 ? sl / (W * W) - d.p : 0);
   }
+  const bool mf = pl->kind == 3;
+  std::vector<int> brow = mf ? boundary_rows(d) : std::vector<int>();
   const size_t S1 = hi.samp[0].size();
   std::vector<double> g0t(S1 * S1);
   for (size_t r = 0; r < S1; ++r)
@@ -300,6 +314,7 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
                  vbytes(crow) + vbytes(dsl) + padded(hi.upslot.size() * sizeof(int)) * 2 + vbytes(g0t);
   for (int k = 0; k < d.n; ++k)
     bytes += 2 * (vbytes(hi.samp[k]) + vbytes(hi.ginv[k]) + vbytes(hi.ef[k]) + vbytes(hi.eb[k]));
+  if (mf) bytes += vbytes(brow) + padded(sizeof(double) * size_t(d.N) * d.batch);
   st = pl->ta.alloc(bytes, s);
   if (st != IGS_OK) return st;
   Arena& ta = pl->ta;
@@ -316,6 +331,11 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
   pl->ncopy = int(crow.size());
   pl->ddsl = reinterpret_cast<const int4*>(upload(ta, dsl, s, &st));
   pl->g0T = upload(ta, g0t, s, &st);
+  if (mf) {
+    pl->dbrow = upload(ta, brow, s, &st);
+    pl->nbrow = int(brow.size());
+    pl->xm = ta.take<double>(size_t(d.N) * d.batch);
+  }
   pl->tmp0 = ta.take<double>(ncoef);
   pl->tmp1 = ta.take<double>(ncoef);
   pl->coef = ta.take<double>(ncoef);
@@ -336,6 +356,29 @@ static igs_status run_t(const Plan& pl, const KProblem& kp, const KInterp<OutT>&
       PhaseTimer t("quad_exact", s);
       HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt, pl.ntiles, false, band, s));
     }
+  } else if (pl.kind == 3) {
+    // matrix-free: only what igs_apply_mf reads -- the sample rows, the
+    // spline coefficients (kept in the plan) and the rows outside the analysis
+    // domain; the band rows of the domain are neither written nor read
+    const QTile* t2 = pl.dt + pl.groups[0] + pl.groups[1];
+    {
+      PhaseTimer t("quad_sample_rows", s);
+      HIP_TRY(launch_quad<OutT>(kp, pl.form, t2, pl.groups[2], d.n == 3, band, s));
+    }
+    {
+      PhaseTimer t("fit", s);
+      if (fit_use_gemm(pl.ip64, d.n, d.batch))
+        HIP_TRY(launch_fit_gemm<OutT>(pl.ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, pl.tmp0, pl.tmp1,
+                                      pl.coef, s));
+      else
+        HIP_TRY(launch_fit<OutT>(pl.ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, pl.tmp0, pl.tmp1, pl.coef,
+                                 pl.g0T, s));
+    }
+    {
+      PhaseTimer t("quad_boundary_rows", s);
+      HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt, pl.groups[0] + pl.groups[1], false, band, s));
+    }
+    return IGS_OK;
   } else if (pl.kind == 2) {
     // face/edge: the quadrature rows (every sample row of every class, and the
     // corner rows), the fit over the augmented sample sets, and one fill over
@@ -650,12 +693,11 @@ struct igs_plan_s {
 };
 
 static igs_status plan_create(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
-                              igs_plan* out, bool fe) {
+                              igs_plan* out, int variant) {
   if (!pb || !out) return IGS_ERR_ARG;
-  if (fe && M < 1) {
-    *out = nullptr;
-    return IGS_ERR_ARG;
-  }
+  *out = nullptr;
+  if (variant != 0 && M < 1) return IGS_ERR_ARG;
+  if (variant == 3 && pb->n != 3) return IGS_ERR_UNSUPPORTED;
   *out = nullptr;
   if (form != IGS_STIFFNESS && form != IGS_MASS) return IGS_ERR_ARG;
   if (dtype != IGS_F64 && dtype != IGS_F32) return IGS_ERR_ARG;
@@ -670,7 +712,7 @@ static igs_status plan_create(const igs_problem* pb, int32_t form, int32_t M, in
   igs_plan_s* h = new igs_plan_s;
   h->pl.P.ar.persistent = true;
   h->pl.ta.persistent = true;
-  h->pl.kind = M == 0 ? 0 : (fe ? 2 : 1);
+  h->pl.kind = M == 0 ? 0 : (variant != 0 ? variant : 1);
   h->pl.form = form;
   h->pl.dtype = dtype;
   h->pl.M = M;
@@ -689,12 +731,48 @@ static igs_status plan_create(const igs_problem* pb, int32_t form, int32_t M, in
 
 igs_status igs_plan_create(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
                            igs_plan* out) {
-  return plan_create(pb, form, M, q, dtype, stream, out, false);
+  return plan_create(pb, form, M, q, dtype, stream, out, 0);
 }
 
 igs_status igs_plan_create_fe(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
                               igs_plan* out) {
-  return plan_create(pb, form, M, q, dtype, stream, out, true);
+  return plan_create(pb, form, M, q, dtype, stream, out, 2);
+}
+
+igs_status igs_plan_create_mf(const igs_problem* pb, int32_t form, int32_t M, int32_t q, void* stream, igs_plan* out) {
+  return plan_create(pb, form, M, q, IGS_F64, stream, out, 3);
+}
+
+static igs_status mf_apply(const Plan& pl, const double* band, const double* x, double* y, int dirichlet,
+                           bool x_masked, hipStream_t s) {
+  const Dims& d = pl.P.d;
+  const hipError_t e = launch_apply_mf<double>(pl.ipd, pl.form, d, pl.dchunks, pl.nchunks, pl.chunk_rows, pl.n2max,
+                                               pl.n3max, pl.ddsl, pl.coef, band, pl.dcopy, pl.ncopy, pl.dbrow,
+                                               pl.nbrow, x, y, pl.xm, dirichlet, x_masked, s);
+  if (e == hipErrorInvalidValue) return IGS_ERR_UNSUPPORTED;
+  return e == hipSuccess ? IGS_OK : IGS_ERR_HIP;
+}
+
+igs_status igs_apply_mf(igs_plan plan, const double* band, const double* x, double* y, int32_t dirichlet,
+                        void* stream) {
+  if (!plan || !band || !x || !y) return IGS_ERR_ARG;
+  if (plan->pl.kind != 3) return IGS_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  plan->last = s;
+  return mf_apply(plan->pl, band, x, y, dirichlet, false, s);
+}
+
+igs_status igs_solve_cg_mf(igs_plan plan, const double* band, const double* f, double* u, double rtol, int32_t maxit,
+                           igs_cg_info* info, void* stream) {
+  if (!plan || !band || !f || !u || !info) return IGS_ERR_ARG;
+  if (plan->pl.kind != 3 || !(rtol > 0.0) || maxit < 1) return IGS_ERR_ARG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  plan->last = s;
+  std::memset(info, 0, sizeof(*info));
+  const Plan& pl = plan->pl;
+  // CG keeps its vectors zero on the Dirichlet dofs: no masking copy
+  auto A = [&](const double* x, double* y) { return mf_apply(pl, band, x, y, 1, true, s); };
+  return solve_cg_op(pl.P.d, A, f, u, rtol, maxit, info, s);
 }
 
 igs_status igs_plan_execute(igs_plan plan, const double* coef, void* band, void* stream) {

@@ -22,6 +22,7 @@
 #include <algorithm>
 
 #include "igs_internal.h"
+#include "profile.h"
 
 namespace igs {
 
@@ -121,6 +122,10 @@ struct FillGeom {
   int nchunks;
   const int* chunks;  // chunk ids that contain analysis-domain rows
   int n2max, n3max;   // largest coefficient block (directions 2, 3) a chunk's tasks use
+  // matrix-free apply (fill_fast_kernel with APPLY): y_i for the evaluated
+  // rows from their interpolated entries and x, instead of band stores
+  const void* ax;
+  void* ay;
 };
 
 // host-side per-delta table (slot, delta1, delta2, delta3)
@@ -322,7 +327,12 @@ constexpr int kRows = 3;
 // instead; the choice is uniform per workgroup.
 constexpr int kStage = 4;  // staged coefficients per thread (block <= kStage * kChunk)
 
-template <int ND, int FORM, int Q, typename T, bool STAGE, int NT>
+// APPLY = true: the matrix-free surrogate apply (Sec. 1; remark after eq.
+// 5.1c): the same evaluation, but each evaluated row accumulates
+// sum_j A~_ij x_j over its interpolated entries (the diagonal as minus their
+// sum for stiffness) into g.ay instead of writing the band; the band is not
+// touched.
+template <int ND, int FORM, int Q, typename T, bool STAGE, int NT, bool APPLY = false>
 __global__ void __launch_bounds__(kChunk)
     fill_fast_kernel(KInterp<T> ip, FillGeom g, const int4* __restrict__ dsl, const double* __restrict__ coef,
                      T* __restrict__ band) {
@@ -370,9 +380,10 @@ __global__ void __launch_bounds__(kChunk)
   bool live[R], inner[R];
   int i1r[R], kr[R], mask[R], f1u[R];
   size_t irow[R];
-  T dsum[R];
+  T dsum[R], yacc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
+    yacc[r] = T(0);
     const int64_t i = c0 + tid + int64_t(r) * kChunk;
     const int64_t pen = i < g.N ? i / g.m1 : pen0;
     const int i1 = i < g.N ? int(i - pen * g.m1) : 0;
@@ -566,6 +577,7 @@ __global__ void __launch_bounds__(kChunk)
     __syncthreads();
     const bool has_lo = FORM == IGS_STIFFNESS || s != sc;
     const size_t su = size_t(s) * ld, sl = Sm1ld - size_t(s) * ld;
+    const int64_t xoff = APPLY ? int64_t(dl1) + int64_t(g.m1) * (dl2 + int64_t(g.m2) * dl3) : 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       // placeholders (0) where the entry is not interpolated: the quadrature of
@@ -586,9 +598,29 @@ __global__ void __launch_bounds__(kChunk)
         vl = (inner[r] && inside(mask[r], -dl1, -dl2, -dl3)) ? vl : T(0);
       }
       if (FORM == IGS_STIFFNESS) dsum[r] += vu + vl;
-      bnd[live[r] ? su + irow[r] : irow[r]] = vu;
-      if (has_lo) bnd[live[r] ? sl + irow[r] : irow[r]] = vl;
+      if constexpr (APPLY) {
+        // an evaluated row's partners stay within p of it, inside the box
+        if (inner[r]) {
+          const T* xb = static_cast<const T*>(g.ax) + size_t(b) * g.N + irow[r];
+          yacc[r] += vu * xb[xoff];
+          if (has_lo) yacc[r] += vl * xb[-xoff];
+        }
+      } else {
+        bnd[live[r] ? su + irow[r] : irow[r]] = vu;
+        if (has_lo) bnd[live[r] ? sl + irow[r] : irow[r]] = vl;
+      }
     }
+  }
+  if constexpr (APPLY) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!inner[r]) continue;
+      const size_t k = size_t(b) * g.N + irow[r];
+      T v = yacc[r];
+      if (FORM == IGS_STIFFNESS) v -= dsum[r] * static_cast<const T*>(g.ax)[k];
+      static_cast<T*>(g.ay)[k] = v;
+    }
+    return;
   }
   // diagonal of the interpolated part (the copy kernel subtracts the copies)
   if (FORM == IGS_STIFFNESS) {
@@ -624,12 +656,17 @@ __global__ void zero_pad_kernel(T* band, int64_t N, int64_t ld, int slots_total)
 // waves' partial sums meet in LDS in a fixed order.
 constexpr int kCopyWaves = 4;
 
-template <int ND, int FORM, int P, typename T>
+// APPLY = true (matrix-free apply): the copied entries are not stored; the row
+// adds sum_j A_ij (x_j - x_i) over them to y_i (stiffness: the diagonal loses
+// them), or sum_j A_ij x_j (mass).  Runs after the evaluation of the domain
+// rows (fill_fast_kernel with APPLY), which wrote y_i.
+template <int ND, int FORM, int P, typename T, bool APPLY = false>
 __global__ void __launch_bounds__(64 * kCopyWaves)
     copy_kernel(KInterp<T> ip, int m1, int m2, int64_t ld, int S, const int* __restrict__ rows, int nrows,
-                T* __restrict__ band) {
+                T* __restrict__ band, const T* __restrict__ x = nullptr, T* __restrict__ y = nullptr, int64_t N = 0) {
   constexpr int W = 2 * P + 1, NL = ND == 3 ? W * W : W;
   __shared__ T part[kCopyWaves][64];
+  __shared__ T xpart[kCopyWaves][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int t = blockIdx.x * 64 + lane;
   const bool ok = t < nrows;
@@ -641,7 +678,8 @@ __global__ void __launch_bounds__(64 * kCopyWaves)
   int o1 = 0;  // bit d1 + P: i1 + d1 leaves the domain
 #pragma unroll
   for (int d1 = -P; d1 <= P; ++d1) o1 |= in_dom(ip, 0, i1 + d1) ? 0 : 1 << (d1 + P);
-  T csum = T(0);
+  T csum = T(0), xsum = T(0);
+  const T* xb = APPLY ? x + size_t(blockIdx.y) * N : nullptr;
   for (int L = w; L < NL; L += kCopyWaves) {
     const int d2 = L % W - P, d3 = ND == 3 ? L / W - P : 0;
     const bool out23 = !in_dom(ip, 1, i2 + d2) || (ND == 3 && !in_dom(ip, 2, i3 + d3));
@@ -657,11 +695,28 @@ __global__ void __launch_bounds__(64 * kCopyWaves)
 #pragma unroll
     for (int k = 0; k < W; ++k)
       if (om >> k & 1) {
-        bnd[size_t(s0 + k) * ld + size_t(i)] = v[k];
+        if constexpr (APPLY)
+          xsum += v[k] * xb[i + off0 + (k - P)];
+        else
+          bnd[size_t(s0 + k) * ld + size_t(i)] = v[k];
         csum += v[k];
       }
   }
-  if (FORM == IGS_STIFFNESS) {
+  if constexpr (APPLY) {
+    part[w][lane] = csum;
+    xpart[w][lane] = xsum;
+    __syncthreads();
+    if (w == 0 && ok) {
+      T c = part[0][lane], xs = xpart[0][lane];
+#pragma unroll
+      for (int k = 1; k < kCopyWaves; ++k) {
+        c += part[k][lane];
+        xs += xpart[k][lane];
+      }
+      T* yi = y + size_t(blockIdx.y) * N + size_t(i);
+      *yi += FORM == IGS_STIFFNESS ? xs - c * xb[i] : xs;
+    }
+  } else if (FORM == IGS_STIFFNESS) {
     part[w][lane] = csum;
     __syncthreads();
     if (w == 0 && ok) {
@@ -672,6 +727,41 @@ __global__ void __launch_bounds__(64 * kCopyWaves)
       bnd[ic] = bnd[ic] - c;
     }
   }
+}
+
+// Matrix-free apply, the rows assembled by quadrature (listed): y_i =
+// sum_s band[s][i] x_{i+delta_s} from the stored rows; Dirichlet rows give 0
+// when dirichlet is set (x is then already zero on the Dirichlet dofs).  One
+// row per thread: consecutive threads read consecutive entries of a slot.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    rows_spmv_kernel(int n, int P, int m1, int m2, int m3, int64_t N, int64_t ld, int S, const int* __restrict__ rows,
+                     int nrows, const T* __restrict__ band, const T* __restrict__ x, T* __restrict__ y, int dirichlet) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= nrows) return;
+  const int b = blockIdx.y;
+  const int64_t i = rows[t];
+  const int i1 = int(i % m1), i2 = int((i / m1) % m2), i3 = n == 3 ? int(i / (int64_t(m1) * m2)) : 0;
+  T* yb = y + size_t(b) * N;
+  if (dirichlet) {
+    const bool dr = i1 == 0 || i1 == m1 - 1 || i2 == 0 || i2 == m2 - 1 || (n == 3 && (i3 == 0 || i3 == m3 - 1));
+    if (dr) {
+      yb[i] = T(0);
+      return;
+    }
+  }
+  const T* bb = band + size_t(b) * S * ld + size_t(i);
+  const T* xb = x + size_t(b) * N;
+  const int W = 2 * P + 1;
+  T acc = T(0);
+  for (int s = 0; s < S; ++s) {
+    const int d1 = s % W - P, d2 = (s / W) % W - P, d3 = n == 3 ? s / (W * W) - P : 0;
+    // entries whose partner leaves the box are stored as 0: clamp the read
+    int64_t j = i + d1 + int64_t(m1) * (d2 + int64_t(m2) * d3);
+    j = j < 0 ? 0 : (j >= N ? N - 1 : j);
+    acc += bb[size_t(s) * ld] * xb[j];
+  }
+  yb[i] = acc;
 }
 
 // ------------------------------------------------------------ launchers ----
@@ -890,6 +980,138 @@ template hipError_t launch_fill<float>(const KInterp<float>&, int, const Dims&, 
                                        const int4*, const double*, float*, hipStream_t);
 template size_t fill_lds_bytes<double>(const KInterp<double>&, int, const Dims&, int);
 template size_t fill_lds_bytes<float>(const KInterp<float>&, int, const Dims&, int);
+
+// ------------------------------------------------------ matrix-free apply ----
+
+// xm = x with the Dirichlet dofs zeroed
+template <typename T>
+__global__ void mask_dirichlet_kernel(int n, int m1, int m2, int m3, int64_t N, int batch, const T* __restrict__ x,
+                                      T* __restrict__ xm) {
+  const int64_t total = N * batch;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = t % N;
+    const int i1 = int(i % m1), i2 = int((i / m1) % m2), i3 = n == 3 ? int(i / (int64_t(m1) * m2)) : 0;
+    const bool dr = i1 == 0 || i1 == m1 - 1 || i2 == 0 || i2 == m2 - 1 || (n == 3 && (i3 == 0 || i3 == m3 - 1));
+    xm[t] = dr ? T(0) : x[t];
+  }
+}
+
+template <int FORM, int Q, typename T>
+static void launch_mf_eval(const KInterp<T>& ip, const FillGeom& g, bool stage, dim3 grid, size_t lds,
+                           const int4* dsl, const double* coef, T* band, hipStream_t s) {
+  if (g.npen * 2 * ip.Sd[0] > kChunk)
+    hipLaunchKernelGGL((fill_fast_kernel<3, FORM, Q, T, true, 2, true>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef,
+                       band);
+  else if (stage)
+    hipLaunchKernelGGL((fill_fast_kernel<3, FORM, Q, T, true, 1, true>), grid, dim3(kChunk), lds, s, ip, g, dsl, coef,
+                       band);
+  else
+    hipLaunchKernelGGL((fill_fast_kernel<3, FORM, Q, T, false, 1, true>), grid, dim3(kChunk), lds, s, ip, g, dsl,
+                       coef, band);
+}
+
+template <int FORM, int P, typename T>
+static void launch_mf_copy(const KInterp<T>& ip, const Dims& d, const int* rows, int nrows, T* band, const T* x, T* y,
+                           hipStream_t s) {
+  if (nrows == 0) return;
+  dim3 grid((nrows + 63) / 64, d.batch);
+  hipLaunchKernelGGL((copy_kernel<3, FORM, P, T, true>), grid, dim3(64 * kCopyWaves), 0, s, ip, d.m[0], d.m[1], d.ld,
+                     d.S, rows, nrows, band, x, y, d.N);
+}
+
+// y = A~ x, matrix-free for the analysis-domain rows (3-D, fast chunked
+// fill): the evaluation of those rows from the spline coefficients, their
+// exact partner entries from the stored rows, and the stored rows
+// themselves.  xm: scratch of N*batch values, used when dirichlet is set and
+// x_masked is false.
+template <typename T>
+hipError_t launch_apply_mf(const KInterp<T>& ip, int form, const Dims& d, const int* chunks, int nchunks,
+                           int chunk_rows, int n2max, int n3max, const int4* dsl, const double* coef, const T* band,
+                           const int* crow, int ncopy, const int* brow, int nbrow, const T* x, T* y, T* xm,
+                           int dirichlet, bool x_masked, hipStream_t s) {
+  if (d.n != 3 || chunk_rows != kChunk * kRows) return hipErrorInvalidValue;
+  FillGeom g;
+  g.n = d.n;
+  g.P = d.p;
+  g.m1 = d.m[0];
+  g.m2 = d.m[1];
+  g.m3 = d.m[2];
+  g.N = d.N;
+  g.ld = d.ld;
+  g.S = d.S;
+  g.npen = fill_npen(d, chunk_rows);
+  g.nchunks = nchunks;
+  g.chunks = chunks;
+  g.n2max = n2max;
+  g.n3max = n3max;
+  // as in launch_fill: two tasks per thread need staging (capped blocks)
+  const bool two = g.npen * 2 * ip.Sd[0] > kChunk;
+  if (g.npen * 2 * ip.Sd[0] > 2 * kChunk) return hipErrorInvalidValue;
+  const int blk = two ? std::min(n2max * n3max * ip.Sd[0], kStage * kChunk) : n2max * n3max * ip.Sd[0];
+  const bool stage = (two || blk <= kStage * kChunk) && fill_lds_bytes<T>(ip, g.npen, d, blk) <= 160 * 1024;
+  if (two && !stage) return hipErrorInvalidValue;
+  const size_t lds = fill_lds_bytes<T>(ip, g.npen, d, stage ? blk : 0);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  const T* xin = x;
+  if (dirichlet && !x_masked) {
+    const int64_t total = d.N * d.batch;
+    hipLaunchKernelGGL((mask_dirichlet_kernel<T>), dim3(int(std::min<int64_t>((total + 255) / 256, 8192))), dim3(256),
+                       0, s, d.n, d.m[0], d.m[1], d.m[2], d.N, d.batch, x, xm);
+    xin = xm;
+  }
+  g.ax = xin;
+  g.ay = y;
+  T* bandw = const_cast<T*>(band);  // read only in the apply modes
+  {
+    PhaseTimer t("mf_domain_rows", s);
+    if (nchunks > 0) {
+      dim3 grid(nchunks, d.batch);
+      const bool mass = form == IGS_MASS;
+      switch (ip.q) {
+        case 1: mass ? launch_mf_eval<IGS_MASS, 1, T>(ip, g, stage, grid, lds, dsl, coef, bandw, s) : launch_mf_eval<IGS_STIFFNESS, 1, T>(ip, g, stage, grid, lds, dsl, coef, bandw, s); break;
+        case 2: mass ? launch_mf_eval<IGS_MASS, 2, T>(ip, g, stage, grid, lds, dsl, coef, bandw, s) : launch_mf_eval<IGS_STIFFNESS, 2, T>(ip, g, stage, grid, lds, dsl, coef, bandw, s); break;
+        case 3: mass ? launch_mf_eval<IGS_MASS, 3, T>(ip, g, stage, grid, lds, dsl, coef, bandw, s) : launch_mf_eval<IGS_STIFFNESS, 3, T>(ip, g, stage, grid, lds, dsl, coef, bandw, s); break;
+        case 4: mass ? launch_mf_eval<IGS_MASS, 4, T>(ip, g, stage, grid, lds, dsl, coef, bandw, s) : launch_mf_eval<IGS_STIFFNESS, 4, T>(ip, g, stage, grid, lds, dsl, coef, bandw, s); break;
+        default: mass ? launch_mf_eval<IGS_MASS, 5, T>(ip, g, stage, grid, lds, dsl, coef, bandw, s) : launch_mf_eval<IGS_STIFFNESS, 5, T>(ip, g, stage, grid, lds, dsl, coef, bandw, s); break;
+      }
+    }
+  }
+  {
+    PhaseTimer t("mf_copied_entries", s);
+    const bool mass = form == IGS_MASS;
+    switch (d.p) {
+      case 1: mass ? launch_mf_copy<IGS_MASS, 1, T>(ip, d, crow, ncopy, bandw, xin, y, s) : launch_mf_copy<IGS_STIFFNESS, 1, T>(ip, d, crow, ncopy, bandw, xin, y, s); break;
+      case 2: mass ? launch_mf_copy<IGS_MASS, 2, T>(ip, d, crow, ncopy, bandw, xin, y, s) : launch_mf_copy<IGS_STIFFNESS, 2, T>(ip, d, crow, ncopy, bandw, xin, y, s); break;
+      case 3: mass ? launch_mf_copy<IGS_MASS, 3, T>(ip, d, crow, ncopy, bandw, xin, y, s) : launch_mf_copy<IGS_STIFFNESS, 3, T>(ip, d, crow, ncopy, bandw, xin, y, s); break;
+      default: mass ? launch_mf_copy<IGS_MASS, 4, T>(ip, d, crow, ncopy, bandw, xin, y, s) : launch_mf_copy<IGS_STIFFNESS, 4, T>(ip, d, crow, ncopy, bandw, xin, y, s); break;
+    }
+  }
+  {
+    PhaseTimer t("mf_stored_rows", s);
+    if (nbrow > 0)
+      hipLaunchKernelGGL((rows_spmv_kernel<T>), dim3((nbrow + 255) / 256, d.batch), dim3(256), 0, s, d.n, d.p, d.m[0],
+                         d.m[1], d.m[2], d.N, d.ld, d.S, brow, nbrow, band, xin, y, dirichlet);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_apply_mf<double>(const KInterp<double>&, int, const Dims&, const int*, int, int, int, int,
+                                            const int4*, const double*, const double*, const int*, int, const int*,
+                                            int, const double*, double*, double*, int, bool, hipStream_t);
+
+// rows outside the analysis domain, in flat order (the rows the matrix-free
+// apply multiplies from the band)
+std::vector<int> boundary_rows(const Dims& d) {
+  std::vector<int> out;
+  const int p = d.p;
+  for (int64_t i = 0; i < d.N; ++i) {
+    const int i1 = int(i % d.m[0]), i2 = int((i / d.m[0]) % d.m[1]);
+    const int i3 = d.n == 3 ? int(i / (int64_t(d.m[0]) * d.m[1])) : 2 * p;
+    const bool in = i1 >= 2 * p && i1 <= d.m[0] - 2 * p - 1 && i2 >= 2 * p && i2 <= d.m[1] - 2 * p - 1 &&
+                    (d.n == 2 || (i3 >= 2 * p && i3 <= d.m[2] - 2 * p - 1));
+    if (!in) out.push_back(int(i));
+  }
+  return out;
+}
 
 // analysis-domain rows within p-1 of the domain's edge in some direction: the
 // rows whose stencil reaches outside the analysis domain, in flat order

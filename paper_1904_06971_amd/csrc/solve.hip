@@ -17,6 +17,7 @@
 // partials, then one block in a fixed order): no floating-point atomics.
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <vector>
 
 #include "igs_internal.h"
@@ -924,6 +925,158 @@ igs_status solve_cg(const Dims& d, const double* band64, const float* band32, co
                     int maxit, igs_cg_info* info, hipStream_t s) {
   if (band32) return replace_cg(d, band64, band32, f, u, rtol, maxit, info, s);
   return refine_loop<double>(d, band64, band64, f, u, rtol, maxit, 0.0, info, s);
+}
+
+// ------------------------------------------------- matrix-free CG (FP64) --
+
+// r = f - q with r_D = 0; per-block partials of r^T r and f_I^T f_I
+__global__ void __launch_bounds__(kSpmvBlock)
+    mf_residual_kernel(SpmvGeom g, const double* __restrict__ f, const double* __restrict__ q, double* __restrict__ r,
+                       double* __restrict__ prr, double* __restrict__ pff) {
+  const int b = blockIdx.y;
+  const int64_t i = int64_t(blockIdx.x) * kSpmvBlock + threadIdx.x;
+  double vr = 0.0, vf = 0.0;
+  if (i < g.N) {
+    const size_t k = size_t(b) * g.N + i;
+    const bool dr = on_dirichlet(g, i);
+    const double fv = dr ? 0.0 : f[k];
+    const double rv = dr ? 0.0 : fv - q[k];
+    r[k] = rv;
+    vr = rv * rv;
+    vf = fv * fv;
+  }
+  vr = block_sum<double>(vr);
+  vf = block_sum<double>(vf);
+  if (threadIdx.x == 0) {
+    prr[size_t(b) * gridDim.x + blockIdx.x] = vr;
+    pff[size_t(b) * gridDim.x + blockIdx.x] = vf;
+  }
+}
+
+__global__ void copy_vec_kernel(int64_t total, const double* __restrict__ a, double* __restrict__ c) {
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x)
+    c[t] = a[t];
+}
+
+// Plain FP64 CG on A_II u_I = f_I with the operator given as a launcher
+// (A(x, y): y = A x with y_D = 0; x is zero on the Dirichlet dofs), the same
+// stopping rule as solve_cg: the recursive residual is followed, and at its
+// convergence the true residual f - A u decides (CG restarts from u if it is
+// not below rtol yet).
+igs_status solve_cg_op(const Dims& d, const std::function<igs_status(const double*, double*)>& A, const double* f,
+                       double* u, double rtol, int maxit, igs_cg_info* info, hipStream_t s) {
+  SpmvGeom g = make_geom(d);
+  const int nblk = int((d.N + kSpmvBlock - 1) / kSpmvBlock);
+  const int dblk = int(std::min<int64_t>((d.N + kRedBlock - 1) / kRedBlock, 1024));
+  const size_t NB = size_t(d.N) * d.batch, nb = size_t(d.batch);
+  Arena ar;
+  igs_status st = ar.alloc(3 * padded(sizeof(double) * NB) + 2 * padded(sizeof(double) * nb * nblk) +
+                               4 * padded(sizeof(double) * nb) + padded(sizeof(int) * nb) +
+                               padded(sizeof(CgScalars) * nb),
+                           s);
+  if (st != IGS_OK) return st;
+  double* r = ar.take<double>(NB);
+  double* p = ar.take<double>(NB);
+  double* q = ar.take<double>(NB);
+  double* part = ar.take<double>(nb * nblk);
+  double* part2 = ar.take<double>(nb * nblk);
+  double* rr = ar.take<double>(nb);
+  double* ff = ar.take<double>(nb);
+  double* tol2 = ar.take<double>(nb);
+  double* spare = ar.take<double>(nb);
+  (void)spare;
+  int* active = ar.take<int>(nb);
+  CgScalars* sc = ar.take<CgScalars>(nb);
+  hipLaunchKernelGGL(zero_dirichlet_kernel, dim3(grid_stride_blocks(NB)), dim3(256), 0, s, g, d.batch, u);
+  std::vector<double> hrr(nb), hff(nb), htol(nb);
+  std::vector<int> hact(nb);
+  std::vector<CgScalars> hsc(nb);
+  int iters = 0, restarts = 0;
+  double worst = 0.0;
+  igs_status result = IGS_NOT_CONVERGED;
+  while (true) {
+    // true residual
+    igs_status ast = A(u, q);
+    if (ast != IGS_OK) return ast;
+    hipLaunchKernelGGL(mf_residual_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, f, q, r, part, part2);
+    hipLaunchKernelGGL(reduce_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, part, nblk, rr);
+    hipLaunchKernelGGL(reduce_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, part2, nblk, ff);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(hrr.data(), rr, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(hff.data(), ff, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    bool all = true;
+    worst = 0.0;
+    for (size_t b = 0; b < nb; ++b) {
+      const double rel = hff[b] > 0.0 ? std::sqrt(hrr[b] / hff[b]) : 0.0;
+      if (!std::isfinite(rel)) {
+        info->relres = rel;
+        info->iterations = iters;
+        info->outer_iterations = restarts + 1;
+        info->status = IGS_BREAKDOWN;
+        return IGS_BREAKDOWN;
+      }
+      worst = std::max(worst, rel);
+      hact[b] = rel > rtol;
+      all &= !hact[b];
+      // the recursive residual is followed to half the target
+      htol[b] = 0.25 * rtol * rtol * hff[b];
+    }
+    if (all) {
+      result = IGS_OK;
+      break;
+    }
+    if (iters >= maxit || restarts >= 8) break;
+    HIP_OK(hipMemcpyAsync(tol2, htol.data(), sizeof(double) * nb, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(active, hact.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(cg_setup_kernel, dim3(1), dim3(64), 0, s, d.batch, rr, tol2, active, sc);
+    hipLaunchKernelGGL(copy_vec_kernel, dim3(grid_stride_blocks(NB)), dim3(256), 0, s, int64_t(NB), r, p);
+    HIP_OK(hipGetLastError());
+    int local = 0;
+    bool stop = false;
+    while (!stop) {
+      const int k = std::min(32, maxit - iters);
+      if (k <= 0) break;
+      for (int it = 0; it < k; ++it) {
+        ast = A(p, q);
+        if (ast != IGS_OK) return ast;
+        PhaseTimer t("cg_vector_ops", s);
+        hipLaunchKernelGGL((dot_kernel<double>), dim3(dblk, d.batch), dim3(kRedBlock), 0, s, d.N, p, q, part);
+        hipLaunchKernelGGL(cg_alpha_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, part, dblk, sc);
+        hipLaunchKernelGGL((cg_update_kernel<double>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, sc, p, q, u,
+                           r, part2);
+        hipLaunchKernelGGL(cg_beta_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, part2, nblk, sc);
+        hipLaunchKernelGGL((cg_pupdate_kernel<double>), dim3(std::min<int64_t>((d.N + 255) / 256, 4096), d.batch),
+                           dim3(256), 0, s, d.N, sc, r, p);
+      }
+      HIP_OK(hipGetLastError());
+      HIP_OK(hipMemcpyAsync(hsc.data(), sc, sizeof(CgScalars) * nb, hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      bool done = true, brk = false;
+      int mx = 0;
+      for (size_t b = 0; b < nb; ++b) {
+        done &= hsc[b].done != 0;
+        brk |= hsc[b].breakdown != 0;
+        mx = std::max(mx, hsc[b].iters);
+      }
+      iters += mx - local;
+      local = mx;
+      if (brk) {
+        info->relres = worst;
+        info->iterations = iters;
+        info->outer_iterations = restarts + 1;
+        info->status = IGS_BREAKDOWN;
+        return IGS_BREAKDOWN;
+      }
+      stop = done;
+    }
+    ++restarts;
+  }
+  info->relres = worst;
+  info->iterations = iters;
+  info->outer_iterations = restarts;
+  info->status = result;
+  return result;
 }
 
 }  // namespace igs

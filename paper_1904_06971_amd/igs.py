@@ -28,7 +28,8 @@ SRC_CONST, SRC_SINE = 0, 1
 EXPORTS = ["igs_band_layout", "igs_validate", "igs_surrogate_layout", "igs_sampling_length", "igs_status_string",
            "igs_version",
            "igs_assemble_exact", "igs_assemble_surrogate", "igs_assemble_noalloc", "igs_assemble_surrogate_fe",
-           "igs_surrogate_fe_layout", "igs_plan_create", "igs_plan_create_fe", "igs_plan_execute", "igs_plan_destroy",
+           "igs_surrogate_fe_layout", "igs_plan_create", "igs_plan_create_fe", "igs_plan_create_mf",
+           "igs_apply_mf", "igs_solve_cg_mf", "igs_plan_execute", "igs_plan_destroy",
            "igs_assemble_rhs", "igs_apply", "igs_solve_cg", "igs_apply_vjp", "igs_compliance_grad",
            "igs_profile_enable", "igs_profile_read"]
 
@@ -105,6 +106,9 @@ def lib():
             "igs_assemble_surrogate_fe": [P, i32, i32, i32, i32, vp, vp],
             "igs_surrogate_fe_layout": [P, i32, i32, ctypes.POINTER(FEInfo)],
             "igs_plan_create_fe": [P, i32, i32, i32, i32, vp, ctypes.POINTER(vp)],
+            "igs_plan_create_mf": [P, i32, i32, i32, vp, ctypes.POINTER(vp)],
+            "igs_apply_mf": [vp, vp, vp, vp, i32, vp],
+            "igs_solve_cg_mf": [vp, vp, vp, vp, f64, i32, ctypes.POINTER(CgInfo), vp],
             "igs_plan_create": [P, i32, i32, i32, i32, vp, ctypes.POINTER(vp)],
             "igs_plan_execute": [vp, vp, vp, vp],
             "igs_plan_destroy": [vp],
@@ -312,7 +316,8 @@ class Plan:
     torch's current stream; the first call synchronises and checks the
     geometry, later calls only queue."""
 
-    def __init__(self, prob, form=STIFFNESS, M=8, q=3, dtype=None, device="cuda", face_edge=False):
+    def __init__(self, prob, form=STIFFNESS, M=8, q=3, dtype=None, device="cuda", face_edge=False,
+                 matrix_free=False):
         torch = _torch()
         self.prob = prob
         self.tdt, self.cdt = _dt(dtype if dtype is not None else torch.float64)
@@ -320,9 +325,13 @@ class Plan:
         self._cc = _coef_tensor(prob, device)
         pb = make_problem(prob, None if self._cc is None else self._cc.data_ptr())
         h = ctypes.c_void_p()
-        create = lib().igs_plan_create_fe if face_edge else lib().igs_plan_create
-        _check(create(ctypes.byref(pb), form, M, q, self.cdt, _stream(), ctypes.byref(h)),
-               "igs_plan_create_fe" if face_edge else "igs_plan_create")
+        if matrix_free:
+            _check(lib().igs_plan_create_mf(ctypes.byref(pb), form, M, q, _stream(), ctypes.byref(h)),
+                   "igs_plan_create_mf")
+        else:
+            create = lib().igs_plan_create_fe if face_edge else lib().igs_plan_create
+            _check(create(ctypes.byref(pb), form, M, q, self.cdt, _stream(), ctypes.byref(h)),
+                   "igs_plan_create_fe" if face_edge else "igs_plan_create")
         self._h = h
 
     def execute(self, out=None, coef=None):
@@ -337,6 +346,26 @@ class Plan:
             cp = coef.data_ptr()
         _check(lib().igs_plan_execute(self._h, cp, band.data_ptr(), _stream()), "igs_plan_execute")
         return band
+
+    def apply(self, band, x, dirichlet=False, out=None):
+        """Matrix-free plans: y = A~ x (igs_apply_mf) with the band of the last
+        execute()."""
+        y = out if out is not None else _torch().empty_like(x)
+        _check(lib().igs_apply_mf(self._h, band.data_ptr(), x.data_ptr(), y.data_ptr(), int(bool(dirichlet)),
+                                  _stream()), "igs_apply_mf")
+        return y
+
+    def solve_cg(self, band, f, u0=None, rtol=1e-10, maxit=100000, check=True):
+        """Matrix-free plans: FP64 CG with igs_apply_mf (igs_solve_cg_mf)."""
+        torch = _torch()
+        u = torch.zeros_like(f) if u0 is None else u0.clone()
+        info = CgInfo()
+        st = lib().igs_solve_cg_mf(self._h, band.data_ptr(), f.data_ptr(), u.data_ptr(), rtol, maxit,
+                                   ctypes.byref(info), _stream())
+        if check and st < 0:
+            _check(st, "igs_solve_cg_mf")
+        return u, {"iterations": info.iterations, "outer_iterations": info.outer_iterations, "status": info.status,
+                   "relres": info.relres}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value is not None:
