@@ -324,6 +324,46 @@ def main():
         b32_err = float((b32.double() - band).abs().max() / band.abs().max())
         extra["fp32_band_max_rel_err"] = b32_err
         log(f"cg: {extra['cg']}")
+        # matrix-free operator (analysis-domain rows evaluated from the spline
+        # coefficients in every product; the band holds only the quadrature rows)
+        pmf = igs.Plan(prob, igs.STIFFNESS, M=M, q=q, matrix_free=True)
+        ms_mfa, ph_mfa = timed_plan(pmf, band, stream, args.steps)
+        ymf = torch.empty_like(x)
+        pmf.apply(band, x, dirichlet=True, out=ymf)
+        torch.cuda.synchronize()
+        igs.profile_enable(True)
+        igs.profile_read()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(10):
+            pmf.apply(band, x, dirichlet=True, out=ymf)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pr_mf = igs.profile_read()
+        igs.profile_enable(False)
+        ms_mf = e0.elapsed_time(e1) / 10
+        t0 = time.perf_counter()
+        umf, imf = pmf.solve_cg(band, f, rtol=1e-10, maxit=20000)
+        torch.cuda.synchronize()
+        tcmf = time.perf_counter() - t0
+        dmf = float((umf - u64).abs().max() / u64.abs().max())
+        pmf.close()
+        stored = info.boundary_rows * lay.slots * 8
+        dom_rows = lay.N - info.boundary_rows
+        flops_mf = dom_rows * lay.slots * (2 * 3 * (q + 1) + 2)
+        t_dom = pr_mf["mf_domain_rows"][1] / pr_mf["mf_domain_rows"][0] * 1e-3
+        extra["matrix_free"] = {
+            "assembly_ms": ms_mfa, "assembly_phases_ms": ph_mfa, "apply_ms": ms_mf,
+            "apply_phases_ms": {k: v[1] / v[0] for k, v in pr_mf.items()},
+            "banded_apply_ms": t64 * 1e3, "band_bytes_read_per_apply": stored,
+            "banded_bytes_read_per_apply": lay.slots * lay.N * 8,
+            "domain_rows_roofline": {"bound": "alu", "achieved": flops_mf / t_dom / 1e12, "peak": FP64_PEAK_TFLOPS,
+                                     "unit": "TFLOP/s", "frac": flops_mf / t_dom / 1e12 / FP64_PEAK_TFLOPS,
+                                     "units": f"{dom_rows} rows x {lay.slots} entries x (2 n (q+1) + 2) flop"},
+            "cg_ms": tcmf * 1e3, "cg_iterations": imf["iterations"], "cg_relres": imf["relres"],
+            "cg_vs_banded_f64_max_rel_diff": dmf, "banded_cg_ms": tc64 * 1e3}
+        log(f"matrix-free: {extra['matrix_free']}")
+        del ymf, umf
         del b32, x, x32, y64, y32
 
         # ---------------------------------------- batched 2D compliance + adjoint
