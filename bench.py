@@ -34,14 +34,21 @@ FP64_PEAK_TFLOPS = 78.6
 # HBM bytes per launch of this workload's kernels from rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch), scaled by what the same
 # counters give for a plain 2^30-byte elementwise copy (FETCH 2.00, WRITE 1.00);
-# profiles/surrogate_3d_p3_128_hbm_counters.md holds the runs.  A figure is only
-# reported while the kernel source still hashes to the one measured.
+# profiles/*_hbm_counters.md hold the runs (keys: phase names of the domain
+# surrogate step, fe_* of the face/edge step, mf_* of the matrix-free apply).
+# A figure is only reported while the kernel sources still hash to the ones
+# measured.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.00, 1.00
 PMC_TRAFFIC = {
-    "quad_boundary_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "d68c6f6080794b15", "fetch_kib": 13910.4,
-                           "write_kib": 2097916.6},
-    "fill": {"sources": ["fill.hip"], "sha256": "6116744f722c5260", "fetch_kib": 153945.6, "write_kib": 4971999.7},
-    "copy": {"sources": ["fill.hip"], "sha256": "6116744f722c5260", "fetch_kib": 360713.4, "write_kib": 301085.9},
+    "quad_boundary_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "5cd0866b048f2900", "fetch_kib": 14046.9, "write_kib": 2097916.6},
+    "fill": {"sources": ["fill.hip"], "sha256": "f24ac6f0d20cb229", "fetch_kib": 150886.0, "write_kib": 4971999.6},
+    "copy": {"sources": ["fill.hip"], "sha256": "f24ac6f0d20cb229", "fetch_kib": 360709.9, "write_kib": 301085.9},
+    "fe_fill": {"sources": ["fill.hip", "plan.cpp"], "sha256": "31819ce7c11dd2c3", "fetch_kib": 951513.8, "write_kib": 6024184.7},
+    "fe_quad_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "5cd0866b048f2900", "fetch_kib": 1503.4, "write_kib": 117649.0},
+    "fe_quad_tiles": {"sources": ["quad.hip", "plan.cpp"], "sha256": "5cd0866b048f2900", "fetch_kib": 661.6, "write_kib": 39873.8},
+    "mf_domain_rows": {"sources": ["fill.hip"], "sha256": "f24ac6f0d20cb229", "fetch_kib": 116716.2, "write_kib": 13497.2},
+    "mf_copied_entries": {"sources": ["fill.hip"], "sha256": "f24ac6f0d20cb229", "fetch_kib": 396897.5, "write_kib": 2612.8},
+    "mf_stored_rows": {"sources": ["fill.hip"], "sha256": "f24ac6f0d20cb229", "fetch_kib": 1080584.2, "write_kib": 4837.5},
 }
 
 
@@ -102,6 +109,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="only the timed step (for profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (reference kernel for HBM byte counters)")
+    ap.add_argument("--leg", choices=["face_edge", "matrix_free"], default=None,
+                    help="only run one other leg's timed steps on the same workload (for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path is single-GPU in this build (sharding is described in the "
@@ -126,6 +135,9 @@ def main():
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 1 << 30, "kernel": "neg (elementwise)", "launches": 3}), flush=True)
+        return
+    if args.leg:
+        profile_leg(args)
         return
     prob = W.c4_precision3d()
     M, q = 8, 3
@@ -252,6 +264,13 @@ def main():
                    "step_hbm_frac": slots * esize / (ms_fe * 1e-3) / 1e9 / HBM_PEAK_GBS,
                    "fill_hbm_frac": slots * esize / (ph_fe["fill"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
             if name == "f64":
+                # the fill writes every slot of every row once (the whole band)
+                tf = ph_fe["fill"] * 1e-3
+                leg["roofline_fill"] = {"bound": "hbm", "achieved": slots * 8 / tf / 1e9, "peak": HBM_PEAK_GBS,
+                                        "unit": "GB/s", "frac": slots * 8 / tf / 1e9 / HBM_PEAK_GBS,
+                                        "traffic": measured_traffic("fe_fill"), "ms": ph_fe["fill"],
+                                        "units": f"{lay.N} rows x {lay.slots} slots x 8 bytes"}
+            if name == "f64":
                 leg["speedup_vs_domain_surrogate"] = ms_step / ms_fe
                 leg["speedup_vs_exact"] = ms_ex / ms_fe
             fe[name] = leg
@@ -360,6 +379,8 @@ def main():
             "domain_rows_roofline": {"bound": "alu", "achieved": flops_mf / t_dom / 1e12, "peak": FP64_PEAK_TFLOPS,
                                      "unit": "TFLOP/s", "frac": flops_mf / t_dom / 1e12 / FP64_PEAK_TFLOPS,
                                      "units": f"{dom_rows} rows x {lay.slots} entries x (2 n (q+1) + 2) flop"},
+            "traffic_per_apply": {k: measured_traffic(k) for k in ("mf_domain_rows", "mf_copied_entries",
+                                                                   "mf_stored_rows")},
             "cg_ms": tcmf * 1e3, "cg_iterations": imf["iterations"], "cg_relres": imf["relres"],
             "cg_vs_banded_f64_max_rel_diff": dmf, "banded_cg_ms": tc64 * 1e3}
         log(f"matrix-free: {extra['matrix_free']}")
@@ -475,6 +496,47 @@ def main():
         **extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def profile_leg(args):
+    """Only the timed steps of one leg on the 3D p=3 128^3 workload (M = 8,
+    q = 3): the face/edge surrogate assembly (kept plan), or the matrix-free
+    apply (its plan executed once, then the products).  Prints one JSON line."""
+    import torch
+
+    from paper_1904_06971_amd import igs
+    from paper_1904_06971_amd import workloads as W
+
+    prob = W.c4_precision3d()
+    lay = igs.layout(prob)
+    band = igs.empty_band(prob, torch.float64)
+    stream = torch.cuda.current_stream()
+    if args.leg == "face_edge":
+        pl = igs.Plan(prob, igs.STIFFNESS, M=8, q=3, face_edge=True)
+        for _ in range(max(1, args.warmup)):
+            pl.execute(out=band)
+        ms, ph = timed_plan(pl, band, stream, args.steps)
+    else:
+        pl = igs.Plan(prob, igs.STIFFNESS, M=8, q=3, matrix_free=True)
+        pl.execute(out=band)
+        x = torch.as_tensor(W.random_vector(lay.N, 33), device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(max(1, args.warmup)):
+            pl.apply(band, x, dirichlet=True, out=y)
+        torch.cuda.synchronize()
+        igs.profile_enable(True)
+        igs.profile_read()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            pl.apply(band, x, dirichlet=True, out=y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pr = igs.profile_read()
+        igs.profile_enable(False)
+        ms, ph = e0.elapsed_time(e1) / args.steps, {k: v[1] / v[0] for k, v in pr.items()}
+    pl.close()
+    print(json.dumps({"leg": args.leg, "ms": ms, "phases_ms": ph, "steps": args.steps}), flush=True)
 
 
 def timed_plan(plan, band, stream, reps):
