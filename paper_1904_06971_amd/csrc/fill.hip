@@ -733,11 +733,15 @@ __global__ void __launch_bounds__(64 * kCopyWaves)
 // sum_s band[s][i] x_{i+delta_s} from the stored rows; Dirichlet rows give 0
 // when dirichlet is set (x is then already zero on the Dirichlet dofs).  One
 // row per thread: consecutive threads read consecutive entries of a slot.
+// Workgroups are dealt round-robin to the 8 XCDs; XCD x takes a contiguous
+// range of the list, so the x planes its rows touch stay in its L2.
 template <typename T>
 __global__ void __launch_bounds__(256)
     rows_spmv_kernel(int n, int P, int m1, int m2, int m3, int64_t N, int64_t ld, int S, const int* __restrict__ rows,
                      int nrows, const T* __restrict__ band, const T* __restrict__ x, T* __restrict__ y, int dirichlet) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int nb = gridDim.x, per = nb / 8;
+  const int bid = (per == 0 || int(blockIdx.x) >= per * 8) ? int(blockIdx.x) : int(blockIdx.x % 8) * per + int(blockIdx.x / 8);
+  const int t = bid * 256 + threadIdx.x;
   if (t >= nrows) return;
   const int b = blockIdx.y;
   const int64_t i = rows[t];

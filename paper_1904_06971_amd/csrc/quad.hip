@@ -862,9 +862,18 @@ __global__ void __launch_bounds__(256)
   const int E3a = max(0, i3 - P), E3b = min(nel3 - 1, i3);
   const int nq1 = (E1b - E1a + 1) * NQ, nq2 = (E2b - E2a + 1) * NQ;
 
-  // stage-2/3 identity: column (delta1, delta2)
-  const int d1 = tid % W, d2 = tid / W;
-  const bool active = tid < W * W;
+  // stage-2/3 identity: column (delta1, delta2) and element group.  The
+  // waves split the direction-2 elements of the row's support (element a2
+  // goes to group a2 mod G, a group being one wave, two for p = 4), so every
+  // wave has stage-2 work; stage 3 is linear in the stage-2 sums, so each group
+  // accumulates its own partial stencil, and the groups' partials are added
+  // (in group order) once, after the last plane.
+  constexpr int NCOL = W * W, WPG = (NCOL + 63) / 64;
+  constexpr int G = (P + 1) < (C::BLOCK / 64) / WPG ? (P + 1) : (C::BLOCK / 64) / WPG;
+  const int grp = wave / WPG;
+  const int col = tid - grp * WPG * 64;
+  const bool active = grp < G && col < NCOL;
+  const int d1 = col % W, d2 = col / W;
   const int j2 = i2 + d2 - P;
   double acc[W];
 #pragma unroll
@@ -918,6 +927,7 @@ __global__ void __launch_bounds__(256)
       double Z00 = 0.0, Z10 = 0.0, Z01 = 0.0, Z11 = 0.0;
 #pragma unroll
       for (int a2 = 0; a2 <= P; ++a2) {
+        if (a2 % G != grp) continue;
         const int e2 = i2 - a2;
         const int b2 = j2 - e2;
         if (e2 < 0 || e2 >= nel2 || b2 < 0 || b2 > P) continue;
@@ -959,7 +969,21 @@ __global__ void __launch_bounds__(256)
     if (g3 < glast) phase_a(g3 + 1);
     __syncthreads();
   }
-  if (active) {
+  // the groups' partial stencils meet in LDS (the point buffer Cs, free after
+  // the last barrier of the plane loop, when it is large enough: stiffness),
+  // added in group order by group 0
+  constexpr bool IN_CS = G * NCOL * W <= C::NC * C::CS;
+  __shared__ double Rx[IN_CS ? 1 : G * NCOL * W];
+  double* red = IN_CS ? Cs : Rx;
+  if (active && grp > 0) {
+#pragma unroll
+    for (int d = 0; d < W; ++d) red[(size_t(grp) * NCOL + col) * W + d] = acc[d];
+  }
+  __syncthreads();
+  if (active && grp == 0) {
+    for (int g = 1; g < G; ++g)
+#pragma unroll
+      for (int d = 0; d < W; ++d) acc[d] += red[(size_t(g) * NCOL + col) * W + d];
     const size_t idx = size_t(i1) + size_t(kp.m[0]) * (i2 + size_t(kp.m[1]) * i3);
 #pragma unroll
     for (int d3 = 0; d3 < W; ++d3) out[size_t(d1 + W * (d2 + W * d3)) * kp.ld + idx] = static_cast<OutT>(acc[d3]);
