@@ -846,6 +846,10 @@ static igs_status vjp(const igs_problem* pb, int M, int q, const double* band64,
       ip.eb[k] = up(wa, hi.eb[k], s, &st);
       ip.ginv[k] = up(wa, gT[k], s, &st);
     }
+    for (int k = 0; k < 3; ++k) {  // the spline block spans the whole sample set
+      ip.flo[k] = hi.flo[k];
+      ip.fhi[k] = hi.fhi[k];
+    }
     ip.Sd[2] = 1;
     ip.nup = nup;
     ip.upslot = up(wa, hi.upslot, s, &st);
@@ -1036,6 +1040,8 @@ static igs_status vjp3(const igs_problem* pb, const Dims& d, const KProblem& kp,
       ip.ef[k] = up(wa, hi.ef[k], s, &st);
       ip.eb[k] = up(wa, hi.eb[k], s, &st);
       ip.ginv[k] = up(wa, gT[k], s, &st);
+      ip.flo[k] = hi.flo[k];  // the spline block spans the whole sample set
+      ip.fhi[k] = hi.fhi[k];
     }
     ip.nup = nup;
     ip.upslot = up(wa, hi.upslot, s, &st);
