@@ -433,11 +433,23 @@ static igs_status run_t(const Plan& pl, const KProblem& kp, const KInterp<OutT>&
                                 pl.coef, band, s));
     }
     {
+      // 3-D: the boundary rows also store each entry whose partner is an
+      // analysis-domain row into that row (its copied exact entry)
+      KProblem kt = kp;
+      if (d.n == 3) {
+        kt.transpose = 1;
+        for (int k = 0; k < 3; ++k) {
+          kt.tr_lo[k] = 2 * d.p;
+          kt.tr_hi[k] = d.m[k] - 2 * d.p - 1;
+        }
+      }
       PhaseTimer t("quad_boundary_rows", s);
-      HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt, pl.groups[0] + pl.groups[1], false, band, s));
+      HIP_TRY(launch_quad<OutT>(kt, pl.form, pl.dt, pl.groups[0] + pl.groups[1], false, band, s));
     }
-    {
-      PhaseTimer t("copy", s);
+    if (pl.ncopy > 0 && (d.n == 2 || pl.form == IGS_STIFFNESS)) {
+      // 2-D: copies of the exact partner entries; 3-D stiffness: their sum
+      // leaves the diagonal of the rows next to the domain's edge
+      PhaseTimer t(d.n == 3 ? "diag_fixup" : "copy", s);
       HIP_TRY(launch_copy<OutT>(ipT, pl.form, d, pl.dcopy, pl.ncopy, band, s));
     }
   }

@@ -660,7 +660,11 @@ constexpr int kCopyWaves = 4;
 // adds sum_j A_ij (x_j - x_i) over them to y_i (stiffness: the diagonal loses
 // them), or sum_j A_ij x_j (mass).  Runs after the evaluation of the domain
 // rows (fill_fast_kernel with APPLY), which wrote y_i.
-template <int ND, int FORM, int P, typename T, bool APPLY = false>
+// FIXUP = true (3-D stiffness, after boundary quadrature with transposed
+// stores): the copied entries are already in place in the row's own slots;
+// the row only subtracts them from its diagonal, reading its own entries
+// (consecutive rows, coalesced) instead of its partners'.
+template <int ND, int FORM, int P, typename T, bool APPLY = false, bool FIXUP = false>
 __global__ void __launch_bounds__(64 * kCopyWaves)
     copy_kernel(KInterp<T> ip, int m1, int m2, int64_t ld, int S, const int* __restrict__ rows, int nrows,
                 T* __restrict__ band, const T* __restrict__ x = nullptr, T* __restrict__ y = nullptr, int64_t N = 0) {
@@ -690,14 +694,16 @@ __global__ void __launch_bounds__(64 * kCopyWaves)
 #pragma unroll
     for (int k = 0; k < W; ++k) {
       v[k] = T(0);
-      if (om >> k & 1) v[k] = bnd[Sm1ld - size_t(s0 + k) * ld + size_t(i + off0 + (k - P))];
+      if (om >> k & 1)
+        v[k] = FIXUP ? bnd[size_t(s0 + k) * ld + size_t(i)]
+                     : bnd[Sm1ld - size_t(s0 + k) * ld + size_t(i + off0 + (k - P))];
     }
 #pragma unroll
     for (int k = 0; k < W; ++k)
       if (om >> k & 1) {
         if constexpr (APPLY)
           xsum += v[k] * xb[i + off0 + (k - P)];
-        else
+        else if constexpr (!FIXUP)
           bnd[size_t(s0 + k) * ld + size_t(i)] = v[k];
         csum += v[k];
       }
@@ -1144,26 +1150,33 @@ std::vector<int> copy_rows(const Dims& d) {
   return out;
 }
 
-template <int ND, int FORM, typename T>
-static void launch_copy_p(const KInterp<T>& ip, const Dims& d, const int* rows, int nrows, T* band, hipStream_t s) {
+template <int ND, int FORM, int P, typename T, bool FIXUP>
+static void launch_copy_pp(const KInterp<T>& ip, const Dims& d, const int* rows, int nrows, T* band, hipStream_t s) {
   dim3 grid((nrows + 63) / 64, d.batch);
+  hipLaunchKernelGGL((copy_kernel<ND, FORM, P, T, false, FIXUP>), grid, dim3(64 * kCopyWaves), 0, s, ip, d.m[0],
+                     d.m[1], d.ld, d.S, rows, nrows, band, static_cast<const T*>(nullptr), static_cast<T*>(nullptr),
+                     int64_t(0));
+}
+
+template <int ND, int FORM, typename T, bool FIXUP = false>
+static void launch_copy_p(const KInterp<T>& ip, const Dims& d, const int* rows, int nrows, T* band, hipStream_t s) {
   switch (d.p) {
-    case 1: hipLaunchKernelGGL((copy_kernel<ND, FORM, 1, T>), grid, dim3(64 * kCopyWaves), 0, s, ip, d.m[0], d.m[1], d.ld, d.S, rows, nrows, band); break;
-    case 2: hipLaunchKernelGGL((copy_kernel<ND, FORM, 2, T>), grid, dim3(64 * kCopyWaves), 0, s, ip, d.m[0], d.m[1], d.ld, d.S, rows, nrows, band); break;
-    case 3: hipLaunchKernelGGL((copy_kernel<ND, FORM, 3, T>), grid, dim3(64 * kCopyWaves), 0, s, ip, d.m[0], d.m[1], d.ld, d.S, rows, nrows, band); break;
-    default: hipLaunchKernelGGL((copy_kernel<ND, FORM, 4, T>), grid, dim3(64 * kCopyWaves), 0, s, ip, d.m[0], d.m[1], d.ld, d.S, rows, nrows, band); break;
+    case 1: launch_copy_pp<ND, FORM, 1, T, FIXUP>(ip, d, rows, nrows, band, s); break;
+    case 2: launch_copy_pp<ND, FORM, 2, T, FIXUP>(ip, d, rows, nrows, band, s); break;
+    case 3: launch_copy_pp<ND, FORM, 3, T, FIXUP>(ip, d, rows, nrows, band, s); break;
+    default: launch_copy_pp<ND, FORM, 4, T, FIXUP>(ip, d, rows, nrows, band, s); break;
   }
 }
 
+// 3-D: the boundary-row quadrature has stored the copied entries (transposed
+// stores, KProblem::transpose), so only the stiffness diagonal is fixed up.
+// 2-D: the copy kernel proper.
 template <typename T>
 hipError_t launch_copy(const KInterp<T>& ip, int form, const Dims& d, const int* rows, int nrows, T* band,
                        hipStream_t s) {
   if (nrows == 0) return hipSuccess;
   if (d.n == 3) {
-    if (form == IGS_MASS)
-      launch_copy_p<3, IGS_MASS, T>(ip, d, rows, nrows, band, s);
-    else
-      launch_copy_p<3, IGS_STIFFNESS, T>(ip, d, rows, nrows, band, s);
+    if (form == IGS_STIFFNESS) launch_copy_p<3, IGS_STIFFNESS, T, true>(ip, d, rows, nrows, band, s);
   } else {
     if (form == IGS_MASS)
       launch_copy_p<2, IGS_MASS, T>(ip, d, rows, nrows, band, s);

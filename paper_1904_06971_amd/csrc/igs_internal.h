@@ -48,6 +48,11 @@ struct KProblem {
   const double* cc;      // control values [batch][cstride]
   Tab1D t[3];
   int* flag;             // device error word: bit 0 = det J <= 0
+  // 3-D tile kernels with transpose != 0 also store every entry A_ij whose
+  // partner j lies in the box [tr_lo, tr_hi]^3 as A_ji into row j (slot -delta):
+  // the exact entries the analysis-domain rows take from rows outside it
+  int transpose;
+  int tr_lo[3], tr_hi[3];
 };
 
 // One tile of rows for the quadrature kernels.

@@ -316,6 +316,8 @@ __global__ void __launch_bounds__((Q3<P, FORM>::BLOCK))
   const int Elo = max(0, tile.z0 - P), Ehi = min(nel3 - 1, tile.z1 - 1);
   __syncthreads();
 
+  const bool tr12 = kp.transpose && i1 + d1 - P >= kp.tr_lo[0] && i1 + d1 - P <= kp.tr_hi[0] && j2 >= kp.tr_lo[1] &&
+                    j2 <= kp.tr_hi[1];
   auto write_row = [&](int i3, int slot_unused, const double* row) {
     (void)slot_unused;
     if (active && i3 >= tile.z0 && i3 < tile.z1) {
@@ -324,6 +326,12 @@ __global__ void __launch_bounds__((Q3<P, FORM>::BLOCK))
       for (int d3 = 0; d3 < W; ++d3) {
         const int s = d1 + W * (d2 + W * d3);
         out[size_t(s) * kp.ld + idx] = static_cast<OutT>(row[d3]);
+        // transposed store into an analysis-domain partner (kp.transpose)
+        const int j3 = i3 + d3 - P;
+        if (tr12 && j3 >= kp.tr_lo[2] && j3 <= kp.tr_hi[2]) {
+          const int64_t j = int64_t(idx) + (d1 - P) + int64_t(kp.m[0]) * (d2 - P) + int64_t(plane) * (d3 - P);
+          out[size_t(kp.S - 1 - s) * kp.ld + size_t(j)] = static_cast<OutT>(row[d3]);
+        }
       }
     }
   };
@@ -710,9 +718,16 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
         stage1_b<P, FORM, S1_VD>(kp, Cs, Ysd, tile.i1 + rr1, rr1, E1a, nq2, lane);
     }
   };
+  // transposed stores (kp.transpose): partner j = i + delta inside the box
+  // [tr_lo, tr_hi]^3 takes A_ij as its entry at slot -delta; in directions 1
+  // and 2 the test is fixed per thread, in direction 3 per delta3
+  const bool tr12 = kp.transpose && i1 + d1 - P >= kp.tr_lo[0] && i1 + d1 - P <= kp.tr_hi[0] &&
+                    i2 + d2 - P >= kp.tr_lo[1] && i2 + d2 - P <= kp.tr_hi[1];
+  const int64_t troff = int64_t(d1 - P) + int64_t(kp.m[0]) * (d2 - P);
   auto store_row = [&](int i3, int a) {
     if (active && i3 >= tile.z0 && i3 < tile.z1) {
       OutT* p = colp + plane * i3;
+      const size_t irow = size_t(i1) + size_t(kp.m[0]) * i2 + plane * i3;
 #pragma unroll
       for (int d3 = 0; d3 < W; ++d3) {
         // entries beyond the triangle belong to partners past the last function: zero
@@ -722,6 +737,12 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
           if (A == a && d3 <= W - 1 - A) v = acc[A][d3];
         });
         p[d3 * sstride] = static_cast<OutT>(v);
+        const int j3 = i3 + d3 - P;
+        if (tr12 && j3 >= kp.tr_lo[2] && j3 <= kp.tr_hi[2]) {
+          const int s = d1 + W * (d2 + W * d3);
+          out[size_t(kp.S - 1 - s) * kp.ld + size_t(int64_t(irow) + troff + int64_t(plane) * (d3 - P))] =
+              static_cast<OutT>(v);
+        }
       }
     }
   };
