@@ -156,8 +156,10 @@ __device__ __forceinline__ double kappa_at(const KProblem& kp, int b, const int*
     case IGS_COEF_SINE3: {
       double F[ND];
       phys_point<ND>(kp, g, xi, F);
-      double v = sin(2.0 * M_PI * F[0]) * cos(2.0 * M_PI * F[1]);
-      if constexpr (ND == 3) v *= sin(2.0 * M_PI * F[2]);
+      // sin(2 pi x) as sinpi(2x): a reduction without the large-argument
+      // path (no private-memory table) and no rounding of 2 pi x
+      double v = sinpi(2.0 * F[0]) * cospi(2.0 * F[1]);
+      if constexpr (ND == 3) v *= sinpi(2.0 * F[2]);
       return kp.c0 + kp.camp * v;
     }
     case IGS_COEF_SPLINE:
@@ -221,257 +223,6 @@ __device__ __forceinline__ void point_data(const KProblem& kp, int b, const int*
   }
 }
 
-// ------------------------------------------------------------ 3-D rows -----
-
-template <int P>
-struct Q3Shape;
-template <> struct Q3Shape<1> { static constexpr int TX = 16, TY = 4; };
-template <> struct Q3Shape<2> { static constexpr int TX = 8, TY = 4; };
-template <> struct Q3Shape<3> { static constexpr int TX = 8, TY = 2; };
-template <> struct Q3Shape<4> { static constexpr int TX = 4, TY = 2; };
-
-template <int P, int FORM>
-struct Q3 {
-  static constexpr int NQ = P + 1, W = 2 * P + 1;
-  static constexpr int TX = Q3Shape<P>::TX, TY = Q3Shape<P>::TY;
-  static constexpr int NQ1 = (TX + P) * NQ, NQ2 = (TY + P) * NQ;
-  static constexpr int YS = NQ2 | 1;  // odd row stride of Ys: lanes on different rows hit different banks
-  static constexpr int NC = FORM == IGS_STIFFNESS ? 6 : 1;
-  static constexpr int NY = FORM == IGS_STIFFNESS ? 8 : 1;
-  static constexpr int NCOMBO = TX * W * TY * W;
-  static constexpr int BLOCK = (NCOMBO + 63) / 64 * 64;
-};
-
-// Stage-1 product for one output: y[delta1] = sum_{q1} b^A_{i1}(q1) b^B_{j1}(q1) C(q1)
-template <int P, int A, int B, int NQ1, int NQ2>
-__device__ __forceinline__ void stage1_3d(const double (*Cc)[NQ2], const double (*Tv)[NQ1],
-                                          const double (*Td)[NQ1], int i1, int E1a, int nelem1, int l2,
-                                          double* y) {
-  constexpr int NQ = P + 1, W = 2 * P + 1;
-#pragma unroll
-  for (int d = 0; d < W; ++d) y[d] = 0.0;
-#pragma unroll
-  for (int a = 0; a <= P; ++a) {
-    const int e1 = i1 - a;
-    if (e1 < 0 || e1 >= nelem1) continue;
-    const int le = (e1 - E1a) * NQ;
-#pragma unroll
-    for (int k1 = 0; k1 < NQ; ++k1) {
-      const int l1 = le + k1;
-      const double ci = (A ? Td[a][l1] : Tv[a][l1]) * Cc[l1][l2];
-#pragma unroll
-      for (int bb = 0; bb <= P; ++bb) y[bb - a + P] += ci * (B ? Td[bb][l1] : Tv[bb][l1]);
-    }
-  }
-}
-
-template <int P, int FORM, typename OutT>
-__global__ void __launch_bounds__((Q3<P, FORM>::BLOCK))
-    quad3d_kernel(KProblem kp, const QTile* __restrict__ tiles, OutT* __restrict__ band) {
-  using C = Q3<P, FORM>;
-  constexpr int NQ = C::NQ, W = C::W, TX = C::TX, TY = C::TY, NQ1 = C::NQ1, NQ2 = C::NQ2;
-  constexpr int YS = C::YS;
-  __shared__ double Cs[C::NC][NQ1][NQ2];
-  __shared__ double Ys[C::NY][TX * W][YS];
-  __shared__ double T1v[P + 1][NQ1], T1d[P + 1][NQ1], T2v[P + 1][NQ2], T2d[P + 1][NQ2];
-
-  const QTile tile = tiles[blockIdx.x];
-  const int b = blockIdx.y;
-  OutT* out = band + size_t(b) * kp.S * kp.ld;
-  const int tid = threadIdx.x;
-  const int nel1 = kp.nelem[0], nel2 = kp.nelem[1], nel3 = kp.nelem[2];
-  const int E1a = max(0, tile.i1 - P), E1b = min(nel1 - 1, tile.i1 + tile.nx - 1);
-  const int E2a = max(0, tile.i2 - P), E2b = min(nel2 - 1, tile.i2 + tile.ny - 1);
-  const int nq1 = (E1b - E1a + 1) * NQ, nq2 = (E2b - E2a + 1) * NQ;
-
-  for (int t = tid; t < nq1 * (P + 1); t += C::BLOCK) {
-    T1v[t % (P + 1)][t / (P + 1)] = kp.t[0].bv[size_t(E1a) * NQ * (P + 1) + t];
-    T1d[t % (P + 1)][t / (P + 1)] = kp.t[0].bd[size_t(E1a) * NQ * (P + 1) + t];
-  }
-  for (int t = tid; t < nq2 * (P + 1); t += C::BLOCK) {
-    T2v[t % (P + 1)][t / (P + 1)] = kp.t[1].bv[size_t(E2a) * NQ * (P + 1) + t];
-    T2d[t % (P + 1)][t / (P + 1)] = kp.t[1].bd[size_t(E2a) * NQ * (P + 1) + t];
-  }
-
-  // this thread's (i1, delta1, i2, delta2) combination; i1 fastest for
-  // contiguous stores
-  const int r1 = tid % TX;
-  int rest = tid / TX;
-  const int r2 = rest % TY;
-  rest /= TY;
-  const int d1 = rest % W;
-  const int d2 = rest / W;
-  const bool active = tid < C::NCOMBO && r1 < tile.nx && r2 < tile.ny;
-  const int i1 = tile.i1 + r1, i2 = tile.i2 + r2;
-  const int j2 = i2 + d2 - P;
-  const size_t rowbase = size_t(i1) + size_t(kp.m[0]) * i2;
-  const size_t plane = size_t(kp.m[0]) * kp.m[1];
-
-  double acc[P + 1][W];
-#pragma unroll
-  for (int s = 0; s < P + 1; ++s)
-#pragma unroll
-    for (int d = 0; d < W; ++d) acc[s][d] = 0.0;
-
-  const int Elo = max(0, tile.z0 - P), Ehi = min(nel3 - 1, tile.z1 - 1);
-  __syncthreads();
-
-  const bool tr12 = kp.transpose && i1 + d1 - P >= kp.tr_lo[0] && i1 + d1 - P <= kp.tr_hi[0] && j2 >= kp.tr_lo[1] &&
-                    j2 <= kp.tr_hi[1];
-  auto write_row = [&](int i3, int slot_unused, const double* row) {
-    (void)slot_unused;
-    if (active && i3 >= tile.z0 && i3 < tile.z1) {
-      const size_t idx = rowbase + plane * i3;
-#pragma unroll
-      for (int d3 = 0; d3 < W; ++d3) {
-        const int s = d1 + W * (d2 + W * d3);
-        out[size_t(s) * kp.ld + idx] = static_cast<OutT>(row[d3]);
-        // transposed store into an analysis-domain partner (kp.transpose)
-        const int j3 = i3 + d3 - P;
-        if (tr12 && j3 >= kp.tr_lo[2] && j3 <= kp.tr_hi[2]) {
-          const int64_t j = int64_t(idx) + (d1 - P) + int64_t(kp.m[0]) * (d2 - P) + int64_t(plane) * (d3 - P);
-          out[size_t(kp.S - 1 - s) * kp.ld + size_t(j)] = static_cast<OutT>(row[d3]);
-        }
-      }
-    }
-  };
-
-  for (int e0 = Elo; e0 <= Ehi; e0 += P + 1) {
-    static_for<0, P + 1>([&](auto ph) {
-      constexpr int PH = decltype(ph)::value;
-      const int e3 = e0 + PH;
-      if (e3 > Ehi) return;
-      for (int k3 = 0; k3 < NQ; ++k3) {
-        const int g3 = e3 * NQ + k3;
-        // phase A: integrand data at the footprint's Gauss points
-        for (int t = tid; t < nq1 * nq2; t += C::BLOCK) {
-          const int l1 = t / nq2, l2 = t - l1 * nq2;
-          const int g[3] = {E1a * NQ + l1, E2a * NQ + l2, g3};
-          double v[C::NC];
-          point_data<3, FORM>(kp, b, g, v);
-#pragma unroll
-          for (int c = 0; c < C::NC; ++c) Cs[c][l1][l2] = v[c];
-        }
-        __syncthreads();
-        // phase B: stage 1 (direction-1 contraction) into Ys
-        const int ntask = C::NY * TX * nq2;
-        for (int t = tid; t < ntask; t += C::BLOCK) {
-          const int l2 = t % nq2;
-          const int rr = t / nq2;
-          const int rr1 = rr % TX;
-          const int k = rr / TX;
-          if (rr1 >= tile.nx) continue;
-          const int ii1 = tile.i1 + rr1;
-          double y[W];
-          if constexpr (FORM == IGS_MASS) {
-            stage1_3d<P, 0, 0, NQ1, NQ2>(Cs[0], T1v, T1d, ii1, E1a, nel1, l2, y);
-          } else {
-            // outputs: K11.dd, K12.dv, K13.dv, K12.vd, K13.vd, K22.vv, K23.vv, K33.vv
-            switch (k) {
-              case 0: stage1_3d<P, 1, 1, NQ1, NQ2>(Cs[0], T1v, T1d, ii1, E1a, nel1, l2, y); break;
-              case 1: stage1_3d<P, 1, 0, NQ1, NQ2>(Cs[1], T1v, T1d, ii1, E1a, nel1, l2, y); break;
-              case 2: stage1_3d<P, 1, 0, NQ1, NQ2>(Cs[2], T1v, T1d, ii1, E1a, nel1, l2, y); break;
-              case 3: stage1_3d<P, 0, 1, NQ1, NQ2>(Cs[1], T1v, T1d, ii1, E1a, nel1, l2, y); break;
-              case 4: stage1_3d<P, 0, 1, NQ1, NQ2>(Cs[2], T1v, T1d, ii1, E1a, nel1, l2, y); break;
-              case 5: stage1_3d<P, 0, 0, NQ1, NQ2>(Cs[3], T1v, T1d, ii1, E1a, nel1, l2, y); break;
-              case 6: stage1_3d<P, 0, 0, NQ1, NQ2>(Cs[4], T1v, T1d, ii1, E1a, nel1, l2, y); break;
-              default: stage1_3d<P, 0, 0, NQ1, NQ2>(Cs[5], T1v, T1d, ii1, E1a, nel1, l2, y); break;
-            }
-          }
-#pragma unroll
-          for (int d = 0; d < W; ++d) Ys[k][rr1 * W + d][l2] = y[d];
-        }
-        __syncthreads();
-        // phase C: stage 2 (direction 2) and stage 3 (direction 3) per thread
-        if (active) {
-          double Z00 = 0.0, Z10 = 0.0, Z01 = 0.0, Z11 = 0.0;
-          const int yrow = r1 * W + d1;
-#pragma unroll
-          for (int a2 = 0; a2 <= P; ++a2) {
-            const int e2 = i2 - a2;
-            const int b2 = j2 - e2;
-            if (e2 < 0 || e2 >= nel2 || b2 < 0 || b2 > P) continue;
-            const int le = (e2 - E2a) * NQ;
-#pragma unroll
-            for (int k2 = 0; k2 < NQ; ++k2) {
-              const int l2 = le + k2;
-              const double vi = T2v[a2][l2], vj = T2v[b2][l2];
-              if constexpr (FORM == IGS_MASS) {
-                Z00 += vi * vj * Ys[0][yrow][l2];
-              } else {
-                const double di = T2d[a2][l2], dj = T2d[b2][l2];
-                const double vv = vi * vj, vd = vi * dj, dv = di * vj, dd = di * dj;
-                const double y0 = Ys[0][yrow][l2], y1 = Ys[1][yrow][l2], y2 = Ys[2][yrow][l2];
-                const double y3 = Ys[3][yrow][l2], y4 = Ys[4][yrow][l2], y5 = Ys[5][yrow][l2];
-                const double y6 = Ys[6][yrow][l2], y7 = Ys[7][yrow][l2];
-                Z00 += vv * y0 + vd * y1 + dv * y3 + dd * y5;
-                Z10 += vv * y4 + vd * y6;
-                Z01 += vv * y2 + dv * y6;
-                Z11 += vv * y7;
-              }
-            }
-          }
-          const double* v3p = kp.t[2].bv + size_t(g3) * (P + 1);
-          const double* d3p = kp.t[2].bd + size_t(g3) * (P + 1);
-          double v3[P + 1], d3[P + 1];
-#pragma unroll
-          for (int a = 0; a <= P; ++a) {
-            v3[a] = v3p[a];
-            d3[a] = d3p[a];
-          }
-#pragma unroll
-          for (int b3 = 0; b3 <= P; ++b3) {
-            double U, V;
-            if constexpr (FORM == IGS_MASS) {
-              U = v3[b3] * Z00;
-              V = 0.0;
-            } else {
-              U = v3[b3] * Z00 + d3[b3] * Z01;
-              V = v3[b3] * Z10 + d3[b3] * Z11;
-            }
-#pragma unroll
-            for (int a3 = 0; a3 <= P; ++a3) {
-              if constexpr (FORM == IGS_MASS)
-                acc[(PH + a3) % (P + 1)][b3 - a3 + P] += v3[a3] * U;
-              else
-                acc[(PH + a3) % (P + 1)][b3 - a3 + P] += v3[a3] * U + d3[a3] * V;
-            }
-          }
-        }
-      }
-      // rows whose last layer was e3 are complete
-      if (e3 < nel3 - 1) {
-        write_row(e3, PH, acc[PH]);
-#pragma unroll
-        for (int d = 0; d < W; ++d) acc[PH][d] = 0.0;
-      } else {
-#pragma unroll
-        for (int a = 0; a <= P; ++a) {
-          write_row(e3 + a, 0, acc[(PH + a) % (P + 1)]);
-#pragma unroll
-          for (int d = 0; d < W; ++d) acc[(PH + a) % (P + 1)][d] = 0.0;
-        }
-      }
-    });
-  }
-}
-
-// ------------------------------------------------ 3-D rows, register-blocked ---
-//
-// Same contraction order as quad3d_kernel with a different work mapping.  Wave
-// w owns the direction-2 combination (i2, delta2) = (tile.i2 + w / W, w % W - P)
-// and lane l the direction-1 combination (i1, delta1) = (tile.i1 + l % TX,
-// l / TX - P), so that one thread carries one (delta1, delta2) column of a row
-// pencil and its rolling window of P+1 rows x W delta3 values.  Per Gauss plane:
-//   stage 1  direction-1 contraction.  A wave owns one i1, so the 1-D basis
-//            values it needs are wave-uniform (scalar loads); its lanes own
-//            (component, l2).  Results go to Ys, two codes per 16 bytes.
-//   stage 2  direction-2 contraction, basis values wave-uniform again,
-//            4 direction-3 codes in registers;
-//   stage 3  direction-3 products into the rolling window;
-//   phase A  integrand data of the next plane at the footprint points -> Cs
-//            (same barrier interval as stages 2-3: they touch different buffers).
-
 // Read-only table viewed in the constant address space: loads at wave-uniform
 // addresses then go through the scalar cache into SGPRs.
 typedef const __attribute__((address_space(4))) double* cdptr;
@@ -482,6 +233,7 @@ struct Q3BShape;
 template <> struct Q3BShape<1> { static constexpr int TY = 5; };
 template <> struct Q3BShape<2> { static constexpr int TY = 3; };
 template <> struct Q3BShape<3> { static constexpr int TY = 2; };
+template <> struct Q3BShape<4> { static constexpr int TY = 1; };
 
 // Stage-1 wave tasks.  A task fixes i1 and one of three product modes; its
 // lanes hold (component, l2).  Codes written to Ys (pair, half):
@@ -498,7 +250,13 @@ struct Q3B {
   static constexpr int TX = 64 / W, TY = Q3BShape<P>::TY;
   static constexpr int NWAVE = TY * W;
   static constexpr int BLOCK = 64 * NWAVE;
-  static constexpr int NQ1 = (TX + P) * NQ, NQ2 = (TY + P) * NQ;
+  // direction-2 elements held in LDS at a time.  Up to p = 3 the tile's whole
+  // footprint (TY + P elements); at p = 4 the five elements of a row's
+  // footprint would need more LDS than a CU has (Cs and Ys together about
+  // 171 KB), so each Gauss plane is taken in groups of up to three elements.
+  static constexpr int EG2 = P <= 3 ? TY + P : 3;
+  static constexpr int NG2 = (TY + P + EG2 - 1) / EG2;  // groups per plane (at most)
+  static constexpr int NQ1 = (TX + P) * NQ, NQ2 = EG2 * NQ;
   static constexpr bool STIFF = FORM == IGS_STIFFNESS;
   static constexpr int NC = STIFF ? 6 : 1;
   static constexpr int NMODE = STIFF ? 3 : 1;
@@ -521,7 +279,8 @@ template <int P, int MODE>
 __device__ __forceinline__ void stage1_core(const KProblem& kp, const double* cb, int ls, int i1, int E1a,
                                             double* y0, double* y1) {
   constexpr int NQ = P + 1, W = 2 * P + 1, NP = P + 1;
-  constexpr int NB = MODE == S1_DDV ? (NQ + 1) / 2 : NQ;  // points per batch
+  // points per batch (their basis rows live in SGPRs: at p = 4 smaller batches)
+  constexpr int NB = MODE == S1_DDV ? (P <= 3 ? (NQ + 1) / 2 : 2) : (P <= 3 ? NQ : 3);
 #pragma unroll
   for (int d = 0; d < W; ++d) y0[d] = y1[d] = 0.0;
   const int nel1 = kp.nelem[0];
@@ -629,7 +388,7 @@ __device__ __forceinline__ void stage1_b(const KProblem& kp, const double* __res
 
 // ------------------------------------------------ 3-D rows, register-blocked ---
 //
-// Same contraction order as quad3d_kernel with a different work mapping.  Wave
+// Sum factorisation of the row quadrature, one direction at a time.  Wave
 // w owns the direction-2 combination (i2, delta2) = (tile.i2 + w / W, w % W - P)
 // and lane l the direction-1 combination (i1, delta1) = (tile.i1 + l % TX,
 // l / TX - P): one thread carries one (delta1, delta2) column of a row pencil
@@ -667,7 +426,14 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
   const int nel1 = kp.nelem[0], nel2 = kp.nelem[1], nel3 = kp.nelem[2];
   const int E1a = max(0, tile.i1 - P), E1b = min(nel1 - 1, tile.i1 + tile.nx - 1);
   const int E2a = max(0, tile.i2 - P), E2b = min(nel2 - 1, tile.i2 + tile.ny - 1);
-  const int nq1 = (E1b - E1a + 1) * NQ, nq2 = (E2b - E2a + 1) * NQ;
+  const int nq1 = (E1b - E1a + 1) * NQ;
+  // direction-2 element groups of a plane (block-uniform): group g holds the
+  // elements from E2a + g EG2 on (a single group up to p = 3)
+  const int ng2 = C::NG2 == 1 ? 1 : (E2b - E2a + C::EG2) / C::EG2;
+  auto grp_e2 = [&](int grp) { return C::NG2 == 1 ? E2a : E2a + grp * C::EG2; };
+  auto grp_nq2 = [&](int grp) {
+    return C::NG2 == 1 ? (E2b - E2a + 1) * NQ : min(C::EG2, E2b + 1 - grp_e2(grp)) * NQ;
+  };
 
   // stage-2/3 identity of this thread
   const int r2 = wave / W, d2 = wave - r2 * W;
@@ -692,20 +458,21 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
     if (lane == 0) v = atomicAdd(&qctr[c], 1);
     return __builtin_amdgcn_readfirstlane(v);
   };
-  auto phase_a = [&](int g3) {
+  auto phase_a = [&](int g3, int grp) {
+    const int nq2 = grp_nq2(grp), e2g = grp_e2(grp);
     const int npt = nq1 * nq2;
     for (int pass = fetch(1); pass * 64 < npt; pass = fetch(1)) {
       const int t = pass * 64 + lane;
       if (t >= npt) continue;
       const int l1 = t / nq2, l2 = t - l1 * nq2;
-      const int g[3] = {E1a * NQ + l1, E2a * NQ + l2, g3};
+      const int g[3] = {E1a * NQ + l1, e2g * NQ + l2, g3};
       double v[C::NC];
       point_data<3, FORM, VC>(kp, b, g, v);
 #pragma unroll
       for (int c = 0; c < C::NC; ++c) Cs[c * C::CS + l1 * NQ2 + l2] = v[c];
     }
   };
-  auto stage1 = [&]() {
+  auto stage1 = [&](int nq2) {
     double* Ysd = reinterpret_cast<double*>(Ys);
     for (int task = fetch(0); task < C::NMODE * TX; task = fetch(0)) {
       const int mode = task / TX, rr1 = task - mode * TX;
@@ -751,12 +518,19 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
   const int g0 = Elo * NQ, glast = Ehi * NQ + NQ - 1;
   if (tid == 0) qctr[0] = qctr[1] = 0;
   __syncthreads();
-  phase_a(g0);
+  phase_a(g0, 0);
   __syncthreads();
 
-  for (int g3 = g0; g3 <= glast; ++g3) {
+  // items (plane g3, direction-2 group); the direction-3 products of a plane
+  // follow its last group
+  double Zc[4] = {0.0, 0.0, 0.0, 0.0};  // a plane's direction-2 sums carried between groups
+  const int nitem = (glast - g0 + 1) * ng2;
+  for (int it = 0; it < nitem; ++it) {
+    const int g3 = C::NG2 == 1 ? g0 + it : g0 + it / ng2;
+    const int grp = C::NG2 == 1 ? 0 : it - (g3 - g0) * ng2;
     const int e3 = g3 / NQ, k3 = g3 - e3 * NQ;
-    stage1();
+    const bool last_grp = grp == ng2 - 1;
+    stage1(grp_nq2(grp));
     // the phase-A counter is idle in this interval (its last use ended at the
     // previous barrier), the stage-1 counter in the next one
     if (tid == 0) qctr[1] = 0;
@@ -768,6 +542,13 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
       // scalar load brings the four products (value/derivative of i2 times
       // value/derivative of j2), each then a single FMA operand
       double Z00 = 0.0, Z10 = 0.0, Z01 = 0.0, Z11 = 0.0;
+      if (C::NG2 > 1 && grp > 0) {
+        Z00 = Zc[0];
+        Z10 = Zc[1];
+        Z01 = Zc[2];
+        Z11 = Zc[3];
+      }
+      const int e2g = grp_e2(grp);
       constexpr int PP = (P + 1) * (P + 1) * 4;  // product-table doubles per point
       cdptr tab2 = uniform_table(kp.t[1].bpr);
 #pragma unroll
@@ -775,8 +556,9 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
         const int e2 = i2 - a2;
         const int b2 = a2 + d2 - P;
         if (e2 < 0 || e2 >= nel2 || b2 < 0 || b2 > P) continue;
+        if (C::NG2 > 1 && (e2 < e2g || e2 >= e2g + C::EG2)) continue;  // another group's element
         cdptr row = tab2 + size_t(e2) * NQ * PP + (a2 * (P + 1) + b2) * 4;
-        const double2* yp = Ys + (e2 - E2a) * NQ * YL + lane;
+        const double2* yp = Ys + (e2 - e2g) * NQ * YL + lane;
 #pragma unroll 2
         for (int k2 = 0; k2 < NQ; ++k2) {
           cdptr rk = row + k2 * PP;
@@ -799,27 +581,34 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
           }
         }
       }
-      cdptr v3 = uniform_table(kp.t[2].bv) + size_t(g3) * (P + 1);
-      cdptr t3 = uniform_table(kp.t[2].bd) + size_t(g3) * (P + 1);
+      if (C::NG2 > 1 && !last_grp) {
+        Zc[0] = Z00;
+        Zc[1] = Z10;
+        Zc[2] = Z01;
+        Zc[3] = Z11;
+      } else {
+        cdptr v3 = uniform_table(kp.t[2].bv) + size_t(g3) * (P + 1);
+        cdptr t3 = uniform_table(kp.t[2].bd) + size_t(g3) * (P + 1);
 #pragma unroll
-      for (int b3 = 0; b3 <= P; ++b3) {
-        double U, V;
-        if constexpr (C::STIFF) {
-          U = v3[b3] * Z00 + t3[b3] * Z01;
-          V = v3[b3] * Z10 + t3[b3] * Z11;
-        } else {
-          U = v3[b3] * Z00;
-          V = 0.0;
-        }
+        for (int b3 = 0; b3 <= P; ++b3) {
+          double U, V;
+          if constexpr (C::STIFF) {
+            U = v3[b3] * Z00 + t3[b3] * Z01;
+            V = v3[b3] * Z10 + t3[b3] * Z11;
+          } else {
+            U = v3[b3] * Z00;
+            V = 0.0;
+          }
 #pragma unroll
-        for (int a3 = 0; a3 <= P; ++a3) {
-          double& w = acc[a3][b3 - a3 + P];
-          w = fma(v3[a3], U, w);
-          if constexpr (C::STIFF) w = fma(t3[a3], V, w);
+          for (int a3 = 0; a3 <= P; ++a3) {
+            double& w = acc[a3][b3 - a3 + P];
+            w = fma(v3[a3], U, w);
+            if constexpr (C::STIFF) w = fma(t3[a3], V, w);
+          }
         }
       }
     }
-    if (k3 == NQ - 1) {
+    if (last_grp && k3 == NQ - 1) {
       if (e3 < nel3 - 1) {
         // row e3 is complete: store it and shift the window
         store_row(e3, 0);
@@ -835,7 +624,7 @@ __global__ void __launch_bounds__((Q3B<P, FORM>::BLOCK))
         for (int a = 0; a <= P; ++a) store_row(e3 + a, a);
       }
     }
-    if (g3 < glast) phase_a(g3 + 1);
+    if (it + 1 < nitem) phase_a(last_grp ? g3 + 1 : g3, last_grp ? 0 : grp + 1);
     __syncthreads();
   }
 }
@@ -1196,7 +985,7 @@ __device__ __forceinline__ double source_at(const KProblem& kp, const int* g, in
     double F[ND];
     phys_point<ND>(kp, g, xi, F);
 #pragma unroll
-    for (int d = 0; d < ND; ++d) f *= sin(M_PI * F[d]);
+    for (int d = 0; d < ND; ++d) f *= sinpi(F[d]);
   }
   return w * fabs(det) * f;
 }
@@ -1385,7 +1174,7 @@ void quad_tile_shape(int n, int p, int* tx, int* ty) {
     case 1: *tx = Q3B<1, IGS_STIFFNESS>::TX; *ty = Q3B<1, IGS_STIFFNESS>::TY; break;
     case 2: *tx = Q3B<2, IGS_STIFFNESS>::TX; *ty = Q3B<2, IGS_STIFFNESS>::TY; break;
     case 3: *tx = Q3B<3, IGS_STIFFNESS>::TX; *ty = Q3B<3, IGS_STIFFNESS>::TY; break;
-    default: *tx = Q3Shape<4>::TX; *ty = Q3Shape<4>::TY; break;
+    default: *tx = Q3B<4, IGS_STIFFNESS>::TX; *ty = Q3B<4, IGS_STIFFNESS>::TY; break;
   }
 }
 
@@ -1408,15 +1197,12 @@ static hipError_t launch_quad_t(const KProblem& kp, const QTile* tiles, int ntil
       hipLaunchKernelGGL((quad3d_row_kernel<P, FORM, false, OutT>), grid, dim3(Q3R<P, FORM>::BLOCK), 0, s, kp,
                          tiles, band);
   } else if (kp.n == 3) {
-    if constexpr (P <= 3) {
-      if (vc)
-        hipLaunchKernelGGL((quad3d_tile_kernel<P, FORM, true, OutT>), grid, dim3(Q3B<P, FORM>::BLOCK), 0, s, kp,
-                           tiles, band);
-      else
-        hipLaunchKernelGGL((quad3d_tile_kernel<P, FORM, false, OutT>), grid, dim3(Q3B<P, FORM>::BLOCK), 0, s, kp,
-                           tiles, band);
-    } else
-      hipLaunchKernelGGL((quad3d_kernel<P, FORM, OutT>), grid, dim3(Q3<P, FORM>::BLOCK), 0, s, kp, tiles, band);
+    if (vc)
+      hipLaunchKernelGGL((quad3d_tile_kernel<P, FORM, true, OutT>), grid, dim3(Q3B<P, FORM>::BLOCK), 0, s, kp,
+                         tiles, band);
+    else
+      hipLaunchKernelGGL((quad3d_tile_kernel<P, FORM, false, OutT>), grid, dim3(Q3B<P, FORM>::BLOCK), 0, s, kp,
+                         tiles, band);
   } else {
     hipLaunchKernelGGL((quad2d_kernel<P, FORM, OutT>), grid, dim3(Q2<P, FORM>::BLOCK), 0, s, kp, tiles, band);
   }
