@@ -597,6 +597,173 @@ def quadrature_rows(prob, M):
     return out | samp
 
 
+# ----------------------------------------------------- per-delta domains ---
+def cardinal_range(m, p):
+    """Indices of the cardinal B-splines along one direction (0-based): those
+    whose support spans p+1 uniform knot intervals, [p, m - p - 1]."""
+    return p, m - p - 1
+
+
+def delta_range(m, p, dd):
+    """Index range of the domain of the stencil function for offset dd along one
+    direction (Sec. 4, the remark after the analysis domain): rows i whose own
+    function and partner i + dd are both cardinal,
+    [p + max(0, -dd), m - p - 1 - max(0, dd)]."""
+    return p + max(0, -dd), m - p - 1 - max(0, dd)
+
+
+def lattice_pd(m, p, M, dd):
+    """Sample indices of the stencil function for offset dd along one direction
+    (reading): the analysis-domain lattice (``lattice``) plus every index of
+    the two transition bands [p, 2p) and (m - 2p - 1, m - p - 1] that lies in
+    ``delta_range``; in index order.  Every offset draws on one common set of
+    sample indices (lattice plus both bands), and M = 1 samples every index."""
+    lo, hi = delta_range(m, p, dd)
+    base = lattice(m, p, M)
+    s = list(range(lo, 2 * p)) + list(base) + list(range(m - 2 * p, hi + 1))
+    return np.array(s, dtype=np.int64)
+
+
+def sample_union_pd(m, p, M):
+    """The common sample indices of every offset along one direction."""
+    return np.unique(np.concatenate([lattice_pd(m, p, M, dd) for dd in range(-p, p + 1)]))
+
+
+def cardinal_mask(prob, idx):
+    m, _, _ = dims(prob)
+    p = prob["p"]
+    ok = np.ones(idx.shape[0], dtype=bool)
+    for d in range(prob["n"]):
+        lo, hi = cardinal_range(m[d], p)
+        ok &= (idx[:, d] >= lo) & (idx[:, d] <= hi)
+    return ok
+
+
+class SurrogatePD:
+    """Surrogate with a domain per stencil function (Sec. 4: the results hold
+    with the analysis domain replaced by the domain of each stencil function,
+    given an interpolation operator per offset; Sec. 5.1-5.3 for the entries).
+
+    Reading:
+      * the domain of Phi_delta is the tensor product of ``delta_range``:
+        rows i such that i and i + delta index cardinal B-splines;
+      * Phi_delta (upper delta: colex offset > 0, also delta = 0 for the mass
+        form) is sampled on the tensor product of ``lattice_pd`` and
+        interpolated by the degree-q tensor spline of ``interp_knots``;
+      * entries: upper delta with i + delta cardinal (i cardinal):
+        Phi~_delta(i); lower delta with both cardinal: Phi~_{-delta}(i + delta)
+        (eq. 5.1b); every other entry exact (at least one function is not
+        cardinal), 0 outside the index box;
+      * stiffness diagonal of cardinal rows: -sum_{k != i} A~_ik (eq. 5.1c);
+        mass diagonal of cardinal rows: Phi~_0(i); rows of non-cardinal
+        functions are exact.
+    Quadrature rows: the non-cardinal rows and the tensor product of
+    ``sample_union_pd``.
+    """
+
+    def __init__(self, prob, form, M, q, b=0, exact=None):
+        self.prob, self.form, self.M, self.q, self.b = prob, form, M, q, b
+        self.exact = exact if exact is not None else (lambda rows: exact_rows(prob, form, rows, b))
+        n, p = prob["n"], prob["p"]
+        m, N, S = dims(prob)
+        self.m, self.N, self.S = m, N, S
+        self.sc = (S - 1) // 2
+        self.off = stencil_offsets(prob)
+        self.U = [sample_union_pd(m[d], p, M) for d in range(n)]
+        self.samp, self.G, self.E = {}, {}, {}
+        for d in range(n):
+            for dd in range(-p, p + 1):
+                sm = lattice_pd(m[d], p, M, dd)
+                if len(sm) < q + 1:
+                    raise ValueError("fewer samples than q+1 in a direction")
+                kn = interp_knots(sm, q)
+                self.samp[(d, dd)] = sm
+                self.G[(d, dd)] = bspline_matrix(kn, q, sm)
+                x = np.clip(np.arange(m[d], dtype=np.float64), sm[0], sm[-1])
+                self.E[(d, dd)] = bspline_matrix(kn, q, x)
+        # exact rows at every sample index (tensor product of the unions)
+        g = np.meshgrid(*self.U[::-1], indexing="ij")
+        uidx = np.stack([x.ravel() for x in g[::-1]], axis=1)
+        self.sample_rows = flat_index(prob, uidx)
+        V = self.exact(self.sample_rows)
+        shapeU = tuple(len(u) for u in self.U)[::-1]
+        V = V.reshape(shapeU + (S,))
+        self.upper = [s for s in range(S) if s > self.sc or (form == MASS and s == self.sc)]
+        self.coef = {}
+        for s in self.upper:
+            c = V[..., s]
+            for d in range(n):                   # restrict to this offset's samples, then solve
+                ax = n - 1 - d
+                pos = np.searchsorted(self.U[d], self.samp[(d, int(self.off[s, d]))])
+                c = np.take(c, pos, axis=ax)
+            for d in range(n):
+                ax = n - 1 - d
+                c = np.moveaxis(c, ax, 0)
+                sh = c.shape
+                c = np.linalg.solve(self.G[(d, int(self.off[s, d]))], c.reshape(sh[0], -1)).reshape(sh)
+                c = np.moveaxis(c, 0, ax)
+            self.coef[s] = c
+
+    def phi(self, s, idx):
+        """Phi~ for upper slot s at multi-indices idx [npts, n]."""
+        n = self.prob["n"]
+        c = self.coef[s]
+        v = c.reshape(c.shape + (1,)) * np.ones(len(idx))
+        for d in range(n):                       # direction 1 is the last axis of c
+            w = self.E[(d, int(self.off[s, d]))][idx[:, d]]
+            v = np.einsum("...jn,nj->...n", v, w)
+        return v.reshape(len(idx))
+
+    def rows(self, rows):
+        prob = self.prob
+        rows = np.asarray(rows, dtype=np.int64)
+        idx = multi_index(prob, rows)
+        card = cardinal_mask(prob, idx)
+        mvec = np.array(self.m)
+        ex = self.exact(rows)
+        out = np.zeros((len(rows), self.S))
+        for s in range(self.S):
+            jidx = idx + self.off[s]
+            inbox = np.all((jidx >= 0) & (jidx < mvec), axis=1)
+            val = np.where(inbox, ex[:, s], 0.0)
+            if s == self.sc:
+                if self.form == MASS:
+                    ii = np.nonzero(card)[0]
+                    val[ii] = self.phi(s, idx[ii])
+                out[:, s] = val
+                continue
+            both = card & inbox & cardinal_mask(prob, np.where(inbox[:, None], jidx, 0))
+            ii = np.nonzero(both)[0]
+            if len(ii):
+                if s > self.sc:
+                    val[ii] = self.phi(s, idx[ii])
+                else:
+                    val[ii] = self.phi(self.S - 1 - s, jidx[ii])
+            out[:, s] = val
+        if self.form == STIFFNESS:
+            ii = np.nonzero(card)[0]
+            out[ii, self.sc] = -(out[ii].sum(axis=1) - out[ii, self.sc])
+        return out
+
+
+def surrogate_pd_rows(prob, form, M, q, rows=None, b=0):
+    _, N, _ = dims(prob)
+    rows = np.arange(N) if rows is None else rows
+    return SurrogatePD(prob, form, M, q, b).rows(rows)
+
+
+def quadrature_rows_pd(prob, M):
+    """Rows the per-delta surrogate assembles by quadrature: the rows of
+    non-cardinal functions plus the tensor product of the sample unions."""
+    m, N, _ = dims(prob)
+    p = prob["p"]
+    idx = multi_index(prob, np.arange(N))
+    samp = np.ones(N, dtype=bool)
+    for d in range(prob["n"]):
+        samp &= np.isin(idx[:, d], sample_union_pd(m[d], p, M))
+    return ~cardinal_mask(prob, idx) | samp
+
+
 # -------------------------------------------------------- linear algebra ---
 def dirichlet_mask(prob):
     """Dofs whose function does not vanish on the boundary: some i_d in {0, m_d-1}."""
