@@ -109,7 +109,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="only the timed step (for profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (reference kernel for HBM byte counters)")
-    ap.add_argument("--leg", choices=["face_edge", "matrix_free"], default=None,
+    ap.add_argument("--leg", choices=["face_edge", "per_delta", "matrix_free"], default=None,
                     help="only run one other leg's timed steps on the same workload (for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -285,6 +285,40 @@ def main():
             del bfe
         extra["face_edge"] = fe
         log(f"face/edge: {fe}")
+
+        # --------------- per-delta domains (Sec. 4 remark), same workload
+        info_pd = igs.surrogate_pd_layout(prob, M, q)
+        pdl = {"quadrature_rows": info_pd.quadrature_rows, "noncardinal_rows": info_pd.noncardinal_rows,
+               "domain_surrogate_quadrature_rows": info.quadrature_rows,
+               "samples_per_direction": list(info_pd.samples)[:3]}
+        for name, tdt, esize in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+            bpd = band if tdt == torch.float64 else igs.empty_band(prob, tdt)
+            ppd = igs.Plan(prob, igs.STIFFNESS, M=M, q=q, dtype=tdt, per_delta=True)
+            ms_pd, ph_pd = timed_plan(ppd, bpd, stream, args.steps)
+            ppd.close()
+            leg = {"ms": ms_pd, "slots_per_s": slots / (ms_pd * 1e-3), "phases_ms": ph_pd,
+                   "step_hbm_frac": slots * esize / (ms_pd * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            if name == "f64":
+                # the fill writes the cardinal rows' interpolated slots once
+                tf = ph_pd["fill"] * 1e-3
+                cb = pd_fill_bytes(prob, lay, esize)
+                leg["roofline_fill"] = {"bound": "hbm", "achieved": cb / tf / 1e9, "peak": HBM_PEAK_GBS,
+                                        "unit": "GB/s", "frac": cb / tf / 1e9 / HBM_PEAK_GBS,
+                                        "traffic": measured_traffic("pd_fill"), "ms": ph_pd["fill"],
+                                        "units": "interpolated entries of the cardinal rows plus their diagonals, "
+                                                 "8 bytes each"}
+                tq = ph_pd["quad_boundary_rows"] * 1e-3
+                fl = quad_flops_per_row(3, prob["p"]) * info_pd.noncardinal_rows
+                leg["roofline_boundary_rows"] = {"bound": "alu", "achieved": fl / tq / 1e12,
+                                                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                                 "frac": fl / tq / 1e12 / FP64_PEAK_TFLOPS, "ms": tq * 1e3,
+                                                 "units": f"{info_pd.noncardinal_rows} quadrature rows"}
+                leg["speedup_vs_domain_surrogate"] = ms_step / ms_pd
+                leg["speedup_vs_exact"] = ms_ex / ms_pd
+            pdl[name] = leg
+            del bpd
+        extra["per_delta"] = pdl
+        log(f"per-delta: {pdl}")
 
         # ------------- 3D p=3 64^3 stiffness and mass, exact vs surrogate M in {4, 8, 16}
         extra["poisson3d_p3_64"] = c2_study(stream, args.steps)
@@ -519,8 +553,9 @@ def profile_leg(args):
     lay = igs.layout(prob)
     band = igs.empty_band(prob, torch.float64)
     stream = torch.cuda.current_stream()
-    if args.leg == "face_edge":
-        pl = igs.Plan(prob, igs.STIFFNESS, M=8, q=3, face_edge=True)
+    if args.leg in ("face_edge", "per_delta"):
+        pl = igs.Plan(prob, igs.STIFFNESS, M=8, q=3, face_edge=args.leg == "face_edge",
+                      per_delta=args.leg == "per_delta")
         for _ in range(max(1, args.warmup)):
             pl.execute(out=band)
         ms, ph = timed_plan(pl, band, stream, args.steps)
@@ -593,22 +628,31 @@ def c2_study(stream, reps):
         pe.close()
         scale = float(ex[:, :, :lay.N].abs().max())
         leg = {"exact": {"ms": ms_ex, "slots_per_s": slots / (ms_ex * 1e-3)}}
-        for fe in (False, True):
+        for var in ("surrogate", "face_edge", "per_delta"):
             errs = {}
             for M in (4, 8, 16):
-                ps = igs.Plan(prob, form, M=M, q=3, face_edge=fe)
+                ps = igs.Plan(prob, form, M=M, q=3, face_edge=var == "face_edge", per_delta=var == "per_delta")
                 ms_s, ph = timed_plan(ps, sb, stream, reps)
                 ps.close()
                 err = float((sb[:, :, :lay.N] - ex[:, :, :lay.N]).abs().max()) / scale
                 errs[M] = err
-                leg[("face_edge_M%d" if fe else "surrogate_M%d") % M] = {
+                leg["%s_M%d" % (var, M)] = {
                     "ms": ms_s, "slots_per_s": slots / (ms_s * 1e-3), "speedup_vs_exact": ms_ex / ms_s,
                     "rel_max_err": err, "phases_ms": ph}
-            leg["face_edge_rate" if fe else "rate"] = {
+            leg["rate" if var == "surrogate" else var + "_rate"] = {
                 "log2_slope_M4_M8": math.log2(errs[8] / errs[4]), "log2_slope_M8_M16": math.log2(errs[16] / errs[8])}
         out[fname] = leg
     del ex, sb
     return out
+
+
+def pd_fill_bytes(prob, lay, esize):
+    """Algorithmic bytes of the per-delta fill: every entry (i, delta) whose
+    row and partner are both cardinal (delta = 0, the diagonal, included),
+    written once."""
+    n, p = prob["n"], prob["p"]
+    C = [lay.m[d] - 2 * p for d in range(n)]
+    return math.prod(sum(C[d] - abs(dl) for dl in range(-p, p + 1)) for d in range(n)) * esize
 
 
 def mesh_dependent_study(stream):

@@ -150,6 +150,16 @@ typedef struct igs_fe_info {
   int64_t quadrature_rows;   /* prod samples[d]: every row assembled by quadrature */
 } igs_fe_info;
 
+/* Per-delta surrogate sampling (host-only, igs_surrogate_pd_layout). */
+typedef struct igs_pd_info {
+  int32_t samples[3];        /* per direction: the common sample indices, the
+                                lattice plus the 2p transition-band indices
+                                [p, 2p) and [m-2p, m-p) (1 if unused) */
+  int32_t max_samples[3];    /* largest sample count of one offset */
+  int64_t noncardinal_rows;  /* N - prod (m_d - 2p): rows of non-cardinal functions */
+  int64_t quadrature_rows;   /* noncardinal_rows + prod samples[d] */
+} igs_pd_info;
+
 typedef struct igs_cg_info {
   int32_t iterations;        /* total CG iterations (inner FP32 ones in mixed mode) */
   int32_t outer_iterations;  /* with an FP32 band: FP64 residual replacements;
@@ -176,6 +186,9 @@ igs_status igs_surrogate_layout(const igs_problem* pb, int32_t M, int32_t q, igs
 
 /* Sampling of the face/edge surrogate (igs_assemble_surrogate_fe).  Host only. */
 igs_status igs_surrogate_fe_layout(const igs_problem* pb, int32_t M, int32_t q, igs_fe_info* out);
+
+/* Sampling of the per-delta surrogate (igs_assemble_surrogate_pd).  Host only. */
+igs_status igs_surrogate_pd_layout(const igs_problem* pb, int32_t M, int32_t q, igs_pd_info* out);
 
 /* Mesh-dependent sampling length (Sec. 7.3.3): M(h) = max{1, floor(c h^e)}
  * with h = 1/nelem and e = (p - q + beta)/(q + 1), so that H = M h obeys
@@ -266,6 +279,30 @@ igs_status igs_assemble_surrogate_fe(const igs_problem* pb, int32_t form, int32_
 igs_status igs_assemble_noalloc(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* band,
                                 void* stream);
 
+/* Surrogate assembly with a domain per stencil function (Sec. 4: the results
+ * hold with the analysis domain replaced by each stencil function's own
+ * domain, given an interpolation operator per offset; entries as in Sec. 5).
+ * Function i is cardinal when its support spans p+1 uniform knot intervals,
+ * i_d in [p, m_d-p-1].  The domain of Phi_delta is the box of rows i with i
+ * and i + delta cardinal: per direction [p + max(0,-delta_d),
+ * m_d-p-1 - max(0,delta_d)].  Phi_delta (upper delta, and delta = 0 for mass)
+ * is sampled on the tensor product of its per-direction samples -- the
+ * analysis-domain lattice (igs_surrogate_layout) plus every transition-band
+ * index [p, 2p) and [m_d-2p, m_d-p) inside its domain -- and interpolated by
+ * the degree-q not-a-knot tensor spline.  Entries: Phi~_delta(i) for upper
+ * delta when i and i + delta are cardinal; A~_ji = A~_ij (eq. 5.1b); every
+ * other entry exact (a non-cardinal function is involved), 0 outside the index
+ * box; stiffness diagonal of cardinal rows -sum_{k!=i} A~_ik (eq. 5.1c), mass
+ * diagonal of cardinal rows Phi~_0(i); rows of non-cardinal functions exact.
+ * Quadrature runs on the non-cardinal rows and the tensor product of the
+ * per-direction sample sets (igs_surrogate_pd_layout: 294,966 + 22^3 rows at
+ * p = 3, 128^3, M = 8, against 567,028 for igs_assemble_surrogate).  M = 1
+ * reproduces igs_assemble_exact to rounding.  Same arguments, dtype semantics,
+ * errors and synchronisation as igs_assemble_surrogate; IGS_ERR_UNSUPPORTED
+ * when an offset has more than 2048 samples in a direction. */
+igs_status igs_assemble_surrogate_pd(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype,
+                                     void* band, void* stream);
+
 /* ---------------------------------------------------------------- plans */
 
 /* A plan keeps what an assembly needs besides the band: the 1-D tables, tile
@@ -292,6 +329,10 @@ igs_status igs_assemble_noalloc(const igs_problem* pb, int32_t form, int32_t M, 
 typedef struct igs_plan_s* igs_plan;
 igs_status igs_plan_create(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
                            igs_plan* out);
+/* igs_plan_create_pd: as igs_plan_create for the per-delta surrogate
+ * (igs_assemble_surrogate_pd); M >= 1. */
+igs_status igs_plan_create_pd(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
+                              igs_plan* out);
 /* igs_plan_create_fe: as igs_plan_create for the face/edge surrogate
  * (igs_assemble_surrogate_fe); M >= 1. */
 igs_status igs_plan_create_fe(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,

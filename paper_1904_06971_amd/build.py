@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libigs.so")
-SOURCES = ["plan.cpp", "capi.cpp", "profile.cpp", "quad.hip", "fill.hip", "fill2d.hip", "fitgemm.hip", "solve.hip", "adjoint.hip"]
+SOURCES = ["plan.cpp", "capi.cpp", "profile.cpp", "quad.hip", "fill.hip", "fill2d.hip", "fillpd.hip", "fitgemm.hip", "solve.hip", "adjoint.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

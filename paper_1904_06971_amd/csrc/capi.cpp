@@ -41,7 +41,14 @@ hipError_t launch_zero_pad(T* band, int64_t N, int64_t ld, int slots_total, hipS
 template <typename T>
 hipError_t launch_copy(const KInterp<T>& ip, int form, const Dims& d, const int* rows, int nrows, T* band,
                        hipStream_t s);
-std::vector<int> copy_rows(const Dims& d);
+// rows of the box [c, m_d - c - 1]^n within p of its edge (partners outside it)
+std::vector<int> copy_rows(const Dims& d, int c);
+template <typename BT>
+hipError_t launch_fit_pd(const KInterpPD& ip, int n, int64_t ld, int S, int batch, const int* upslot, const BT* band,
+                         double* tmp0, double* tmp1, double* coef, hipStream_t s);
+template <typename T>
+hipError_t launch_fill_pd(const KInterpPD& ip, int form, const Dims& d, const double* coef, T* band, hipStream_t s);
+size_t fill_pd_lds_bytes(const KInterpPD& ip);
 igs_status launch_apply(const Dims& d, int dtype, const void* band, const void* x, void* y, int dirichlet,
                         hipStream_t s);
 igs_status solve_cg(const Dims& d, const double* band64, const float* band32, const double* f, double* u, double rtol,
@@ -220,7 +227,7 @@ static igs_status check_sampling(const Dims& d, int M, int q) {
 // free it; igs_plan_* keep it for repeated runs.
 
 struct Plan {
-  int kind = 0;  // 0 exact, 1 surrogate, 2 face/edge surrogate, 3 matrix-free surrogate
+  int kind = 0;  // 0 exact, 1 surrogate, 2 face/edge, 3 matrix-free, 4 per-delta domains
   int form = 0, dtype = 0, M = 0, q = 0;
   Prepared P;
   Arena ta;
@@ -238,6 +245,9 @@ struct Plan {
   const int* dbrow = nullptr;  // matrix-free: rows outside the analysis domain
   int nbrow = 0;
   double* xm = nullptr;        // matrix-free: Dirichlet-masked copy of x
+  KInterpPD ippd{};            // per-delta: interpolation tables
+  const int* dupslot = nullptr;
+  int pdg[3] = {0, 0, 0};      // per-delta sample tiles: [0] tiles, [2] single rows
   int state = 0;  // geometry flag: 0 not read yet, 1 read and clear, 2 set
   Plan() = default;
   Plan(const Plan&) = delete;
@@ -295,7 +305,7 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
   std::vector<int> chunks = fill_chunks(d, pl->chunk_rows, hi.lo, hi.hi);
   // face/edge: every entry is interpolated or (corners) copied by the identity
   // part of the fit, so no entry is left for the copy kernel
-  std::vector<int> crow = fe ? std::vector<int>() : copy_rows(d);
+  std::vector<int> crow = fe ? std::vector<int>() : copy_rows(d, 2 * d.p);
   std::vector<int> dsl;  // (slot, delta1, delta2, delta3) per interpolated slot
   for (int sl : hi.upslot) {
     const int W = d.W;
@@ -348,6 +358,90 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
   return IGS_OK;
 }
 
+// Per-delta domains (Sec. 4 remark): quadrature of the rows of non-cardinal
+// functions (tiles over the shell outside [p, m_d - p - 1]) and of the common
+// sample rows; one fit and one fill per stencil function on its own domain.
+static igs_status build_surrogate_pd(const igs_problem* pb, hipStream_t s, Plan* pl) {
+  igs_status st = prepare(pb, s, &pl->P);
+  if (st != IGS_OK) return st;
+  const Dims& d = pl->P.d;
+  const int form = pl->form, M = pl->M, q = pl->q, p = d.p;
+  st = check_sampling(d, M, q);
+  if (st != IGS_OK) return st;
+  HostInterpPD hi;
+  st = build_interp_pd(d, form, M, q, &hi);
+  if (st != IGS_OK) return st;
+  int tx, ty;
+  quad_tile_shape(d.n, d.p, &tx, &ty);
+  const int zchunk = pick_zchunk(d, tx, ty);
+  int sg[2];
+  std::vector<QTile> tiles = tiles_shell(d, p, tx, ty, zchunk, sg);
+  pl->groups[0] = sg[0];
+  pl->groups[1] = sg[1];
+  pl->groups[2] = 0;
+  int g2[3];
+  std::vector<QTile> st_tiles = tiles_fe(d, hi.U, tx, ty, zchunk, g2);
+  pl->pdg[0] = g2[0];
+  pl->pdg[1] = 0;
+  pl->pdg[2] = g2[2];
+  tiles.insert(tiles.end(), st_tiles.begin(), st_tiles.end());
+  const int sm = hi.smax;
+  const size_t per = d.n == 3 ? size_t(sm) * sm * sm : size_t(sm) * sm;
+  const size_t ncoef = per * hi.upslot.size() * d.batch;
+  std::vector<int> crow = copy_rows(d, p);
+  size_t bytes = padded(tiles.size() * sizeof(QTile)) + 3 * padded(ncoef * sizeof(double)) + vbytes(crow) +
+                 vbytes(hi.upslot);
+  for (int k = 0; k < d.n; ++k)
+    bytes += vbytes(hi.U[k]) + vbytes(hi.pos[k]) + vbytes(hi.ginv[k]) + vbytes(hi.ef[k]) + vbytes(hi.eb[k]);
+  st = pl->ta.alloc(bytes, s);
+  if (st != IGS_OK) return st;
+  Arena& ta = pl->ta;
+  pl->dt = upload(ta, tiles, s, &st);
+  pl->ntiles = int(tiles.size());
+  KInterpPD& ip = pl->ippd;
+  std::memset(&ip, 0, sizeof(ip));
+  ip.q = q;
+  ip.p = p;
+  ip.W = d.W;
+  ip.smax = sm;
+  ip.nup = int(hi.upslot.size());
+  ip.form = form;
+  for (int k = 0; k < 3; ++k) {
+    ip.m[k] = k < d.n ? d.m[k] : 1;
+    for (int e = 0; e < kMaxW; ++e) {
+      ip.S[k][e] = e < d.W ? hi.S[k][e] : 1;
+      ip.lo[k][e] = e < d.W ? hi.lo[k][e] : 0;
+      ip.hi[k][e] = e < d.W ? hi.hi[k][e] : 0;
+    }
+    if (k < d.n) {
+      ip.nu[k] = int(hi.U[k].size());
+      ip.U[k] = upload(ta, hi.U[k], s, &st);
+      ip.pos[k] = upload(ta, hi.pos[k], s, &st);
+      ip.ginv[k] = upload(ta, hi.ginv[k], s, &st);
+      ip.ef[k] = upload(ta, hi.ef[k], s, &st);
+      ip.eb[k] = upload(ta, hi.eb[k], s, &st);
+    }
+  }
+  pl->dupslot = upload(ta, hi.upslot, s, &st);
+  pl->dcopy = upload(ta, crow, s, &st);
+  pl->ncopy = int(crow.size());
+  pl->tmp0 = ta.take<double>(ncoef);
+  pl->tmp1 = ta.take<double>(ncoef);
+  pl->coef = ta.take<double>(ncoef);
+  if (st == IGS_OK) st = ta.flush();
+  if (st != IGS_OK) return st;
+  if (fill_pd_lds_bytes(ip) > 64 * 1024) return IGS_ERR_UNSUPPORTED;
+  // the copy / diagonal fix-up kernels only test partners against the box of
+  // cardinal rows
+  pl->ipd = KInterp<double>{};
+  pl->ipf = KInterp<float>{};
+  for (int k = 0; k < 3; ++k) {
+    pl->ipd.lo[k] = pl->ipf.lo[k] = k < d.n ? p : 0;
+    pl->ipd.hi[k] = pl->ipf.hi[k] = k < d.n ? d.m[k] - p - 1 : 0;
+  }
+  return IGS_OK;
+}
+
 template <typename OutT>
 static igs_status run_t(const Plan& pl, const KProblem& kp, const KInterp<OutT>& ipT, OutT* band, hipStream_t s) {
   const Dims& d = pl.P.d;
@@ -379,6 +473,44 @@ static igs_status run_t(const Plan& pl, const KProblem& kp, const KInterp<OutT>&
       HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt, pl.groups[0] + pl.groups[1], false, band, s));
     }
     return IGS_OK;
+  } else if (pl.kind == 4) {
+    // per-delta domains: sample rows, fit, fill of the cardinal rows' entries
+    // whose partner is cardinal, then the non-cardinal rows, which (3-D) also
+    // store every entry of a cardinal partner there (transposed store), and the
+    // copy (2-D) or diagonal fix-up (3-D stiffness) of those entries
+    const QTile* ts = pl.dt + pl.groups[0] + pl.groups[1];
+    {
+      PhaseTimer t("quad_pd_sample_tiles", s);
+      HIP_TRY(launch_quad<OutT>(kp, pl.form, ts, pl.pdg[0], false, band, s));
+    }
+    if (pl.pdg[2] > 0) {
+      PhaseTimer t("quad_pd_sample_rows", s);
+      HIP_TRY(launch_quad<OutT>(kp, pl.form, ts + pl.pdg[0], pl.pdg[2], true, band, s));
+    }
+    {
+      PhaseTimer t("fit", s);
+      HIP_TRY(launch_fit_pd<OutT>(pl.ippd, d.n, d.ld, d.S, d.batch, pl.dupslot, band, pl.tmp0, pl.tmp1, pl.coef, s));
+    }
+    {
+      PhaseTimer t("fill", s);
+      HIP_TRY(launch_fill_pd<OutT>(pl.ippd, pl.form, d, pl.coef, band, s));
+    }
+    {
+      KProblem kt = kp;
+      if (d.n == 3) {
+        kt.transpose = 1;
+        for (int k = 0; k < 3; ++k) {
+          kt.tr_lo[k] = d.p;
+          kt.tr_hi[k] = d.m[k] - d.p - 1;
+        }
+      }
+      PhaseTimer t("quad_boundary_rows", s);
+      HIP_TRY(launch_quad<OutT>(kt, pl.form, pl.dt, pl.groups[0] + pl.groups[1], false, band, s));
+    }
+    if (pl.ncopy > 0 && (d.n == 2 || pl.form == IGS_STIFFNESS)) {
+      PhaseTimer t(d.n == 3 ? "diag_fixup" : "copy", s);
+      HIP_TRY(launch_copy<OutT>(ipT, pl.form, d, pl.dcopy, pl.ncopy, band, s));
+    }
   } else if (pl.kind == 2) {
     // face/edge: the quadrature rows (every sample row of every class, and the
     // corner rows), the fit over the augmented sample sets, and one fill over
@@ -490,7 +622,9 @@ static igs_status one_shot(const igs_problem* pb, int kind, int form, int M, int
   pl.dtype = dtype;
   pl.M = M;
   pl.q = q;
-  igs_status st = kind == 0 ? build_exact(pb, s, &pl) : build_surrogate(pb, s, &pl);
+  igs_status st = kind == 0 ? build_exact(pb, s, &pl)
+                  : kind == 4 ? build_surrogate_pd(pb, s, &pl)
+                              : build_surrogate(pb, s, &pl);
   if (st != IGS_OK) return st;
   st = run_plan(pl, nullptr, band, s);
   if (st != IGS_OK) return st;
@@ -699,6 +833,43 @@ igs_status igs_surrogate_fe_layout(const igs_problem* pb, int32_t M, int32_t q, 
   return IGS_OK;
 }
 
+igs_status igs_assemble_surrogate_pd(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype,
+                                     void* band, void* stream) {
+  if (!pb || !band) return IGS_ERR_ARG;
+  if (form != IGS_STIFFNESS && form != IGS_MASS) return IGS_ERR_ARG;
+  if (dtype != IGS_F64 && dtype != IGS_F32) return IGS_ERR_ARG;
+  Dims d;
+  igs_status st = make_dims(pb, &d);
+  if (st != IGS_OK) return st;
+  st = check_sampling(d, M, q);
+  if (st != IGS_OK) return st;
+  return one_shot(pb, 4, form, M, q, dtype, band, static_cast<hipStream_t>(stream));
+}
+
+igs_status igs_surrogate_pd_layout(const igs_problem* pb, int32_t M, int32_t q, igs_pd_info* out) {
+  if (!out) return IGS_ERR_ARG;
+  Dims d;
+  igs_status st = make_dims(pb, &d);
+  if (st != IGS_OK) return st;
+  st = check_sampling(d, M, q);
+  if (st != IGS_OK) return st;
+  HostInterpPD hi;
+  st = build_interp_pd(d, IGS_STIFFNESS, M, q, &hi);
+  if (st != IGS_OK) return st;
+  std::memset(out, 0, sizeof(*out));
+  int64_t card = 1, samp = 1;
+  for (int k = 0; k < 3; ++k) {
+    out->samples[k] = k < d.n ? int32_t(hi.U[k].size()) : 1;
+    out->max_samples[k] = 1;
+    for (int e = 0; k < d.n && e < d.W; ++e) out->max_samples[k] = std::max(out->max_samples[k], hi.S[k][e]);
+    if (k < d.n) card *= d.m[k] - 2 * d.p;
+    samp *= out->samples[k];
+  }
+  out->noncardinal_rows = d.N - card;
+  out->quadrature_rows = out->noncardinal_rows + samp;
+  return IGS_OK;
+}
+
 struct igs_plan_s {
   igs::Plan pl;
   hipStream_t last = nullptr;
@@ -729,7 +900,9 @@ static igs_status plan_create(const igs_problem* pb, int32_t form, int32_t M, in
   h->pl.dtype = dtype;
   h->pl.M = M;
   h->pl.q = q;
-  st = h->pl.kind == 0 ? build_exact(pb, s, &h->pl) : build_surrogate(pb, s, &h->pl);
+  st = h->pl.kind == 0   ? build_exact(pb, s, &h->pl)
+       : h->pl.kind == 4 ? build_surrogate_pd(pb, s, &h->pl)
+                         : build_surrogate(pb, s, &h->pl);
   // the plan's memory and tables are complete before any other stream uses them
   if (st == IGS_OK && hipStreamSynchronize(s) != hipSuccess) st = IGS_ERR_HIP;
   if (st != IGS_OK) {
@@ -749,6 +922,11 @@ igs_status igs_plan_create(const igs_problem* pb, int32_t form, int32_t M, int32
 igs_status igs_plan_create_fe(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
                               igs_plan* out) {
   return plan_create(pb, form, M, q, dtype, stream, out, 2);
+}
+
+igs_status igs_plan_create_pd(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* stream,
+                              igs_plan* out) {
+  return plan_create(pb, form, M, q, dtype, stream, out, 4);
 }
 
 igs_status igs_plan_create_mf(const igs_problem* pb, int32_t form, int32_t M, int32_t q, void* stream, igs_plan* out) {

@@ -1125,12 +1125,12 @@ std::vector<int> boundary_rows(const Dims& d) {
 
 // analysis-domain rows within p-1 of the domain's edge in some direction: the
 // rows whose stencil reaches outside the analysis domain, in flat order
-std::vector<int> copy_rows(const Dims& d) {
+std::vector<int> copy_rows(const Dims& d, int c) {
   const int p = d.p;
   int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   for (int k = 0; k < d.n; ++k) {
-    lo[k] = 2 * p;
-    hi[k] = d.m[k] - 2 * p - 1;
+    lo[k] = c;
+    hi[k] = d.m[k] - c - 1;
   }
   auto edge = [&](int k, int i) { return k < d.n && (i < lo[k] + p || i > hi[k] - p); };
   std::vector<int> out;

@@ -79,6 +79,25 @@ struct KInterp {
                          // outside it ginv is the identity (face/edge layers)
 };
 
+// Interpolation with a domain per stencil function (per-delta surrogate).
+// Per direction d and offset e = delta_d + p, the stencil function's domain is
+// the index range [lo, hi] where row i and partner i + delta_d index cardinal
+// B-splines; its samples are a subset of the direction's common sample
+// indices U (the analysis-domain lattice plus the two transition bands).
+constexpr int kMaxW = 9;  // 2p + 1 offsets per direction, p <= 4
+struct KInterpPD {
+  int q, p, W, smax, nup, form;
+  int m[3];
+  int S[3][kMaxW];                  // samples of offset e (first = lo, last = hi)
+  int lo[3][kMaxW], hi[3][kMaxW];   // domain index range of offset e
+  int nu[3];                        // size of U per direction
+  const int* U[3];                  // [nu] common sample indices
+  const int* pos[3];                // [W][smax] position in U of sample k of offset e
+  const double* ginv[3];            // [W][smax][smax] inverse collocation matrices
+  const int* ef[3];                 // [W][m] first spline coefficient alive at index i
+  const double* eb[3];              // [W][q+1][m] spline values at index i
+};
+
 // ---------------------------------------------------------------- host plan
 
 struct Dims {
@@ -119,6 +138,25 @@ igs_status build_interp(const Dims& d, int form, int M, int q, int boxlen[3], Ho
 // the degree-q spline on the lattice part and the identity on the layers, and
 // the fill covers every index.  samp[d] then lists every quadrature index.
 igs_status build_interp_fe(const Dims& d, int form, int M, int q, int boxlen[3], HostInterp* hi);
+
+struct HostInterpPD {
+  int q, p, W, smax;
+  std::vector<int> U[3];
+  int S[3][kMaxW], lo[3][kMaxW], hi[3][kMaxW];
+  std::vector<int> pos[3];      // [W][smax]
+  std::vector<double> ginv[3];  // [W][smax][smax]
+  std::vector<int> ef[3];       // [W][m]
+  std::vector<double> eb[3];    // [W][q+1][m]
+  std::vector<int> upslot;
+};
+// Per-delta surrogate (Sec. 4 remark): per direction the common sample set U
+// and, per offset, its samples, inverse collocation matrix and evaluation
+// tables.  IGS_ERR_SAMPLES when an offset has fewer than q+1 samples.
+igs_status build_interp_pd(const Dims& d, int form, int M, int q, HostInterpPD* hi);
+// Rows outside the box [c, m_d - c - 1]^n as tiles streamed along the last
+// direction (groups[0]: rows of the box's pencils outside it in i1, groups[1]:
+// the other pencils), long tiles first.
+std::vector<QTile> tiles_shell(const Dims& d, int c, int tx, int ty, int zchunk, int groups[2]);
 
 // Tile lists.
 std::vector<QTile> tiles_all(const Dims& d, int tx, int ty, int zchunk);

@@ -255,46 +255,58 @@ igs_status sample_lattice(int m, int p, int M, std::vector<int>* s) {
   return IGS_OK;
 }
 
+// Degree-q interpolation on the sample indices s (increasing): the inverse
+// collocation matrix (row-major S x S) and, for every index i in [s_0,
+// s_{S-1}], the first spline coefficient alive at i and the q+1 values there
+// (ef[i], eb[i (q+1) + c]; ef and eb span m indices).
+static igs_status spline_1d(const std::vector<int>& s, int q, int m, std::vector<double>* ginv, std::vector<int>* ef,
+                            std::vector<double>* eb) {
+  const int S = int(s.size());
+  if (S < q + 1) return IGS_ERR_SAMPLES;
+  // knots: end samples repeated q+1 times; interior = samples (odd q,
+  // not-a-knot) or midpoints of consecutive samples (even q)
+  std::vector<double> t;
+  for (int r = 0; r <= q; ++r) t.push_back(s[0]);
+  if (q % 2 == 1) {
+    for (int r = (q + 1) / 2; r <= S - 1 - (q + 1) / 2; ++r) t.push_back(s[r]);
+  } else {
+    for (int r = q / 2; r <= S - 2 - q / 2; ++r) t.push_back(0.5 * (s[r] + s[r + 1]));
+  }
+  for (int r = 0; r <= q; ++r) t.push_back(s[S - 1]);
+  // span of a point: last span with t[k] <= x, capped at the last nonempty one
+  auto span_of = [&](double x) {
+    int sp = q;
+    while (sp + 1 < S && t[sp + 1] <= x) ++sp;
+    return sp;
+  };
+  std::vector<double> G(size_t(S) * S, 0.0);
+  double vals[16];
+  for (int r = 0; r < S; ++r) {
+    int sp = span_of(s[r]);
+    span_basis(t, sp, q, s[r], vals);
+    for (int c = 0; c <= q; ++c) G[size_t(r) * S + sp - q + c] = vals[c];
+  }
+  if (!invert(G, S, ginv)) return IGS_ERR_SAMPLES;
+  ef->assign(m, 0);
+  eb->assign(size_t(m) * (q + 1), 0.0);
+  for (int i = s[0]; i <= s[S - 1]; ++i) {
+    int sp = span_of(i);
+    span_basis(t, sp, q, i, vals);
+    (*ef)[i] = sp - q;
+    for (int c = 0; c <= q; ++c) (*eb)[size_t(i) * (q + 1) + c] = vals[c];
+  }
+  return IGS_OK;
+}
+
 igs_status build_interp(const Dims& d, int form, int M, int q, int boxlen[3], HostInterp* hi) {
   hi->q = q;
   for (int k = 0; k < d.n; ++k) {
     igs_status st = sample_lattice(d.m[k], d.p, M, &hi->samp[k]);
     if (st != IGS_OK) return st;
     const int S = int(hi->samp[k].size());
-    if (S < q + 1) return IGS_ERR_SAMPLES;
-    // knots: end samples repeated q+1 times; interior = samples (odd q,
-    // not-a-knot) or midpoints of consecutive samples (even q)
     const std::vector<int>& s = hi->samp[k];
-    std::vector<double> t;
-    for (int r = 0; r <= q; ++r) t.push_back(s[0]);
-    if (q % 2 == 1) {
-      for (int r = (q + 1) / 2; r <= S - 1 - (q + 1) / 2; ++r) t.push_back(s[r]);
-    } else {
-      for (int r = q / 2; r <= S - 2 - q / 2; ++r) t.push_back(0.5 * (s[r] + s[r + 1]));
-    }
-    for (int r = 0; r <= q; ++r) t.push_back(s[S - 1]);
-    // span of a point: last span with t[k] <= x, capped at the last nonempty one
-    auto span_of = [&](double x) {
-      int sp = q;
-      while (sp + 1 < S && t[sp + 1] <= x) ++sp;
-      return sp;
-    };
-    std::vector<double> G(size_t(S) * S, 0.0);
-    double vals[16];
-    for (int r = 0; r < S; ++r) {
-      int sp = span_of(s[r]);
-      span_basis(t, sp, q, s[r], vals);
-      for (int c = 0; c <= q; ++c) G[size_t(r) * S + sp - q + c] = vals[c];
-    }
-    if (!invert(G, S, &hi->ginv[k])) return IGS_ERR_SAMPLES;
-    hi->ef[k].assign(d.m[k], 0);
-    hi->eb[k].assign(size_t(d.m[k]) * (q + 1), 0.0);
-    for (int i = s[0]; i <= s[S - 1]; ++i) {
-      int sp = span_of(i);
-      span_basis(t, sp, q, i, vals);
-      hi->ef[k][i] = sp - q;
-      for (int c = 0; c <= q; ++c) hi->eb[k][size_t(i) * (q + 1) + c] = vals[c];
-    }
+    st = spline_1d(s, q, d.m[k], &hi->ginv[k], &hi->ef[k], &hi->eb[k]);
+    if (st != IGS_OK) return st;
     // widest coefficient span of any window of boxlen[k] consecutive indices
     int nc = 0;
     for (int i = s[0]; i <= s[S - 1]; ++i) {
@@ -374,6 +386,76 @@ igs_status build_interp_fe(const Dims& d, int form, int M, int q, int boxlen[3],
     hi->flo[k] = 0;
     hi->fhi[k] = 1;
   }
+  return IGS_OK;
+}
+
+igs_status build_interp_pd(const Dims& d, int form, int M, int q, HostInterpPD* hi) {
+  const int p = d.p, W = 2 * p + 1;
+  if (W > kMaxW) return IGS_ERR_UNSUPPORTED;
+  hi->q = q;
+  hi->p = p;
+  hi->W = W;
+  hi->smax = 1;
+  std::vector<int> samp[3][kMaxW];
+  for (int k = 0; k < d.n; ++k) {
+    std::vector<int> base;
+    igs_status st = sample_lattice(d.m[k], p, M, &base);
+    if (st != IGS_OK) return st;
+    const int m = d.m[k];
+    // common set: band [p, 2p), the lattice, band [m - 2p, m - p)
+    hi->U[k].clear();
+    for (int i = p; i < 2 * p; ++i) hi->U[k].push_back(i);
+    for (int v : base) hi->U[k].push_back(v);
+    for (int i = m - 2 * p; i < m - p; ++i) hi->U[k].push_back(i);
+    for (int e = 0; e < W; ++e) {
+      const int dd = e - p;
+      const int lo = p + std::max(0, -dd), hi_ = m - p - 1 - std::max(0, dd);
+      for (int v : hi->U[k])
+        if (v >= lo && v <= hi_) samp[k][e].push_back(v);
+      hi->S[k][e] = int(samp[k][e].size());
+      hi->lo[k][e] = lo;
+      hi->hi[k][e] = hi_;
+      if (hi->S[k][e] < q + 1) return IGS_ERR_SAMPLES;
+      hi->smax = std::max(hi->smax, hi->S[k][e]);
+    }
+  }
+  const int sm = hi->smax;
+  for (int k = 0; k < 3; ++k) {
+    hi->pos[k].clear();
+    hi->ginv[k].clear();
+    hi->ef[k].clear();
+    hi->eb[k].clear();
+    if (k >= d.n) {
+      for (int e = 0; e < W; ++e) hi->S[k][e] = 1, hi->lo[k][e] = hi->hi[k][e] = 0;
+      continue;
+    }
+    const int m = d.m[k];
+    hi->pos[k].assign(size_t(W) * sm, 0);
+    hi->ginv[k].assign(size_t(W) * sm * sm, 0.0);
+    hi->ef[k].assign(size_t(W) * m, 0);
+    hi->eb[k].assign(size_t(W) * (q + 1) * m, 0.0);
+    for (int e = 0; e < W; ++e) {
+      const std::vector<int>& s = samp[k][e];
+      const int S = int(s.size());
+      for (int r = 0; r < S; ++r)
+        hi->pos[k][size_t(e) * sm + r] =
+            int(std::lower_bound(hi->U[k].begin(), hi->U[k].end(), s[r]) - hi->U[k].begin());
+      std::vector<double> gi, eb;
+      std::vector<int> ef;
+      igs_status st = spline_1d(s, q, m, &gi, &ef, &eb);
+      if (st != IGS_OK) return st;
+      for (int r = 0; r < S; ++r)
+        for (int c = 0; c < S; ++c) hi->ginv[k][(size_t(e) * sm + r) * sm + c] = gi[size_t(r) * S + c];
+      for (int i = 0; i < m; ++i) {
+        hi->ef[k][size_t(e) * m + i] = ef[i];
+        for (int c = 0; c <= q; ++c) hi->eb[k][(size_t(e) * (q + 1) + c) * m + i] = eb[size_t(i) * (q + 1) + c];
+      }
+    }
+  }
+  hi->upslot.clear();
+  const int sc = (d.S - 1) / 2;
+  for (int s = 0; s < d.S; ++s)
+    if (s > sc || (form == IGS_MASS && s == sc)) hi->upslot.push_back(s);
   return IGS_OK;
 }
 
@@ -458,6 +540,29 @@ std::vector<QTile> tiles_surrogate(const Dims& d, const std::vector<int> samp[3]
     for (int s2 : samp[1]) tile_rect(&out, samp[0].front(), samp[0].back() + 1, 0, 1, tx, 1, s2, s2 + 1, 1);
   }
   groups[2] = int(out.size()) - groups[0] - groups[1];
+  return out;
+}
+
+std::vector<QTile> tiles_shell(const Dims& d, int c, int tx, int ty, int zchunk, int groups[2]) {
+  std::vector<QTile> out;
+  const int lo1 = c, hi1 = d.m[0] - c, lo2 = c, hi2 = d.m[1] - c;
+  if (d.n == 3) {
+    const int lo3 = c, hi3 = d.m[2] - c;
+    tile_rect(&out, 0, lo1, lo2, hi2, tx, ty, lo3, hi3, zchunk);
+    tile_rect(&out, hi1, d.m[0], lo2, hi2, tx, ty, lo3, hi3, zchunk);
+    groups[0] = int(out.size());
+    tile_rect(&out, 0, d.m[0], 0, lo2, tx, ty, 0, d.m[2], zchunk);
+    tile_rect(&out, 0, d.m[0], hi2, d.m[1], tx, ty, 0, d.m[2], zchunk);
+    tile_rect(&out, 0, d.m[0], lo2, hi2, tx, ty, 0, lo3, zchunk);
+    tile_rect(&out, 0, d.m[0], lo2, hi2, tx, ty, hi3, d.m[2], zchunk);
+  } else {
+    tile_rect(&out, 0, lo1, 0, 1, tx, 1, lo2, hi2, zchunk);
+    tile_rect(&out, hi1, d.m[0], 0, 1, tx, 1, lo2, hi2, zchunk);
+    groups[0] = int(out.size());
+    tile_rect(&out, 0, d.m[0], 0, 1, tx, 1, 0, lo2, zchunk);
+    tile_rect(&out, 0, d.m[0], 0, 1, tx, 1, hi2, d.m[1], zchunk);
+  }
+  groups[1] = int(out.size()) - groups[0];
   return out;
 }
 

@@ -28,7 +28,8 @@ SRC_CONST, SRC_SINE = 0, 1
 EXPORTS = ["igs_band_layout", "igs_validate", "igs_surrogate_layout", "igs_sampling_length", "igs_status_string",
            "igs_version",
            "igs_assemble_exact", "igs_assemble_surrogate", "igs_assemble_noalloc", "igs_assemble_surrogate_fe",
-           "igs_surrogate_fe_layout", "igs_plan_create", "igs_plan_create_fe", "igs_plan_create_mf",
+           "igs_surrogate_fe_layout", "igs_assemble_surrogate_pd", "igs_surrogate_pd_layout", "igs_plan_create",
+           "igs_plan_create_fe", "igs_plan_create_pd", "igs_plan_create_mf",
            "igs_apply_mf", "igs_solve_cg_mf", "igs_plan_execute", "igs_plan_destroy",
            "igs_assemble_rhs", "igs_apply", "igs_solve_cg", "igs_apply_vjp", "igs_compliance_grad",
            "igs_profile_enable", "igs_profile_read"]
@@ -70,6 +71,11 @@ class FEInfo(ctypes.Structure):
                 ("quadrature_rows", ctypes.c_int64)]
 
 
+class PDInfo(ctypes.Structure):
+    _fields_ = [("samples", ctypes.c_int32 * 3), ("max_samples", ctypes.c_int32 * 3),
+                ("noncardinal_rows", ctypes.c_int64), ("quadrature_rows", ctypes.c_int64)]
+
+
 class ProfilePhase(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int32), ("ms", ctypes.c_double)]
 
@@ -106,6 +112,9 @@ def lib():
             "igs_assemble_surrogate_fe": [P, i32, i32, i32, i32, vp, vp],
             "igs_surrogate_fe_layout": [P, i32, i32, ctypes.POINTER(FEInfo)],
             "igs_plan_create_fe": [P, i32, i32, i32, i32, vp, ctypes.POINTER(vp)],
+            "igs_assemble_surrogate_pd": [P, i32, i32, i32, i32, vp, vp],
+            "igs_surrogate_pd_layout": [P, i32, i32, ctypes.POINTER(PDInfo)],
+            "igs_plan_create_pd": [P, i32, i32, i32, i32, vp, ctypes.POINTER(vp)],
             "igs_plan_create_mf": [P, i32, i32, i32, vp, ctypes.POINTER(vp)],
             "igs_apply_mf": [vp, vp, vp, vp, i32, vp],
             "igs_solve_cg_mf": [vp, vp, vp, vp, f64, i32, ctypes.POINTER(CgInfo), vp],
@@ -296,6 +305,25 @@ def assemble_surrogate_fe(prob, form=STIFFNESS, M=8, q=3, dtype=None, out=None, 
     return band
 
 
+def assemble_surrogate_pd(prob, form=STIFFNESS, M=8, q=3, dtype=None, out=None, device="cuda"):
+    """igs_assemble_surrogate_pd: surrogate with a domain per stencil function."""
+    torch = _torch()
+    tdt, cdt = _dt(dtype if dtype is not None else torch.float64)
+    band = out if out is not None else empty_band(prob, tdt, device)
+    cc = _coef_tensor(prob, band.device)
+    pb = make_problem(prob, None if cc is None else cc.data_ptr())
+    _check(lib().igs_assemble_surrogate_pd(ctypes.byref(pb), form, M, q, cdt, band.data_ptr(), _stream()),
+           "igs_assemble_surrogate_pd")
+    return band
+
+
+def surrogate_pd_layout(prob, M, q):
+    info = PDInfo()
+    _check(lib().igs_surrogate_pd_layout(ctypes.byref(make_problem(prob, coef_ptr=1)), M, q, ctypes.byref(info)),
+           "igs_surrogate_pd_layout")
+    return info
+
+
 def assemble_noalloc(prob, form=STIFFNESS, M=0, q=3, dtype=None, out=None, device="cuda"):
     """igs_assemble_noalloc: M = 0 full assembly, M >= 1 surrogate, with the
     library's static scratch instead of device allocations (the band is the
@@ -312,12 +340,13 @@ def assemble_noalloc(prob, form=STIFFNESS, M=0, q=3, dtype=None, out=None, devic
 
 class Plan:
     """A kept assembly plan (igs_plan_*): M = 0 full assembly, M >= 1 surrogate
-    (face_edge=True: igs_plan_create_fe).  execute() queues the assembly on
+    (face_edge=True: igs_plan_create_fe; per_delta=True: igs_plan_create_pd;
+    matrix_free=True: igs_plan_create_mf).  execute() queues the assembly on
     torch's current stream; the first call synchronises and checks the
     geometry, later calls only queue."""
 
     def __init__(self, prob, form=STIFFNESS, M=8, q=3, dtype=None, device="cuda", face_edge=False,
-                 matrix_free=False):
+                 matrix_free=False, per_delta=False):
         torch = _torch()
         self.prob = prob
         self.tdt, self.cdt = _dt(dtype if dtype is not None else torch.float64)
@@ -329,9 +358,8 @@ class Plan:
             _check(lib().igs_plan_create_mf(ctypes.byref(pb), form, M, q, _stream(), ctypes.byref(h)),
                    "igs_plan_create_mf")
         else:
-            create = lib().igs_plan_create_fe if face_edge else lib().igs_plan_create
-            _check(create(ctypes.byref(pb), form, M, q, self.cdt, _stream(), ctypes.byref(h)),
-                   "igs_plan_create_fe" if face_edge else "igs_plan_create")
+            name = "igs_plan_create_fe" if face_edge else "igs_plan_create_pd" if per_delta else "igs_plan_create"
+            _check(getattr(lib(), name)(ctypes.byref(pb), form, M, q, self.cdt, _stream(), ctypes.byref(h)), name)
         self._h = h
 
     def execute(self, out=None, coef=None):

@@ -81,6 +81,25 @@ def test_surrogate_fe_layout_matches_oracle(oracle, prob, M, q):
         assert info.quadrature_rows == np.prod([info.samples[d] for d in range(n)])
 
 
+@pytest.mark.parametrize("prob,M,q", [(W.problem(2, 2, 30), 4, 3), (W.problem(3, 3, 40), 6, 3),
+                                      (W.c4_precision3d(), 8, 3), (W.problem(3, 4, 30), 5, 2)])
+def test_surrogate_pd_layout_matches_oracle(oracle, prob, M, q):
+    """Per-delta sampling: per-direction common sample sets, the largest
+    per-offset sample count, non-cardinal and quadrature row counts against the
+    oracle's own definitions."""
+    info = igs.surrogate_pd_layout(prob, M, q)
+    m, N, _ = oracle.dims(prob)
+    p, n = prob["p"], prob["n"]
+    for d in range(n):
+        assert info.samples[d] == len(oracle.sample_union_pd(m[d], p, M))
+        assert info.max_samples[d] == max(len(oracle.lattice_pd(m[d], p, M, dd)) for dd in range(-p, p + 1))
+    assert info.noncardinal_rows == N - np.prod([m[d] - 2 * p for d in range(n)])
+    if N < 400000:
+        assert info.quadrature_rows == int(oracle.quadrature_rows_pd(prob, M).sum())
+    else:
+        assert info.quadrature_rows == info.noncardinal_rows + np.prod([info.samples[d] for d in range(n)])
+
+
 def test_published_sizes():
     """Sizes quoted for the workloads: 34^2 = 1156 dofs; 67^3 = 300,763 dofs with
     343-entry stencils; 132^3 with 729-entry stencils; 131^3 ~ 2.25M dofs; 259^2."""
