@@ -48,7 +48,7 @@ hipError_t launch_fit_pd(const KInterpPD& ip, int n, int64_t ld, int S, int batc
                          double* tmp0, double* tmp1, double* coef, hipStream_t s);
 template <typename T>
 hipError_t launch_fill_pd(const KInterpPD& ip, int form, const Dims& d, const double* coef, T* band, hipStream_t s);
-size_t fill_pd_lds_bytes(const KInterpPD& ip);
+size_t fill_pd_lds_bytes(const KInterpPD& ip, int S);
 igs_status launch_apply(const Dims& d, int dtype, const void* band, const void* x, void* y, int dirichlet,
                         hipStream_t s);
 igs_status solve_cg(const Dims& d, const double* band64, const float* band32, const double* f, double* u, double rtol,
@@ -430,7 +430,7 @@ static igs_status build_surrogate_pd(const igs_problem* pb, hipStream_t s, Plan*
   pl->coef = ta.take<double>(ncoef);
   if (st == IGS_OK) st = ta.flush();
   if (st != IGS_OK) return st;
-  if (fill_pd_lds_bytes(ip) > 64 * 1024) return IGS_ERR_UNSUPPORTED;
+  if (fill_pd_lds_bytes(ip, d.S) > (d.n == 3 ? 160 : 64) * 1024) return IGS_ERR_UNSUPPORTED;
   // the copy / diagonal fix-up kernels only test partners against the box of
   // cardinal rows
   pl->ipd = KInterp<double>{};

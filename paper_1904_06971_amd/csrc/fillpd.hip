@@ -182,126 +182,229 @@ __global__ void __launch_bounds__(64 * kPdWaves)
   }
 }
 
-// 3-D fill.  A block owns one plane i3 and kP2 consecutive pencils i2 (a wave
-// takes every fourth); per slot the block first contracts the coefficients
-// over direction 3 into a slab C3[k2][k1] covering the coefficient rows k2 its
-// pencils need (LDS, shared by the pencils), then each wave contracts
+// 3-D fill.  A block owns one plane i3 and kP2 consecutive pencils i2 (wave w
+// takes pencils w, w + 4, ...) and walks the active slots in groups of kGrp.
+// Phase 1: per slot of the group, one wave contracts the coefficients over
+// direction 3 into a slab C3[k2][k1] covering the coefficient rows k2 the
+// block's pencils need (global loads only).  Phase 2: each wave contracts
 // direction 2 for one pencil at a time into its line t[k1] and evaluates
-// direction 1 along the pencil.  The direction-2 spline rows of every offset
-// at the block's evaluation indices i2 - p .. i2 + kP2 - 1 + p are staged in
-// LDS once.
+// direction 1 along the pencil (LDS reads and band stores only).  Loads and
+// stores share one in-order counter on this hardware, so a load issued after
+// stores waits for them too; grouping keeps that wait to once per group.  The
+// spline rows of directions 1 and 2 at the block's evaluation indices are
+// staged in LDS (direction 1 per segment of 128 rows).
 constexpr int kP2 = 16;
+constexpr int kGrp = 8;
+constexpr int kSeg = 64 * 2;  // rows per lane pair and segment
 
-template <int FORM, int Q, typename T>
+struct Pd3Layout {
+  size_t c3, tl, e2b, e2f, e1b, e1f, slist, total;  // byte offsets
+};
+
+__host__ __device__ inline Pd3Layout pd3_layout(int sm, int W, int q, int p, int S) {
+  Pd3Layout L;
+  const size_t NJ = kP2 + 2 * p, NJ1 = kSeg + 2 * p;
+  L.c3 = 0;
+  L.tl = L.c3 + size_t(kGrp) * (kP2 + q + 1) * sm * sizeof(double);
+  L.e2b = L.tl + size_t(kPdWaves) * (kP2 / kPdWaves) * sm * sizeof(double);
+  L.e1b = L.e2b + size_t(W) * (q + 1) * NJ * sizeof(double);
+  L.e2f = L.e1b + size_t(W) * (q + 1) * NJ1 * sizeof(double);
+  L.e1f = L.e2f + size_t(W) * NJ * sizeof(int);
+  L.slist = L.e1f + size_t(W) * NJ1 * sizeof(int);
+  L.total = L.slist + size_t(S + 1) * sizeof(int);
+  return L;
+}
+
+// t / d for t, d < 2^16 with a 32-bit multiply-high and one exact correction
+// (d and its reciprocal m = floor(2^32 / d) + 1 are wave-uniform)
+__device__ __forceinline__ int div_small(int t, int d, unsigned m) {
+  int q = int(__umulhi(unsigned(t), m));
+  if (t - q * d >= d) ++q;
+  if (t - q * d < 0) --q;
+  return q;
+}
+
+template <int FORM, int P, int Q, typename T>
 __global__ void __launch_bounds__(64 * kPdWaves)
     fill_pd3_kernel(KInterpPD ip, int64_t ld, int S, int nchunk2, const double* __restrict__ coef,
                     T* __restrict__ band) {
   extern __shared__ double sh[];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, tid = threadIdx.x;
-  const int sm = ip.smax, W = ip.W, p = ip.p;
+  constexpr int W = 2 * P + 1, p = P;
+  const int sm = ip.smax;
   const int m1 = ip.m[0], m2 = ip.m[1], m3 = ip.m[2];
-  const int NJ = kP2 + 2 * p;                       // evaluation indices of direction 2
-  double* C3 = sh;                                  // [(kP2 + Q + 1)][sm]
-  double* tl = C3 + size_t(kP2 + Q + 1) * sm + size_t(w) * sm;
-  double* E2b = C3 + size_t(kP2 + Q + 1 + kPdWaves) * sm;   // [W][Q+1][NJ]
-  int* E2f = reinterpret_cast<int*>(E2b + size_t(W) * (Q + 1) * NJ);  // [W][NJ]
+  const Pd3Layout L = pd3_layout(sm, W, Q, p, S);
+  char* base = reinterpret_cast<char*>(sh);
+  double* C3 = reinterpret_cast<double*>(base + L.c3);
+  double* tl = reinterpret_cast<double*>(base + L.tl) + size_t(w) * (kP2 / kPdWaves) * sm;  // [NPW][sm]
+  double* E2b = reinterpret_cast<double*>(base + L.e2b);
+  double* E1b = reinterpret_cast<double*>(base + L.e1b);
+  int* E2f = reinterpret_cast<int*>(base + L.e2f);
+  int* E1f = reinterpret_cast<int*>(base + L.e1f);
+  int* slist = reinterpret_cast<int*>(base + L.slist);
+  constexpr int NJ = kP2 + 2 * p, NJ1 = kSeg + 2 * p;
+  const size_t c3n = size_t(kP2 + Q + 1) * sm;  // one slab
   const int c2 = blockIdx.x % nchunk2;
   const int i3 = p + blockIdx.x / nchunk2;
   const int c0 = p + c2 * kP2, c1 = min(c0 + kP2 - 1, m2 - p - 1);
-  const int j0 = c0 - p;                            // first evaluation index staged
+  const int j0 = c0 - p;  // first staged evaluation index of direction 2
   for (int t = tid; t < W * NJ; t += 64 * kPdWaves) {
     const int e = t / NJ, jj = t - e * NJ, j = min(j0 + jj, m2 - 1);
     E2f[t] = ip.ef[1][e * m2 + j];
 #pragma unroll
     for (int a = 0; a <= Q; ++a) E2b[(e * (Q + 1) + a) * NJ + jj] = ip.eb[1][(size_t(e) * (Q + 1) + a) * m2 + j];
   }
-  __syncthreads();
   const int b = blockIdx.y;
   T* out = band + size_t(b) * S * ld;
   const int64_t per = int64_t(sm) * sm * sm;
   const double* cb = coef + size_t(b) * ip.nup * per;
   const int sc = (S - 1) / 2;
   constexpr bool STIFF = FORM == IGS_STIFFNESS;
-  constexpr int NPW = kP2 / kPdWaves;               // pencils per wave
+  constexpr int NPW = kP2 / kPdWaves;  // pencils per wave
+  constexpr int NCH = kSeg / 64;
   const int hi1c = m1 - p - 1;
-  for (int seg0 = p; seg0 <= hi1c; seg0 += 64 * kPdChunks) {
-    double rs[NPW][kPdChunks];
+  // slot s's offsets, function and domain for this block and segment
+  struct Prm {
+    int e1, e2, e3, f1e, f2e, f3e, sh1, sh2, sh3, u, a2lo, a2hi, lo1, hi1;
+  };
+  auto prm = [&](int s, int seg0) {
+    Prm R;
+    R.e1 = s % W;
+    R.e2 = (s / W) % W;
+    R.e3 = s / (W * W);
+    const bool upper = s >= sc;
+    R.f1e = upper ? R.e1 : W - 1 - R.e1;
+    R.f2e = upper ? R.e2 : W - 1 - R.e2;
+    R.f3e = upper ? R.e3 : W - 1 - R.e3;
+    R.sh1 = upper ? 0 : R.e1 - p;
+    R.sh2 = upper ? 0 : R.e2 - p;
+    R.sh3 = upper ? 0 : R.e3 - p;
+    R.u = (upper ? s : S - 1 - s) - sc - (STIFF ? 1 : 0);
+    R.a2lo = max(c0, ip.lo[1][R.e2]);
+    R.a2hi = min(c1, ip.hi[1][R.e2]);
+    R.lo1 = max(ip.lo[0][R.e1], seg0);
+    R.hi1 = min(ip.hi[0][R.e1], seg0 + kSeg - 1);
+    return R;
+  };
+  for (int seg0 = p; seg0 <= hi1c; seg0 += kSeg) {
+    const int J1 = seg0 - p;  // first staged evaluation index of direction 1
+    __syncthreads();          // previous segment done with the staged rows
+    for (int t = tid; t < W * NJ1; t += 64 * kPdWaves) {
+      const int e = t / NJ1, jj = t - e * NJ1, j = min(J1 + jj, m1 - 1);
+      E1f[t] = ip.ef[0][e * m1 + j];
+#pragma unroll
+      for (int a = 0; a <= Q; ++a) E1b[(e * (Q + 1) + a) * NJ1 + jj] = ip.eb[0][(size_t(e) * (Q + 1) + a) * m1 + j];
+    }
+    if (tid == 0) {
+      int n = 0;
+      for (int s = 0; s < S; ++s) {
+        if (STIFF && s == sc) continue;
+        const Prm R = prm(s, seg0);
+        if (i3 < ip.lo[2][R.e3] || i3 > ip.hi[2][R.e3] || R.a2lo > R.a2hi || R.lo1 > R.hi1) continue;
+        slist[n++] = s;
+      }
+      slist[S] = n;
+    }
+    __syncthreads();
+    const int nact = slist[S];
+    double rs[NPW][NCH];
 #pragma unroll
     for (int r = 0; r < NPW; ++r)
 #pragma unroll
-      for (int c = 0; c < kPdChunks; ++c) rs[r][c] = 0.0;
-    for (int s = 0; s < S; ++s) {
-      if (STIFF && s == sc) continue;
-      const int e1 = s % W, e2 = (s / W) % W, e3 = s / (W * W);
-      if (i3 < ip.lo[2][e3] || i3 > ip.hi[2][e3]) continue;
-      const int a2lo = max(c0, ip.lo[1][e2]), a2hi = min(c1, ip.hi[1][e2]);
-      if (a2lo > a2hi) continue;
-      const int lo1 = max(ip.lo[0][e1], seg0), hi1 = min(ip.hi[0][e1], seg0 + 64 * kPdChunks - 1);
-      if (lo1 > hi1) continue;
-      const bool upper = s >= sc;
-      const int f1e = upper ? e1 : W - 1 - e1, f2e = upper ? e2 : W - 1 - e2, f3e = upper ? e3 : W - 1 - e3;
-      const int sh1 = upper ? 0 : e1 - p, sh2 = upper ? 0 : e2 - p, sh3 = upper ? 0 : e3 - p;
-      const int u = (upper ? s : S - 1 - s) - sc - (STIFF ? 1 : 0);
-      // direction-1 spline rows of this lane's rows (issued before the barrier)
-      int f1[kPdChunks];
-      double b1[kPdChunks][Q + 1];
+      for (int c = 0; c < NCH; ++c) rs[r][c] = 0.0;
+    for (int g0 = 0; g0 < nact; g0 += kGrp) {
+      const int ng = min(kGrp, nact - g0);
+      // phase 1: slabs of the group's slots, slot gi by wave gi % 4
+      for (int gi = w; gi < ng; gi += kPdWaves) {
+        const Prm R = prm(slist[g0 + gi], seg0);
+        const int j3 = i3 + R.sh3;
+        const int f3 = ip.ef[2][R.f3e * m3 + j3];
+        double b3[Q + 1];
 #pragma unroll
-      for (int c = 0; c < kPdChunks; ++c) {
-        const int i1 = seg0 + 64 * c + lane;
-        const int j1 = min(max(i1 + sh1, 0), m1 - 1);
-        f1[c] = ip.ef[0][f1e * m1 + j1];
+        for (int a = 0; a <= Q; ++a) b3[a] = ip.eb[2][(size_t(R.f3e) * (Q + 1) + a) * m3 + j3];
+        const int K2lo = E2f[R.f2e * NJ + (R.a2lo + R.sh2 - j0)];
+        const int nk2 = E2f[R.f2e * NJ + (R.a2hi + R.sh2 - j0)] + Q + 1 - K2lo;
+        const int S1 = ip.S[0][R.f1e];
+        const double* cu = cb + size_t(R.u) * per;
+        double* slab = C3 + size_t(gi) * c3n;
+        const int nel = nk2 * S1;
+        const unsigned rS1 = unsigned(0xffffffffu / unsigned(S1)) + 1u;
+        // four elements per lane and pass: their loads are in flight together
+        for (int t0 = 0; t0 < nel; t0 += 256) {
+          double v[4][Q + 1];
 #pragma unroll
-        for (int a = 0; a <= Q; ++a) b1[c][a] = ip.eb[0][(size_t(f1e) * (Q + 1) + a) * m1 + j1];
-      }
-      const int j3 = i3 + sh3;
-      const int f3 = ip.ef[2][f3e * m3 + j3];
-      double b3[Q + 1];
+          for (int j = 0; j < 4; ++j) {
+            const int t = min(t0 + 64 * j + lane, nel - 1);
+            const int kq = div_small(t, S1, rS1);
+            const int k2 = K2lo + kq, k1 = t - kq * S1;
 #pragma unroll
-      for (int a = 0; a <= Q; ++a) b3[a] = ip.eb[2][(size_t(f3e) * (Q + 1) + a) * m3 + j3];
-      const int K2lo = E2f[f2e * NJ + (a2lo + sh2 - j0)];
-      const int nk2 = E2f[f2e * NJ + (a2hi + sh2 - j0)] + Q + 1 - K2lo;
-      const int S1 = ip.S[0][f1e];
-      const double* cu = cb + size_t(u) * per;
-      __syncthreads();  // the previous slot's slab and lines are no longer read
-      for (int t = tid; t < nk2 * S1; t += 64 * kPdWaves) {
-        const int k2 = K2lo + t / S1, k1 = t % S1;
-        double acc = 0.0;
+            for (int a3 = 0; a3 <= Q; ++a3) v[j][a3] = cu[(size_t(f3 + a3) * sm + k2) * sm + k1];
+          }
 #pragma unroll
-        for (int a3 = 0; a3 <= Q; ++a3) acc += cu[(size_t(f3 + a3) * sm + k2) * sm + k1] * b3[a3];
-        C3[t] = acc;
-      }
-      __syncthreads();
-      T* os = out + size_t(s) * ld + size_t(m1) * size_t(m2) * i3;
+          for (int j = 0; j < 4; ++j) {
+            const int t = t0 + 64 * j + lane;
+            double acc = 0.0;
 #pragma unroll
-      for (int r = 0; r < NPW; ++r) {
-        const int i2 = c0 + w + kPdWaves * r;
-        if (i2 < a2lo || i2 > a2hi) continue;  // wave-uniform
-        const int jj = i2 + sh2 - j0;
-        const int f2 = E2f[f2e * NJ + jj] - K2lo;
-        double b2[Q + 1];
-#pragma unroll
-        for (int a = 0; a <= Q; ++a) b2[a] = E2b[(f2e * (Q + 1) + a) * NJ + jj];
-        wave_sync();
-        for (int k1 = lane; k1 < S1; k1 += 64) {
-          double acc = 0.0;
-#pragma unroll
-          for (int a2 = 0; a2 <= Q; ++a2) acc += C3[(f2 + a2) * S1 + k1] * b2[a2];
-          tl[k1] = acc;
-        }
-        wave_sync();
-        T* orow = os + size_t(m1) * i2;
-#pragma unroll
-        for (int c = 0; c < kPdChunks; ++c) {
-          const int i1 = seg0 + 64 * c + lane;
-          if (i1 >= lo1 && i1 <= hi1) {
-            double v = 0.0;
-#pragma unroll
-            for (int a = 0; a <= Q; ++a) v += tl[f1[c] + a] * b1[c][a];
-            orow[i1] = static_cast<T>(v);
-            rs[r][c] += v;
+            for (int a3 = 0; a3 <= Q; ++a3) acc += v[j][a3] * b3[a3];
+            if (t < nel) slab[t] = acc;
           }
         }
       }
+      __syncthreads();
+      // phase 2: every wave, every slot of the group, its pencils
+      for (int gi = 0; gi < ng; ++gi) {
+        const int s = slist[g0 + gi];
+        const Prm R = prm(s, seg0);
+        const int K2lo = E2f[R.f2e * NJ + (R.a2lo + R.sh2 - j0)];
+        const int S1 = ip.S[0][R.f1e];
+        const double* slab = C3 + size_t(gi) * c3n;
+        T* os = out + size_t(s) * ld + size_t(m1) * size_t(m2) * i3;
+        // this lane's direction-1 rows for the slot
+        int f1[NCH];
+        double b1[NCH][Q + 1];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          const int jj = min(max(seg0 + 64 * c + lane + R.sh1 - J1, 0), NJ1 - 1);
+          f1[c] = E1f[R.f1e * NJ1 + jj];
+#pragma unroll
+          for (int a = 0; a <= Q; ++a) b1[c][a] = E1b[(R.f1e * (Q + 1) + a) * NJ1 + jj];
+        }
+        // lines t[k1] of the wave's pencils: lane pairs (k1, pencil r)
+        wave_sync();  // the previous slot's lines are no longer read
+        for (int t = lane; t < NPW * S1; t += 64) {
+          const int r = t % NPW, k1 = t / NPW;
+          const int i2 = c0 + w + kPdWaves * r;
+          const int jj = min(max(i2 + R.sh2 - j0, 0), NJ - 1);
+          const bool ok = i2 >= R.a2lo && i2 <= R.a2hi;
+          const int f2 = ok ? E2f[R.f2e * NJ + jj] - K2lo : 0;
+          const double* e2 = E2b + R.f2e * (Q + 1) * NJ + jj;
+          const double* sl = slab + f2 * S1 + k1;
+          double acc = 0.0;
+#pragma unroll
+          for (int a2 = 0; a2 <= Q; ++a2) acc += sl[a2 * S1] * e2[a2 * NJ];
+          tl[r * sm + k1] = acc;
+        }
+        wave_sync();
+        // rows: every (pencil, chunk) of this lane
+#pragma unroll
+        for (int r = 0; r < NPW; ++r) {
+          const int i2 = c0 + w + kPdWaves * r;
+          if (i2 < R.a2lo || i2 > R.a2hi) continue;  // wave-uniform
+          T* orow = os + size_t(m1) * i2;
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            const int i1 = seg0 + 64 * c + lane;
+            if (i1 >= R.lo1 && i1 <= R.hi1) {
+              double v = 0.0;
+#pragma unroll
+              for (int a = 0; a <= Q; ++a) v += tl[r * sm + f1[c] + a] * b1[c][a];
+              orow[i1] = static_cast<T>(v);
+              rs[r][c] += v;
+            }
+          }
+        }
+      }
+      __syncthreads();  // the group's slabs are no longer read
     }
     if constexpr (STIFF) {
 #pragma unroll
@@ -309,7 +412,7 @@ __global__ void __launch_bounds__(64 * kPdWaves)
         const int i2 = c0 + w + kPdWaves * r;
         if (i2 > c1) continue;
 #pragma unroll
-        for (int c = 0; c < kPdChunks; ++c) {
+        for (int c = 0; c < NCH; ++c) {
           const int i1 = seg0 + 64 * c + lane;
           if (i1 <= hi1c) out[size_t(sc) * ld + size_t(m1) * (i2 + size_t(m2) * i3) + i1] = static_cast<T>(-rs[r][c]);
         }
@@ -360,27 +463,33 @@ static void launch_fill_pd_q(const KInterpPD& ip, int64_t ld, int S, int npen, i
   }
 }
 
-static size_t fill_pd3_lds(const KInterpPD& ip) {
-  const size_t NJ = kP2 + 2 * ip.p;
-  return (size_t(kP2 + ip.q + 1 + kPdWaves) * ip.smax + size_t(ip.W) * (ip.q + 1) * NJ) * sizeof(double) +
-         size_t(ip.W) * NJ * sizeof(int);
+static size_t fill_pd3_lds(const KInterpPD& ip, int S) { return pd3_layout(ip.smax, ip.W, ip.q, ip.p, S).total; }
+
+size_t fill_pd_lds_bytes(const KInterpPD& ip, int S) {
+  return ip.m[2] > 1 ? fill_pd3_lds(ip, S) : size_t(kPdWaves) * ip.smax * sizeof(double);
 }
 
-size_t fill_pd_lds_bytes(const KInterpPD& ip) {
-  return ip.m[2] > 1 ? fill_pd3_lds(ip) : size_t(kPdWaves) * ip.smax * sizeof(double);
+template <int FORM, int P, typename T>
+static void launch_fill_pd3_p(const KInterpPD& ip, const Dims& d, const double* coef, T* band, hipStream_t s) {
+  const int nchunk2 = (d.m[1] - 2 * d.p + kP2 - 1) / kP2;
+  dim3 grid(nchunk2 * (d.m[2] - 2 * d.p), d.batch);
+  const size_t lds = fill_pd3_lds(ip, d.S);
+  switch (ip.q) {
+    case 1: hipLaunchKernelGGL((fill_pd3_kernel<FORM, P, 1, T>), grid, dim3(64 * kPdWaves), lds, s, ip, d.ld, d.S, nchunk2, coef, band); break;
+    case 2: hipLaunchKernelGGL((fill_pd3_kernel<FORM, P, 2, T>), grid, dim3(64 * kPdWaves), lds, s, ip, d.ld, d.S, nchunk2, coef, band); break;
+    case 3: hipLaunchKernelGGL((fill_pd3_kernel<FORM, P, 3, T>), grid, dim3(64 * kPdWaves), lds, s, ip, d.ld, d.S, nchunk2, coef, band); break;
+    case 4: hipLaunchKernelGGL((fill_pd3_kernel<FORM, P, 4, T>), grid, dim3(64 * kPdWaves), lds, s, ip, d.ld, d.S, nchunk2, coef, band); break;
+    default: hipLaunchKernelGGL((fill_pd3_kernel<FORM, P, 5, T>), grid, dim3(64 * kPdWaves), lds, s, ip, d.ld, d.S, nchunk2, coef, band); break;
+  }
 }
 
 template <int FORM, typename T>
 static void launch_fill_pd3(const KInterpPD& ip, const Dims& d, const double* coef, T* band, hipStream_t s) {
-  const int nchunk2 = (d.m[1] - 2 * d.p + kP2 - 1) / kP2;
-  dim3 grid(nchunk2 * (d.m[2] - 2 * d.p), d.batch);
-  const size_t lds = fill_pd3_lds(ip);
-  switch (ip.q) {
-    case 1: hipLaunchKernelGGL((fill_pd3_kernel<FORM, 1, T>), grid, dim3(64 * kPdWaves), lds, s, ip, d.ld, d.S, nchunk2, coef, band); break;
-    case 2: hipLaunchKernelGGL((fill_pd3_kernel<FORM, 2, T>), grid, dim3(64 * kPdWaves), lds, s, ip, d.ld, d.S, nchunk2, coef, band); break;
-    case 3: hipLaunchKernelGGL((fill_pd3_kernel<FORM, 3, T>), grid, dim3(64 * kPdWaves), lds, s, ip, d.ld, d.S, nchunk2, coef, band); break;
-    case 4: hipLaunchKernelGGL((fill_pd3_kernel<FORM, 4, T>), grid, dim3(64 * kPdWaves), lds, s, ip, d.ld, d.S, nchunk2, coef, band); break;
-    default: hipLaunchKernelGGL((fill_pd3_kernel<FORM, 5, T>), grid, dim3(64 * kPdWaves), lds, s, ip, d.ld, d.S, nchunk2, coef, band); break;
+  switch (d.p) {
+    case 1: launch_fill_pd3_p<FORM, 1, T>(ip, d, coef, band, s); break;
+    case 2: launch_fill_pd3_p<FORM, 2, T>(ip, d, coef, band, s); break;
+    case 3: launch_fill_pd3_p<FORM, 3, T>(ip, d, coef, band, s); break;
+    default: launch_fill_pd3_p<FORM, 4, T>(ip, d, coef, band, s); break;
   }
 }
 
