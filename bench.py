@@ -35,20 +35,22 @@ FP64_PEAK_TFLOPS = 78.6
 # FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch), scaled by what the same
 # counters give for a plain 2^30-byte elementwise copy (FETCH 2.00, WRITE 1.00);
 # profiles/*_hbm_counters.md hold the runs (keys: phase names of the domain
-# surrogate step, fe_* of the face/edge step, mf_* of the matrix-free apply).
+# surrogate step, fe_* of the face/edge step, mf_* of the matrix-free apply,
+# pd_fill of the per-delta step).
 # A figure is only reported while the kernel sources still hash to the ones
 # measured.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.00, 1.00
 PMC_TRAFFIC = {
-    "quad_boundary_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "5cd0866b048f2900", "fetch_kib": 14046.9, "write_kib": 2097916.6},
-    "fill": {"sources": ["fill.hip"], "sha256": "f24ac6f0d20cb229", "fetch_kib": 150886.0, "write_kib": 4971999.6},
-    "copy": {"sources": ["fill.hip"], "sha256": "f24ac6f0d20cb229", "fetch_kib": 360709.9, "write_kib": 301085.9},
-    "fe_fill": {"sources": ["fill.hip", "plan.cpp"], "sha256": "31819ce7c11dd2c3", "fetch_kib": 951513.8, "write_kib": 6024184.7},
-    "fe_quad_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "5cd0866b048f2900", "fetch_kib": 1503.4, "write_kib": 117649.0},
-    "fe_quad_tiles": {"sources": ["quad.hip", "plan.cpp"], "sha256": "5cd0866b048f2900", "fetch_kib": 661.6, "write_kib": 39873.8},
-    "mf_domain_rows": {"sources": ["fill.hip"], "sha256": "f24ac6f0d20cb229", "fetch_kib": 116716.2, "write_kib": 13497.2},
-    "mf_copied_entries": {"sources": ["fill.hip"], "sha256": "f24ac6f0d20cb229", "fetch_kib": 396897.5, "write_kib": 2612.8},
-    "mf_stored_rows": {"sources": ["fill.hip"], "sha256": "f24ac6f0d20cb229", "fetch_kib": 1080584.2, "write_kib": 4837.5},
+    "quad_boundary_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "0be35537fd1b737f", "fetch_kib": 15088.2, "write_kib": 2429549.0},
+    "fill": {"sources": ["fill.hip"], "sha256": "1b24ae819da400f1", "fetch_kib": 151710.0, "write_kib": 4971999.7},
+    "diag_fixup": {"sources": ["fill.hip"], "sha256": "1b24ae819da400f1", "fetch_kib": 361338.8, "write_kib": 2612.8},
+    "fe_fill": {"sources": ["fill.hip", "plan.cpp"], "sha256": "b34ef57f1c9f7821", "fetch_kib": 949979.0, "write_kib": 6024184.8},
+    "fe_quad_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "0be35537fd1b737f", "fetch_kib": 1506.7, "write_kib": 117649.0},
+    "fe_quad_tiles": {"sources": ["quad.hip", "plan.cpp"], "sha256": "0be35537fd1b737f", "fetch_kib": 677.4, "write_kib": 39873.8},
+    "mf_domain_rows": {"sources": ["fill.hip"], "sha256": "1b24ae819da400f1", "fetch_kib": 116784.4, "write_kib": 13497.2},
+    "mf_copied_entries": {"sources": ["fill.hip"], "sha256": "1b24ae819da400f1", "fetch_kib": 396878.9, "write_kib": 2612.8},
+    "mf_stored_rows": {"sources": ["fill.hip"], "sha256": "1b24ae819da400f1", "fetch_kib": 1018252.4, "write_kib": 4821.3},
+    "pd_fill": {"sources": ["fillpd.hip", "plan.cpp"], "sha256": "2eb2fe809d26d3e7", "fetch_kib": 98490.9, "write_kib": 5143617.4},
 }
 
 
