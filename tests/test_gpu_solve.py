@@ -147,6 +147,26 @@ def test_cg_not_converged(igs):
     assert info["status"] == 1 and info["iterations"] <= 3 + 32
 
 
+@pytest.mark.parametrize("case", ["fused", "large", "fp32"])
+def test_cg_breakdown(igs, case):
+    """IGS_BREAKDOWN: CG on a negative definite matrix (the negated mass band)
+    meets p^T A p < 0 in its first iteration.  The small 2D problem takes the
+    fused scalar kernels, the 3D one (more than 1024 partial sums per problem)
+    the separate reduction kernels, the FP32 band the residual-replacement
+    loop."""
+    import torch
+
+    prob = W.c1_poisson2d() if case != "large" else W.problem(3, 2, 70)
+    band = -igs.assemble_exact(prob, 1)
+    f = igs.assemble_rhs(prob, 0, 1.0)
+    b32 = band.to(torch.float32) if case == "fp32" else None
+    u, info = igs.solve_cg(prob, band, f, band32=b32, rtol=1e-10, maxit=1000, check=False)
+    assert info["status"] == 2, info
+    assert bool(torch.isfinite(u).all())
+    with pytest.raises(igs.IGSError, match="BREAKDOWN"):
+        igs.solve_cg(prob, band, f, band32=b32, rtol=1e-10, maxit=1000)
+
+
 def test_cg_large(igs, oracle):
     """A problem with more than 1024 SpMV workgroups per problem (373,248 dofs),
     where the CG scalars are reduced by separate kernels: the returned solution
