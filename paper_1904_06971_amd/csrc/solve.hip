@@ -52,6 +52,15 @@ __device__ __forceinline__ bool on_dirichlet(const SpmvGeom& g, int64_t i) {
   return d;
 }
 
+// part[k0] + part[k0 + kRedBlock] + ... (k < n), added in that order; the
+// loads go out eight at a time
+__device__ __forceinline__ double strided_sum(const double* __restrict__ part, int k0, int n) {
+  double s = 0.0;
+#pragma unroll 8
+  for (int k = k0; k < n; k += kRedBlock) s += part[k];
+  return s;
+}
+
 // Per-problem scalars, kept on the device between kernels.
 struct CgScalars {
   double rr;      // r^T r
@@ -81,8 +90,10 @@ struct CgScalars {
 // multiple of 64, so the band load is aligned and stays inside the slot; row
 // indices past N read padding and are not stored.  Modes:
 //   0  y = A x (Dirichlet rows 0 when mask is set)
-//   1  CG step q = A p, Dirichlet rows 0, finished problems skipped,
-//      per-block partials of p^T q
+//   1  CG product: w = A r (Dirichlet rows 0), then on the thread's own rows
+//      p = r + beta p and q = w + beta q, which is A p by linearity, so the
+//      direction update needs neither a pass of its own nor the halo of p;
+//      finished problems skipped; per-block partials of p^T q
 //   2  (FP64) r = f - A u, Dirichlet rows 0, partials of r^T r and f^T f
 //   3  (FP64) r32 = float(f - A u) on problems with a residual replacement
 //      due, partials of r^T r
@@ -120,11 +131,68 @@ struct SpmvShape {
   static constexpr int NT = kSpmvBlock / R;  // threads per block
 };
 
+// Sum of part[b][0..n) in exactly the order of a kRedBlock-thread reduction
+// (strided per-thread sums, the wavefront butterfly, wavefront sums in order),
+// computed by a workgroup of NT threads: thread t plays the virtual threads
+// t + j NT.  Any NT therefore gives the same bits as sum_parts below.
+template <int NT>
+__device__ __forceinline__ double sum_parts_nt(const double* __restrict__ part, int b, int n) {
+  constexpr int V = kRedBlock / NT;
+  static_assert(V * NT == kRedBlock && NT % 64 == 0, "whole wavefronts");
+  __shared__ double red[kRedBlock / 64];
+  const double* pb = part + size_t(b) * n;
+  double v[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    v[j] = 0.0;
+    v[j] = strided_sum(pb, threadIdx.x + j * NT, n);
+  }
+#pragma unroll
+  for (int j = 0; j < V; ++j)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off, 64);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int j = 0; j < V; ++j) red[(threadIdx.x >> 6) + j * (NT / 64)] = v[j];
+  __syncthreads();
+  double s = red[0];
+#pragma unroll
+  for (int k = 1; k < kRedBlock / 64; ++k) s += red[k];
+  __syncthreads();
+  return s;
+}
+
+// r^T r after `it` completed CG steps: record it and decide convergence
+__device__ __forceinline__ void record_rr(CgScalars& c, double s, int it) {
+  c.rrv[it & 1] = s;
+  c.iters = it;
+  if (!isfinite(s)) {
+    c.done = 1;
+    c.breakdown = 1;
+  } else if (s <= c.tol2) {
+    c.done = 1;
+  }
+}
+
+// Direction update of the CG product (mode 1): p = r + beta p, q = w + beta q.
+//   bsrc 0  first step: p = r, q = w
+//   bsrc 1  beta from the per-problem scalars
+//   bsrc 2  plain CG with fused scalars: every workgroup sums the previous
+//           step's partials of r^T r (rrp) itself, beta = rr_new / rr_old, and
+//           workgroup 0 records rr_new (record_rr with `it`)
+template <typename T>
+struct CgDir {
+  T* p;
+  const double* rrp;
+  int it;
+  int bsrc;
+};
+
 template <typename T, int P, int ND, int MODE>
 __global__ void __launch_bounds__(SpmvShape<T>::NT)
     spmv_band_kernel(SpmvGeom g, const T* __restrict__ band, const T* __restrict__ x, const double* __restrict__ f,
-                     T* __restrict__ y, float* __restrict__ y32, int mask, const CgScalars* __restrict__ sc,
-                     double* __restrict__ part, double* __restrict__ part2) {
+                     T* __restrict__ y, float* __restrict__ y32, int mask, CgScalars* __restrict__ sc,
+                     double* __restrict__ part, double* __restrict__ part2, CgDir<T> cd) {
   static_assert(MODE < 2 || sizeof(T) == 8, "residual modes take the FP64 band");
   constexpr int R = SpmvShape<T>::R, NT = SpmvShape<T>::NT;
   constexpr bool STAGE = SpmvShape<T>::STAGE;
@@ -143,12 +211,41 @@ __global__ void __launch_bounds__(SpmvShape<T>::NT)
   const int64_t i0 = int64_t(lb) * kSpmvBlock;
   const int tid = threadIdx.x;
   const int64_t r0 = i0 + R * tid;
+  T beta = T(0);
+  if constexpr (MODE == 1) {
+    if (cd.bsrc == 2) {
+      const double s = sum_parts_nt<NT>(cd.rrp, b, gridDim.x);
+      const double rr_old = sc[b].rrv[(cd.it - 1) & 1];
+      const bool stop = !isfinite(s) || s <= sc[b].tol2;  // the same in every workgroup
+      if (lb == 0 && tid == 0) record_rr(sc[b], s, cd.it);
+      if (stop) return;
+      beta = T(s / rr_old);
+    } else if (cd.bsrc == 1) {
+      beta = T(sc[b].beta);
+    }
+  }
   const T* xb = x + size_t(b) * g.N;
   const T* bb = band + size_t(b) * g.S * g.ld;
   const int64_t m1 = g.m[0], m12 = int64_t(g.m[0]) * g.m[1];
   T acc[R];
 #pragma unroll
   for (int q = 0; q < R; ++q) acc[q] = T(0);
+  // mode 1: the thread's rows of r, p and q; for FP64 loaded before the band
+  // loop so that their latency hides behind it (FP32: after it, since the
+  // early loads cost the staged kernel its occupancy)
+  constexpr bool PREF = MODE == 1 && sizeof(T) == 8;
+  T rown[R], pown[R], qown[R];
+  auto load_own = [&]() {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int64_t i = r0 + q < g.N ? r0 + q : g.N - 1;
+      const size_t k0 = size_t(b) * g.N + i;
+      rown[q] = xb[i];
+      pown[q] = cd.bsrc == 0 ? T(0) : cd.p[k0];
+      qown[q] = cd.bsrc == 0 ? T(0) : y[k0];
+    }
+  };
+  if constexpr (PREF) load_own();
   for (int z = 0; z < NZ; ++z) {
     const int64_t o3 = ND == 3 ? (z - P) * m12 : 0;
     if constexpr (STAGE) {
@@ -205,6 +302,7 @@ __global__ void __launch_bounds__(SpmvShape<T>::NT)
       }
     }
   }
+  if constexpr (MODE == 1 && !PREF) load_own();
   double sa = 0.0, sf = 0.0;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
@@ -217,7 +315,16 @@ __global__ void __launch_bounds__(SpmvShape<T>::NT)
     if (MODE == 0) {
       o = (mask && dir) ? T(0) : acc[q];
     } else if (MODE == 1) {
-      o = dir ? T(0) : acc[q];
+      const T w = dir ? T(0) : acc[q];
+      T pn = rown[q];
+      if (cd.bsrc == 0) {
+        o = w;
+      } else {
+        pn = pn + beta * pown[q];
+        o = w + beta * qown[q];
+      }
+      cd.p[k0] = pn;
+      sa += double(pn) * double(o);
     } else {
       fv = dir ? 0.0 : f[k0];
       o = dir ? T(0) : T(fv - double(acc[q]));
@@ -226,7 +333,6 @@ __global__ void __launch_bounds__(SpmvShape<T>::NT)
       y32[k0] = float(o);
     else
       y[k0] = o;
-    if (MODE == 1) sa += double(o) * double(xb[i]);
     if (MODE >= 2) {
       sa += double(o) * double(o);
       sf += fv * fv;
@@ -243,12 +349,12 @@ __global__ void __launch_bounds__(SpmvShape<T>::NT)
 
 template <typename T, int MODE>
 static void launch_spmv_band(const SpmvGeom& g, int nblk, int batch, const T* band, const T* x, const double* f,
-                             T* y, float* y32, int mask, const CgScalars* sc, double* part, double* part2,
-                             hipStream_t s) {
+                             T* y, float* y32, int mask, CgScalars* sc, double* part, double* part2, hipStream_t s,
+                             const CgDir<T>& cd = CgDir<T>{}) {
   const dim3 grid(nblk, batch), block(SpmvShape<T>::NT);
 #define IGS_SPMV(PP, NDD)                                                                                         \
   hipLaunchKernelGGL((spmv_band_kernel<T, PP, NDD, MODE>), grid, block, 0, s, g, band, x, f, y, y32, mask, sc, part, \
-                     part2)
+                     part2, cd)
   if (g.n == 3) {
     switch (g.p) {
       case 1: IGS_SPMV(1, 3); break;
@@ -269,15 +375,23 @@ static void launch_spmv_band(const SpmvGeom& g, int nblk, int batch, const T* ba
 
 template <int MODE>
 static void launch_spmv32(const SpmvGeom& g, int nblk, int batch, const float* band, const float* x, float* y,
-                          int mask, const CgScalars* sc, double* part, hipStream_t s) {
+                          int mask, CgScalars* sc, double* part, hipStream_t s) {
   launch_spmv_band<float, MODE>(g, nblk, batch, band, x, nullptr, y, nullptr, mask, sc, part, nullptr, s);
 }
 
 template <int MODE>
 static void launch_spmv64(const SpmvGeom& g, int nblk, int batch, const double* band, const double* x,
-                          const double* f, double* y, float* y32, int mask, const CgScalars* sc, double* part,
+                          const double* f, double* y, float* y32, int mask, CgScalars* sc, double* part,
                           double* part2, hipStream_t s) {
   launch_spmv_band<double, MODE>(g, nblk, batch, band, x, f, y, y32, mask, sc, part, part2, s);
+}
+
+// CG product (mode 1): from r, p = r + beta p and q = A r + beta q = A p in
+// place (see CgDir), partials of p^T q
+template <typename T>
+static void launch_cg_product(const SpmvGeom& g, int nblk, int batch, const T* band, const T* r, const CgDir<T>& cd,
+                              T* q, CgScalars* sc, double* pap, hipStream_t s) {
+  launch_spmv_band<T, 1>(g, nblk, batch, band, r, nullptr, q, nullptr, 1, sc, pap, nullptr, s, cd);
 }
 
 // x with its Dirichlet dofs zeroed (the restriction of igs_apply)
@@ -299,23 +413,21 @@ __device__ __forceinline__ double block_sum(double v) {
 // out[b] = sum of part[b][0..nblk) in a fixed order (one block per problem)
 __global__ void __launch_bounds__(kRedBlock) reduce_kernel(const double* __restrict__ part, int nblk, double* out) {
   const int b = blockIdx.x;
-  double s = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += kRedBlock) s += part[size_t(b) * nblk + k];
+  double s = strided_sum(part + size_t(b) * nblk, threadIdx.x, nblk);
   s = block_sum<double>(s);
   if (threadIdx.x == 0) out[b] = s;
 }
 
-// inner CG start: rhat = r / scale (type T), d = 0, p = rhat, rr = |rhat|^2
+// inner CG start: rhat = r / scale (type T), d = 0 (the first step's product
+// takes p = rhat)
 template <typename T>
 __global__ void cg_init_kernel(int64_t N, int batch, const double* __restrict__ r, const double* __restrict__ scale,
-                               T* __restrict__ rh, T* __restrict__ p, T* __restrict__ d) {
+                               T* __restrict__ rh, T* __restrict__ d) {
   const int64_t total = N * batch;
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
     const int b = int(t / N);
     const double s = scale[b];
-    const T v = s > 0.0 ? T(r[t] / s) : T(0);
-    rh[t] = v;
-    p[t] = v;
+    rh[t] = s > 0.0 ? T(r[t] / s) : T(0);
     d[t] = T(0);
   }
 }
@@ -345,7 +457,7 @@ __global__ void __launch_bounds__(kRedBlock) cg_alpha_kernel(const double* __res
   const int b = blockIdx.x;
   if (sc[b].done) return;
   double s = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += kRedBlock) s += part[size_t(b) * nblk + k];
+  s += strided_sum(part + size_t(b) * nblk, threadIdx.x, nblk);
   s = block_sum<double>(s);
   if (threadIdx.x == 0) {
     if (!(s > 0.0) || !isfinite(s)) {
@@ -385,7 +497,7 @@ __global__ void __launch_bounds__(kRedBlock) cg_beta_kernel(const double* __rest
   const int b = blockIdx.x;
   if (sc[b].done) return;
   double s = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += kRedBlock) s += part[size_t(b) * nblk + k];
+  s += strided_sum(part + size_t(b) * nblk, threadIdx.x, nblk);
   s = block_sum<double>(s);
   if (threadIdx.x == 0) {
     sc[b].beta = s / sc[b].rr;
@@ -413,16 +525,16 @@ __global__ void cg_pupdate_kernel(int64_t N, const CgScalars* __restrict__ sc, c
   }
 }
 
-// Fused plain-CG steps, for problems with at most kFuseParts partial sums per
+// Fused CG scalars, for problems with at most kFuseParts partial sums per
 // problem (each workgroup reads all of them, so the cost grows with their
 // square).  Every workgroup reduces the same per-block partial sums in the
 // same order, so all of them hold the same scalar and none waits for another;
-// only workgroup 0 records it.  Iteration k reads r^T r from rrv[k & 1] and
-// the next one's from rrv[(k + 1) & 1].
+// only workgroup 0 records it.  Step k reads r^T r from rrv[k & 1]; the
+// product of step k + 1 writes rrv[(k + 1) & 1].
 constexpr int kFuseParts = 1024;
 __device__ __forceinline__ double sum_parts(const double* __restrict__ part, int b, int nparts) {
   double s = 0.0;
-  for (int k = threadIdx.x; k < nparts; k += kRedBlock) s += part[size_t(b) * nparts + k];
+  s += strided_sum(part + size_t(b) * nparts, threadIdx.x, nparts);
   return block_sum<double>(s);
 }
 
@@ -457,31 +569,15 @@ __global__ void __launch_bounds__(kSpmvBlock)
   if (threadIdx.x == 0) part[size_t(b) * gridDim.x + lb] = v;
 }
 
-// beta = rr_new / rr, p = r + beta p; convergence on the recursive residual
-template <typename T>
-__global__ void __launch_bounds__(kSpmvBlock)
-    cg_dir_kernel(int64_t N, int par, CgScalars* __restrict__ sc, const double* __restrict__ rrp,
-                  const T* __restrict__ r, T* __restrict__ p) {
-  const int b = blockIdx.y;
+// r^T r after `it` steps from the step's partials, recorded as the next
+// step's product would record it (the same sum in the same order), so the
+// host sees convergence at the end of a chunk of steps
+__global__ void __launch_bounds__(kRedBlock) cg_rr_kernel(const double* __restrict__ rrp, int nparts,
+                                                          CgScalars* sc, int it) {
+  const int b = blockIdx.x;
   if (sc[b].done) return;
-  const double s = sum_parts(rrp, b, gridDim.x);
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  if (lb == 0 && threadIdx.x == 0) {
-    sc[b].rrv[par ^ 1] = s;
-    sc[b].iters += 1;
-    if (!isfinite(s)) {
-      sc[b].done = 1;
-      sc[b].breakdown = 1;
-    } else if (s <= sc[b].tol2) {
-      sc[b].done = 1;
-    }
-  }
-  const T beta = T(s / sc[b].rrv[par]);
-  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
-  if (i < N) {
-    const size_t k = size_t(b) * N + i;
-    p[k] = r[k] + beta * p[k];
-  }
+  const double s = sum_parts(rrp, b, nparts);
+  if (threadIdx.x == 0) record_rr(sc[b], s, it);
 }
 
 // u += scale * d (FP64 update of the refinement)
@@ -578,8 +674,53 @@ struct SolveBufs {
   CgScalars* sc;
 };
 
+// Number of CG steps to enqueue before the host next reads the scalars.  A
+// read drains the stream, so the host reads rarely: from the decrease of r^T r
+// since its previous read it extrapolates (at the geometric rate observed) the
+// steps the slowest unfinished problem still needs to reach its tolerance, and
+// enqueues that many (at least 8, at most four times the previous chunk; 32
+// at first).  Steps enqueued after a problem has finished return at once.
+class ChunkPlanner {
+ public:
+  // rr0: r^T r of each problem at step 0
+  explicit ChunkPlanner(std::vector<double> rr0) : rr_(std::move(rr0)), it_(rr_.size(), 0) {}
+  int first() const { return last_; }
+  // after a read at step `it`; rr[b] the current r^T r of problem b
+  int next(const std::vector<CgScalars>& sc, const std::vector<double>& rr, int it) {
+    double need = 0.0;
+    bool known = true;
+    for (size_t b = 0; b < rr_.size(); ++b) {
+      if (sc[b].done) continue;
+      const double r1 = rr[b], r0 = rr_[b];
+      const int dk = it - it_[b];
+      if (!(r1 > 0.0) || !(r0 > 0.0) || dk <= 0 || !(r1 < r0)) {
+        known = false;
+      } else {
+        const double rate = std::log(r1 / r0) / dk;  // < 0
+        need = std::max(need, std::log(sc[b].tol2 / r1) / rate);
+      }
+      rr_[b] = r1;
+      it_[b] = it;
+    }
+    int n = known ? int(std::ceil(need)) : 2 * last_;
+    n = std::min(std::max(n, 8), 4 * last_);
+    last_ = n;
+    return n;
+  }
+
+ private:
+  std::vector<double> rr_;
+  std::vector<int> it_;
+  int last_ = 32;
+};
+
 // One inner CG on A_T dhat = rhat, rhat = r / scale, from dhat = 0, to
 // |rhat - A dhat| <= sqrt(tol2) (per problem), at most `budget` iterations.
+// A step is the product kernel (A r, the direction update of p and q = A p,
+// p^T q partials) and the update kernel (alpha, dhat and r, r^T r partials);
+// with at most kFuseParts partials per problem each kernel sums them itself
+// (two launches per step), else one-workgroup kernels compute alpha and beta
+// between them.
 template <typename T>
 static igs_status inner_cg(const Dims& d, const T* band, const SolveBufs& sb, T* rh, T* p, T* q, T* dv, int budget,
                            std::vector<CgScalars>* host_sc, int* iters, hipStream_t s) {
@@ -587,47 +728,47 @@ static igs_status inner_cg(const Dims& d, const T* band, const SolveBufs& sb, T*
   const int nblk = int((d.N + kSpmvBlock - 1) / kSpmvBlock);
   const int dblk = int(std::min<int64_t>((d.N + kRedBlock - 1) / kRedBlock, 1024));
   hipLaunchKernelGGL((cg_init_kernel<T>), dim3(grid_stride_blocks(d.N * d.batch)), dim3(256), 0, s, d.N, d.batch,
-                     sb.r64, sb.scale, rh, p, dv);
+                     sb.r64, sb.scale, rh, dv);
   hipLaunchKernelGGL((dot_kernel<T>), dim3(dblk, d.batch), dim3(kRedBlock), 0, s, d.N, rh, rh, sb.part);
   hipLaunchKernelGGL(reduce_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, dblk, sb.rr);
   hipLaunchKernelGGL(cg_setup_kernel, dim3(1), dim3(64), 0, s, d.batch, sb.rr, sb.tol2, sb.active, sb.sc);
   HIP_OK(hipGetLastError());
-  const int chunk = 32;
-  int done_iters = 0;
-  while (true) {
-    const int k = std::min(chunk, budget - done_iters);
-    if (k <= 0) break;
-    for (int it = 0; it < k; ++it) {
+  const bool fused = nblk <= kFuseParts;
+  // |rhat|^2 = 1 for the problems that iterate
+  ChunkPlanner plan(std::vector<double>(d.batch, 1.0));
+  std::vector<double> rrh(d.batch);
+  int chunk = plan.first();
+  int it = 0;
+  while (it < budget) {
+    const int k = std::min(chunk, budget - it);
+    for (int j = 0; j < k; ++j, ++it) {
+      const CgDir<T> cd{p, sb.part2, it, it == 0 ? 0 : (fused ? 2 : 1)};
       {
         PhaseTimer t(sizeof(T) == 8 ? "cg_spmv_f64" : "cg_spmv_f32", s);
-        if constexpr (sizeof(T) == 4)
-          launch_spmv32<1>(g, nblk, d.batch, band, p, q, 1, sb.sc, sb.part, s);
-        else
-          launch_spmv64<1>(g, nblk, d.batch, band, p, nullptr, q, nullptr, 1, sb.sc, sb.part, nullptr, s);
+        launch_cg_product<T>(g, nblk, d.batch, band, rh, cd, q, sb.sc, sb.part, s);
       }
       PhaseTimer t("cg_vector_ops", s);
-      if (nblk <= kFuseParts) {
-        const int par = (done_iters + it) & 1;
-        hipLaunchKernelGGL((cg_step_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, par, sb.sc,
+      if (fused) {
+        hipLaunchKernelGGL((cg_step_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, it & 1, sb.sc,
                            sb.part, p, q, dv, rh, sb.part2);
-        hipLaunchKernelGGL((cg_dir_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, par, sb.sc,
-                           sb.part2, rh, p);
       } else {
         hipLaunchKernelGGL(cg_alpha_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
         hipLaunchKernelGGL((cg_update_kernel<T>), dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, sb.sc, p, q,
                            dv, rh, sb.part2);
         hipLaunchKernelGGL(cg_beta_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part2, nblk, sb.sc);
-        hipLaunchKernelGGL((cg_pupdate_kernel<T>), dim3(std::min<int64_t>((d.N + 255) / 256, 4096), d.batch),
-                           dim3(256), 0, s, d.N, sb.sc, rh, p);
       }
     }
+    if (fused) hipLaunchKernelGGL(cg_rr_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part2, nblk, sb.sc, it);
     HIP_OK(hipGetLastError());
-    done_iters += k;
     HIP_OK(hipMemcpyAsync(host_sc->data(), sb.sc, sizeof(CgScalars) * d.batch, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     bool all = true;
-    for (int b = 0; b < d.batch; ++b) all &= (*host_sc)[b].done != 0;
+    for (int b = 0; b < d.batch; ++b) {
+      all &= (*host_sc)[b].done != 0;
+      rrh[b] = fused ? (*host_sc)[b].rrv[it & 1] : (*host_sc)[b].rr;
+    }
     if (all) break;
+    chunk = plan.next(*host_sc, rrh, it);
   }
   int mx = 0;
   for (int b = 0; b < d.batch; ++b) mx = std::max(mx, (*host_sc)[b].iters);
@@ -740,14 +881,10 @@ static igs_status refine_loop(const Dims& d, const double* band64, const T* band
 // restarted: the search direction survives each correction.)
 constexpr double kReplace = 0.1;
 
-// r32 = float(r64), p = r32
-__global__ void rc_init_kernel(int64_t total, const double* __restrict__ r64, float* __restrict__ r32,
-                               float* __restrict__ p) {
-  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x) {
-    const float v = float(r64[t]);
-    r32[t] = v;
-    p[t] = v;
-  }
+// r32 = float(r64) (the first step's product takes p = r32)
+__global__ void rc_init_kernel(int64_t total, const double* __restrict__ r64, float* __restrict__ r32) {
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total; t += int64_t(gridDim.x) * blockDim.x)
+    r32[t] = float(r64[t]);
 }
 
 // u += alpha p (FP64), r -= alpha q (FP32), partial |r|^2 (FP64 sums)
@@ -773,13 +910,45 @@ __global__ void __launch_bounds__(kSpmvBlock)
   if (threadIdx.x == 0) part[size_t(b) * gridDim.x + lb] = v;
 }
 
+// rc_update with alpha = rr / (p^T A p) summed by every workgroup (at most
+// kFuseParts partials per problem)
+__global__ void __launch_bounds__(kSpmvBlock)
+    rc_step_kernel(int64_t N, CgScalars* __restrict__ sc, const double* __restrict__ pap,
+                   const float* __restrict__ p, const float* __restrict__ q, double* __restrict__ u,
+                   float* __restrict__ r, double* __restrict__ part) {
+  const int b = blockIdx.y;
+  if (sc[b].done) return;
+  const double s = sum_parts(pap, b, gridDim.x);
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  if (!(s > 0.0) || !isfinite(s)) {
+    if (lb == 0 && threadIdx.x == 0) {
+      sc[b].done = 1;
+      sc[b].breakdown = 1;
+    }
+    return;
+  }
+  const double alpha = sc[b].rr / s;
+  const float af = float(alpha);
+  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
+  double v = 0.0;
+  if (i < N) {
+    const size_t k = size_t(b) * N + i;
+    u[k] += alpha * double(p[k]);
+    const float rn = r[k] - af * q[k];
+    r[k] = rn;
+    v = double(rn) * double(rn);
+  }
+  v = block_sum<double>(v);
+  if (threadIdx.x == 0) part[size_t(b) * gridDim.x + lb] = v;
+}
+
 // beta = rr_new / rr, or schedule a replacement (beta then comes from the
 // replaced residual)
 __global__ void __launch_bounds__(kRedBlock) rc_beta_kernel(const double* __restrict__ part, int nblk, CgScalars* sc) {
   const int b = blockIdx.x;
   if (sc[b].done) return;
   double s = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += kRedBlock) s += part[size_t(b) * nblk + k];
+  s += strided_sum(part + size_t(b) * nblk, threadIdx.x, nblk);
   s = block_sum<double>(s);
   if (threadIdx.x == 0) {
     if (!isfinite(s)) {
@@ -800,7 +969,7 @@ __global__ void __launch_bounds__(kRedBlock) rc_replace_kernel(const double* __r
   const int b = blockIdx.x;
   if (sc[b].done || !sc[b].replace) return;
   double s = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += kRedBlock) s += part[size_t(b) * nblk + k];
+  s += strided_sum(part + size_t(b) * nblk, threadIdx.x, nblk);
   s = block_sum<double>(s);
   if (threadIdx.x == 0) {
     sc[b].replace = 0;
@@ -868,37 +1037,51 @@ static igs_status replace_cg(const Dims& d, const double* band64, const float* b
   }
   HIP_OK(hipMemcpyAsync(sb.tol2, tol2.data(), sizeof(double) * nb, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(sb.active, active.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(rc_init_kernel, dim3(grid_stride_blocks(NB)), dim3(256), 0, s, int64_t(NB), sb.r64, r32, p);
+  hipLaunchKernelGGL(rc_init_kernel, dim3(grid_stride_blocks(NB)), dim3(256), 0, s, int64_t(NB), sb.r64, r32);
   hipLaunchKernelGGL(cg_setup_kernel, dim3(1), dim3(64), 0, s, d.batch, sb.rr, sb.tol2, sb.active, sb.sc);
   HIP_OK(hipGetLastError());
 
+  // a step: the product (A32 r32, the direction update of p and q = A32 p), the
+  // update (alpha; u and r32; partials of |r32|^2), beta or a scheduled
+  // replacement, and the replacement itself (its kernels return at once on
+  // the steps that have none)
+  const bool fused = nblk <= kFuseParts;
   std::vector<CgScalars> hsc(nb);
-  const int chunk = 32;
-  int done_iters = 0;
-  while (done_iters < maxit) {
-    const int k = std::min(chunk, maxit - done_iters);
-    for (int it = 0; it < k; ++it) {
+  ChunkPlanner plan(rr);
+  int chunk = plan.first();
+  int it = 0;
+  while (it < maxit) {
+    const int k = std::min(chunk, maxit - it);
+    for (int j = 0; j < k; ++j, ++it) {
+      const CgDir<float> cd{p, nullptr, it, it == 0 ? 0 : 1};
       {
         PhaseTimer t("cg_spmv_f32", s);
-        launch_spmv32<1>(g, nblk, d.batch, band32, p, q, 1, sb.sc, sb.part, s);
+        launch_cg_product<float>(g, nblk, d.batch, band32, r32, cd, q, sb.sc, sb.part, s);
       }
       PhaseTimer t("cg_vector_ops", s);
-      hipLaunchKernelGGL(cg_alpha_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
-      hipLaunchKernelGGL(rc_update_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, sb.sc, p, q, u, r32,
-                         sb.part2);
+      if (fused) {
+        hipLaunchKernelGGL(rc_step_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, sb.sc, sb.part, p, q, u,
+                           r32, sb.part2);
+      } else {
+        hipLaunchKernelGGL(cg_alpha_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
+        hipLaunchKernelGGL(rc_update_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, sb.sc, p, q, u, r32,
+                           sb.part2);
+      }
       hipLaunchKernelGGL(rc_beta_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part2, nblk, sb.sc);
       launch_spmv64<3>(g, nblk, d.batch, band64, u, f, nullptr, r32, 1, sb.sc, sb.part, nullptr, s);
       hipLaunchKernelGGL(rc_replace_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
-      hipLaunchKernelGGL((cg_pupdate_kernel<float>), dim3(std::min<int64_t>((d.N + 255) / 256, 4096), d.batch),
-                         dim3(256), 0, s, d.N, sb.sc, r32, p);
     }
     HIP_OK(hipGetLastError());
-    done_iters += k;
     HIP_OK(hipMemcpyAsync(hsc.data(), sb.sc, sizeof(CgScalars) * nb, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     bool all = true;
-    for (size_t b = 0; b < nb; ++b) all &= hsc[b].done != 0;
+    std::vector<double> rrh(nb);
+    for (size_t b = 0; b < nb; ++b) {
+      all &= hsc[b].done != 0;
+      rrh[b] = hsc[b].rr;
+    }
     if (all) break;
+    chunk = plan.next(hsc, rrh, it);
   }
   // report the FP64 residual of the returned solution
   st = true_residual(&rr, &ff);
