@@ -73,10 +73,16 @@ struct CgScalars {
   int replace;    // residual replacement due after this iteration
   int nrep;       // replacements made
   int pad;
-  // plain CG: r^T r of iterations k (rrv[k & 1]) and k + 1 (rrv[(k + 1) & 1]);
-  // the fused kernels of iteration k read one and write the other
+  // fused scalars: r^T r of iterations k (rrv[k & 1]) and k + 1
+  // (rrv[(k + 1) & 1]); the kernels of iteration k read one and write the other
   double rrv[2];
+  // fused residual replacement: what launch slot k does (kSlotStep or
+  // kSlotReplace), in kind[k & 1]
+  int kind[2];
 };
+constexpr int kSlotStep = 0, kSlotReplace = 1;
+// residual replacement: when the FP32 recursive |r|^2 has fallen by kReplace^2
+constexpr double kReplace = 0.1;
 
 // Banded SpMV for both band types.  A thread owns R consecutive rows, so one
 // 16-byte band load per slot serves all of them (R = 2 for FP64, 4 for FP32):
@@ -180,13 +186,76 @@ __device__ __forceinline__ void record_rr(CgScalars& c, double s, int it) {
 //   bsrc 2  plain CG with fused scalars: every workgroup sums the previous
 //           step's partials of r^T r (rrp) itself, beta = rr_new / rr_old, and
 //           workgroup 0 records rr_new (record_rr with `it`)
+//   bsrc 3  FP32 CG with FP64 residual replacement, fused scalars: launch
+//           slot `it` decides its role (replace_slot)
 template <typename T>
 struct CgDir {
   T* p;
-  const double* rrp;
+  const double* rrp;   // partials of r^T r after the previous step
+  const double* rrp2;  // bsrc 3: partials of |f - A u|^2 of the previous slot's replacement
   int it;
   int bsrc;
 };
+
+// FP32 CG with FP64 residual replacement, fused scalars (at most kFuseParts
+// partials per problem).  Every launch slot runs the product and the update
+// kernel; from what slot it - 1 left, the product decides whether slot it is
+// a step (the product runs, then the update) or a replacement (only the
+// update kernel runs, as the FP64 residual, giving r and rr_ref).  After a
+// step: |r|^2 from its partials; non-finite -> breakdown; fallen by kReplace^2
+// since the last replacement, or at the tolerance -> a replacement slot;
+// otherwise beta = |r|^2 / rr.  After a replacement: |r|^2 of the FP64
+// residual is the new rr and rr_ref, converged when at the tolerance, else
+// beta = |r|^2 / rr (rr of the step before the replacement).  Every workgroup
+// computes the same sums and decisions; workgroup 0 (rec) records them in the
+// slots of parity it & 1, which no workgroup of this kernel reads.  Returns
+// false when the slot runs no product.
+template <int NT>
+__device__ __forceinline__ bool replace_slot(CgScalars& c, const double* rrp, const double* rrp2, int b, int nparts,
+                                             int it, bool rec, double* beta) {
+  const int cur = it & 1, prv = cur ^ 1;
+  const double rr_old = c.rrv[prv];
+  if (c.kind[prv] == kSlotStep) {
+    const double s = sum_parts_nt<NT>(rrp, b, nparts);
+    const bool bad = !isfinite(s);
+    const bool rep = !bad && (s <= kReplace * kReplace * c.rr_ref || s <= c.tol2);
+    if (rec) {
+      if (bad) {
+        c.done = 1;
+        c.breakdown = 1;
+      } else if (rep) {
+        c.kind[cur] = kSlotReplace;
+        c.rrv[cur] = rr_old;
+      } else {
+        c.kind[cur] = kSlotStep;
+        c.rrv[cur] = s;
+        c.iters += 1;
+      }
+    }
+    if (bad || rep) return false;
+    *beta = s / rr_old;
+    return true;
+  }
+  const double s = sum_parts_nt<NT>(rrp2, b, nparts);
+  const bool bad = !isfinite(s);
+  const bool conv = !bad && s <= c.tol2;
+  if (rec) {
+    c.nrep += 1;
+    c.iters += 1;
+    if (bad) {
+      c.done = 1;
+      c.breakdown = 1;
+    } else {
+      c.rr_ref = s;
+      c.rrv[cur] = s;
+      c.kind[cur] = kSlotStep;
+      if (conv) c.done = 1;
+    }
+  }
+  if (bad || conv) return false;
+  *beta = s / rr_old;
+  return true;
+}
 
 template <typename T, int P, int ND, int MODE>
 __global__ void __launch_bounds__(SpmvShape<T>::NT)
@@ -222,6 +291,10 @@ __global__ void __launch_bounds__(SpmvShape<T>::NT)
       beta = T(s / rr_old);
     } else if (cd.bsrc == 1) {
       beta = T(sc[b].beta);
+    } else if (cd.bsrc == 3) {
+      double bt = 0.0;
+      if (!replace_slot<NT>(sc[b], cd.rrp, cd.rrp2, b, gridDim.x, cd.it, lb == 0 && tid == 0, &bt)) return;
+      beta = T(bt);
     }
   }
   const T* xb = x + size_t(b) * g.N;
@@ -447,6 +520,7 @@ __global__ void cg_setup_kernel(int batch, const double* __restrict__ rr, const 
   s.replace = 0;
   s.nrep = 0;
   s.pad = 0;
+  s.kind[0] = s.kind[1] = kSlotStep;
   s.rrv[0] = s.rr;
   s.rrv[1] = 0.0;
   sc[b] = s;
@@ -742,7 +816,7 @@ static igs_status inner_cg(const Dims& d, const T* band, const SolveBufs& sb, T*
   while (it < budget) {
     const int k = std::min(chunk, budget - it);
     for (int j = 0; j < k; ++j, ++it) {
-      const CgDir<T> cd{p, sb.part2, it, it == 0 ? 0 : (fused ? 2 : 1)};
+      const CgDir<T> cd{p, sb.part2, nullptr, it, it == 0 ? 0 : (fused ? 2 : 1)};
       {
         PhaseTimer t(sizeof(T) == 8 ? "cg_spmv_f64" : "cg_spmv_f32", s);
         launch_cg_product<T>(g, nblk, d.batch, band, rh, cd, q, sb.sc, sb.part, s);
@@ -879,7 +953,6 @@ static igs_status refine_loop(const Dims& d, const double* band64, const T* band
 // f - A64 u of the FP64 band.  Convergence is decided on those FP64 residuals
 // only.  (An FP64 iterative refinement whose correction solves are not
 // restarted: the search direction survives each correction.)
-constexpr double kReplace = 0.1;
 
 // r32 = float(r64) (the first step's product takes p = r32)
 __global__ void rc_init_kernel(int64_t total, const double* __restrict__ r64, float* __restrict__ r32) {
@@ -910,16 +983,54 @@ __global__ void __launch_bounds__(kSpmvBlock)
   if (threadIdx.x == 0) part[size_t(b) * gridDim.x + lb] = v;
 }
 
-// rc_update with alpha = rr / (p^T A p) summed by every workgroup (at most
-// kFuseParts partials per problem)
+// The second kernel of launch slot `it` of the fused residual-replacement
+// loop (replace_slot).  Step slots: rc_update with alpha = rrv / (p^T A p)
+// summed by every workgroup (at most kFuseParts partials per problem).
+// Replacement slots: r = float(f - A64 u) with Dirichlet rows 0, partials of
+// |f - A64 u|^2 (FP64, before rounding) in rep; one row per thread, slots in
+// colex order, columns outside [0, N) clamped (their band entries are 0).
+// Slower per row than the banded product, but it runs on a few slots only.
 __global__ void __launch_bounds__(kSpmvBlock)
-    rc_step_kernel(int64_t N, CgScalars* __restrict__ sc, const double* __restrict__ pap,
+    rc_step_kernel(SpmvGeom g, CgScalars* __restrict__ sc, const double* __restrict__ pap,
                    const float* __restrict__ p, const float* __restrict__ q, double* __restrict__ u,
-                   float* __restrict__ r, double* __restrict__ part) {
+                   float* __restrict__ r, double* __restrict__ part, const double* __restrict__ band64,
+                   const double* __restrict__ f, double* __restrict__ rep, int it) {
   const int b = blockIdx.y;
   if (sc[b].done) return;
-  const double s = sum_parts(pap, b, gridDim.x);
+  const int64_t N = g.N;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  if (sc[b].kind[it & 1] == kSlotReplace) {
+    const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
+    double v = 0.0;
+    if (i < N) {
+      const size_t k = size_t(b) * N + i;
+      double o = 0.0;
+      if (!on_dirichlet(g, i)) {
+        const double* bb = band64 + size_t(b) * g.S * g.ld + i;
+        const double* ub = u + size_t(b) * N;
+        const int64_t m1 = g.m[0], m12 = int64_t(g.m[0]) * g.m[1];
+        const int W = g.W, P = g.p, W3 = g.n == 3 ? W : 1;
+        double acc = 0.0;
+        for (int c = 0; c < W3; ++c)
+          for (int e = 0; e < W; ++e) {
+            const int64_t base = i + (g.n == 3 ? (c - P) * m12 : 0) + (e - P) * m1 - P;
+            const double* bs = bb + size_t((c * W + e) * W) * g.ld;
+            for (int a = 0; a < W; ++a) {
+              int64_t j = base + a;
+              j = j < 0 ? 0 : (j >= N ? N - 1 : j);
+              acc += bs[size_t(a) * g.ld] * ub[j];
+            }
+          }
+        o = f[k] - acc;
+      }
+      r[k] = float(o);
+      v = o * o;
+    }
+    v = block_sum<double>(v);
+    if (threadIdx.x == 0) rep[size_t(b) * gridDim.x + lb] = v;
+    return;
+  }
+  const double s = sum_parts(pap, b, gridDim.x);
   if (!(s > 0.0) || !isfinite(s)) {
     if (lb == 0 && threadIdx.x == 0) {
       sc[b].done = 1;
@@ -927,7 +1038,7 @@ __global__ void __launch_bounds__(kSpmvBlock)
     }
     return;
   }
-  const double alpha = sc[b].rr / s;
+  const double alpha = sc[b].rrv[it & 1] / s;
   const float af = float(alpha);
   const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
   double v = 0.0;
@@ -994,7 +1105,7 @@ static igs_status replace_cg(const Dims& d, const double* band64, const float* b
   const size_t NB = size_t(d.N) * d.batch;
   const size_t nb = size_t(d.batch);
   Arena ar;
-  size_t bytes = padded(sizeof(double) * NB) + 2 * padded(sizeof(double) * nb * nblk) + 4 * padded(sizeof(double) * nb) +
+  size_t bytes = padded(sizeof(double) * NB) + 3 * padded(sizeof(double) * nb * nblk) + 4 * padded(sizeof(double) * nb) +
                  padded(sizeof(int) * nb) + padded(sizeof(CgScalars) * nb) + 3 * padded(sizeof(float) * NB);
   igs_status st = ar.alloc(bytes, s);
   if (st != IGS_OK) return st;
@@ -1002,6 +1113,7 @@ static igs_status replace_cg(const Dims& d, const double* band64, const float* b
   sb.r64 = ar.take<double>(NB);
   sb.part = ar.take<double>(nb * nblk);
   sb.part2 = ar.take<double>(nb * nblk);
+  double* part3 = ar.take<double>(nb * nblk);
   sb.rr = ar.take<double>(nb);
   sb.ff = ar.take<double>(nb);
   sb.scale = ar.take<double>(nb);
@@ -1041,10 +1153,16 @@ static igs_status replace_cg(const Dims& d, const double* band64, const float* b
   hipLaunchKernelGGL(cg_setup_kernel, dim3(1), dim3(64), 0, s, d.batch, sb.rr, sb.tol2, sb.active, sb.sc);
   HIP_OK(hipGetLastError());
 
-  // a step: the product (A32 r32, the direction update of p and q = A32 p), the
-  // update (alpha; u and r32; partials of |r32|^2), beta or a scheduled
-  // replacement, and the replacement itself (its kernels return at once on
-  // the steps that have none)
+  // At most kFuseParts partials per problem: launch slots of two kernels
+  // (replace_slot): the product (A32 r32, the direction update of p and
+  // q = A32 p; it decides the slot's role) and the update (step slots: alpha,
+  // u and r32, partials of |r32|^2; replacement slots: the FP64 residual).
+  // The last two slots of a solve are the replacement that confirms
+  // convergence and the product that records it.
+  // Otherwise one-workgroup kernels between them: the product, alpha, the
+  // update, beta or a scheduled replacement, the FP64 residual and the
+  // replacement's scalars (the last two return at once on the steps that
+  // have no replacement).
   const bool fused = nblk <= kFuseParts;
   std::vector<CgScalars> hsc(nb);
   ChunkPlanner plan(rr);
@@ -1053,23 +1171,23 @@ static igs_status replace_cg(const Dims& d, const double* band64, const float* b
   while (it < maxit) {
     const int k = std::min(chunk, maxit - it);
     for (int j = 0; j < k; ++j, ++it) {
-      const CgDir<float> cd{p, nullptr, it, it == 0 ? 0 : 1};
+      const CgDir<float> cd{p, sb.part2, part3, it, it == 0 ? 0 : (fused ? 3 : 1)};
       {
         PhaseTimer t("cg_spmv_f32", s);
         launch_cg_product<float>(g, nblk, d.batch, band32, r32, cd, q, sb.sc, sb.part, s);
       }
       PhaseTimer t("cg_vector_ops", s);
       if (fused) {
-        hipLaunchKernelGGL(rc_step_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, sb.sc, sb.part, p, q, u,
-                           r32, sb.part2);
+        hipLaunchKernelGGL(rc_step_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, g, sb.sc, sb.part, p, q, u,
+                           r32, sb.part2, band64, f, part3, it);
       } else {
         hipLaunchKernelGGL(cg_alpha_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
         hipLaunchKernelGGL(rc_update_kernel, dim3(nblk, d.batch), dim3(kSpmvBlock), 0, s, d.N, sb.sc, p, q, u, r32,
                            sb.part2);
+        hipLaunchKernelGGL(rc_beta_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part2, nblk, sb.sc);
+        launch_spmv64<3>(g, nblk, d.batch, band64, u, f, nullptr, r32, 1, sb.sc, sb.part, nullptr, s);
+        hipLaunchKernelGGL(rc_replace_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
       }
-      hipLaunchKernelGGL(rc_beta_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part2, nblk, sb.sc);
-      launch_spmv64<3>(g, nblk, d.batch, band64, u, f, nullptr, r32, 1, sb.sc, sb.part, nullptr, s);
-      hipLaunchKernelGGL(rc_replace_kernel, dim3(d.batch), dim3(kRedBlock), 0, s, sb.part, nblk, sb.sc);
     }
     HIP_OK(hipGetLastError());
     HIP_OK(hipMemcpyAsync(hsc.data(), sb.sc, sizeof(CgScalars) * nb, hipMemcpyDeviceToHost, s));
@@ -1078,10 +1196,12 @@ static igs_status replace_cg(const Dims& d, const double* band64, const float* b
     std::vector<double> rrh(nb);
     for (size_t b = 0; b < nb; ++b) {
       all &= hsc[b].done != 0;
-      rrh[b] = hsc[b].rr;
+      // fused: the product of slot it - 1 recorded r^T r in rrv[(it - 1) & 1]
+      rrh[b] = fused ? hsc[b].rrv[(it - 1) & 1] : hsc[b].rr;
     }
     if (all) break;
-    chunk = plan.next(hsc, rrh, it);
+    // fused: two more slots confirm and record convergence
+    chunk = plan.next(hsc, rrh, fused ? it - 1 : it) + (fused ? 2 : 0);
   }
   // report the FP64 residual of the returned solution
   st = true_residual(&rr, &ff);
