@@ -139,34 +139,44 @@ struct SpmvShape {
 
 // Sum of part[b][0..n) in exactly the order of a kRedBlock-thread reduction
 // (strided per-thread sums, the wavefront butterfly, wavefront sums in order),
-// computed by a workgroup of NT threads: thread t plays the virtual threads
-// t + j NT.  Any NT therefore gives the same bits as sum_parts below.
+// computed by a workgroup of NT threads (a multiple of 64): thread t plays the
+// virtual threads t + j NT below kRedBlock.  Any NT therefore gives the same
+// bits as sum_parts below.  In two halves: load() issues the loads (no
+// barrier, so a kernel can start it early and let other loads overlap it),
+// combine() adds up across the workgroup.
 template <int NT>
-__device__ __forceinline__ double sum_parts_nt(const double* __restrict__ part, int b, int n) {
-  constexpr int V = kRedBlock / NT;
-  static_assert(V * NT == kRedBlock && NT % 64 == 0, "whole wavefronts");
-  __shared__ double red[kRedBlock / 64];
-  const double* pb = part + size_t(b) * n;
+struct PartSum {
+  static constexpr int V = (kRedBlock + NT - 1) / NT;
+  static_assert(NT % 64 == 0, "whole wavefronts");
   double v[V];
+  __device__ __forceinline__ void load(const double* __restrict__ part, int b, int n) {
+    const double* pb = part + size_t(b) * n;
 #pragma unroll
-  for (int j = 0; j < V; ++j) {
-    v[j] = 0.0;
-    v[j] = strided_sum(pb, threadIdx.x + j * NT, n);
+    for (int j = 0; j < V; ++j) {
+      const int vt = threadIdx.x + j * NT;  // the same validity across a wavefront
+      v[j] = vt < kRedBlock ? strided_sum(pb, vt, n) : 0.0;
+    }
   }
+  __device__ __forceinline__ double combine() {
+    __shared__ double red[kRedBlock / 64];
 #pragma unroll
-  for (int j = 0; j < V; ++j)
+    for (int j = 0; j < V; ++j)
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off, 64);
-  if ((threadIdx.x & 63) == 0)
+      for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off, 64);
+    if ((threadIdx.x & 63) == 0)
 #pragma unroll
-    for (int j = 0; j < V; ++j) red[(threadIdx.x >> 6) + j * (NT / 64)] = v[j];
-  __syncthreads();
-  double s = red[0];
+      for (int j = 0; j < V; ++j) {
+        const int vt = threadIdx.x + j * NT;
+        if (vt < kRedBlock) red[vt >> 6] = v[j];
+      }
+    __syncthreads();
+    double s = red[0];
 #pragma unroll
-  for (int k = 1; k < kRedBlock / 64; ++k) s += red[k];
-  __syncthreads();
-  return s;
-}
+    for (int k = 1; k < kRedBlock / 64; ++k) s += red[k];
+    __syncthreads();
+    return s;
+  }
+};
 
 // r^T r after `it` completed CG steps: record it and decide convergence
 __device__ __forceinline__ void record_rr(CgScalars& c, double s, int it) {
@@ -208,15 +218,15 @@ struct CgDir {
 // residual is the new rr and rr_ref, converged when at the tolerance, else
 // beta = |r|^2 / rr (rr of the step before the replacement).  Every workgroup
 // computes the same sums and decisions; workgroup 0 (rec) records them in the
-// slots of parity it & 1, which no workgroup of this kernel reads.  Returns
-// false when the slot runs no product.
+// slots of parity it & 1, which no workgroup of this kernel reads.  ps holds
+// the loaded partials (cg_product_load).  Returns false when the slot runs no
+// product.
 template <int NT>
-__device__ __forceinline__ bool replace_slot(CgScalars& c, const double* rrp, const double* rrp2, int b, int nparts,
-                                             int it, bool rec, double* beta) {
+__device__ __forceinline__ bool replace_slot(CgScalars& c, PartSum<NT>& ps, int it, bool rec, double* beta) {
   const int cur = it & 1, prv = cur ^ 1;
   const double rr_old = c.rrv[prv];
   if (c.kind[prv] == kSlotStep) {
-    const double s = sum_parts_nt<NT>(rrp, b, nparts);
+    const double s = ps.combine();
     const bool bad = !isfinite(s);
     const bool rep = !bad && (s <= kReplace * kReplace * c.rr_ref || s <= c.tol2);
     if (rec) {
@@ -236,7 +246,7 @@ __device__ __forceinline__ bool replace_slot(CgScalars& c, const double* rrp, co
     *beta = s / rr_old;
     return true;
   }
-  const double s = sum_parts_nt<NT>(rrp2, b, nparts);
+  const double s = ps.combine();
   const bool bad = !isfinite(s);
   const bool conv = !bad && s <= c.tol2;
   if (rec) {
@@ -254,6 +264,39 @@ __device__ __forceinline__ bool replace_slot(CgScalars& c, const double* rrp, co
   }
   if (bad || conv) return false;
   *beta = s / rr_old;
+  return true;
+}
+
+// The partials a CG product workgroup (mode 1, see CgDir) of NT threads
+// reduces for its direction-update scalar, loaded at its start.
+template <typename T, int NT>
+__device__ __forceinline__ void cg_product_load(const CgScalars* sc, const CgDir<T>& cd, int b, int nparts,
+                                                PartSum<NT>& ps) {
+  if (cd.bsrc == 2) ps.load(cd.rrp, b, nparts);
+  if (cd.bsrc == 3) ps.load(sc[b].kind[(cd.it - 1) & 1] == kSlotStep ? cd.rrp : cd.rrp2, b, nparts);
+}
+
+// The direction-update scalar itself, from the loaded partials; rec: the
+// workgroup that records the scalars.  False when the workgroup has nothing
+// to do (the problem has finished, or the slot is a replacement).
+template <typename T, int NT>
+__device__ __forceinline__ bool cg_product_beta(CgScalars* sc, const CgDir<T>& cd, int b, bool rec, PartSum<NT>& ps,
+                                                T* beta) {
+  *beta = T(0);
+  if (cd.bsrc == 2) {
+    const double s = ps.combine();
+    const double rr_old = sc[b].rrv[(cd.it - 1) & 1];
+    const bool stop = !isfinite(s) || s <= sc[b].tol2;  // the same in every workgroup
+    if (rec) record_rr(sc[b], s, cd.it);
+    if (stop) return false;
+    *beta = T(s / rr_old);
+  } else if (cd.bsrc == 1) {
+    *beta = T(sc[b].beta);
+  } else if (cd.bsrc == 3) {
+    double bt = 0.0;
+    if (!replace_slot<NT>(sc[b], ps, cd.it, rec, &bt)) return false;
+    *beta = T(bt);
+  }
   return true;
 }
 
@@ -280,22 +323,14 @@ __global__ void __launch_bounds__(SpmvShape<T>::NT)
   const int64_t i0 = int64_t(lb) * kSpmvBlock;
   const int tid = threadIdx.x;
   const int64_t r0 = i0 + R * tid;
+  // mode 1: the direction-update scalar before the band loop (after it, the
+  // staged FP32 kernel needs more registers than three wavefronts per SIMD
+  // allow; spmv2_kernel, the 2D product, overlaps its reduction instead)
   T beta = T(0);
   if constexpr (MODE == 1) {
-    if (cd.bsrc == 2) {
-      const double s = sum_parts_nt<NT>(cd.rrp, b, gridDim.x);
-      const double rr_old = sc[b].rrv[(cd.it - 1) & 1];
-      const bool stop = !isfinite(s) || s <= sc[b].tol2;  // the same in every workgroup
-      if (lb == 0 && tid == 0) record_rr(sc[b], s, cd.it);
-      if (stop) return;
-      beta = T(s / rr_old);
-    } else if (cd.bsrc == 1) {
-      beta = T(sc[b].beta);
-    } else if (cd.bsrc == 3) {
-      double bt = 0.0;
-      if (!replace_slot<NT>(sc[b], cd.rrp, cd.rrp2, b, gridDim.x, cd.it, lb == 0 && tid == 0, &bt)) return;
-      beta = T(bt);
-    }
+    PartSum<NT> ps;
+    cg_product_load<T, NT>(sc, cd, b, gridDim.x, ps);
+    if (!cg_product_beta<T, NT>(sc, cd, b, lb == 0 && tid == 0, ps, &beta)) return;
   }
   const T* xb = x + size_t(b) * g.N;
   const T* bb = band + size_t(b) * g.S * g.ld;
@@ -421,6 +456,116 @@ __global__ void __launch_bounds__(SpmvShape<T>::NT)
   if (threadIdx.x == 0) part[size_t(b) * gridDim.x + lb] = a;
 }
 
+// 2D products (modes 0 and 1) with one wavefront per delta2 run.  A workgroup
+// of W = 2P+1 wavefronts owns kSpmvBlock rows; wavefront k forms the partial
+// sums of run k (delta2 = k - P) for all of them (4 rows per lane: W band
+// loads of 4 values and 2P+4 values of x from L2 per lane), the partials meet
+// in LDS, and the threads add them in run order and finish the rows (the
+// epilogue of spmv_band_kernel; one row per thread, two for P = 1).  W times the wavefronts of
+// spmv_band_kernel, each with a W times shorter load chain: on the small
+// batches of 2D solves one wavefront per 256 rows left a few per SIMD and the
+// products latency-bound.
+template <typename T, int P, int MODE, bool STREAM>
+__global__ void __launch_bounds__(64 * (2 * P + 1))
+    spmv2_kernel(SpmvGeom g, const T* __restrict__ band, const T* __restrict__ x, T* __restrict__ y, int mask,
+                 CgScalars* __restrict__ sc, double* __restrict__ part, CgDir<T> cd) {
+  static_assert(MODE < 2, "products only");
+  constexpr int W = 2 * P + 1, NT = 64 * W, R = 4, NX = 2 * P + R;
+  typedef typename VecR<T, R>::v VT;
+  __shared__ __align__(16) T red[W * kSpmvBlock];
+  const int b = blockIdx.y;
+  if (MODE == 1 && sc[b].done) return;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t i0 = int64_t(lb) * kSpmvBlock;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const T* xb = x + size_t(b) * g.N;
+  // mode 1: the partials of the direction-update scalar, loaded now and added
+  // up after the band loop
+  PartSum<NT> ps;
+  if constexpr (MODE == 1) cg_product_load<T, NT>(sc, cd, b, gridDim.x, ps);
+  // the rows this thread finishes (t = tid + f NT below kSpmvBlock; FR = 2 for
+  // P = 1, whose workgroup has 192 threads), and (mode 1) their r, p and q,
+  // loaded early
+  constexpr int FR = (kSpmvBlock + NT - 1) / NT;
+  T rown[FR], pown[FR], qown[FR];
+#pragma unroll
+  for (int f = 0; f < FR; ++f) {
+    const int t = tid + f * NT;
+    const int64_t io = i0 + t;
+    rown[f] = pown[f] = qown[f] = T(0);
+    if (MODE == 1 && t < kSpmvBlock && io < g.N) {
+      const size_t ko = size_t(b) * g.N + io;
+      rown[f] = xb[io];
+      if (cd.bsrc != 0) {
+        pown[f] = cd.p[ko];
+        qown[f] = y[ko];
+      }
+    }
+  }
+  const int64_t r0 = i0 + R * lane;
+  VT acc;
+#pragma unroll
+  for (int q = 0; q < R; ++q) acc[q] = T(0);
+  if (r0 < g.N) {
+    // columns outside [0, N) carry zero band entries: clamp to stay in bounds
+    const int64_t base = r0 + int64_t(wv - P) * g.m[0] - P;
+    T xw[NX];
+#pragma unroll
+    for (int e = 0; e < NX; ++e) {
+      int64_t j = base + e;
+      j = j < 0 ? 0 : (j >= g.N ? g.N - 1 : j);
+      xw[e] = xb[j];
+    }
+    const T* bk = band + size_t(b) * g.S * g.ld + size_t(wv) * W * g.ld + r0;
+    VT bv[W];
+#pragma unroll
+    for (int d1 = 0; d1 < W; ++d1)
+      bv[d1] = STREAM ? __builtin_nontemporal_load(reinterpret_cast<const VT*>(bk + size_t(d1) * g.ld))
+                      : *reinterpret_cast<const VT*>(bk + size_t(d1) * g.ld);
+#pragma unroll
+    for (int d1 = 0; d1 < W; ++d1)
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] = fma(bv[d1][q], xw[d1 + q], acc[q]);
+  }
+  *reinterpret_cast<VT*>(red + wv * kSpmvBlock + R * lane) = acc;
+  __syncthreads();
+  // the scalars after the band loop (nothing is written before this point, so
+  // a slot without a product only loses its reads): the latency of their
+  // reduction then overlaps the band loads
+  T beta = T(0);
+  if constexpr (MODE == 1)
+    if (!cg_product_beta<T, NT>(sc, cd, b, lb == 0 && tid == 0, ps, &beta)) return;
+  double sa = 0.0;
+#pragma unroll
+  for (int f = 0; f < FR; ++f) {
+    const int t = tid + f * NT;
+    const int64_t io = i0 + t;
+    if (t >= kSpmvBlock || io >= g.N) continue;
+    const size_t ko = size_t(b) * g.N + io;
+    T a = red[t];
+#pragma unroll
+    for (int k = 1; k < W; ++k) a += red[k * kSpmvBlock + t];
+    const bool dir = on_dirichlet(g, io);
+    if (MODE == 0) {
+      y[ko] = (mask && dir) ? T(0) : a;
+    } else {
+      const T w = dir ? T(0) : a;
+      T pn = rown[f], o = w;
+      if (cd.bsrc != 0) {
+        pn = rown[f] + beta * pown[f];
+        o = w + beta * qown[f];
+      }
+      cd.p[ko] = pn;
+      y[ko] = o;
+      sa += double(pn) * double(o);
+    }
+  }
+  if constexpr (MODE == 1) {
+    const double a = block_sum_n<NT>(sa);
+    if (tid == 0) part[size_t(b) * gridDim.x + lb] = a;
+  }
+}
+
 // Bands of at most this many bytes (all problems of a call) are read with
 // ordinary loads, so that they stay in the 256 MiB last-level cache between the
 // products of a solve; larger ones stream past it with non-temporal loads,
@@ -451,6 +596,22 @@ static void launch_spmv_band(const SpmvGeom& g, int nblk, int batch, const T* ba
       case 3: IGS_SPMV(3, 3); break;
       default: IGS_SPMV(4, 3); break;
     }
+  } else if constexpr (MODE < 2) {
+#define IGS_SPMV2(PP)                                                                                             \
+  do {                                                                                                            \
+    const dim3 blk2(64 * (2 * PP + 1));                                                                           \
+    if (stream)                                                                                                   \
+      hipLaunchKernelGGL((spmv2_kernel<T, PP, MODE, true>), grid, blk2, 0, s, g, band, x, y, mask, sc, part, cd);  \
+    else                                                                                                          \
+      hipLaunchKernelGGL((spmv2_kernel<T, PP, MODE, false>), grid, blk2, 0, s, g, band, x, y, mask, sc, part, cd); \
+  } while (0)
+    switch (g.p) {
+      case 1: IGS_SPMV2(1); break;
+      case 2: IGS_SPMV2(2); break;
+      case 3: IGS_SPMV2(3); break;
+      default: IGS_SPMV2(4); break;
+    }
+#undef IGS_SPMV2
   } else {
     switch (g.p) {
       case 1: IGS_SPMV(1, 2); break;
@@ -636,8 +797,20 @@ __global__ void __launch_bounds__(kSpmvBlock)
                    double* __restrict__ part) {
   const int b = blockIdx.y;
   if (sc[b].done) return;
-  const double s = sum_parts(pap, b, gridDim.x);
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
+  const size_t k = size_t(b) * N + i;
+  // the partials of p^T q and this row's vectors go out together
+  PartSum<kSpmvBlock> ps;
+  ps.load(pap, b, gridDim.x);
+  T pv = T(0), qv = T(0), dv = T(0), rv = T(0);
+  if (i < N) {
+    pv = p[k];
+    qv = q[k];
+    dv = d[k];
+    rv = r[k];
+  }
+  const double s = ps.combine();
   if (!(s > 0.0) || !isfinite(s)) {
     if (lb == 0 && threadIdx.x == 0) {
       sc[b].done = 1;
@@ -646,12 +819,10 @@ __global__ void __launch_bounds__(kSpmvBlock)
     return;
   }
   const T alpha = T(sc[b].rrv[par] / s);
-  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
   double v = 0.0;
   if (i < N) {
-    const size_t k = size_t(b) * N + i;
-    d[k] += alpha * p[k];
-    const T rn = r[k] - alpha * q[k];
+    d[k] = dv + alpha * pv;
+    const T rn = rv - alpha * qv;
     r[k] = rn;
     v = double(rn) * double(rn);
   }
@@ -1046,7 +1217,20 @@ __global__ void __launch_bounds__(kSpmvBlock)
     if (threadIdx.x == 0) rep[size_t(b) * gridDim.x + lb] = v;
     return;
   }
-  const double s = sum_parts(pap, b, gridDim.x);
+  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
+  const size_t k = size_t(b) * N + i;
+  // the partials of p^T q and this row's vectors go out together
+  PartSum<kSpmvBlock> ps;
+  ps.load(pap, b, gridDim.x);
+  float pv = 0.f, qv = 0.f, rv = 0.f;
+  double uv = 0.0;
+  if (i < N) {
+    pv = p[k];
+    qv = q[k];
+    rv = r[k];
+    uv = u[k];
+  }
+  const double s = ps.combine();
   if (!(s > 0.0) || !isfinite(s)) {
     if (lb == 0 && threadIdx.x == 0) {
       sc[b].done = 1;
@@ -1056,12 +1240,10 @@ __global__ void __launch_bounds__(kSpmvBlock)
   }
   const double alpha = sc[b].rrv[it & 1] / s;
   const float af = float(alpha);
-  const int64_t i = int64_t(lb) * kSpmvBlock + threadIdx.x;
   double v = 0.0;
   if (i < N) {
-    const size_t k = size_t(b) * N + i;
-    u[k] += alpha * double(p[k]);
-    const float rn = r[k] - af * q[k];
+    u[k] = uv + alpha * double(pv);
+    const float rn = rv - af * qv;
     r[k] = rn;
     v = double(rn) * double(rn);
   }
