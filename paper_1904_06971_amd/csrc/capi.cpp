@@ -537,6 +537,35 @@ static igs_status run_t(const Plan& pl, const KProblem& kp, const KInterp<OutT>&
       HIP_TRY(launch_fill<OutT>(ipT, pl.form, d, pl.dchunks, pl.nchunks, pl.chunk_rows, pl.n2max, pl.n3max, pl.ddsl,
                                 pl.coef, band, s));
     }
+  } else if (d.n == 2 && fill_is_2d(d)) {
+    // 2-D, pencils short enough for fill2d, which stores only the
+    // analysis-domain rows: the rows outside the domain and the lattice lines
+    // in one quadrature launch (their tiles do not overlap), then the fit, the
+    // fill, and the copy kernel, which reads the exact entries of the rows
+    // outside the domain.  Four launches where the order below takes five;
+    // on small meshes each costs latency, not bandwidth.
+    {
+      PhaseTimer t("quad_rows", s);
+      HIP_TRY(launch_quad<OutT>(kp, pl.form, pl.dt, pl.groups[0] + pl.groups[1] + pl.groups[2], false, band, s));
+    }
+    {
+      PhaseTimer t("fit", s);
+      if (fit_use_gemm(pl.ip64, d.n, d.batch))
+        HIP_TRY(launch_fit_gemm<OutT>(pl.ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, pl.tmp0, pl.tmp1,
+                                      pl.coef, s));
+      else
+        HIP_TRY(launch_fit<OutT>(pl.ip64, d.n, d.m[0], d.m[1], d.ld, d.S, d.batch, band, pl.tmp0, pl.tmp1, pl.coef,
+                                 pl.g0T, s));
+    }
+    {
+      PhaseTimer t("fill", s);
+      HIP_TRY(launch_fill<OutT>(ipT, pl.form, d, pl.dchunks, pl.nchunks, pl.chunk_rows, pl.n2max, pl.n3max, pl.ddsl,
+                                pl.coef, band, s));
+    }
+    if (pl.ncopy > 0) {
+      PhaseTimer t("copy", s);
+      HIP_TRY(launch_copy<OutT>(ipT, pl.form, d, pl.dcopy, pl.ncopy, band, s));
+    }
   } else {
     // Order: sample rows, fit and fill first; the fill writes whole lines of
     // the analysis-domain pencils, placeholders included, and reads nothing of

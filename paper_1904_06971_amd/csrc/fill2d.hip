@@ -18,10 +18,11 @@ namespace igs {
 //      which is the lower entry of row i1 + d1; the latter goes to LDS;
 //   C  each row reads its lower entry Phi~_u(i1 - d1, i2 - d2) from LDS.
 // Nothing is staged but the two contraction lines and one pencil of values, so
-// the LDS footprint is (2 S1 + m1) values whatever the mesh.  Entries that are
-// not interpolated get placeholders (0) and rows outside the analysis domain
-// zeros; the boundary-row quadrature and the copy kernel overwrite them as in
-// the other fill kernels.
+// the LDS footprint is (2 S1 + m1) values whatever the mesh.  Only the rows of
+// the fill range [lo1, hi1] are stored (the rows outside it come from the
+// boundary-row quadrature, which may run before this kernel); entries that
+// are not interpolated get placeholders (0), which the copy kernel
+// overwrites.
 // PF: every direction-2 task has its own thread (2 S1 <= blockDim.x); its
 // operands for the next delta are loaded while the rows finish this one.
 template <int FORM, int Q, int R, typename T, bool PF>
@@ -130,7 +131,7 @@ __global__ void __launch_bounds__(1024)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i1 = tid + r * nt;
-      if (i1 >= m1) continue;
+      if (!in1[r]) continue;
       T vl = T(0);
       if (in1[r] && lo2) {
         const int k1 = i1 - d1;
@@ -145,7 +146,7 @@ __global__ void __launch_bounds__(1024)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i1 = tid + r * nt;
-      if (i1 < m1) bnd[size_t(sc) * ld + i1] = in1[r] ? -dsum[r] : T(0);
+      if (in1[r]) bnd[size_t(sc) * ld + i1] = -dsum[r];
     }
   }
 }
