@@ -614,7 +614,9 @@ static igs_status run_t(const Plan& pl, const KProblem& kp, const KInterp<OutT>&
       HIP_TRY(launch_copy<OutT>(ipT, pl.form, d, pl.dcopy, pl.ncopy, band, s));
     }
   }
-  {
+  // the 2-D fill zeroes the padding columns itself
+  const bool fill_pads = fill_is_2d(d) && (pl.kind == 1 || pl.kind == 2);
+  if (!fill_pads) {
     PhaseTimer t("zero_pad", s);
     HIP_TRY(launch_zero_pad<OutT>(band, d.N, d.ld, d.S * d.batch, s));
   }

@@ -27,8 +27,19 @@ namespace igs {
 // operands for the next delta are loaded while the rows finish this one.
 template <int FORM, int Q, int R, typename T, bool PF>
 __global__ void __launch_bounds__(1024)
-    fill2d_kernel(KInterp<T> ip, int m1, int64_t ld, int S, const int4* __restrict__ dsl,
+    fill2d_kernel(KInterp<T> ip, int m1, int64_t N, int64_t ld, int S, const int4* __restrict__ dsl,
                   const double* __restrict__ coef, T* __restrict__ band) {
+  // the last workgroup of each problem zeroes its band's padding columns
+  // [N, ld) (no launch of its own after the fill)
+  if (blockIdx.x == gridDim.x - 1) {
+    T* bb = band + size_t(blockIdx.y) * S * ld;
+    const int64_t pad = ld - N;
+    for (int64_t t = threadIdx.x; t < pad * S; t += blockDim.x) {
+      const int64_t sl = t / pad;
+      bb[sl * ld + N + (t - sl * pad)] = T(0);
+    }
+    return;
+  }
   extern __shared__ char smem_raw[];
   const int S1 = ip.Sd[0], S2 = ip.Sd[1];
   T* Tl = reinterpret_cast<T*>(smem_raw);  // [2][S1]
@@ -154,13 +165,13 @@ __global__ void __launch_bounds__(1024)
 template <int FORM, int R, typename T, bool PF>
 static void launch_fill2d_q(const KInterp<T>& ip, const Dims& d, int nt, size_t lds, const int4* dsl,
                             const double* coef, T* band, hipStream_t s) {
-  dim3 grid(ip.hi[1] - ip.lo[1] + 1, d.batch);
+  dim3 grid(ip.hi[1] - ip.lo[1] + 2, d.batch);  // + the padding workgroup
   switch (ip.q) {
-    case 1: hipLaunchKernelGGL((fill2d_kernel<FORM, 1, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
-    case 2: hipLaunchKernelGGL((fill2d_kernel<FORM, 2, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
-    case 3: hipLaunchKernelGGL((fill2d_kernel<FORM, 3, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
-    case 4: hipLaunchKernelGGL((fill2d_kernel<FORM, 4, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
-    default: hipLaunchKernelGGL((fill2d_kernel<FORM, 5, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.ld, d.S, dsl, coef, band); break;
+    case 1: hipLaunchKernelGGL((fill2d_kernel<FORM, 1, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.N, d.ld, d.S, dsl, coef, band); break;
+    case 2: hipLaunchKernelGGL((fill2d_kernel<FORM, 2, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.N, d.ld, d.S, dsl, coef, band); break;
+    case 3: hipLaunchKernelGGL((fill2d_kernel<FORM, 3, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.N, d.ld, d.S, dsl, coef, band); break;
+    case 4: hipLaunchKernelGGL((fill2d_kernel<FORM, 4, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.N, d.ld, d.S, dsl, coef, band); break;
+    default: hipLaunchKernelGGL((fill2d_kernel<FORM, 5, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.N, d.ld, d.S, dsl, coef, band); break;
   }
 }
 
