@@ -774,11 +774,76 @@ __global__ void __launch_bounds__(256)
   yb[i] = acc;
 }
 
+// 2-D fit in one launch, for small sample grids (S1 S2 <= kFit2dLds): one
+// workgroup per (upper stencil function, problem) gathers its S1 x S2 sample
+// values into LDS, applies ginv_1 along direction 1 into a second LDS grid and
+// ginv_2 along direction 2 into the coefficients, with fit_pass_kernel's
+// arithmetic (the identity outside [flo, fhi), four partial sums).  On small
+// 2-D meshes the two passes are two latency-bound launches; here each
+// workgroup does both.  Its work grows as S^3 on nup x batch workgroups, so
+// larger grids keep the two passes (2D p=2 q=5: 64^2 and 128^2 elements,
+// S <= 26, fit 13 -> 8 us; at S = 36 and 50 one workgroup per function was
+// slower than the passes).
+constexpr int kFit2dLds = 1024;  // values per grid (two grids: 16 KB)
+template <typename BT>
+__global__ void __launch_bounds__(256)
+    fit2d_lds_kernel(KInterp<double> ip, int m1, int64_t ld, int S, const BT* __restrict__ band,
+                     double* __restrict__ coef) {
+  __shared__ double X[kFit2dLds], Y[kFit2dLds];
+  const int S1 = ip.Sd[0], S2 = ip.Sd[1], n12 = S1 * S2;
+  const int u = blockIdx.x, b = blockIdx.y;
+  const BT* bs = band + (size_t(b) * S + ip.upslot[u]) * ld;
+  for (int t = threadIdx.x; t < n12; t += blockDim.x) {
+    const int k1 = t % S1, k2 = t / S1;
+    X[t] = double(bs[size_t(m1) * ip.samp[1][k2] + ip.samp[0][k1]]);
+  }
+  __syncthreads();
+  // one direction: out[k] = sum_j ginv_d[kd][j] in[k with kd -> j]
+  auto pass = [&](int d, const double* in, double* out, bool global) {
+    const int Sd = ip.Sd[d], flo = ip.flo[d], fhi = ip.fhi[d];
+    const size_t stride = d == 0 ? 1 : size_t(S1);
+    for (int t = threadIdx.x; t < n12; t += blockDim.x) {
+      const int k1 = t % S1, k2 = t / S1;
+      const int kd = d == 0 ? k1 : k2;
+      const double* sp = in + (d == 0 ? size_t(k2) * S1 : size_t(k1));
+      double v;
+      if (kd < flo || kd >= fhi) {
+        v = sp[kd * stride];
+      } else {
+        const double* g = ip.ginv[d] + size_t(kd) * Sd;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        const int J4 = flo + ((fhi - flo) & ~3);
+        for (int j = flo; j < J4; j += 4) {
+          a0 += g[j] * sp[j * stride];
+          a1 += g[j + 1] * sp[(j + 1) * stride];
+          a2 += g[j + 2] * sp[(j + 2) * stride];
+          a3 += g[j + 3] * sp[(j + 3) * stride];
+        }
+        for (int j = J4; j < fhi; ++j) a0 += g[j] * sp[j * stride];
+        v = (a0 + a1) + (a2 + a3);
+      }
+      if (global)
+        out[(size_t(b) * ip.nup + u) * n12 + t] = v;
+      else
+        out[t] = v;
+    }
+  };
+  pass(0, X, Y, false);
+  __syncthreads();
+  pass(1, Y, coef, true);
+}
+
+bool fit_2d_lds(const KInterp<double>& ip, int n) { return n == 2 && ip.Sd[0] * ip.Sd[1] <= kFit2dLds; }
+
 // ------------------------------------------------------------ launchers ----
 
 template <typename BT>
 hipError_t launch_fit(const KInterp<double>& ip, int n, int m1, int m2, int64_t ld, int S, int batch, const BT* band,
                       double* tmp0, double* tmp1, double* coef, const double* g0T, hipStream_t s) {
+  if (fit_2d_lds(ip, n)) {
+    hipLaunchKernelGGL((fit2d_lds_kernel<BT>), dim3(ip.nup, batch), dim3(256), 0, s, ip, m1, ld, S, band, coef);
+    return hipGetLastError();
+  }
   int64_t total = int64_t(ip.Sd[0]) * ip.Sd[1] * (n == 3 ? ip.Sd[2] : 1) * ip.nup * batch;
   int blocks = int(std::min<int64_t>((total + 255) / 256, 65535));
   double* bufs[3];
