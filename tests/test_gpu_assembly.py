@@ -108,6 +108,33 @@ def test_surrogate_m1_equals_exact(igs, oracle, prob, form):
     assert rel_maxnorm(t, a) < 1e-13
 
 
+@pytest.mark.parametrize("prob,form,M,q", [
+    (W.problem(2, 2, 37), 0, 4, 3), (W.problem(2, 3, (70, 41)), 1, 5, 5), (W.problem(2, 2, 140), 0, 3, 5),
+    (W.problem(3, 2, 14), 0, 3, 3), (W.problem(3, 3, 20), 1, 4, 3),
+])
+def test_surrogate_writes_every_word(igs, oracle, prob, form, M, q):
+    """Into a band filled with NaN first, with a plan executed twice: every
+    row equals the oracle's and the padding columns are zero.  In 2D the rows
+    outside the analysis domain come from the quadrature launch that runs
+    before the fill (which stores only domain rows), and the fill zeroes the
+    padding; the sample grids take the one-launch fit up to 1024 values and the
+    two passes above (140^2 elements, M = 3: 45 x 45 samples)."""
+    import torch
+
+    _, N, _ = oracle.dims(prob)
+    band = igs.empty_band(prob, torch.float64)
+    band.fill_(float("nan"))
+    pl = igs.Plan(prob, form, M=M, q=q)
+    pl.execute(out=band)
+    band.fill_(float("nan"))
+    pl.execute(out=band)
+    pl.close()
+    ref = oracle.surrogate_rows(prob, form, M, q)
+    assert rel_maxnorm(_full(igs, band, prob), ref) < TOL64
+    if igs.layout(prob).ld > N:
+        assert float(band[:, :, N:].abs().max()) == 0.0
+
+
 def test_surrogate_structure(igs, oracle):
     """Bitwise symmetry of interpolated pairs and zero row sums (eq. 5.1c)."""
     prob = W.problem(3, 3, 30)
