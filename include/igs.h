@@ -54,7 +54,7 @@ extern "C" {
 typedef enum igs_status {
   IGS_OK = 0,
   IGS_ERR_ARG = -1,         /* null pointer, bad enum, bad size */
-  IGS_ERR_UNSUPPORTED = -2, /* valid input outside what this build implements */
+  IGS_ERR_UNSUPPORTED = -2, /* valid input outside what the library implements */
   IGS_ERR_KNOTS = -3,       /* a supplied knot vector is not open uniform */
   IGS_ERR_SAMPLES = -4,     /* fewer than q+1 samples, or no analysis-domain rows */
   IGS_ERR_GEOMETRY = -5,    /* det J <= 0 at a quadrature point */

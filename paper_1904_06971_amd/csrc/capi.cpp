@@ -766,7 +766,7 @@ const char* igs_status_string(int32_t status) {
   switch (status) {
     case IGS_OK: return "ok";
     case IGS_ERR_ARG: return "invalid argument";
-    case IGS_ERR_UNSUPPORTED: return "unsupported by this build";
+    case IGS_ERR_UNSUPPORTED: return "unsupported by the library";
     case IGS_ERR_KNOTS: return "knot vector is not open uniform";
     case IGS_ERR_SAMPLES: return "too few samples for the interpolation degree";
     case IGS_ERR_GEOMETRY: return "geometry map folds (det J <= 0 at a quadrature point)";
