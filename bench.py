@@ -41,12 +41,12 @@ FP64_PEAK_TFLOPS = 78.6
 # measured.
 PMC_FETCH_SCALE, PMC_WRITE_SCALE = 2.00, 1.00
 PMC_TRAFFIC = {
-    "quad_boundary_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "28b22772c78230b7", "fetch_kib": 15032.9, "write_kib": 2429544.7},
+    "quad_boundary_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "a5c4085700c26a0f", "fetch_kib": 14977.6, "write_kib": 2429550.5},
     "fill": {"sources": ["fill.hip"], "sha256": "a839a6953e4cbe7c", "fetch_kib": 152703.5, "write_kib": 4971999.7},
     "diag_fixup": {"sources": ["fill.hip"], "sha256": "a839a6953e4cbe7c", "fetch_kib": 361340.0, "write_kib": 2612.8},
     "fe_fill": {"sources": ["fill.hip", "plan.cpp"], "sha256": "6407a3d7e3a2617e", "fetch_kib": 946652.3, "write_kib": 6024184.5},
-    "fe_quad_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "28b22772c78230b7", "fetch_kib": 2136.8, "write_kib": 128213.8},
-    "fe_quad_tiles": {"sources": ["quad.hip", "plan.cpp"], "sha256": "28b22772c78230b7", "fetch_kib": 682.6, "write_kib": 39873.8},
+    "fe_quad_rows": {"sources": ["quad.hip", "plan.cpp"], "sha256": "a5c4085700c26a0f", "fetch_kib": 2133.6, "write_kib": 128203.9},
+    "fe_quad_tiles": {"sources": ["quad.hip", "plan.cpp"], "sha256": "a5c4085700c26a0f", "fetch_kib": 682.5, "write_kib": 39873.8},
     "mf_domain_rows": {"sources": ["fill.hip"], "sha256": "a839a6953e4cbe7c", "fetch_kib": 117030.8, "write_kib": 13497.2},
     "mf_copied_entries": {"sources": ["fill.hip"], "sha256": "a839a6953e4cbe7c", "fetch_kib": 396878.9, "write_kib": 2612.8},
     "mf_stored_rows": {"sources": ["fill.hip"], "sha256": "a839a6953e4cbe7c", "fetch_kib": 1018429.4, "write_kib": 4820.7},

@@ -651,12 +651,13 @@ struct Q3R {
   static_assert(W * W <= BLOCK, "stage-2 threads");
 };
 
-// Constant coefficient: at least five waves per SIMD (96 VGPRs at p = 3
-// instead of 108, 8 bytes of spill): 3-4% faster sample rows and 5% faster
-// face/edge single rows at 128^3 p = 3; the variable-coefficient variants
-// would spill 136-232 bytes and keep the compiler's choice.
+// Constant coefficient, p <= 3: at least five waves per SIMD (96 VGPRs at
+// p = 3 instead of 108, 8 bytes of spill): 3-4% faster sample rows and 5%
+// faster face/edge single rows at 128^3 p = 3; the variable-coefficient
+// variants would spill 136-232 bytes, and p = 4 cannot reach five waves, so
+// they keep the compiler's choice.
 template <int P, int FORM, bool VC, typename OutT>
-__global__ void __launch_bounds__(256, VC ? 1 : 5)
+__global__ void __launch_bounds__(256, (VC || P == 4) ? 1 : 5)
     quad3d_row_kernel(KProblem kp, const QTile* __restrict__ tiles, OutT* __restrict__ band) {
   using C = Q3R<P, FORM>;
   constexpr int NQ = C::NQ, W = C::W, NQR = C::NQR;
