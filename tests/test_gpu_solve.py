@@ -129,6 +129,28 @@ def test_cg_mixed_batched(igs, oracle):
         assert rel_maxnorm(u[b].cpu().numpy(), uref) < 1e-8
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_cg_batch_with_finished_problem(igs, oracle, mixed):
+    """A batch whose middle problem has f = 0 (finished before the first
+    step): its u stays exactly 0 while the fused product and update kernels
+    (FP64) or the launch slots (FP32 with FP64 residual replacement) skip it,
+    and the other problems reach the FP64 solution."""
+    import torch
+
+    prob = W.c5_adjoint2d(nelem=40, batch=3, cn=8)
+    band = igs.assemble_surrogate(prob, 0, M=4, q=3)
+    b32 = igs.assemble_surrogate(prob, 0, M=4, q=3, dtype=torch.float32) if mixed else None
+    f = igs.assemble_rhs(prob, 0, 1.0)
+    f[1] = 0.0
+    u, info = igs.solve_cg(prob, band, f, band32=b32, rtol=1e-11)
+    assert info["status"] == 0 and info["relres"] <= 1e-11
+    assert float(u[1].abs().max()) == 0.0
+    for b in (0, 2):
+        rows = igs.band_rows(band, prob, b)
+        uref, _, _ = oracle.cg(prob, rows, f[b].cpu().numpy(), rtol=1e-13)
+        assert rel_maxnorm(u[b].cpu().numpy(), uref) < 1e-8
+
+
 def test_cg_mixed_not_converged(igs):
     import torch
 
