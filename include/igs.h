@@ -368,6 +368,28 @@ igs_status igs_plan_destroy(igs_plan plan);
  * x = F(xi).  f: device [batch][N] FP64.  Synchronous on return. */
 igs_status igs_assemble_rhs(const igs_problem* pb, int32_t source, double c, double* f, void* stream);
 
+/* Asynchronous assembly: the same work as igs_assemble_exact (M = 0) or
+ * igs_assemble_surrogate (M >= 1, degree q), and as igs_assemble_rhs, queued
+ * on `stream` without waiting for it.  Same arguments, validation and host-side
+ * errors (returned before any GPU work is queued); the call's device scratch is
+ * freed in stream order, so `pb` and host memory may be reused on return, while
+ * device inputs (spline coefficients) must stay valid until the stream has run
+ * the call.  The device-side error of these calls -- a geometry map whose
+ * Jacobian determinant is not positive at some quadrature point (Sec. 3.2,
+ * eq. ChangeOfVars needs an invertible map) -- cannot be known on return: each
+ * call records it in a status word of (current device, stream), made on the
+ * first asynchronous call on that stream (IGS_ERR_HIP if it cannot be made).
+ * igs_check(stream) waits for the stream, returns IGS_ERR_GEOMETRY if any
+ * asynchronous call queued on it since the last check recorded the error (the
+ * band or load vector of that call is then undefined), clears the word, and
+ * otherwise returns IGS_OK (also for a stream no asynchronous call has used).
+ * Synchronous calls report only their own errors and leave the word alone.
+ * Host threads that queue and check on one stream concurrently race. */
+igs_status igs_assemble_async(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* band,
+                              void* stream);
+igs_status igs_assemble_rhs_async(const igs_problem* pb, int32_t source, double c, double* f, void* stream);
+igs_status igs_check(void* stream);
+
 /* ---------------------------------------------------------------- solve */
 
 /* y = A x with the band of `dtype` (x, y of the same type, device [batch][N]).

@@ -643,8 +643,60 @@ static igs_status check_plan(Plan* pl, hipStream_t s, bool always) {
   return st;
 }
 
+// ---------------------------------------------------- asynchronous calls
+//
+// A status word per (device, stream), made on the first asynchronous call on
+// that stream: each such call queues fold_status_kernel after its kernels,
+// which sets the word when the call's own geometry flag is set; igs_check
+// reads and clears it.  Words live until the process ends.
+__global__ void fold_status_kernel(const int* flag, int* word) {
+  if (threadIdx.x == 0 && (*flag & 1)) *word = 1;
+}
+
+static std::mutex g_status_mu;
+static std::vector<std::pair<std::pair<int, hipStream_t>, int*>> g_status;
+
+// The word of (current device, s); made (zeroed) when create is set, else
+// null if no asynchronous call has used the stream yet.
+static igs_status status_word(hipStream_t s, bool create, int** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_status_mu);
+  for (auto& e : g_status)
+    if (e.first.first == dev && e.first.second == s) {
+      *out = e.second;
+      return IGS_OK;
+    }
+  *out = nullptr;
+  if (!create) return IGS_OK;
+  void* w = nullptr;
+  HIP_TRY(hipMalloc(&w, 256));
+  const int zero = 0;
+  hipError_t e = hipMemcpy(w, &zero, sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(w);
+    return IGS_ERR_HIP;
+  }
+  g_status.push_back({{dev, s}, static_cast<int*>(w)});
+  *out = static_cast<int*>(w);
+  return IGS_OK;
+}
+
+static igs_status fold_status(const int* flag, hipStream_t s) {
+  int* w = nullptr;
+  igs_status st = status_word(s, true, &w);
+  if (st != IGS_OK) return st;
+  hipLaunchKernelGGL(fold_status_kernel, dim3(1), dim3(64), 0, s, flag, w);
+  HIP_TRY(hipGetLastError());
+  return IGS_OK;
+}
+
+// async: queue the work and fold the geometry flag into the stream's status
+// word instead of reading it; the plan's device memory is released in stream
+// order (hipFreeAsync on s), its host staging was consumed by the time the
+// upload call returned (pageable-memory copies are staged before return).
 static igs_status one_shot(const igs_problem* pb, int kind, int form, int M, int q, int dtype, void* band,
-                           hipStream_t s, ScratchPool* pool = nullptr) {
+                           hipStream_t s, ScratchPool* pool = nullptr, bool async = false) {
   Plan pl;
   pl.P.ar.pool = pool;
   pl.ta.pool = pool;
@@ -659,6 +711,7 @@ static igs_status one_shot(const igs_problem* pb, int kind, int form, int M, int
   if (st != IGS_OK) return st;
   st = run_plan(pl, nullptr, band, s);
   if (st != IGS_OK) return st;
+  if (async) return fold_status(pl.P.kp.flag, s);
   return check_plan(&pl, s, true);
 }
 
@@ -1012,7 +1065,8 @@ igs_status igs_plan_destroy(igs_plan plan) {
   return ok ? IGS_OK : IGS_ERR_HIP;
 }
 
-igs_status igs_assemble_rhs(const igs_problem* pb, int32_t source, double c, double* f, void* stream) {
+static igs_status assemble_rhs(const igs_problem* pb, int32_t source, double c, double* f, void* stream,
+                               bool async) {
   if (!pb || !f) return IGS_ERR_ARG;
   if (source != 0 && source != 1) return IGS_ERR_ARG;
   Dims d;
@@ -1035,7 +1089,49 @@ igs_status igs_assemble_rhs(const igs_problem* pb, int32_t source, double c, dou
     PhaseTimer t("rhs", s);
     HIP_TRY(launch_rhs(P.kp, dt, int(tiles.size()), source, c, f, s));
   }
+  if (async) return fold_status(P.kp.flag, s);
   return finish(P, s);
+}
+
+igs_status igs_assemble_rhs(const igs_problem* pb, int32_t source, double c, double* f, void* stream) {
+  return assemble_rhs(pb, source, c, f, stream, false);
+}
+
+igs_status igs_assemble_rhs_async(const igs_problem* pb, int32_t source, double c, double* f, void* stream) {
+  return assemble_rhs(pb, source, c, f, stream, true);
+}
+
+igs_status igs_assemble_async(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* band,
+                              void* stream) {
+  if (!pb || !band) return IGS_ERR_ARG;
+  if (form != IGS_STIFFNESS && form != IGS_MASS) return IGS_ERR_ARG;
+  if (dtype != IGS_F64 && dtype != IGS_F32) return IGS_ERR_ARG;
+  if (M < 0) return IGS_ERR_ARG;
+  Dims d;
+  igs_status st = make_dims(pb, &d);
+  if (st != IGS_OK) return st;
+  if (M >= 1) {
+    st = check_sampling(d, M, q);
+    if (st != IGS_OK) return st;
+  }
+  return one_shot(pb, M == 0 ? 0 : 1, form, M, q, dtype, band, static_cast<hipStream_t>(stream), nullptr, true);
+}
+
+igs_status igs_check(void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int* w = nullptr;
+  igs_status st = status_word(s, false, &w);
+  if (st != IGS_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s));
+  if (!w) return IGS_OK;
+  int v = 0;
+  HIP_TRY(hipMemcpyAsync(&v, w, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (!v) return IGS_OK;
+  const int zero = 0;
+  HIP_TRY(hipMemcpyAsync(w, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return IGS_ERR_GEOMETRY;
 }
 
 igs_status igs_apply(const igs_problem* pb, int32_t dtype, const void* band, const void* x, void* y, int32_t dirichlet,

@@ -31,7 +31,7 @@ EXPORTS = ["igs_band_layout", "igs_validate", "igs_surrogate_layout", "igs_sampl
            "igs_surrogate_fe_layout", "igs_assemble_surrogate_pd", "igs_surrogate_pd_layout", "igs_plan_create",
            "igs_plan_create_fe", "igs_plan_create_pd", "igs_plan_create_mf",
            "igs_apply_mf", "igs_solve_cg_mf", "igs_plan_execute", "igs_plan_destroy",
-           "igs_assemble_rhs", "igs_apply", "igs_solve_cg", "igs_apply_vjp", "igs_compliance_grad",
+           "igs_assemble_rhs", "igs_assemble_async", "igs_assemble_rhs_async", "igs_check", "igs_apply", "igs_solve_cg", "igs_apply_vjp", "igs_compliance_grad",
            "igs_profile_enable", "igs_profile_read"]
 
 
@@ -122,6 +122,9 @@ def lib():
             "igs_plan_execute": [vp, vp, vp, vp],
             "igs_plan_destroy": [vp],
             "igs_assemble_rhs": [P, i32, f64, vp, vp],
+            "igs_assemble_async": [P, i32, i32, i32, i32, vp, vp],
+            "igs_assemble_rhs_async": [P, i32, f64, vp, vp],
+            "igs_check": [vp],
             "igs_apply": [P, i32, vp, vp, vp, i32, vp],
             "igs_solve_cg": [P, vp, vp, vp, vp, f64, i32, ctypes.POINTER(CgInfo), vp],
             "igs_apply_vjp": [P, i32, i32, vp, vp, vp, vp, vp, vp],
@@ -415,6 +418,40 @@ def assemble_rhs(prob, source=SRC_CONST, c=1.0, out=None, device="cuda"):
     pb = make_problem(prob, None if cc is None else cc.data_ptr())
     _check(lib().igs_assemble_rhs(ctypes.byref(pb), source, float(c), f.data_ptr(), _stream()), "igs_assemble_rhs")
     return f
+
+
+def assemble_async(prob, form=STIFFNESS, M=0, q=3, dtype=None, out=None, device="cuda"):
+    """igs_assemble_async: M = 0 full assembly, M >= 1 surrogate, queued on
+    torch's current stream without synchronising; a geometry fault is reported
+    by check().  The coefficient tensor of spline kinds is made on the same
+    stream, so torch reuses its memory only after the queued kernels."""
+    torch = _torch()
+    tdt, cdt = _dt(dtype if dtype is not None else torch.float64)
+    band = out if out is not None else empty_band(prob, tdt, device)
+    cc = _coef_tensor(prob, band.device)
+    pb = make_problem(prob, None if cc is None else cc.data_ptr())
+    _check(lib().igs_assemble_async(ctypes.byref(pb), form, M, q, cdt, band.data_ptr(), _stream()),
+           "igs_assemble_async")
+    return band
+
+
+def assemble_rhs_async(prob, source=SRC_CONST, c=1.0, out=None, device="cuda"):
+    """igs_assemble_rhs_async: the load vector, queued without synchronising."""
+    torch = _torch()
+    lay = layout(prob)
+    f = out if out is not None else torch.empty((prob.get("batch", 1), lay.N), dtype=torch.float64, device=device)
+    cc = _coef_tensor(prob, f.device)
+    pb = make_problem(prob, None if cc is None else cc.data_ptr())
+    _check(lib().igs_assemble_rhs_async(ctypes.byref(pb), source, float(c), f.data_ptr(), _stream()),
+           "igs_assemble_rhs_async")
+    return f
+
+
+def check():
+    """igs_check on torch's current stream: waits for it, raises IGSError
+    (IGS_ERR_GEOMETRY) if an asynchronous call queued on it since the last
+    check met a folding geometry, and clears that record."""
+    _check(lib().igs_check(_stream()), "igs_check")
 
 
 def apply(prob, band, x, dirichlet=False, out=None):

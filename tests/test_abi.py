@@ -142,6 +142,9 @@ def test_validation_errors(mutate, expected):
     assert L.igs_assemble_surrogate_fe(ctypes.byref(pb), 0, 4, 3, 0, dummy, None) == expected
     assert L.igs_plan_create_fe(ctypes.byref(pb), 0, 4, 3, 0, None, ctypes.byref(ctypes.c_void_p())) == expected
     assert L.igs_assemble_rhs(ctypes.byref(pb), 0, 1.0, dummy, None) == expected
+    assert L.igs_assemble_async(ctypes.byref(pb), 0, 0, 0, 0, dummy, None) == expected
+    assert L.igs_assemble_async(ctypes.byref(pb), 0, 4, 3, 0, dummy, None) == expected
+    assert L.igs_assemble_rhs_async(ctypes.byref(pb), 0, 1.0, dummy, None) == expected
     assert L.igs_apply(ctypes.byref(pb), 0, dummy, dummy, dummy, 0, None) == expected
     h = ctypes.c_void_p(16)
     assert L.igs_plan_create(ctypes.byref(pb), 0, 4, 3, 0, None, ctypes.byref(h)) == expected
@@ -212,6 +215,14 @@ def test_null_and_enum_arguments():
     assert L.igs_assemble_noalloc(ctypes.byref(pb), 0, -1, 3, 0, dummy, None) == -1
     assert L.igs_assemble_noalloc(ctypes.byref(pb), 0, 4, 6, 0, dummy, None) == -2
     assert L.igs_assemble_rhs(ctypes.byref(pb), 3, 1.0, dummy, None) == -1
+    assert L.igs_assemble_async(None, 0, 0, 0, 0, dummy, None) == -1
+    assert L.igs_assemble_async(ctypes.byref(pb), 0, 0, 0, 0, None, None) == -1
+    assert L.igs_assemble_async(ctypes.byref(pb), 2, 0, 0, 0, dummy, None) == -1
+    assert L.igs_assemble_async(ctypes.byref(pb), 0, 0, 0, 5, dummy, None) == -1
+    assert L.igs_assemble_async(ctypes.byref(pb), 0, -1, 3, 0, dummy, None) == -1
+    assert L.igs_assemble_async(ctypes.byref(pb), 0, 4, 6, 0, dummy, None) == -2
+    assert L.igs_assemble_rhs_async(ctypes.byref(pb), 3, 1.0, dummy, None) == -1
+    assert L.igs_assemble_rhs_async(ctypes.byref(pb), 0, 1.0, None, None) == -1
     info = igs.CgInfo()
     assert L.igs_solve_cg(ctypes.byref(pb), dummy, None, dummy, dummy, 0.0, 10, ctypes.byref(info), None) == -1
     h = ctypes.c_void_p()

@@ -237,6 +237,42 @@ def test_geometry_fold_reported(igs):
     assert e.value.status == -5
 
 
+def test_async_calls_and_check(igs):
+    """igs_assemble_async and igs_assemble_rhs_async queue the kernels of the
+    synchronous calls (bitwise equal results).  A folding geometry returns
+    IGS_OK at call time; igs_check on the same stream reports
+    IGS_ERR_GEOMETRY once and clears it, and a check on another stream does
+    not see it."""
+    import torch
+
+    prob = W.problem(2, 2, 32)
+    for M in (0, 4):
+        ref = igs.assemble_exact(prob, 0) if M == 0 else igs.assemble_surrogate(prob, 0, M=M, q=3)
+        out = igs.assemble_async(prob, 0, M=M, q=3)
+        igs.check()
+        assert torch.equal(out, ref)
+    ref = igs.assemble_rhs(prob, 1, 2.0)
+    out = igs.assemble_rhs_async(prob, 1, 2.0)
+    igs.check()
+    assert torch.equal(out, ref)
+
+    bad = W.problem(2, 2, 16, ga=0.5)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        igs.assemble_async(bad, 0)
+        igs.assemble_rhs_async(bad, 0, 1.0)
+        igs.assemble_async(prob, 0, M=4, q=3)
+    igs.check()  # the current (default) stream has no error recorded
+    with torch.cuda.stream(side):
+        with pytest.raises(igs.IGSError) as e:
+            igs.check()
+        assert e.value.status == -5
+        igs.check()  # cleared by the previous check
+        out = igs.assemble_async(prob, 1, M=4, q=3)
+        igs.check()
+    assert torch.equal(out, igs.assemble_surrogate(prob, 1, M=4, q=3))
+
+
 # ------------------------------------------------------------------ plans ---
 @pytest.mark.parametrize("prob,form,M,q", [(W.problem(3, 3, (26, 24, 25)), 0, 4, 3), (W.problem(2, 2, 32), 1, 4, 3),
                                            (W.problem(3, 2, 12), 0, 0, 0)])
