@@ -426,10 +426,10 @@ igs_status igs_solve_cg(const igs_problem* pb, const double* band64, const float
  * ybar_i x_j through the transpose of the surrogate construction onto the
  * quadrature rows and contracts them with dA_ij/dc_k = int dkappa/dc_k
  * grad B_i^T K grad B_j, recomputing Jacobians at the quadrature points.
- * band64 (device) must hold A~(c) when xbar is requested.  n = 2 with
- * p <= 4 and n = 3 with p <= 3 (an element's (p+1)^3 x (p+1)^3 weight matrix
- * is held in LDS); cbar for n = 3, p = 4 returns IGS_ERR_UNSUPPORTED.
- * Synchronous on return. */
+ * band64 (device) must hold A~(c) when xbar is requested.  Every n and p of
+ * the assembly (an element's (p+1)^n x (p+1)^n weight matrix is held in
+ * LDS; for n = 3, p = 4 with its contraction tables made one derivative
+ * pattern at a time).  Synchronous on return. */
 igs_status igs_apply_vjp(const igs_problem* pb, int32_t M, int32_t q, const double* band64, const double* x,
                          const double* ybar, double* xbar, double* cbar, void* stream);
 

@@ -329,7 +329,7 @@ __global__ void adj_red2_kernel(KProblem kp, const int* __restrict__ qlo, const 
 
 // ------------------------------------------------------------------ 3-D ----
 //
-// The same construction for n = 3 (p <= 3: an element's weight matrix of
+// The same construction for n = 3 (an element's weight matrix of
 // (p+1)^3 x (p+1)^3 entries is held in LDS).
 
 struct AdjGeom3 {
@@ -467,6 +467,90 @@ __global__ void adj_scatter3_kernel(AdjGeom3 g, KInterp<double> ip, int batch, c
   }
 }
 
+// The value stored at Gauss point (g1, g2, g3) of problem b from the nine
+// contracted sums G[a*3+b] = sum W[i][j] d_a B_i d_b B_j at that point:
+// sum_ab Khat_ab G_ab with Khat = w adj(J) adj(J)^T / |det J|, times
+// dkappa/dc's point factor exp(sum c_k N_k) for the exponential spline.
+__device__ double elem3_point_value(const KProblem& kp, int b, int g1, int g2, int g3, const double* G) {
+  const int gg[3] = {g1, g2, g3};
+  double xi[3], tr[3][4], J[3][3];
+  double wq = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    xi[d] = kp.t[d].x[gg[d]];
+    wq *= kp.t[d].w[gg[d]];
+    for (int k = 0; k < 4; ++k) tr[d][k] = kp.t[d].trig[4 * gg[d] + k];
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) J[r][c] = r == c ? 1.0 : 0.0;
+  const double ga = kp.ga;
+  if (kp.geom == IGS_GEOM_SINE) {
+    // F = xi + a (sin pi x1 sin 2pi x2 sin pi x3, sin 2pi x1 sin pi x2 sin pi x3,
+    //             sin pi x1 sin pi x2 sin 2pi x3); tr = sin pi x, pi cos pi x, sin 2pi x, 2pi cos 2pi x
+    J[0][0] += ga * tr[0][1] * tr[1][2] * tr[2][0];
+    J[0][1] += ga * tr[0][0] * tr[1][3] * tr[2][0];
+    J[0][2] += ga * tr[0][0] * tr[1][2] * tr[2][1];
+    J[1][0] += ga * tr[0][3] * tr[1][0] * tr[2][0];
+    J[1][1] += ga * tr[0][2] * tr[1][1] * tr[2][0];
+    J[1][2] += ga * tr[0][2] * tr[1][0] * tr[2][1];
+    J[2][0] += ga * tr[0][1] * tr[1][0] * tr[2][2];
+    J[2][1] += ga * tr[0][0] * tr[1][1] * tr[2][2];
+    J[2][2] += ga * tr[0][0] * tr[1][0] * tr[2][3];
+  } else if (kp.geom == IGS_GEOM_POLY2) {
+    double qd[3], dq[3];
+    for (int d = 0; d < 3; ++d) {
+      qd[d] = xi[d] * (1.0 - xi[d]);
+      dq[d] = 1.0 - 2.0 * xi[d];
+    }
+    for (int c = 0; c < 3; ++c) {
+      double dprod = dq[c];
+      for (int d = 0; d < 3; ++d)
+        if (d != c) dprod *= qd[d];
+      for (int r = 0; r < 3; ++r) J[r][c] += ga * (r + 1) * dprod;
+    }
+  }
+  double adj[3][3];
+  adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const double det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+  if (!(det > 0.0)) atomicOr(kp.flag, 1);
+  const double sc = wq / fabs(det);
+  double val = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int bb = 0; bb < 3; ++bb) {
+      double k = 0.0;
+      for (int c = 0; c < 3; ++c) k += adj[a][c] * adj[bb][c];
+      val += sc * k * G[a * 3 + bb];
+    }
+  if (kp.coef == IGS_COEF_EXP_SPLINE) {
+    const double* cc = kp.cc + b * kp.cstride;
+    const int nd = kp.cdeg + 1;
+    const double* c0 = kp.t[0].cb + size_t(g1) * nd;
+    const double* c1 = kp.t[1].cb + size_t(g2) * nd;
+    const double* c2 = kp.t[2].cb + size_t(g3) * nd;
+    const int f0 = kp.t[0].cf[g1], f1 = kp.t[1].cf[g2], f2 = kp.t[2].cf[g3];
+    double gsum = 0.0;
+    for (int r3 = 0; r3 < nd; ++r3) {
+      double s2 = 0.0;
+      for (int r2 = 0; r2 < nd; ++r2) {
+        double s1 = 0.0;
+        for (int r1 = 0; r1 < nd; ++r1)
+          s1 += c0[r1] * cc[(size_t(f2 + r3) * kp.cn[1] + f1 + r2) * kp.cn[0] + f0 + r1];
+        s2 += c1[r2] * s1;
+      }
+      gsum += c2[r3] * s2;
+    }
+    val *= exp(gsum);
+  }
+  return val;
+}
+
 // Reverse quadrature, one workgroup per element: the element's weight matrix
 // W[i][j] = wbar_{i, j-i} (quadrature rows only) contracted with the basis
 // values/derivatives at the element's Gauss points, direction 3, then 2,
@@ -557,83 +641,109 @@ __global__ void __launch_bounds__(256)
       }
       G[ab] = acc;
     }
-    // Khat = w adj adj^T / |det J| at the point
-    const int gg[3] = {g1, g2, g3};
-    double xi[3], tr[3][4], J[3][3];
-    double wq = 1.0;
-    for (int d = 0; d < 3; ++d) {
-      xi[d] = kp.t[d].x[gg[d]];
-      wq *= kp.t[d].w[gg[d]];
-      for (int k = 0; k < 4; ++k) tr[d][k] = kp.t[d].trig[4 * gg[d] + k];
-    }
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) J[r][c] = r == c ? 1.0 : 0.0;
-    const double ga = kp.ga;
-    if (kp.geom == IGS_GEOM_SINE) {
-      // F = xi + a (sin pi x1 sin 2pi x2 sin pi x3, sin 2pi x1 sin pi x2 sin pi x3,
-      //             sin pi x1 sin pi x2 sin 2pi x3); tr = sin pi x, pi cos pi x, sin 2pi x, 2pi cos 2pi x
-      J[0][0] += ga * tr[0][1] * tr[1][2] * tr[2][0];
-      J[0][1] += ga * tr[0][0] * tr[1][3] * tr[2][0];
-      J[0][2] += ga * tr[0][0] * tr[1][2] * tr[2][1];
-      J[1][0] += ga * tr[0][3] * tr[1][0] * tr[2][0];
-      J[1][1] += ga * tr[0][2] * tr[1][1] * tr[2][0];
-      J[1][2] += ga * tr[0][2] * tr[1][0] * tr[2][1];
-      J[2][0] += ga * tr[0][1] * tr[1][0] * tr[2][2];
-      J[2][1] += ga * tr[0][0] * tr[1][1] * tr[2][2];
-      J[2][2] += ga * tr[0][0] * tr[1][0] * tr[2][3];
-    } else if (kp.geom == IGS_GEOM_POLY2) {
-      double qd[3], dq[3];
-      for (int d = 0; d < 3; ++d) {
-        qd[d] = xi[d] * (1.0 - xi[d]);
-        dq[d] = 1.0 - 2.0 * xi[d];
-      }
-      for (int c = 0; c < 3; ++c) {
-        double dprod = dq[c];
-        for (int d = 0; d < 3; ++d)
-          if (d != c) dprod *= qd[d];
-        for (int r = 0; r < 3; ++r) J[r][c] += ga * (r + 1) * dprod;
-      }
-    }
-    double adj[3][3];
-    adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-    adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-    adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-    adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-    adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-    adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-    adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-    adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-    adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-    const double det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
-    if (!(det > 0.0)) atomicOr(kp.flag, 1);
-    const double sc = wq / fabs(det);
-    double val = 0.0;
-    for (int a = 0; a < 3; ++a)
-      for (int bb = 0; bb < 3; ++bb) {
-        double k = 0.0;
-        for (int c = 0; c < 3; ++c) k += adj[a][c] * adj[bb][c];
-        val += sc * k * G[a * 3 + bb];
-      }
-    if (kp.coef == IGS_COEF_EXP_SPLINE) {
-      const double* cc = kp.cc + b * kp.cstride;
-      const int nd = kp.cdeg + 1;
-      const double* c0 = kp.t[0].cb + size_t(g1) * nd;
-      const double* c1 = kp.t[1].cb + size_t(g2) * nd;
-      const double* c2 = kp.t[2].cb + size_t(g3) * nd;
-      const int f0 = kp.t[0].cf[g1], f1 = kp.t[1].cf[g2], f2 = kp.t[2].cf[g3];
-      double gsum = 0.0;
-      for (int r3 = 0; r3 < nd; ++r3) {
-        double s2 = 0.0;
-        for (int r2 = 0; r2 < nd; ++r2) {
-          double s1 = 0.0;
-          for (int r1 = 0; r1 < nd; ++r1)
-            s1 += c0[r1] * cc[(size_t(f2 + r3) * kp.cn[1] + f1 + r2) * kp.cn[0] + f0 + r1];
-          s2 += c1[r2] * s1;
+    const double val = elem3_point_value(kp, b, g1, g2, g3, G);
+    const size_t Q1 = size_t(kp.nelem[0]) * NQ, Q2 = size_t(kp.nelem[1]) * NQ, Q3 = size_t(kp.nelem[2]) * NQ;
+    pv[size_t(b) * Q1 * Q2 * Q3 + (size_t(g3) * Q2 + g2) * Q1 + g1] = val;
+  }
+}
+
+// The same reverse quadrature for elements whose three contraction tables do
+// not fit in LDS together (p = 4: the 125 x 125 weight matrix alone takes
+// 122 KiB).  The direction-3 table is made for one (value, derivative) code
+// at a time, the direction-2 table for one (a, b) at a time, and direction 1
+// goes straight into the point's register sums; LDS holds the weight matrix,
+// one direction-3 code and one (a, b) (155,000 bytes at p = 4).
+template <int P>
+__global__ void __launch_bounds__(256)
+    adj_elem3_split_kernel(KProblem kp, AdjGeom3 g, const int4* __restrict__ elems, const double* __restrict__ wbar,
+                           double* __restrict__ pv) {
+  constexpr int NP = P + 1, NL = NP * NP * NP, NQ = P + 1, NP2 = NP * NP, NP4 = NP2 * NP2;
+  static_assert(NQ * NQ * NQ <= 256, "one thread per Gauss point of the element");
+  __shared__ double Wl[NL * NL];
+  __shared__ double T3[NP4 * NQ];       // one code3: [i1 + NP j1 + NP^2 i2 + NP^3 j2][k3]
+  __shared__ double T2[NP2 * NQ * NQ];  // one (a, b): [i1 + NP j1][k2 + NQ k3]
+  const int tid = threadIdx.x;
+  const int b = blockIdx.y;
+  const int4 e = elems[blockIdx.x];
+  const double* w = wbar + size_t(b) * g.S * g.ld;
+  for (int t = tid; t < NL * NL; t += 256) {
+    const int il = t / NL, jl = t % NL;
+    const int a1 = il % NP, a2 = (il / NP) % NP, a3 = il / NP2;
+    const int b1 = jl % NP, b2 = (jl / NP) % NP, b3 = jl / NP2;
+    const int i1 = e.x + a1, i2 = e.y + a2, i3 = e.z + a3;
+    const int s = (b1 - a1 + P) + g.W * ((b2 - a2 + P) + g.W * (b3 - a3 + P));
+    double v = 0.0;
+    if (quad_row3(g, i1, i2, i3)) v = w[size_t(s) * g.ld + i1 + size_t(g.m1) * (i2 + size_t(g.m2) * i3)];
+    Wl[t] = v;
+  }
+  const bool owner = tid < NQ * NQ * NQ;
+  const int k1 = tid % NQ, k2o = (tid / NQ) % NQ, k3o = tid / (NQ * NQ);
+  const int g1 = e.x * NQ + k1;
+  const double* bv1 = kp.t[0].bv + size_t(owner ? g1 : 0) * NP;
+  const double* bd1 = kp.t[0].bd + size_t(owner ? g1 : 0) * NP;
+  const double* bv2 = kp.t[1].bv;
+  const double* bd2 = kp.t[1].bd;
+  const double* bv3 = kp.t[2].bv;
+  const double* bd3 = kp.t[2].bd;
+  double G[9];
+#pragma unroll
+  for (int ab = 0; ab < 9; ++ab) G[ab] = 0.0;
+#pragma unroll
+  for (int code = 0; code < 4; ++code) {
+    __syncthreads();  // Wl written (first code) / T3 of the previous code read
+    for (int t = tid; t < NP4 * NQ; t += 256) {
+      const int k3 = t % NQ;
+      const int r = t / NQ;
+      const int i1 = r % NP, j1 = (r / NP) % NP, i2 = (r / NP2) % NP, j2 = r / (NP2 * NP);
+      const size_t gq = size_t(e.z * NQ + k3) * NP;
+      double acc = 0.0;
+      for (int a3 = 0; a3 < NP; ++a3) {
+        const double fa = (code & 2) ? bd3[gq + a3] : bv3[gq + a3];
+        for (int b3 = 0; b3 < NP; ++b3) {
+          const double fb = (code & 1) ? bd3[gq + b3] : bv3[gq + b3];
+          acc += fa * fb * Wl[(i1 + NP * i2 + NP2 * a3) * NL + (j1 + NP * j2 + NP2 * b3)];
         }
-        gsum += c2[r3] * s2;
       }
-      val *= exp(gsum);
+      T3[t] = acc;
     }
+#pragma unroll
+    for (int ab = 0; ab < 9; ++ab) {
+      const int a = ab / 3, bb = ab % 3;
+      if ((((a == 2) << 1) | (bb == 2)) != code) continue;
+      const int al2 = a == 1, be2 = bb == 1;
+      __syncthreads();  // T3 of this code written / T2 of the previous (a, b) read
+      for (int t = tid; t < NP2 * NQ * NQ; t += 256) {
+        const int k23 = t % (NQ * NQ);
+        const int k2 = k23 % NQ, k3 = k23 / NQ;
+        const int ij1 = t / (NQ * NQ);
+        const size_t gq = size_t(e.y * NQ + k2) * NP;
+        double acc = 0.0;
+        for (int a2 = 0; a2 < NP; ++a2) {
+          const double fa = al2 ? bd2[gq + a2] : bv2[gq + a2];
+          for (int b2 = 0; b2 < NP; ++b2) {
+            const double fb = be2 ? bd2[gq + b2] : bv2[gq + b2];
+            acc += fa * fb * T3[(ij1 + NP2 * a2 + NP2 * NP * b2) * NQ + k3];
+          }
+        }
+        T2[t] = acc;
+      }
+      __syncthreads();
+      if (owner) {
+        double acc = 0.0;
+        for (int a1 = 0; a1 < NP; ++a1) {
+          const double fa = a == 0 ? bd1[a1] : bv1[a1];
+          for (int b1 = 0; b1 < NP; ++b1) {
+            const double fb = bb == 0 ? bd1[b1] : bv1[b1];
+            acc += fa * fb * T2[(a1 + NP * b1) * NQ * NQ + k2o + NQ * k3o];
+          }
+        }
+        G[ab] = acc;
+      }
+    }
+  }
+  if (owner) {
+    const int g2 = e.y * NQ + k2o, g3 = e.z * NQ + k3o;
+    const double val = elem3_point_value(kp, b, g1, g2, g3, G);
     const size_t Q1 = size_t(kp.nelem[0]) * NQ, Q2 = size_t(kp.nelem[1]) * NQ, Q3 = size_t(kp.nelem[2]) * NQ;
     pv[size_t(b) * Q1 * Q2 * Q3 + (size_t(g3) * Q2 + g2) * Q1 + g1] = val;
   }
@@ -896,13 +1006,12 @@ static igs_status vjp(const igs_problem* pb, int M, int q, const double* band64,
   return finish_problem(kp, s);
 }
 
-// n = 3: the same steps with a third direction (p <= 3)
+// n = 3: the same steps with a third direction
 static igs_status vjp3(const igs_problem* pb, const Dims& d, const KProblem& kp, const HostTables& ht, int M, int q,
                        const double* band64, const double* x, const double* ybar, double* xbar, double* cbar,
                        bool negate_y, hipStream_t s) {
   const bool want_c = cbar != nullptr;
   if (want_c && pb->coef.kind != IGS_COEF_SPLINE && pb->coef.kind != IGS_COEF_EXP_SPLINE) return IGS_ERR_ARG;
-  if (want_c && d.p > 3) return IGS_ERR_UNSUPPORTED;
   if (xbar && !band64) return IGS_ERR_ARG;
   const int form = IGS_STIFFNESS;
   const bool sur = M >= 1;
@@ -1079,7 +1188,10 @@ static igs_status vjp3(const igs_problem* pb, const Dims& d, const KProblem& kp,
       switch (d.p) {
         case 1: hipLaunchKernelGGL((adj_elem3_kernel<1>), grid, dim3(256), 0, s, kp, g, delems, wbar, pv); break;
         case 2: hipLaunchKernelGGL((adj_elem3_kernel<2>), grid, dim3(256), 0, s, kp, g, delems, wbar, pv); break;
-        default: hipLaunchKernelGGL((adj_elem3_kernel<3>), grid, dim3(256), 0, s, kp, g, delems, wbar, pv); break;
+        case 3: hipLaunchKernelGGL((adj_elem3_kernel<3>), grid, dim3(256), 0, s, kp, g, delems, wbar, pv); break;
+        default:
+          hipLaunchKernelGGL((adj_elem3_split_kernel<4>), grid, dim3(256), 0, s, kp, g, delems, wbar, pv);
+          break;
       }
     }
   }

@@ -277,6 +277,57 @@ def test_vjp3_p3_surrogate(igs, oracle):
     assert rel_maxnorm(cbar[0].cpu().numpy()[ks], ref) < 1e-11
 
 
+def test_vjp3_p4_exact_matches_oracle(igs, oracle):
+    """3D p = 4 (125 x 125 element weight matrix, the split-table element
+    kernel): cbar of the exact assembly, where every row is a quadrature row,
+    against the oracle on a batch of two exp-spline fields."""
+    import torch
+
+    rng = np.random.default_rng(25)
+    batch = 2
+    cc = rng.normal(0, 0.4, (batch, 64))
+    prob = _prob3(cc, batch, 6, 4)
+    _, N, _ = oracle.dims(prob)
+    x = rng.standard_normal((batch, N))
+    yb = rng.standard_normal((batch, N))
+    band = igs.assemble_exact(prob, 0)
+    _, cbar = igs.apply_vjp(prob, 0, 3, band, torch.as_tensor(x, device="cuda"), torch.as_tensor(yb, device="cuda"),
+                            want_x=False)
+    ks = [0, 42]
+    for b in range(batch):
+        ref = oracle.bilinear_grad(prob, 0, 3, yb[b], x[b], ks, b=b, surrogate=False)
+        got = cbar[b].cpu().numpy()[ks]
+        assert rel_maxnorm(got, ref) < 1e-11, (b, got, ref)
+
+
+def test_vjp3_p4_surrogate_fd(igs, oracle):
+    """3D p = 4 surrogate (M = 3, q = 3, 22^3 elements, 4 samples per
+    direction): cbar against central differences (step 1e-6) of the GPU's own
+    ybar^T A~(c) x."""
+    import torch
+
+    rng = np.random.default_rng(26)
+    cc = rng.normal(0, 0.4, (1, 64))
+    prob = _prob3(cc, 1, 22, 4)
+    _, N, _ = oracle.dims(prob)
+    x = torch.as_tensor(rng.standard_normal((1, N)), device="cuda")
+    yb = torch.as_tensor(rng.standard_normal((1, N)), device="cuda")
+    band = igs.assemble_surrogate(prob, 0, M=3, q=3)
+    _, cbar = igs.apply_vjp(prob, 3, 3, band, x, yb, want_x=False)
+
+    def form(c):
+        p = _prob3(c, 1, 22, 4)
+        return igs.apply(p, igs.assemble_surrogate(p, 0, M=3, q=3), x)
+
+    g = cbar[0].cpu().numpy()
+    for k in (2, 21, 47):
+        cp, cm = cc.copy(), cc.copy()
+        cp[0, k] += 1e-6
+        cm[0, k] -= 1e-6
+        fd = float(((form(cp) - form(cm)) * yb).sum()) / 2e-6
+        assert abs(fd - g[k]) <= 1e-6 * np.abs(g).max(), (k, fd, g[k])
+
+
 def test_c5_surrogate_band_every_problem(igs, oracle):
     """The batch-8 2D p = 3 256^2 exp-spline surrogate band (M = 8, q = 3) of
     the differentiation workload against the oracle's surrogate, for every
