@@ -656,8 +656,9 @@ __global__ void fold_status_kernel(const int* flag, int* word) {
 static std::mutex g_status_mu;
 static std::vector<std::pair<std::pair<int, hipStream_t>, int*>> g_status;
 
-// The word of (current device, s); made (zeroed) when create is set, else
-// null if no asynchronous call has used the stream yet.
+// The word of (current device, s); made when create is set (zeroed by a copy
+// ordered on s, ahead of the kernel that may set it), else null if no
+// asynchronous call has used the stream yet.
 static igs_status status_word(hipStream_t s, bool create, int** out) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
@@ -671,8 +672,8 @@ static igs_status status_word(hipStream_t s, bool create, int** out) {
   if (!create) return IGS_OK;
   void* w = nullptr;
   HIP_TRY(hipMalloc(&w, 256));
-  const int zero = 0;
-  hipError_t e = hipMemcpy(w, &zero, sizeof(int), hipMemcpyHostToDevice);
+  static const int kZero = 0;  // static storage: valid whenever the copy reads it
+  hipError_t e = hipMemcpyAsync(w, &kZero, sizeof(int), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) {
     (void)hipFree(w);
     return IGS_ERR_HIP;
