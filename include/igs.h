@@ -229,9 +229,10 @@ igs_status igs_assemble_exact(const igs_problem* pb, int32_t form, int32_t dtype
  * dtype IGS_F32 is the precision form: quadrature in FP64 rounded on store,
  * interpolation evaluated in FP32 from FP64-fitted coefficients, FP32
  * diagonal sums.  Synchronous on return.
- * Limits: in 2D, pencils of more than 4096 functions in direction 1 take a
- * chunked fill whose per-chunk tables must fit in 160 KB of LDS; when they do
- * not (small M on such meshes) the call returns IGS_ERR_UNSUPPORTED. */
+ * Limits: in 2D, pencils of more than 8192 functions in direction 1, or of
+ * 4097..8192 when 2 S1 + m1 values (S1 samples in direction 1) exceed 160 KB
+ * of LDS, take a chunked fill whose per-chunk tables must fit in LDS; when
+ * they do not (small M on such meshes) the call returns IGS_ERR_UNSUPPORTED. */
 igs_status igs_assemble_surrogate(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype,
                                   void* band, void* stream);
 

@@ -31,6 +31,7 @@ void fill_block_dims(const Dims& d, const std::vector<int> ef[3], int q, const s
 std::vector<int> fill_chunks(const Dims& d, int rows, const int lo[3], const int hi[3]);
 int fill_npen(const Dims& d, int rows);
 bool fill_is_2d(const Dims& d);
+bool fill2d_wide_fits(const Dims& d, int S1, size_t tsize);
 bool fit_use_gemm(const KInterp<double>& ip, int n, int batch);
 template <typename BT>
 hipError_t launch_fit_gemm(const KInterp<double>& ip, int n, int m1, int m2, int64_t ld, int S, int batch,
@@ -317,6 +318,9 @@ static igs_status build_surrogate(const igs_problem* pb, hipStream_t s, Plan* pl
   const bool mf = pl->kind == 3;
   std::vector<int> brow = mf ? boundary_rows(d) : std::vector<int>();
   const size_t S1 = hi.samp[0].size();
+  // 2-D pencils past the register-held fill's length take the 2-D fill with
+  // reloaded weights when its LDS footprint fits, else the chunked fill
+  pl->P.d.wide2d = fill2d_wide_fits(d, int(S1), pl->dtype == IGS_F64 ? sizeof(double) : sizeof(float)) ? 1 : 0;
   std::vector<double> g0t(S1 * S1);
   for (size_t r = 0; r < S1; ++r)
     for (size_t c = 0; c < S1; ++c) g0t[c * S1 + r] = hi.ginv[0][r * S1 + c];

@@ -25,7 +25,10 @@ namespace igs {
 // overwrites.
 // PF: every direction-2 task has its own thread (2 S1 <= blockDim.x); its
 // operands for the next delta are loaded while the rows finish this one.
-template <int FORM, int Q, int R, typename T, bool PF>
+// WREG: each row's q+1 direction-1 weights stay in registers for the whole
+// delta loop; without it (long pencils, R = 8 rows per thread) they are
+// loaded again for every delta (L2 hits).
+template <int FORM, int Q, int R, typename T, bool PF, bool WREG>
 __global__ void __launch_bounds__(1024)
     fill2d_kernel(KInterp<T> ip, int m1, int64_t N, int64_t ld, int S, const int4* __restrict__ dsl,
                   const double* __restrict__ coef, T* __restrict__ band) {
@@ -51,7 +54,7 @@ __global__ void __launch_bounds__(1024)
   T* bnd = band + size_t(b) * S * ld + size_t(i2) * m1;
   const double* cb = coef + size_t(b) * ip.nup * S1 * S2;
 
-  T w1[R][Q + 1];
+  T w1[WREG ? R : 1][Q + 1];
   int f1[R];
   bool in1[R];
   T dsum[R];
@@ -60,8 +63,10 @@ __global__ void __launch_bounds__(1024)
     const int i1 = tid + r * nt;
     in1[r] = i1 < m1 && i1 >= ip.lo[0] && i1 <= ip.hi[0];
     f1[r] = in1[r] ? ip.ef[0][i1] : 0;
+    if constexpr (WREG) {
 #pragma unroll
-    for (int a = 0; a <= Q; ++a) w1[r][a] = in1[r] ? ip.eb[0][size_t(i1) * (Q + 1) + a] : T(0);
+      for (int a = 0; a <= Q; ++a) w1[r][a] = in1[r] ? ip.eb[0][size_t(i1) * (Q + 1) + a] : T(0);
+    }
     dsum[r] = T(0);
   }
 
@@ -128,10 +133,18 @@ __global__ void __launch_bounds__(1024)
       vu[r] = T(0);
       T vl = T(0);
       if (in1[r]) {
+        T wr[Q + 1];
 #pragma unroll
         for (int a = 0; a <= Q; ++a) {
-          vu[r] += w1[r][a] * Tl[f1[r] + a];
-          vl += w1[r][a] * Tl[S1 + f1[r] + a];
+          if constexpr (WREG)
+            wr[a] = w1[WREG ? r : 0][a];
+          else
+            wr[a] = ip.eb[0][size_t(i1) * (Q + 1) + a];
+        }
+#pragma unroll
+        for (int a = 0; a <= Q; ++a) {
+          vu[r] += wr[a] * Tl[f1[r] + a];
+          vl += wr[a] * Tl[S1 + f1[r] + a];
         }
         if (!(up2 && i1 + d1 >= ip.lo[0] && i1 + d1 <= ip.hi[0])) vu[r] = T(0);
       }
@@ -162,48 +175,71 @@ __global__ void __launch_bounds__(1024)
   }
 }
 
-template <int FORM, int R, typename T, bool PF>
+template <int FORM, int R, typename T, bool PF, bool WREG>
 static void launch_fill2d_q(const KInterp<T>& ip, const Dims& d, int nt, size_t lds, const int4* dsl,
                             const double* coef, T* band, hipStream_t s) {
   dim3 grid(ip.hi[1] - ip.lo[1] + 2, d.batch);  // + the padding workgroup
   switch (ip.q) {
-    case 1: hipLaunchKernelGGL((fill2d_kernel<FORM, 1, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.N, d.ld, d.S, dsl, coef, band); break;
-    case 2: hipLaunchKernelGGL((fill2d_kernel<FORM, 2, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.N, d.ld, d.S, dsl, coef, band); break;
-    case 3: hipLaunchKernelGGL((fill2d_kernel<FORM, 3, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.N, d.ld, d.S, dsl, coef, band); break;
-    case 4: hipLaunchKernelGGL((fill2d_kernel<FORM, 4, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.N, d.ld, d.S, dsl, coef, band); break;
-    default: hipLaunchKernelGGL((fill2d_kernel<FORM, 5, R, T, PF>), grid, dim3(nt), lds, s, ip, d.m[0], d.N, d.ld, d.S, dsl, coef, band); break;
+    case 1: hipLaunchKernelGGL((fill2d_kernel<FORM, 1, R, T, PF, WREG>), grid, dim3(nt), lds, s, ip, d.m[0], d.N, d.ld, d.S, dsl, coef, band); break;
+    case 2: hipLaunchKernelGGL((fill2d_kernel<FORM, 2, R, T, PF, WREG>), grid, dim3(nt), lds, s, ip, d.m[0], d.N, d.ld, d.S, dsl, coef, band); break;
+    case 3: hipLaunchKernelGGL((fill2d_kernel<FORM, 3, R, T, PF, WREG>), grid, dim3(nt), lds, s, ip, d.m[0], d.N, d.ld, d.S, dsl, coef, band); break;
+    case 4: hipLaunchKernelGGL((fill2d_kernel<FORM, 4, R, T, PF, WREG>), grid, dim3(nt), lds, s, ip, d.m[0], d.N, d.ld, d.S, dsl, coef, band); break;
+    default: hipLaunchKernelGGL((fill2d_kernel<FORM, 5, R, T, PF, WREG>), grid, dim3(nt), lds, s, ip, d.m[0], d.N, d.ld, d.S, dsl, coef, band); break;
   }
 }
 
-template <int FORM, int R, typename T>
+template <int FORM, int R, typename T, bool WREG>
 static void launch_fill2d_pf(const KInterp<T>& ip, const Dims& d, int nt, size_t lds, const int4* dsl,
                              const double* coef, T* band, hipStream_t s) {
   // prefetching needs one thread per task; at q = 5 its registers beside the
   // rows' weights spill, and the plain loop is faster there
   if (2 * ip.Sd[0] <= nt && ip.q <= 4)
-    launch_fill2d_q<FORM, R, T, true>(ip, d, nt, lds, dsl, coef, band, s);
+    launch_fill2d_q<FORM, R, T, true, WREG>(ip, d, nt, lds, dsl, coef, band, s);
   else
-    launch_fill2d_q<FORM, R, T, false>(ip, d, nt, lds, dsl, coef, band, s);
+    launch_fill2d_q<FORM, R, T, false, WREG>(ip, d, nt, lds, dsl, coef, band, s);
 }
 
-// 2D pencils of up to kFill2dRows rows take fill2d_kernel
+// 2D pencils of up to kFill2dRows rows take fill2d_kernel with the weights in
+// registers; up to kFill2dWideRows, when the plan found that the LDS
+// footprint fits (Dims::wide2d), with the weights reloaded per delta
 constexpr int kFill2dR = 4;
 constexpr int kFill2dRows = 1024 * kFill2dR;
+constexpr int kFill2dWideR = 8;
+constexpr int kFill2dWideRows = 1024 * kFill2dWideR;
 
-bool fill_is_2d(const Dims& d) { return d.n == 2 && d.m[0] <= kFill2dRows; }
+static size_t fill2d_lds(int S1, int m1, size_t tsize) { return (size_t(2) * S1 + m1) * tsize; }
+
+bool fill_is_2d(const Dims& d) {
+  return d.n == 2 && (d.m[0] <= kFill2dRows || (d.wide2d && d.m[0] <= kFill2dWideRows));
+}
+
+bool fill2d_wide_fits(const Dims& d, int S1, size_t tsize) {
+  return d.n == 2 && d.m[0] > kFill2dRows && d.m[0] <= kFill2dWideRows &&
+         fill2d_lds(S1, d.m[0], tsize) <= 160 * 1024;
+}
 
 template <typename T>
 hipError_t launch_fill2d(const KInterp<T>& ip, int form, const Dims& d, const int4* dsl, const double* coef, T* band,
                          hipStream_t s) {
-  const int rows_per = (d.m[0] + kFill2dR - 1) / kFill2dR;
+  const bool wide = d.m[0] > kFill2dRows;
+  const int R = wide ? kFill2dWideR : kFill2dR;
+  const int rows_per = (d.m[0] + R - 1) / R;
   const int nt = std::min(1024, (rows_per + 63) / 64 * 64);
-  const size_t lds = (size_t(2) * ip.Sd[0] + d.m[0]) * sizeof(T);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  const size_t lds = fill2d_lds(ip.Sd[0], d.m[0], sizeof(T));
+  if (lds > 160 * 1024 || d.m[0] > kFill2dWideRows) return hipErrorInvalidValue;
   if (ip.hi[1] < ip.lo[1]) return hipSuccess;
-  if (form == IGS_MASS)
-    launch_fill2d_pf<IGS_MASS, kFill2dR, T>(ip, d, nt, lds, dsl, coef, band, s);
-  else
-    launch_fill2d_pf<IGS_STIFFNESS, kFill2dR, T>(ip, d, nt, lds, dsl, coef, band, s);
+  if (wide) {
+    // no prefetch: its registers beside eight rows' sums would spill
+    if (form == IGS_MASS)
+      launch_fill2d_q<IGS_MASS, kFill2dWideR, T, false, false>(ip, d, nt, lds, dsl, coef, band, s);
+    else
+      launch_fill2d_q<IGS_STIFFNESS, kFill2dWideR, T, false, false>(ip, d, nt, lds, dsl, coef, band, s);
+  } else {
+    if (form == IGS_MASS)
+      launch_fill2d_pf<IGS_MASS, kFill2dR, T, true>(ip, d, nt, lds, dsl, coef, band, s);
+    else
+      launch_fill2d_pf<IGS_STIFFNESS, kFill2dR, T, true>(ip, d, nt, lds, dsl, coef, band, s);
+  }
   return hipGetLastError();
 }
 

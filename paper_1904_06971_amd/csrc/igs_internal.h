@@ -105,6 +105,10 @@ struct Dims {
   int nelem[3], m[3];
   int64_t N, ld;
   int batch;
+  // 2-D surrogate plans: 1 when the pencils are too long for the 2-D fill
+  // with register-held weights but its LDS footprint fits (set by the plan;
+  // make_dims leaves it 0)
+  int wide2d;
 };
 
 igs_status make_dims(const igs_problem* pb, Dims* d);

@@ -205,17 +205,32 @@ def test_surrogate_fit_tiled_batch(igs, oracle):
         assert rel_maxnorm(igs.band_rows(band, prob, b), ref) < TOL64
 
 
-def test_surrogate_2d_too_wide(igs, oracle):
-    """Past 4096 functions in direction 1 the 2D fill falls back to the chunked
-    kernel, whose per-chunk tables outgrow LDS at small sampling steps: a clean
-    IGS_ERR_UNSUPPORTED, while a larger step still assembles."""
-    prob = W.problem(2, 1, (4200, 8))
+@pytest.mark.parametrize("prob,form,M,q,f32", [
+    (W.problem(2, 1, (4200, 8)), 0, 2, 1, False), (W.problem(2, 1, (4200, 8)), 0, 16, 1, False),
+    (W.problem(2, 2, (4300, 12)), 1, 2, 3, False), (W.problem(2, 1, (4200, 8)), 0, 2, 1, True),
+    # m1 = 8192, the widest pencil of the reloaded-weight fill (1024 threads x 8 rows)
+    (W.problem(2, 1, (8191, 5)), 0, 4, 1, False),
+])
+def test_surrogate_2d_wide(igs, oracle, prob, form, M, q, f32):
+    """Pencils of 4097 to 8192 functions in direction 1: the 2D fill with the
+    direction-1 weights reloaded per delta (eight rows per thread), stiffness
+    and mass, FP64 and FP32 storage."""
+    import torch
+
+    band = igs.assemble_surrogate(prob, form, M=M, q=q, dtype=torch.float32 if f32 else torch.float64)
+    ref = oracle.surrogate_rows(prob, form, M, q)
+    assert rel_maxnorm(_full(igs, band, prob), ref) < (2e-6 if f32 else TOL64)
+
+
+def test_surrogate_2d_too_wide(igs):
+    """Past 8192 functions in direction 1 (or when the 2D fill's pencil and
+    coefficient lines exceed LDS) the chunked fill takes over, whose per-chunk
+    tables outgrow LDS at small sampling steps: a clean IGS_ERR_UNSUPPORTED
+    before any GPU work."""
+    prob = W.problem(2, 1, (8300, 8))
     with pytest.raises(igs.IGSError) as e:
         igs.assemble_surrogate(prob, 0, M=2, q=1)
     assert e.value.status == -2
-    band = igs.assemble_surrogate(prob, 0, M=16, q=1)
-    ref = oracle.surrogate_rows(prob, 0, 16, 1)
-    assert rel_maxnorm(_full(igs, band, prob), ref) < TOL64
 
 
 @pytest.mark.parametrize("form", [0, 1])
