@@ -385,7 +385,10 @@ igs_status igs_assemble_rhs(const igs_problem* pb, int32_t source, double c, dou
  * band or load vector of that call is then undefined), clears the word, and
  * otherwise returns IGS_OK (also for a stream no asynchronous call has used).
  * Synchronous calls report only their own errors and leave the word alone.
- * Host threads that queue and check on one stream concurrently race. */
+ * Words are kept until the process ends and are keyed by the stream handle:
+ * check a stream before destroying it, or a new stream that receives the same
+ * handle inherits its record.  Host threads that queue and check on one
+ * stream concurrently race. */
 igs_status igs_assemble_async(const igs_problem* pb, int32_t form, int32_t M, int32_t q, int32_t dtype, void* band,
                               void* stream);
 igs_status igs_assemble_rhs_async(const igs_problem* pb, int32_t source, double c, double* f, void* stream);
