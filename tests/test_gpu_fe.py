@@ -50,6 +50,8 @@ FE_CASES = [
     (W.problem(3, 2, 22), 0, 4, 3), (W.problem(3, 3, (26, 24, 25)), 0, 4, 3), (W.problem(3, 3, 26), 1, 4, 3),
     (W.problem(3, 4, (17, 16, 17)), 0, 2, 1), (W.problem(3, 2, 20, coef="sine3", camp=0.5), 0, 3, 2),
     (W.problem(3, 1, (17, 13, 15)), 1, 3, 1), (W.problem(3, 3, 22), 0, 3, 4),
+    # 2D pencils longer than 4096 functions (the 2D fill with reloaded weights)
+    (W.problem(2, 1, (4200, 8)), 0, 4, 1), (W.problem(2, 2, (4300, 12)), 1, 3, 2),
 ]
 
 
