@@ -226,7 +226,7 @@ def test_surrogate_2d_too_wide(igs):
     """Past 8192 functions in direction 1 (or when the 2D fill's pencil and
     coefficient lines exceed LDS) the chunked fill takes over, whose per-chunk
     tables outgrow LDS at small sampling steps: a clean IGS_ERR_UNSUPPORTED
-    before any GPU work."""
+    from the plan, before any kernel runs."""
     prob = W.problem(2, 1, (8300, 8))
     with pytest.raises(igs.IGSError) as e:
         igs.assemble_surrogate(prob, 0, M=2, q=1)
