@@ -372,7 +372,8 @@ igs_status igs_assemble_rhs(const igs_problem* pb, int32_t source, double c, dou
 /* Asynchronous assembly: the same work as igs_assemble_exact (M = 0) or
  * igs_assemble_surrogate (M >= 1, degree q), and as igs_assemble_rhs, queued
  * on `stream` without waiting for it.  Same arguments, validation and host-side
- * errors (returned before any GPU work is queued); the call's device scratch is
+ * errors (argument and validation errors before any GPU work is queued,
+ * IGS_ERR_UNSUPPORTED from the plan before any kernel); the call's device scratch is
  * freed in stream order, so `pb` and host memory may be reused on return, while
  * device inputs (spline coefficients) must stay valid until the stream has run
  * the call.  The device-side error of these calls -- a geometry map whose
